@@ -1,0 +1,364 @@
+"""Pins of the CPU oracle against facts outside the oracle itself.
+
+Each test ties one part of the oracle to a published value, a closed form, a
+statistical law stated in the paper (eq. (1), Lemma 1, Theorem 1), an
+independent algorithm (brute force over all 2^32 addresses, Alg. 2 read
+literally) or an invariant of the method, chosen so that a plausible mistake
+(a dropped term, a wrong shift, a swapped operand) fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from conftest import golden_path, read_golden_kv
+from paper_1803_11449_amd import traffic as T
+
+DEF = oracle.Params()  # g=1024, k=14, r=5, alpha=6
+
+
+def rand_pairs(rng, n, n_src=None):
+    src = rng.integers(0, 2**32, size=n, dtype=np.uint64) if n_src is None \
+        else rng.integers(0, 2**32, size=n_src, dtype=np.uint64)[
+            rng.integers(0, n_src, size=n)]
+    dst = rng.integers(0, 2**32, size=n, dtype=np.uint64)
+    return np.stack([src, dst], axis=1).astype(np.uint32)
+
+
+def host_pairs(host, dsts):
+    return np.stack([np.full(len(dsts), host, dtype=np.uint32),
+                     np.asarray(dsts, dtype=np.uint32)], axis=1)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    w = T.generate(T.spec_single_window_1m(), T.config_seed(1))
+    pairs = w.pairs.numpy().view(np.uint32)
+    return w, pairs, oracle.build_sketch(DEF, pairs)
+
+
+# ------------------------------------------------------------- hash family
+
+def test_splitmix64_published_vectors():
+    with open(golden_path("splitmix64_vectors.txt")) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    assert rows
+    for row in rows:
+        seed, expect = int(row[0]), [int(x) for x in row[1:]]
+        got = oracle.splitmix64(seed, len(expect))
+        assert [int(x) for x in got] == expect
+
+
+def test_hash_coefficients_are_splitmix_outputs_with_odd_multipliers():
+    seed = 0x1234
+    v = [int(x) for x in oracle.splitmix64(seed, 4)]
+    c = [int(x) for x in oracle.hash_coeffs(seed)]
+    assert c == [v[0] | 1, v[1], v[2] | 1, v[3]]
+
+
+def test_hash_ranges_and_uniformity():
+    rng = np.random.default_rng(7)
+    a = rng.integers(0, 2**32, size=1 << 20, dtype=np.uint64).astype(np.uint32)
+    seq = np.arange(1 << 20, dtype=np.uint32)
+    for keys, random_keys in ((a, True), (seq, False)):
+        c0 = oracle.dh(DEF, 0, keys)
+        b = oracle.h1(DEF, keys)
+        assert c0.max() < 2**DEF.k and b.max() < DEF.g
+        for vals, m in ((c0, 2**DEF.k), (b, DEF.g)):
+            counts = np.bincount(vals, minlength=m).astype(np.float64)
+            e = keys.size / m
+            chi2 = ((counts - e) ** 2 / e).sum()
+            # chi-square with m-1 dof: mean m-1, sd sqrt(2(m-1)); 8 sd margin.
+            # Sequential keys under multiply-shift are a Weyl sequence and
+            # spread more evenly than random ones: bound them from above only.
+            sd = math.sqrt(2 * (m - 1))
+            assert chi2 < (m - 1) + 8 * sd, (m, chi2)
+            if random_keys:
+                assert chi2 > (m - 1) - 8 * sd, (m, chi2)
+
+
+@pytest.mark.parametrize("p", [DEF, oracle.Params(1024, 18, 5, 5),
+                               oracle.Params(256, 16, 3, 16),
+                               oracle.Params(512, 10, 8, 4)])
+def test_eq3_block_inversion(p):
+    """eq. (3): DH_i(a) xor DH_0(a) is the k-bit block of a at bit (i-1)*alpha."""
+    rng = np.random.default_rng(3)
+    a = rng.integers(0, 2**32, size=4096, dtype=np.uint64)
+    c0 = oracle.dh(p, 0, a.astype(np.uint32)).astype(np.uint64)
+    for i in range(1, p.r):
+        ci = oracle.dh(p, i, a.astype(np.uint32)).astype(np.uint64)
+        s = (i - 1) * p.alpha
+        block = (a >> np.uint64(s)) & np.uint64(2**p.k - 1) if s < 32 else np.zeros_like(a)
+        assert np.array_equal(ci ^ c0, block)
+
+
+# --------------------------------------------------------------- parameters
+
+def test_paper_parameters_and_constraints():
+    gp = read_golden_kv("paper_parameters.txt")
+    p = oracle.Params(gp["g"], gp["k"], gp["r"], gp["alpha"])
+    assert oracle.check_params(p)
+    assert (p.r - 2) * p.alpha + p.k == gp["constraint_sum"]
+    # the naive design the paper rejects: one g-bit LE per host
+    assert gp["naive_hosts"] * gp["g"] // 8 == gp["naive_bytes"]
+    # the default sketch: r rows of 2^k LEs of g bits
+    assert p.words() * 4 == 5 * 2**14 * 128
+
+
+@pytest.mark.parametrize("g,k,r,alpha,ok", [
+    (1024, 14, 5, 6, True), (1024, 14, 5, 5, False),   # 3*5+14 = 29 < 32
+    (1024, 14, 5, 15, False),                         # alpha > k
+    (1000, 14, 5, 6, False), (16, 14, 5, 6, False),   # g not a power of 2 >= 32
+    (1024, 18, 5, 5, True), (1024, 16, 3, 16, True), (1024, 16, 3, 15, False),
+    (1024, 25, 5, 6, False), (1024, 14, 9, 6, False),
+])
+def test_param_validation(g, k, r, alpha, ok):
+    assert oracle.check_params(oracle.Params(g, k, r, alpha)) == ok
+
+
+# ------------------------------------------------------------------ update
+
+def test_single_pair_sets_r_bits_at_eq2_positions():
+    """Alg. 1 on one pair: exactly one bit per row, all at the same bit index
+    of their LE, in LEs whose xor with row 0's LE is a's bit block (eq. 3)."""
+    p = DEF
+    a, b = 0xC0A80101, 0x08080808
+    sk = oracle.build_sketch(p, np.array([[a, b]], dtype=np.uint32))
+    wpl = p.g // 32
+    nz = np.flatnonzero(sk)
+    assert nz.size == p.r
+    assert all(bin(int(sk[w])).count("1") == 1 for w in nz)
+    le = nz // wpl
+    rows, cells = le >> p.k, le & (2**p.k - 1)
+    assert list(rows) == list(range(p.r))
+    bitpos = [(w % wpl) * 32 + int(sk[w]).bit_length() - 1 for w in nz]
+    assert len(set(bitpos)) == 1
+    for i in range(1, p.r):
+        assert cells[i] ^ cells[0] == (a >> ((i - 1) * p.alpha)) & (2**p.k - 1)
+
+
+def test_update_order_chunking_and_duplicates_invariant():
+    rng = np.random.default_rng(11)
+    pairs = rand_pairs(rng, 50_000, n_src=500)
+    ref = oracle.build_sketch(DEF, pairs)
+    perm = pairs[rng.permutation(len(pairs))]
+    sk = oracle.new_sketch(DEF)
+    for chunk in np.array_split(perm, 7):
+        oracle.update(DEF, sk, chunk)
+    assert np.array_equal(sk, ref)
+    dup = np.concatenate([pairs, pairs[::3], pairs[:10]])
+    assert np.array_equal(oracle.build_sketch(DEF, dup), ref)
+
+
+def test_empty_sketch():
+    sk = oracle.new_sketch(DEF)
+    z0, zr = oracle.zero_counts(DEF, sk)
+    assert (z0 == DEF.g).all() and (zr == DEF.g * 2**DEF.k).all()
+    s = oracle.scalars(DEF, zr, 1024.0)
+    assert s["psi"] == 0.0 and s["D"] == DEF.g
+    assert all(len(h) == 0 for h in oracle.hot_lists(DEF, sk, 1024.0))
+    ip, sz, c, _ = oracle.restore(DEF, sk, 1024.0)
+    assert ip.size == 0
+
+
+def test_saturated_row_is_an_error():
+    sk = oracle.new_sketch(DEF)
+    row = 2**DEF.k * DEF.g // 32
+    sk[2 * row:3 * row] = 0xFFFFFFFF
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.restore(DEF, sk, 1024.0)
+    assert e.value.code == oracle.E_SATURATED
+
+
+# ------------------------------------------------------------- thresholds
+
+def test_hot_threshold_is_eq1_estimate_above_theta():
+    """Zmin = g*exp(-theta/g): z0 < Zmin exactly when eq. (1) on the LE
+    estimates more than theta (theta = g = 1024 gives Zmin = 1024/e)."""
+    g, theta = 1024, 1024.0
+    zmin = oracle.scalars(DEF, np.full(5, g * 2**14, dtype=np.uint64), theta)["zmin"]
+    assert zmin == pytest.approx(1024 / math.e, rel=1e-15)
+    est = lambda z0: -g * math.log(z0 / g)
+    hot_z = [z for z in range(1, g + 1) if z < zmin]
+    assert max(hot_z) == 376
+    assert est(376) > theta > est(377)
+    # an LE with 376 zeros is hot, one with 377 is not
+    sk = oracle.new_sketch(DEF)
+    wpl = g // 32
+    for cell, ones in ((5, g - 376), (9, g - 377)):
+        le = np.zeros(g, dtype=np.uint8)
+        le[:ones] = 1
+        words = np.packbits(le, bitorder="little").view(np.uint32)
+        sk[cell * wpl:(cell + 1) * wpl] = words
+    he = oracle.hot_lists(DEF, sk, theta)
+    assert list(he[0]) == [5]
+
+
+def test_psi_closed_form_and_threshold_order(cfg1):
+    """Lemma 1 with the mean of w(i)' equals 1 - (prod ZR(i)/(g 2^k))^(1/r);
+    T_rep = D*exp(-theta/g) <= Zmin since D <= g."""
+    _, _, sk = cfg1
+    _, zr = oracle.zero_counts(DEF, sk)
+    s = oracle.scalars(DEF, zr, 1024.0)
+    m = DEF.g * 2**DEF.k
+    closed = 1.0 - np.prod(zr.astype(np.float64) / m) ** (1.0 / DEF.r)
+    assert s["psi"] == pytest.approx(closed, rel=1e-12)
+    assert s["D"] == pytest.approx(DEF.g * (1 - closed**DEF.r), rel=1e-12)
+    trep = s["D"] * math.exp(-1024.0 / DEF.g)
+    assert trep <= s["zmin"]
+
+
+def test_lemma1_flow_count_statistical():
+    """w distinct flows with distinct sources: the row zero counts give
+    w' ~= w (Sec. 3.3) and psi ~= 1 - exp(-w/(g 2^k)) (Lemma 1)."""
+    rng = np.random.default_rng(5)
+    w = 2_000_000
+    pairs = rand_pairs(rng, w)
+    sk = oracle.build_sketch(DEF, pairs)
+    _, zr = oracle.zero_counts(DEF, sk)
+    s = oracle.scalars(DEF, zr, 1024.0)
+    assert abs(s["w"] / w - 1) < 2e-3
+    assert s["psi"] == pytest.approx(1 - math.exp(-w / (DEF.g * 2**DEF.k)), rel=2e-3)
+
+
+@pytest.mark.slow
+def test_theorem1_eq4_removes_sharing_bias():
+    """Hosts sharing LEs with heavy background (psi ~ 0.5): eq. (4) is
+    unbiased within the linear-counting error, while eq. (1) applied to the
+    ULE without the psi^r correction of Theorem 1 over-estimates."""
+    rng = np.random.default_rng(17)
+    p = DEF
+    n_bg = int(0.69 * p.g * 2**p.k)
+    hosts = rng.choice(2**32, size=200, replace=False).astype(np.uint32)
+    n = 1500
+    parts = [rand_pairs(rng, n_bg)]
+    for h in hosts:
+        parts.append(host_pairs(h, rng.choice(2**32, size=n, replace=False)))
+    pairs = np.concatenate(parts)
+    sk = oracle.build_sketch(p, pairs)
+    _, zr = oracle.zero_counts(p, sk)
+    s = oracle.scalars(p, zr, 1024.0)
+    assert 0.45 < s["psi"] < 0.55
+    sz, c = oracle.estimate(p, sk, s["psi"], hosts)
+    rel = c / n - 1
+    naive = -p.g * np.log(sz / p.g) / n - 1
+    assert abs(rel.mean()) < 0.008, rel.mean()
+    assert naive.mean() > 0.014, naive.mean()
+
+
+# ---------------------------------------------------------------- restore
+
+def planted_small(seed=1, n_hosts=4, card=3000, background=20000):
+    rng = np.random.default_rng(seed)
+    hosts = rng.choice(2**32, size=n_hosts, replace=False).astype(np.uint32)
+    parts = [rand_pairs(rng, background, n_src=5000)]
+    for h in hosts:
+        parts.append(host_pairs(h, rng.choice(2**32, size=card, replace=False)))
+    return hosts, np.concatenate(parts)
+
+
+def test_single_isolated_host_is_recovered():
+    """One source with n >> theta distinct destinations and nothing else:
+    the SPL is that source; its SZ is the zero count of its one LE; C is
+    eq. (4) and lies within the linear-counting error of n."""
+    rng = np.random.default_rng(2)
+    host, n = np.uint32(0x0A0B0C0D), 3000
+    pairs = host_pairs(host, rng.choice(2**32, size=n, replace=False))
+    sk = oracle.build_sketch(DEF, pairs)
+    ip, sz, c, s = oracle.restore(DEF, sk, 1024.0)
+    assert list(ip) == [host]
+    row0 = sk[: 2**DEF.k * DEF.g // 32]
+    ones = sum(bin(int(x)).count("1") for x in row0)
+    assert sz[0] == DEF.g - ones
+    zr = np.full(DEF.r, DEF.g * 2**DEF.k - ones, dtype=np.float64)
+    psi = 1 - np.prod(zr / (DEF.g * 2**DEF.k)) ** (1 / DEF.r)
+    d = DEF.g * (1 - psi**DEF.r)
+    assert c[0] == pytest.approx(-DEF.g * math.log(sz[0] / d), rel=1e-12)
+    # linear counting sd at n/g ~ 2.9 is about 4%; allow 5 sd
+    assert abs(c[0] / n - 1) < 0.2
+
+
+def test_join_equals_alg2_and_bruteforce_tiny():
+    hosts, pairs = planted_small()
+    sk = oracle.build_sketch(DEF, pairs)
+    he = oracle.hot_lists(DEF, sk, 1024.0)
+    assert 0 < np.prod([len(h) for h in he]) <= 200_000
+    j = oracle.candidates(DEF, sk, 1024.0, "join")
+    a2 = oracle.candidates(DEF, sk, 1024.0, "alg2")
+    bf = oracle.candidates(DEF, sk, 1024.0, "brute")
+    assert np.array_equal(j, a2) and np.array_equal(j, bf)
+    assert set(hosts) <= set(j)
+
+
+@pytest.mark.parametrize("p", [oracle.Params(1024, 16, 3, 16),
+                               oracle.Params(256, 12, 6, 5),
+                               oracle.Params(512, 18, 5, 5)])
+def test_join_equals_bruteforce_other_params(p):
+    hosts, pairs = planted_small(seed=4, n_hosts=6, card=2500, background=50000)
+    sk = oracle.build_sketch(p, pairs)
+    j = oracle.candidates(p, sk, 700.0, "join")
+    bf = oracle.candidates(p, sk, 700.0, "brute")
+    assert np.array_equal(j, bf)
+    assert set(hosts) <= set(j)
+
+
+def test_config1_join_equals_bruteforce(cfg1):
+    _, _, sk = cfg1
+    j = oracle.candidates(DEF, sk, 1024.0, "join")
+    bf = oracle.candidates(DEF, sk, 1024.0, "brute")
+    assert np.array_equal(j, bf)
+    assert len(j) > 50
+
+
+def test_candidates_rehash_to_hot_cells_and_norehash_superset(cfg1):
+    _, _, sk = cfg1
+    he = [set(h) for h in oracle.hot_lists(DEF, sk, 1024.0)]
+    cand = oracle.candidates(DEF, sk, 1024.0, "join")
+    for i in range(DEF.r):
+        assert set(oracle.dh(DEF, i, cand)) <= he[i]
+    loose = oracle.candidates(DEF, sk, 1024.0, "join_norehash")
+    assert set(cand) <= set(loose)
+
+
+def test_spl_subset_of_candidates_and_threshold_monotone(cfg1):
+    _, _, sk = cfg1
+    prev = None
+    c_at = {}
+    for theta in (800.0, 1024.0, 1600.0):
+        ip, sz, c, s = oracle.restore(DEF, sk, theta)
+        cand = oracle.candidates(DEF, sk, theta, "join")
+        assert set(ip) <= set(cand)
+        assert (c >= theta).all()
+        assert np.all(np.diff(ip.astype(np.int64)) > 0)
+        for a, v in zip(ip, c):
+            c_at.setdefault(a, v)
+            assert c_at[a] == v          # C(a) does not depend on theta
+        if prev is not None:
+            assert set(ip) <= prev
+        prev = set(ip)
+
+
+def test_config1_recovers_planted_and_true_super_points(cfg1):
+    w, pairs, sk = cfg1
+    ip, sz, c, _ = oracle.restore(DEF, sk, 1024.0)
+    assert set(w.planted_src) <= set(ip)
+    hosts, card = oracle.exact_cardinality(pairs)
+    strong = hosts[card >= 1.25 * 1024]
+    found = np.isin(strong, ip).mean()
+    assert found >= 0.95, found
+
+
+# ------------------------------------------------------------ ground truth
+
+def test_exact_cardinality_against_python_sets():
+    rng = np.random.default_rng(9)
+    src = rng.integers(0, 50, size=20_000).astype(np.uint32) * 7919
+    dst = rng.integers(0, 3000, size=20_000).astype(np.uint32)
+    pairs = np.stack([src, dst], axis=1)
+    sets = {}
+    for s, d in pairs:
+        sets.setdefault(int(s), set()).add(int(d))
+    hosts, card = oracle.exact_cardinality(pairs)
+    assert list(hosts) == sorted(sets)
+    assert list(card) == [len(sets[h]) for h in sorted(sets)]

@@ -1,0 +1,216 @@
+"""Benchmark: one DDHF window end to end on one MI355X.
+
+A step is the whole hot path over one window: reset the sketch, stream the
+window's (src,dst) pairs into it (Alg. 1), restore the super points
+(Alg. 2 / Algs. 3-4 / eq. (4)) and hand the list to the host. The window is
+the 100M-pair large window (Zipf(1.0) over 4M sources, 500 planted super
+points log-uniform in [1024, 50000], 50 sequential scanners, 10% duplicate
+pairs, theta = 1024) on a k = 18, alpha = 5 sketch (160 MiB); the pairs are
+generated on the device and are resident in HBM before timing starts.
+
+Prints one JSON line. value = pairs per second over the whole step (reset +
+update + restore, wall clock, inputs in HBM), in Mpps. Also reported: the
+update kernel's own rate, the restore latency (window close to super point
+list on the host) p50/p99 over the timed steps, the roofline of the
+dominant kernel and the CPU oracle's rate on the same window.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "sketch update Mpps + restore ms/window; p50/p99 window-to-report latency"
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
+PAIR_BYTES = 8
+
+
+def sized_k(n_pairs: int, g: int = 1024) -> tuple[int, int]:
+    """Smallest k >= 14 with n/(g 2^k) <= 0.45; alpha = ceil((32-k)/(r-2)), r=5."""
+    k = 14
+    while n_pairs / (g * 2**k) > 0.45:
+        k += 1
+    return k, math.ceil((32 - k) / 3)
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    i = min(len(xs) - 1, max(0, int(math.ceil(q / 100 * len(xs))) - 1))
+    return xs[i]
+
+
+def cpu_threads() -> int:
+    env = os.environ.get("OMP_NUM_THREADS")
+    n = len(os.sched_getaffinity(0))
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(1, min(n, 16))
+
+
+def run_cpu_baseline(pairs_host, p, theta, n_sample):
+    """The oracle as it is: Alg. 1 single-threaded over a sample of the
+    window, then its restore (the candidate set by scanning all 2^32
+    addresses on `threads` threads, eq. (4) estimates) on the sample's
+    sketch. Rate = sample pairs / (update + restore) time."""
+    import oracle
+    threads = cpu_threads()
+    sample = pairs_host[: 2 * n_sample]
+    t0 = time.perf_counter()
+    sk = oracle.build_sketch(p, sample)
+    t1 = time.perf_counter()
+    try:
+        oracle.restore(p, sk, theta, mode="brute", nthreads=threads)
+    except oracle.OracleError:
+        pass
+    t2 = time.perf_counter()
+    return {
+        "value": n_sample / (t2 - t0) / 1e6, "unit": "Mpps", "cores": threads,
+        "kind": "oracle",
+        "sample": (f"first {n_sample} pairs of the same window; update "
+                   f"{t1 - t0:.2f} s on 1 thread ({n_sample / (t1 - t0) / 1e6:.1f} Mpps), "
+                   f"restore by 2^32 scan {t2 - t1:.2f} s on {threads} threads"),
+        "update_s": t1 - t0, "restore_s": t2 - t1,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--pairs", type=int, default=100_000_000)
+    ap.add_argument("--theta", type=float, default=1024.0)
+    ap.add_argument("--cpu-sample", type=int, default=100_000_000,
+                    help="pairs of the window the oracle baseline processes")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run one plain device copy of this many MiB "
+                         "(for scaling HBM counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sketch would shard by an OR all-reduce, not built here).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1803_11449_amd import ddhf, traffic
+
+    dev = torch.device("cuda:0")
+    spec = traffic.spec_large_window_100m(args.pairs)
+    k, alpha = sized_k(spec.n_pairs)
+    g, r = 1024, 5
+    print(f"bench: generating {spec.n_pairs} pairs on {dev}", file=sys.stderr, flush=True)
+    w = traffic.generate(spec, traffic.config_seed(2), device=dev)
+    pairs = w.pairs
+    torch.cuda.synchronize()
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    sk = ddhf.Sketch(g, k, r, alpha, traffic.HASH_SEED, device=0)
+    stream = torch.cuda.current_stream(dev)
+    n = spec.n_pairs
+
+    def step(record=None):
+        sk.reset()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        sk.update(pairs)
+        ev1.record(stream)
+        ev1.synchronize()               # window closed: every pair is in
+        t_close = time.perf_counter()
+        recs, info = sk.restore(args.theta)
+        t_rep = time.perf_counter()
+        if record is not None:
+            record["update_ms"].append(ev0.elapsed_time(ev1))
+            record["restore_ms"].append((t_rep - t_close) * 1e3)
+            record["n_sp"] = len(recs)
+            record["info"] = info
+        return recs
+
+    print("bench: warmup", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    rec = {"update_ms": [], "restore_ms": []}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(rec)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    print(f"bench: {args.steps} steps in {total:.3f} s", file=sys.stderr, flush=True)
+
+    ms_per_step = total / args.steps * 1e3
+    upd_ms = percentile(rec["update_ms"], 50)
+    upd_mean = sum(rec["update_ms"]) / len(rec["update_ms"])
+    update_mpps = n / (upd_mean / 1e3) / 1e6
+    alg_bytes = n * PAIR_BYTES
+    achieved = alg_bytes / (upd_mean / 1e3) / 1e9
+    info = rec["info"]
+
+    out = {
+        "metric": METRIC,
+        "value": round(n * args.steps / total / 1e6, 3),
+        "unit": "Mpps",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "large_window_100m", "n_pairs": n, "g": g, "k": k,
+                   "r": r, "alpha": alpha, "theta": args.theta,
+                   "zipf_s": spec.zipf_s, "sources": spec.n_sources,
+                   "planted": len(spec.planted_card), "scanners": spec.n_scanners,
+                   "dup_frac": spec.dup_frac},
+        "update_mpps": round(update_mpps, 2),
+        "update_ms_p50": round(upd_ms, 4),
+        "restore_ms_p50": round(percentile(rec["restore_ms"], 50), 4),
+        "restore_ms_p99": round(percentile(rec["restore_ms"], 99), 4),
+        "latency_ms_p50": round(percentile(rec["restore_ms"], 50), 4),
+        "latency_ms_p99": round(percentile(rec["restore_ms"], 99), 4),
+        "super_points": rec["n_sp"],
+        "candidates": info["n_candidates"],
+        "he_count": info["he_count"][:r],
+        "psi": round(info["psi"], 6),
+        "roofline": {"kernel": "k_update", "bound": "hbm",
+                     "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        host = pairs.cpu().numpy().view(np.uint32).reshape(-1)
+        import oracle
+        cb = run_cpu_baseline(host, oracle.Params(g, k, r, alpha, traffic.HASH_SEED),
+                              args.theta, min(args.cpu_sample, n))
+        out["cpu_baseline"] = {kk: (round(v, 3) if isinstance(v, float) else v)
+                               for kk, v in cb.items()}
+    sk.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

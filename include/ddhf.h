@@ -1,0 +1,171 @@
+/*
+ * ddhf.h - C ABI of libddhf, the MI355X (gfx950) implementation of the
+ * double direction hash functions (DDHF) super point detector of
+ * J. Xu, "Economical and efficient network super points detection based on
+ * GPU" (arXiv 1803.11449).
+ *
+ * The library owns one sketch per handle: r rows ("LA") of 2^k linear
+ * estimators ("LE") of g bits each (the DHLA of Sec. 3.2), in device memory.
+ * sketch_update streams (src,dst) IPv4 pairs into it (Alg. 1);
+ * sketch_restore recovers the super points of the window from it (Alg. 2,
+ * computed as in Sec. 4.2: hot-LE scan, incremental join of Algs. 3-4,
+ * estimate by eq. (4)); sketch_reset starts a new window.
+ *
+ * Conventions for every entry point
+ *  - Status codes are returned; nothing is thrown across the ABI. On failure
+ *    sketch_last_error() gives a message (per calling thread).
+ *  - hip_stream is a hipStream_t passed as void* (NULL = the null stream).
+ *    Device work is issued on it in order.
+ *  - A handle is not thread-safe: use one handle from one thread/stream at a
+ *    time. Several handles may share a device and a stream.
+ *  - The device is params->device; every call makes it current for its
+ *    duration and restores the caller's current device before returning.
+ *
+ * Hash family (the paper leaves H1 and DH0 as unspecified random hashes):
+ *   DH0(x) = ((A0*x + B0) mod 2^64) >> (64-k)           LE of row 0
+ *   H1(y)  = ((A1*y + B1) mod 2^64) >> (64-log2 g)      bit inside the LE
+ *   DH_i(x) = ((x >> (i-1)*alpha) mod 2^k) xor DH0(x)   eq. (2), i = 1..r-1
+ * A0,B0,A1,B1 are the first four SplitMix64 outputs from params->seed
+ * (A0, A1 with bit 0 set).
+ *
+ * Sketch layout in device memory (also the format of download/upload):
+ * uint32 words; bit b of LE c in row i is bit (b % 32) of word
+ *   (i * 2^k + c) * (g/32) + b/32.
+ * One LE of the default g = 1024 is 128 bytes.
+ */
+#ifndef DDHF_H
+#define DDHF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sketch sketch_t;
+
+/* Sketch parameters (Sec. 3.2-3.3; the paper's experiments use g = 1024,
+ * k = 14, r = 5, alpha = 6, Sec. 5).
+ * Valid iff: g a power of two in [32, 65536]; 5 <= k <= 24; 3 <= r <= 8;
+ * 1 <= alpha <= k; (r-2)*alpha + k >= 32 (Sec. 3.3: every address bit lies in
+ * some block); k - alpha <= 20 (bucket tables of the join). */
+typedef struct {
+  uint32_t g;       /* bits per LE */
+  uint32_t k;       /* log2 of the LEs per row */
+  uint32_t r;       /* rows = hash functions */
+  uint32_t alpha;   /* bit stride between neighbouring blocks */
+  uint64_t seed;    /* seed of the hash coefficients */
+  int32_t device;   /* HIP device ordinal */
+} sketch_params_t;
+
+/* One reported super point: its address, the zero count SZ of its ULE
+ * (the AND of its r LEs, Def. 1) and its cardinality estimate
+ * C = -g*ln(SZ/(g - g*psi^r)) (eq. (4)); est = +INFINITY when sz == 0. */
+typedef struct {
+  uint32_t ip;
+  uint32_t sz;
+  double est;
+} sketch_sp_t;
+
+/* Diagnostics of the last restore (all optional to read). */
+typedef struct {
+  uint64_t zr[8];           /* ZR(i): zero bits in row i (Sec. 3.3) */
+  uint32_t he_count[8];     /* |HE(i)|: hot LEs in row i (Alg. 2) */
+  uint64_t n_partials[8];   /* partial addresses after join stage i
+                               (index 2 = Alg. 3, 3..r-2 = Alg. 4) */
+  uint64_t n_candidates;    /* addresses whose r LEs are all hot */
+  uint64_t n_reported;      /* super points (SZ <= szmax) */
+  double psi;               /* one-bit probability (Lemma 1) */
+  double d;                 /* g - g*psi^r (eq. (4)) */
+  double zmin;              /* g*exp(-theta/g) (Alg. 2) */
+  double trep;              /* d*exp(-theta/g): C >= theta <=> SZ <= trep */
+  uint32_t zhot;            /* hot <=> z0 <= zhot (= ceil(zmin) - 1) */
+  uint32_t szmax;           /* report <=> SZ <= szmax (= floor(trep)) */
+} sketch_info_t;
+
+enum {
+  SKETCH_OK = 0,
+  SKETCH_E_INVAL = -1,      /* bad argument or parameters */
+  SKETCH_E_NOMEM = -2,      /* device or host allocation failed */
+  SKETCH_E_HIP = -3,        /* a HIP runtime call failed */
+  SKETCH_E_CAPACITY = -4,   /* output buffer too small; *n_out = needed */
+  SKETCH_E_SATURATED = -5   /* a row has no zero bit left (psi = 1) */
+};
+
+/* Fill *p with the paper's defaults (g 1024, k 14, r 5, alpha 6), a fixed
+ * seed and device 0. */
+void sketch_params_default(sketch_params_t *p);
+
+/* Check the parameters (see sketch_params_t); SKETCH_OK or SKETCH_E_INVAL. */
+int sketch_params_check(const sketch_params_t *p);
+
+/* Bytes of device memory the sketch itself takes: r * 2^k * g / 8.
+ * 0 if the parameters are invalid. */
+size_t sketch_bytes(const sketch_params_t *p);
+
+/* Allocate a sketch on params->device with every bit 0 (Sec. 4: the DHLA
+ * is zeroed at the start of a period), plus the restore work buffers.
+ * *out receives the handle. Errors: INVAL (parameters, NULL), NOMEM, HIP. */
+int sketch_create(const sketch_params_t *params, sketch_t **out);
+
+/* Release the handle and all its device memory. Waits for the device. NULL
+ * is ignored. */
+void sketch_destroy(sketch_t *s);
+
+/* Alg. 1 (Sec. 3.2, Sec. 4.1) for n_pairs pairs: for each (a,b), set bit
+ * H1(b) of LE DH_i(a) in every row i. d_pairs is DEVICE memory holding
+ * 2*n_pairs uint32 words, interleaved a0,b0,a1,b1,... (a = the measured
+ * host, b = the opposite host), 8-byte aligned, owned by the caller and
+ * kept alive until the stream has passed this call. Asynchronous on
+ * hip_stream; accumulates into the window (OR is order-free, so any split
+ * into calls gives the same sketch). n_pairs == 0 is a no-op.
+ * Errors: INVAL (NULL handle, NULL or misaligned d_pairs with n_pairs > 0),
+ * HIP (launch failure). */
+int sketch_update(sketch_t *s, const uint32_t *d_pairs, size_t n_pairs,
+                  void *hip_stream);
+
+/* Alg. 2 (Sec. 3.3) computed as in Sec. 4.2: LEs with z0 < g*exp(-theta/g)
+ * are hot; the join of Algs. 3-4 rebuilds every address whose r LEs are
+ * all hot and which re-hashes to its own LE in row 0; each is reported iff
+ * its eq. (4) estimate C >= theta (decided exactly as SZ <= floor(trep)).
+ * out is HOST memory for cap records, filled ascending by address.
+ * Synchronous: returns after the records are on the host. Does not change
+ * the sketch, so it may be called again with another theta.
+ * theta must be > 0. Errors: INVAL; CAPACITY (cap too small: *n_out = the
+ * number needed, out untouched); SATURATED (some row has no zero bit);
+ * NOMEM; HIP. *n_out (required) and *info (nullable) are written on
+ * success, CAPACITY and SATURATED. */
+int sketch_restore(sketch_t *s, double theta, sketch_sp_t *out, size_t cap,
+                   size_t *n_out, sketch_info_t *info, void *hip_stream);
+
+/* Start a new window: every bit of the sketch back to 0 (Sec. 4).
+ * Asynchronous on hip_stream. */
+int sketch_reset(sketch_t *s, void *hip_stream);
+
+/* ---- test and checkpoint hooks ---- */
+
+/* Copy the sketch to HOST memory host_words (n_words must equal
+ * sketch_bytes()/4). Synchronous. Errors: INVAL, HIP. */
+int sketch_download(const sketch_t *s, uint32_t *host_words, size_t n_words,
+                    void *hip_stream);
+
+/* Replace the sketch with HOST memory host_words (n_words must equal
+ * sketch_bytes()/4). Synchronous. Errors: INVAL, HIP. */
+int sketch_upload(sketch_t *s, const uint32_t *host_words, size_t n_words,
+                  void *hip_stream);
+
+/* The candidate set of sketch_restore before the estimate step: every
+ * address whose r LEs are all hot for theta, ascending, into HOST memory
+ * out. Synchronous. Errors as sketch_restore. */
+int sketch_candidates(sketch_t *s, double theta, uint32_t *out, size_t cap,
+                      size_t *n_out, void *hip_stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *sketch_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDHF_H */

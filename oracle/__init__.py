@@ -85,6 +85,16 @@ def lib() -> ctypes.CDLL:
     return _lib
 
 
+def default_threads() -> int:
+    """Threads for the parallel parts (the 2^32 scan): the CPU share this
+    process may use (affinity, OMP_NUM_THREADS), at most 16."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, min(n, 16))
+
+
 def _ptr(a: np.ndarray) -> int:
     return a.ctypes.data
 
@@ -198,7 +208,7 @@ def hot_lists(p: Params, sketch: np.ndarray, theta: float):
 
 def candidates(p: Params, sketch: np.ndarray, theta: float, mode="join",
                nthreads: int | None = None) -> np.ndarray:
-    nth = nthreads or os.cpu_count() or 1
+    nth = nthreads or default_threads()
     cap = 1 << 16
     while True:
         out = np.zeros(cap, dtype=np.uint32)
@@ -223,7 +233,7 @@ def estimate(p: Params, sketch: np.ndarray, psi: float, ips):
 def restore(p: Params, sketch: np.ndarray, theta: float, mode="join",
             nthreads: int | None = None):
     """Alg. 2: returns (ips, sz, C, scalars) ascending by address."""
-    nth = nthreads or os.cpu_count() or 1
+    nth = nthreads or default_threads()
     cap = 1 << 14
     while True:
         ip = np.zeros(cap, dtype=np.uint32)

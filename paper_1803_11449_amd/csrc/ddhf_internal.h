@@ -1,0 +1,87 @@
+// Internal declarations shared by the library's translation units: the
+// device-side hash group, kernel argument blocks, device state and the
+// kernel launchers. Not part of the public ABI (include/ddhf.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ddhf {
+
+// Geometry and hash coefficients of one sketch, passed by value to kernels.
+struct Geom {
+  uint32_t g;        // bits per LE
+  uint32_t k;        // log2 LEs per row
+  uint32_t r;        // rows
+  uint32_t alpha;    // block stride
+  uint32_t log2g;
+  uint32_t wpl;      // 32-bit words per LE = g/32
+  uint32_t shift[8]; // bit offset of block i: min((i-1)*alpha, 32); [0] unused
+  uint64_t a0, b0;   // DH0 coefficients
+  uint64_t a1, b1;   // H1 coefficients
+};
+
+// DH0: multiply-add-shift to k bits.
+__device__ __forceinline__ uint32_t hash_dh0(const Geom &G, uint32_t x) {
+  return (uint32_t)((G.a0 * (uint64_t)x + G.b0) >> (64 - G.k));
+}
+
+// H1: multiply-add-shift to log2(g) bits.
+__device__ __forceinline__ uint32_t hash_h1(const Geom &G, uint32_t y) {
+  return (uint32_t)((G.a1 * (uint64_t)y + G.b1) >> (64 - G.log2g));
+}
+
+// BL(i): k bits of x starting at bit (i-1)*alpha (0 past bit 31).
+__device__ __forceinline__ uint32_t bit_block(const Geom &G, uint32_t i,
+                                              uint32_t x) {
+  return (uint32_t)(((uint64_t)x >> G.shift[i]) & ((1u << G.k) - 1));
+}
+
+// Device-resident state of one restore. Zeroed at the start of each restore
+// by a fill kernel.
+struct DevState {
+  unsigned long long zr[8];          // ZR(i)
+  unsigned long long n_out[8];       // outputs of join stage i (2..r-1)
+  unsigned long long n_cand;         // candidates (after re-hash)
+  unsigned long long n_spl;          // reported
+  uint32_t he_count[8];              // |HE(i)|
+  double psi, d, trep;
+  uint32_t szmax;
+  uint32_t saturated;
+  uint32_t pad[2];
+};
+
+// Restore work buffers (device pointers) and capacities.
+struct RestoreBufs {
+  DevState *st;
+  uint32_t *hotmask;      // r * 2^k bits
+  uint32_t *he;           // r * 2^k entries, row i at i*2^k, ascending
+  uint32_t *bk_off;       // r * (nb+1): bucket offsets of row i (rows >= 2)
+  uint32_t *bk_cur;       // r * nb: fill cursors
+  uint32_t *bk_val;       // r * 2^k: row entries grouped by bucket
+  uint2 *part[2];         // ping-pong partial addresses (sub, c0)
+  size_t part_cap[2];
+  uint32_t *cand;         // candidate addresses
+  size_t cand_cap;
+  uint4 *spl;             // records {ip, sz, est.lo, est.hi}, unsorted
+  uint4 *spl_sorted;      // the same, ascending by ip
+  size_t spl_cap;
+  uint32_t *cand_sorted;
+};
+
+// ---- launchers (update.hip) ----
+hipError_t launch_update(const Geom &G, uint32_t *sketch, const uint32_t *pairs,
+                         size_t n, int grid, int variant, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *p, size_t n_words, uint32_t value,
+                           int grid, hipStream_t st);
+
+// ---- launchers (restore.hip) ----
+// Runs every restore step up to and including the candidate list (and, when
+// estimate != 0, the estimate, report filter and sort). All counts stay on
+// the device; the caller reads DevState afterwards.
+hipError_t launch_restore(const Geom &G, const uint32_t *sketch,
+                          const RestoreBufs &B, uint32_t zhot, double e_theta,
+                          int estimate, int grid, hipStream_t st);
+
+}  // namespace ddhf

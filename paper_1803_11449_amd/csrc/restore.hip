@@ -1,0 +1,682 @@
+// Window-end restore (Alg. 2, Sec. 3.3, laid out as in Sec. 4.2).
+//
+//  1 hot scan      one read of the whole sketch: z0 = g - popcount of every
+//                  LE, ZR(i) per row, and a bitmap of hot LEs (z0 <= zhot,
+//                  i.e. z0 < Zmin = g*exp(-theta/g)). HBM-bound.
+//  2 HE compaction one workgroup per row turns the hot bitmap into HE(i),
+//                  ascending, by a block prefix sum.
+//  3 buckets       rows >= 2: HE(i) grouped by its low k-alpha bits, so a
+//                  join probe finds exactly the entries whose overlap bits
+//                  match instead of testing all of HE(i) (Algs. 3-4 test
+//                  every tuple; the bucketed probe enumerates the same
+//                  accepted tuples and skips only failing ones).
+//  4 scalars       psi (Lemma 1 with the flow-count estimate of Sec. 3.3),
+//                  D = g(1 - psi^r) (eq. (4)), T_rep = D*exp(-theta/g) and
+//                  the integer report bound floor(T_rep), in float64.
+//  5 join          stage 1 (Alg. 3) over HE(0) x HE(1) probing row 2;
+//                  stages 3..r-1 (Alg. 4) over the partial addresses probing
+//                  row i. Each stage appends its outputs with one atomic per
+//                  wave; counts are exact even past a buffer's capacity so
+//                  the host can grow it and run again. The last stage keeps
+//                  a rebuilt address only if it fits 32 bits and DH0 of it
+//                  is the CL_0 it was built from.
+//  6 estimate      per candidate, AND of its r LEs (ULE), SZ = g - popcount,
+//                  report iff SZ <= floor(T_rep) (<=> C >= theta),
+//                  C = -g*ln(SZ/D) (eq. (4)), +inf when SZ = 0.
+//  7 sort          reported records ascending by address.
+#include <math.h>
+
+#include "ddhf_internal.h"
+
+namespace ddhf {
+
+// ------------------------------------------------------------ wave helpers
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t t = __shfl_up(v, d, 64);
+    if (lane >= (uint32_t)d) v += t;
+  }
+  return v;
+}
+
+// Reserve `nout` consecutive slots of a global list for this lane, with one
+// atomic per wave. Must be called by all 64 lanes of the wave.
+__device__ __forceinline__ unsigned long long wave_reserve(
+    unsigned long long *counter, uint32_t nout) {
+  const uint32_t incl = wave_incl_scan(nout);
+  const uint32_t total = __shfl(incl, 63, 64);
+  unsigned long long base = 0;
+  if (lane_id() == 63 && total) base = atomicAdd(counter, (unsigned long long)total);
+  base = __shfl(base, 63, 64);
+  return base + (incl - nout);
+}
+
+// Exclusive prefix sum over a workgroup of NT threads (NT a multiple of 64).
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total,
+                                                    uint32_t *sh) {
+  constexpr int NW = NT / 64;
+  const uint32_t lane = lane_id(), wid = threadIdx.x >> 6;
+  const uint32_t inc = wave_incl_scan(v);
+  if (lane == 63) sh[wid] = inc;
+  __syncthreads();
+  if (wid == 0) {
+    uint32_t s = lane < NW ? sh[lane] : 0;
+    s = wave_incl_scan(s);
+    if (lane < NW) sh[lane] = s;
+  }
+  __syncthreads();
+  const uint32_t off = wid ? sh[wid - 1] : 0;
+  *total = sh[NW - 1];
+  __syncthreads();
+  return off + inc - v;
+}
+
+// How lanes share one LE of WPL words: LPL lanes, each reading VPL uint4.
+template <int WPL>
+struct LeShape {
+  static constexpr int V4 = WPL >= 4 ? WPL / 4 : 0;
+  static constexpr int LPL = WPL >= 4 ? (V4 < 64 ? V4 : 64) : 1;
+  static constexpr int VPL = WPL >= 4 ? V4 / LPL : 0;
+};
+
+// ----------------------------------------------------------- 0: state init
+
+__global__ void k_state_init(DevState *st) {
+  uint32_t *p = reinterpret_cast<uint32_t *>(st);
+  for (uint32_t i = threadIdx.x; i < sizeof(DevState) / 4; i += blockDim.x) p[i] = 0;
+}
+
+// -------------------------------------------------------------- 1: hot scan
+
+// Each block scans a contiguous run of `chunk` LEs; a pass covers
+// 256/LPL LEs and HS_UNROLL passes are loaded before any is reduced, so every
+// lane keeps several 16-byte loads in flight. ZR(i) is summed in registers
+// and folded into LDS only when a lane's run crosses into the next row.
+constexpr int HS_UNROLL = 4;
+
+template <int WPL>
+__global__ __launch_bounds__(256) void k_hot_scan(Geom G, const uint32_t *__restrict__ sk,
+                                                  uint32_t zhot,
+                                                  uint32_t *__restrict__ hotmask,
+                                                  DevState *__restrict__ st, uint64_t chunk) {
+  using S = LeShape<WPL>;
+  constexpr uint32_t GROUPS = 256 / S::LPL;
+  __shared__ unsigned long long zr_sh[8];
+  if (threadIdx.x < 8) zr_sh[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t n_le = (uint64_t)G.r << G.k;
+  const uint64_t e_begin = (uint64_t)blockIdx.x * chunk;
+  const uint64_t e_end = e_begin + chunk < n_le ? e_begin + chunk : n_le;
+  const uint32_t grp = threadIdx.x / S::LPL, sub = threadIdx.x % S::LPL;
+  uint32_t cur_row = (uint32_t)(e_begin >> G.k);
+  unsigned long long acc = 0;
+  for (uint64_t e0 = e_begin; e0 < e_end; e0 += (uint64_t)GROUPS * HS_UNROLL) {
+    uint32_t ones[HS_UNROLL];
+#pragma unroll
+    for (int u = 0; u < HS_UNROLL; u++) {
+      const uint64_t e = e0 + (uint64_t)u * GROUPS + grp;
+      ones[u] = 0;
+      if (e < e_end) {
+        if constexpr (WPL >= 4) {
+          const uint4 *le = reinterpret_cast<const uint4 *>(sk + e * WPL);
+#pragma unroll
+          for (int v = 0; v < S::VPL; v++) {
+            const uint4 q = le[v * S::LPL + sub];
+            ones[u] += __popc(q.x) + __popc(q.y) + __popc(q.z) + __popc(q.w);
+          }
+        } else {
+#pragma unroll
+          for (int w = 0; w < WPL; w++) ones[u] += __popc(sk[e * WPL + w]);
+        }
+      }
+    }
+    if constexpr (S::LPL > 1) {
+#pragma unroll
+      for (int u = 0; u < HS_UNROLL; u++)
+#pragma unroll
+        for (int m = S::LPL / 2; m >= 1; m >>= 1) ones[u] += __shfl_xor(ones[u], m, 64);
+    }
+    if (sub == 0) {
+#pragma unroll
+      for (int u = 0; u < HS_UNROLL; u++) {
+        const uint64_t e = e0 + (uint64_t)u * GROUPS + grp;
+        if (e >= e_end) continue;
+        const uint32_t z0 = G.g - ones[u];
+        const uint32_t row = (uint32_t)(e >> G.k);
+        if (row != cur_row) {
+          if (acc) atomicAdd(&zr_sh[cur_row], acc);
+          acc = 0;
+          cur_row = row;
+        }
+        acc += z0;
+        if (z0 <= zhot) atomicOr(&hotmask[e >> 5], 1u << (e & 31));
+      }
+    }
+  }
+  if (sub == 0 && acc) atomicAdd(&zr_sh[cur_row], acc);
+  __syncthreads();
+  if (threadIdx.x < G.r && zr_sh[threadIdx.x])
+    atomicAdd(&st->zr[threadIdx.x], zr_sh[threadIdx.x]);
+}
+
+// ---------------------------------------------------------- 2: HE compaction
+
+__global__ __launch_bounds__(1024) void k_he_compact(Geom G,
+                                                     const uint32_t *__restrict__ hotmask,
+                                                     uint32_t *__restrict__ he,
+                                                     DevState *__restrict__ st) {
+  __shared__ uint32_t sh[17];
+  const uint32_t row = blockIdx.x;
+  const uint32_t nw = (1u << G.k) >> 5;
+  const uint32_t *hm = hotmask + (size_t)row * nw;
+  const uint32_t per = (nw + blockDim.x - 1) / blockDim.x;
+  const uint32_t w0 = min(threadIdx.x * per, nw), w1 = min(w0 + per, nw);
+  uint32_t cnt = 0;
+  for (uint32_t w = w0; w < w1; w++) cnt += __popc(hm[w]);
+  uint32_t total;
+  const uint32_t excl = block_excl_scan<1024>(cnt, &total, sh);
+  uint32_t *out = he + ((size_t)row << G.k) + excl;
+  for (uint32_t w = w0; w < w1; w++) {
+    uint32_t m = hm[w];
+    while (m) {
+      const uint32_t b = __ffs(m) - 1;
+      *out++ = (w << 5) | b;
+      m &= m - 1;
+    }
+  }
+  if (threadIdx.x == 0) st->he_count[row] = total;
+}
+
+// --------------------------------------------------------------- 3: buckets
+
+__global__ __launch_bounds__(1024) void k_buckets(Geom G, const uint32_t *__restrict__ he,
+                                                  uint32_t *__restrict__ bk_off,
+                                                  uint32_t *__restrict__ bk_cur,
+                                                  uint32_t *__restrict__ bk_val,
+                                                  const DevState *__restrict__ st) {
+  __shared__ uint32_t sh[17];
+  const uint32_t row = blockIdx.x + 2;
+  const uint32_t nb = 1u << (G.k - G.alpha), M = nb - 1;
+  uint32_t *off = bk_off + (size_t)row * (nb + 1);
+  uint32_t *cur = bk_cur + (size_t)row * nb;
+  const uint32_t *h = he + ((size_t)row << G.k);
+  uint32_t *val = bk_val + ((size_t)row << G.k);
+  const uint32_t n = st->he_count[row];
+  const uint32_t tid = threadIdx.x, bs = blockDim.x;
+  for (uint32_t b = tid; b < nb; b += bs) cur[b] = 0;
+  __syncthreads();
+  for (uint32_t x = tid; x < n; x += bs) atomicAdd(&cur[h[x] & M], 1u);
+  __syncthreads();
+  const uint32_t per = (nb + bs - 1) / bs;
+  const uint32_t b0 = min(tid * per, nb), b1 = min(b0 + per, nb);
+  uint32_t s = 0;
+  for (uint32_t b = b0; b < b1; b++) s += cur[b];
+  uint32_t total;
+  uint32_t run = block_excl_scan<1024>(s, &total, sh);
+  for (uint32_t b = b0; b < b1; b++) {
+    const uint32_t c = cur[b];
+    off[b] = run;
+    cur[b] = run;
+    run += c;
+  }
+  if (tid == 0) off[nb] = total;
+  __syncthreads();
+  for (uint32_t x = tid; x < n; x += bs) {
+    const uint32_t c = h[x];
+    const uint32_t pos = atomicAdd(&cur[c & M], 1u);
+    val[pos] = c;
+  }
+}
+
+// --------------------------------------------------------------- 4: scalars
+
+__global__ void k_scalars(Geom G, DevState *st, double e_theta) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double m = (double)G.g * (double)(1ull << G.k);
+  double lsum = 0.0;
+  for (uint32_t i = 0; i < G.r; i++) {
+    if (st->zr[i] == 0) {
+      st->saturated = 1;
+      st->psi = 1.0;
+      st->d = 0.0;
+      st->trep = 0.0;
+      st->szmax = 0;
+      return;
+    }
+    lsum += log((double)st->zr[i] / m);
+  }
+  const double psi = 1.0 - exp(lsum / (double)G.r);
+  double pr = 1.0;
+  for (uint32_t i = 0; i < G.r; i++) pr *= psi;
+  const double d = (double)G.g * (1.0 - pr);
+  const double trep = d * e_theta;
+  st->psi = psi;
+  st->d = d;
+  st->trep = trep;
+  st->szmax = (uint32_t)floor(trep);
+}
+
+// ------------------------------------------------------------------ 5: join
+
+// Does bucket entry c (row i, 2 <= i <= r-1) extend partial address `sub`
+// built with CL_0 = c0? Writes the extended address. Bits of the address at
+// or above 32 must be 0 for a 32-bit host; such tuples are dropped here,
+// where they first appear, rather than at the last stage.
+__device__ __forceinline__ bool extend(const Geom &G, uint32_t i, uint32_t sub,
+                                       uint32_t c0, uint32_t c, uint32_t *out) {
+  const uint32_t blk = c0 ^ c;
+  const uint32_t top = blk >> (G.k - G.alpha);   // the alpha new bits
+  const uint32_t pos = G.k + (i - 2) * G.alpha;  // where they go
+  if (pos >= 32) {
+    *out = sub;
+    return top == 0;
+  }
+  const uint64_t s2 = (uint64_t)sub | ((uint64_t)top << pos);
+  *out = (uint32_t)s2;
+  return (s2 >> 32) == 0;
+}
+
+// Join outputs are staged per wave in LDS and copied out in runs, so the
+// global list counter sees one atomic per STAGE_CAP outputs rather than one
+// per wave step (a single hot counter serialises otherwise).
+constexpr int STAGE_CAP = 1024;
+
+__device__ __forceinline__ void lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+}
+
+template <typename T>
+struct Stage {
+  T *buf;         // this wave's slice of LDS
+  uint32_t fill;  // wave-uniform
+};
+
+template <typename T>
+__device__ __forceinline__ void stage_flush(Stage<T> &s, unsigned long long *counter,
+                                            T *out, size_t cap) {
+  if (s.fill == 0) return;
+  unsigned long long base = 0;
+  if (lane_id() == 0) base = atomicAdd(counter, (unsigned long long)s.fill);
+  base = __shfl(base, 0, 64);
+  lds_fence();
+  for (uint32_t i = lane_id(); i < s.fill; i += 64)
+    if (base + i < cap) out[base + i] = s.buf[i];
+  lds_fence();
+  s.fill = 0;
+}
+
+template <bool LAST>
+struct JoinOut {
+  using T = uint2;  // (partial address, CL_0)
+  static __device__ __forceinline__ T make(uint32_t a, uint32_t c0) { return make_uint2(a, c0); }
+};
+template <>
+struct JoinOut<true> {
+  using T = uint32_t;  // rebuilt address
+  static __device__ __forceinline__ T make(uint32_t a, uint32_t) { return a; }
+};
+
+// One wave step of a join stage: each lane holds a partial address `sub`
+// (with its CL_0) and the range [b0,b1) of bucket entries of row `row` whose
+// overlap bits match; every entry that extends it is emitted (after the
+// 32-bit and re-hash tests on the last stage). All 64 lanes must call.
+template <bool LAST>
+__device__ __forceinline__ void join_step(const Geom &G, uint32_t row, uint32_t sub,
+                                          uint32_t c0, uint32_t b0, uint32_t b1,
+                                          const uint32_t *__restrict__ val,
+                                          Stage<typename JoinOut<LAST>::T> &s,
+                                          unsigned long long *counter,
+                                          typename JoinOut<LAST>::T *out, size_t cap) {
+  using O = JoinOut<LAST>;
+  uint32_t nout = 0;
+  for (uint32_t j = b0; j < b1; j++) {
+    uint32_t a;
+    bool ok = extend(G, row, sub, c0, val[j], &a);
+    if (LAST) ok = ok && hash_dh0(G, a) == c0;
+    nout += ok;
+  }
+  const uint32_t incl = wave_incl_scan(nout);
+  const uint32_t total = __shfl(incl, 63, 64);
+  if (total == 0) return;
+  if (s.fill + total > (uint32_t)STAGE_CAP) stage_flush(s, counter, out, cap);
+  const uint32_t excl = incl - nout;
+  if (total > (uint32_t)STAGE_CAP) {
+    // larger than the stage: reserve in the global list directly
+    unsigned long long base = 0;
+    if (lane_id() == 0) base = atomicAdd(counter, (unsigned long long)total);
+    base = __shfl(base, 0, 64) + excl;
+    for (uint32_t j = b0; j < b1 && nout; j++) {
+      uint32_t a;
+      bool ok = extend(G, row, sub, c0, val[j], &a);
+      if (LAST) ok = ok && hash_dh0(G, a) == c0;
+      if (!ok) continue;
+      if (base < cap) out[base] = O::make(a, c0);
+      base++;
+    }
+    return;
+  }
+  uint32_t pos = s.fill + excl;
+  for (uint32_t j = b0; j < b1 && nout; j++) {
+    uint32_t a;
+    bool ok = extend(G, row, sub, c0, val[j], &a);
+    if (LAST) ok = ok && hash_dh0(G, a) == c0;
+    if (!ok) continue;
+    s.buf[pos++] = O::make(a, c0);
+  }
+  s.fill += total;
+}
+
+// Stage 1 (Alg. 3): every (CL_0, CL_1) of HE(0) x HE(1), probing HE(2)'s
+// bucket ((BL(1) >> alpha) xor CL_0) mod 2^(k-alpha). A wave takes one CL_0
+// (a scalar) and 64 consecutive CL_1.
+template <bool LAST>
+__global__ __launch_bounds__(256) void k_join_first(
+    Geom G, const uint32_t *__restrict__ he, const uint32_t *__restrict__ bk_off,
+    const uint32_t *__restrict__ bk_val, DevState *__restrict__ st,
+    typename JoinOut<LAST>::T *__restrict__ out, size_t cap) {
+  using T = typename JoinOut<LAST>::T;
+  __shared__ uint2 stage_mem[4 * STAGE_CAP];
+  if (st->saturated) return;
+  const uint32_t h0 = st->he_count[0], h1 = st->he_count[1];
+  if (h0 == 0 || h1 == 0) return;
+  const uint32_t nb = 1u << (G.k - G.alpha), M = nb - 1;
+  const uint32_t *HE0 = he, *HE1 = he + (1u << G.k);
+  const uint32_t *off = bk_off + 2 * (size_t)(nb + 1);
+  const uint32_t *val = bk_val + ((size_t)2 << G.k);
+  unsigned long long *counter = LAST ? &st->n_cand : &st->n_out[2];
+  Stage<T> s{reinterpret_cast<T *>(stage_mem) + (threadIdx.x >> 6) * STAGE_CAP, 0};
+
+  const uint32_t nch = (h1 + 63) >> 6;
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
+  const uint32_t dq = n_waves / nch, dr = n_waves % nch;
+  uint32_t x0 = wave / nch, ch = wave % nch;
+  while (x0 < h0) {
+    const uint32_t c0 = HE0[x0];
+    const uint32_t x1 = (ch << 6) + lane_id();
+    uint32_t blk1 = 0, b0 = 0, b1 = 0;
+    if (x1 < h1) {
+      blk1 = c0 ^ HE1[x1];
+      const uint32_t key = ((blk1 >> G.alpha) ^ c0) & M;
+      b0 = off[key];
+      b1 = off[key + 1];
+    }
+    join_step<LAST>(G, 2, blk1, c0, b0, b1, val, s, counter, out, cap);
+    x0 += dq;
+    ch += dr;
+    if (ch >= nch) {
+      ch -= nch;
+      x0++;
+    }
+  }
+  stage_flush(s, counter, out, cap);
+}
+
+// Stage i >= 3 (Alg. 4): every partial address of stage i-1, probing HE(i)'s
+// bucket ((partial >> (i-1)*alpha) xor CL_0) mod 2^(k-alpha).
+template <bool LAST>
+__global__ __launch_bounds__(256) void k_join_next(
+    Geom G, uint32_t row, const uint2 *__restrict__ in, size_t in_cap,
+    const uint32_t *__restrict__ bk_off, const uint32_t *__restrict__ bk_val,
+    DevState *__restrict__ st, typename JoinOut<LAST>::T *__restrict__ out, size_t cap) {
+  using T = typename JoinOut<LAST>::T;
+  __shared__ uint2 stage_mem[4 * STAGE_CAP];
+  if (st->saturated) return;
+  const unsigned long long n_in_all = st->n_out[row - 1];
+  const uint64_t n_in = n_in_all < in_cap ? n_in_all : in_cap;
+  const uint32_t nb = 1u << (G.k - G.alpha), M = nb - 1;
+  const uint32_t *off = bk_off + (size_t)row * (nb + 1);
+  const uint32_t *val = bk_val + ((size_t)row << G.k);
+  const uint32_t sh = G.shift[row];
+  unsigned long long *counter = LAST ? &st->n_cand : &st->n_out[row];
+  Stage<T> s{reinterpret_cast<T *>(stage_mem) + (threadIdx.x >> 6) * STAGE_CAP, 0};
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t step = ((uint64_t)gridDim.x * blockDim.x) & ~63ull;
+  for (uint64_t base = wave << 6; base < n_in; base += step) {
+    const uint64_t t = base + lane_id();
+    uint32_t sub = 0, c0 = 0, b0 = 0, b1 = 0;
+    if (t < n_in) {
+      const uint2 p = in[t];
+      sub = p.x;
+      c0 = p.y;
+      const uint32_t key = ((uint32_t)((uint64_t)sub >> sh) ^ c0) & M;
+      b0 = off[key];
+      b1 = off[key + 1];
+    }
+    join_step<LAST>(G, row, sub, c0, b0, b1, val, s, counter, out, cap);
+  }
+  stage_flush(s, counter, out, cap);
+}
+
+// ------------------------------------------------------------ 6: estimate
+
+template <int WPL>
+__global__ __launch_bounds__(256) void k_estimate(Geom G, const uint32_t *__restrict__ sk,
+                                                  const uint32_t *__restrict__ cand,
+                                                  size_t cand_cap, DevState *__restrict__ st,
+                                                  uint4 *__restrict__ spl, size_t spl_cap) {
+  using S = LeShape<WPL>;
+  if (st->saturated) return;
+  const unsigned long long nc_all = st->n_cand;
+  const uint64_t nc = nc_all < cand_cap ? nc_all : cand_cap;
+  const uint32_t szmax = st->szmax;
+  const double d = st->d;
+  const uint32_t sub = threadIdx.x % S::LPL;
+  const uint64_t step = (uint64_t)gridDim.x * blockDim.x / S::LPL;
+  for (uint64_t base = ((uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u)) / S::LPL;
+       base < nc; base += step) {
+    const uint64_t e = base + lane_id() / S::LPL;
+    const bool valid = e < nc;
+    const uint32_t a = valid ? cand[e] : 0u;
+    uint32_t ones = 0;
+    if (valid) {
+      const uint32_t c0 = hash_dh0(G, a);
+      if constexpr (WPL >= 4) {
+#pragma unroll
+        for (int v = 0; v < S::VPL; v++) {
+          uint4 acc = make_uint4(~0u, ~0u, ~0u, ~0u);
+          for (uint32_t i = 0; i < G.r; i++) {
+            const uint32_t cell = i == 0 ? c0 : (bit_block(G, i, a) ^ c0);
+            const uint4 *le =
+                reinterpret_cast<const uint4 *>(sk + ((size_t)((i << G.k) | cell)) * WPL);
+            const uint4 q = le[v * S::LPL + sub];
+            acc.x &= q.x; acc.y &= q.y; acc.z &= q.z; acc.w &= q.w;
+          }
+          ones += __popc(acc.x) + __popc(acc.y) + __popc(acc.z) + __popc(acc.w);
+        }
+      } else {
+        for (int w = 0; w < WPL; w++) {
+          uint32_t acc = ~0u;
+          for (uint32_t i = 0; i < G.r; i++) {
+            const uint32_t cell = i == 0 ? c0 : (bit_block(G, i, a) ^ c0);
+            acc &= sk[((size_t)((i << G.k) | cell)) * WPL + w];
+          }
+          ones += __popc(acc);
+        }
+      }
+    }
+    if constexpr (S::LPL > 1) {
+#pragma unroll
+      for (int m = S::LPL / 2; m >= 1; m >>= 1) ones += __shfl_xor(ones, m, 64);
+    }
+    const uint32_t sz = G.g - ones;
+    const bool report = valid && sub == 0 && sz <= szmax;
+    unsigned long long slot = wave_reserve(&st->n_spl, report ? 1u : 0u);
+    if (report && slot < spl_cap) {
+      const double est = sz ? -(double)G.g * log((double)sz / d) : (double)INFINITY;
+      const unsigned long long bits = __double_as_longlong(est);
+      spl[slot] = make_uint4(a, sz, (uint32_t)bits, (uint32_t)(bits >> 32));
+    }
+  }
+}
+
+// ----------------------------------------------------------------- 7: sort
+
+// Records with distinct 32-bit keys (the address in .x for uint4 records,
+// the value itself for uint32) are sorted ascending. Up to SMALL_SORT
+// entries: one workgroup, a bitonic network over (key << 32 | index) in LDS.
+// Beyond that: every element's rank is the number of smaller keys, counted
+// against LDS tiles of all keys, by as many blocks as the grid has.
+constexpr uint32_t SMALL_SORT = 8192;
+
+template <typename T>
+__device__ __forceinline__ uint32_t sort_key(const T &v);
+template <>
+__device__ __forceinline__ uint32_t sort_key<uint4>(const uint4 &v) { return v.x; }
+template <>
+__device__ __forceinline__ uint32_t sort_key<uint32_t>(const uint32_t &v) { return v; }
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_sort_small(const T *__restrict__ in,
+                                                     const unsigned long long *__restrict__ count,
+                                                     size_t cap, T *__restrict__ out) {
+  __shared__ unsigned long long key[SMALL_SORT];
+  const unsigned long long n_all = *count;
+  const uint32_t n = (uint32_t)(n_all < cap ? n_all : cap);
+  if (n > SMALL_SORT || n == 0) return;
+  uint32_t N = 2;
+  while (N < n) N <<= 1;
+  for (uint32_t i = threadIdx.x; i < N; i += blockDim.x)
+    key[i] = i < n ? ((unsigned long long)sort_key<T>(in[i]) << 32) | i : ~0ull;
+  __syncthreads();
+  for (uint32_t k = 2; k <= N; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) {
+        const uint32_t ixj = i ^ j;
+        if (ixj > i) {
+          const unsigned long long a = key[i], b = key[ixj];
+          if ((a > b) == ((i & k) == 0)) {
+            key[i] = b;
+            key[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) out[i] = in[(uint32_t)key[i]];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_rank_sort(const T *__restrict__ in,
+                                                   const unsigned long long *__restrict__ count,
+                                                   size_t cap, T *__restrict__ out) {
+  constexpr int TILE = 2048;
+  __shared__ uint32_t tile[TILE];
+  const unsigned long long n_all = *count;
+  const uint64_t n = n_all < cap ? n_all : cap;
+  if (n <= SMALL_SORT) return;
+  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n;
+       base += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t j = base + threadIdx.x;
+    T mine{};
+    uint32_t key = 0xFFFFFFFFu;
+    if (j < n) {
+      mine = in[j];
+      key = sort_key<T>(mine);
+    }
+    uint32_t rank = 0;
+    for (uint64_t t0 = 0; t0 < n; t0 += TILE) {
+      const uint32_t len = (uint32_t)((n - t0) < TILE ? (n - t0) : TILE);
+      __syncthreads();
+      for (uint32_t t = threadIdx.x; t < len; t += blockDim.x) tile[t] = sort_key<T>(in[t0 + t]);
+      __syncthreads();
+      for (uint32_t t = 0; t < len; t++) rank += tile[t] < key;
+    }
+    if (j < n) out[rank] = mine;
+  }
+}
+
+template <typename T>
+static void launch_sort(const T *in, const unsigned long long *count, size_t cap, T *out,
+                        int grid, hipStream_t st) {
+  k_sort_small<T><<<1, 1024, 0, st>>>(in, count, cap, out);
+  k_rank_sort<T><<<grid, 256, 0, st>>>(in, count, cap, out);
+}
+
+// ------------------------------------------------------------ orchestration
+
+template <int WPL>
+static hipError_t launch_wpl(const Geom &G, const uint32_t *sketch, const RestoreBufs &B,
+                             uint32_t zhot, double e_theta, int estimate, int grid,
+                             hipStream_t st) {
+  const uint32_t r = G.r, k = G.k;
+  const size_t n_le = (size_t)r << k;
+  // 0: clear state and the hot bitmap
+  k_state_init<<<1, 256, 0, st>>>(B.st);
+  hipError_t e = launch_fill_u32(B.hotmask, n_le / 32, 0u, grid, st);
+  if (e != hipSuccess) return e;
+  // 1: hot scan
+  {
+    using S = LeShape<WPL>;
+    const uint64_t pass = (uint64_t)(256 / S::LPL) * HS_UNROLL;
+    const uint64_t passes = (n_le + pass - 1) / pass;
+    const uint64_t blocks = passes < (uint64_t)grid ? passes : (uint64_t)grid;
+    const uint64_t chunk = (passes + blocks - 1) / blocks * pass;
+    const int gs = (int)((n_le + chunk - 1) / chunk);
+    k_hot_scan<WPL><<<gs, 256, 0, st>>>(G, sketch, zhot, B.hotmask, B.st, chunk);
+  }
+  // 2: HE(i)
+  k_he_compact<<<r, 1024, 0, st>>>(G, B.hotmask, B.he, B.st);
+  // 3: buckets for rows 2..r-1
+  k_buckets<<<r - 2, 1024, 0, st>>>(G, B.he, B.bk_off, B.bk_cur, B.bk_val, B.st);
+  // 4: scalars
+  k_scalars<<<1, 64, 0, st>>>(G, B.st, e_theta);
+  // 5: join
+  if (r == 3) {
+    k_join_first<true><<<grid, 256, 0, st>>>(G, B.he, B.bk_off, B.bk_val, B.st, B.cand,
+                                             B.cand_cap);
+  } else {
+    k_join_first<false><<<grid, 256, 0, st>>>(G, B.he, B.bk_off, B.bk_val, B.st, B.part[0],
+                                              B.part_cap[0]);
+    for (uint32_t row = 3; row < r; row++) {
+      // stage 1 wrote part[0]; stage row reads part[(row-3)%2], writes the other
+      const int ib = (row - 3) & 1;
+      const int ob = ib ^ 1;
+      if (row + 1 == r)
+        k_join_next<true><<<grid, 256, 0, st>>>(G, row, B.part[ib], B.part_cap[ib], B.bk_off,
+                                                B.bk_val, B.st, B.cand, B.cand_cap);
+      else
+        k_join_next<false><<<grid, 256, 0, st>>>(G, row, B.part[ib], B.part_cap[ib], B.bk_off,
+                                                 B.bk_val, B.st, B.part[ob], B.part_cap[ob]);
+    }
+  }
+  if (!estimate) {
+    launch_sort<uint32_t>(B.cand, &B.st->n_cand, B.cand_cap, B.cand_sorted, grid, st);
+    return hipGetLastError();
+  }
+  // 6: estimate and report
+  k_estimate<WPL><<<grid, 256, 0, st>>>(G, sketch, B.cand, B.cand_cap, B.st, B.spl,
+                                        B.spl_cap);
+  // 7: sort
+  launch_sort<uint4>(B.spl, &B.st->n_spl, B.spl_cap, B.spl_sorted, grid, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_restore(const Geom &G, const uint32_t *sketch, const RestoreBufs &B,
+                          uint32_t zhot, double e_theta, int estimate, int grid,
+                          hipStream_t st) {
+  switch (G.wpl) {
+    case 1: return launch_wpl<1>(G, sketch, B, zhot, e_theta, estimate, grid, st);
+    case 2: return launch_wpl<2>(G, sketch, B, zhot, e_theta, estimate, grid, st);
+    case 4: return launch_wpl<4>(G, sketch, B, zhot, e_theta, estimate, grid, st);
+    case 8: return launch_wpl<8>(G, sketch, B, zhot, e_theta, estimate, grid, st);
+    case 16: return launch_wpl<16>(G, sketch, B, zhot, e_theta, estimate, grid, st);
+    case 32: return launch_wpl<32>(G, sketch, B, zhot, e_theta, estimate, grid, st);
+    case 64: return launch_wpl<64>(G, sketch, B, zhot, e_theta, estimate, grid, st);
+    case 128: return launch_wpl<128>(G, sketch, B, zhot, e_theta, estimate, grid, st);
+    case 256: return launch_wpl<256>(G, sketch, B, zhot, e_theta, estimate, grid, st);
+    case 512: return launch_wpl<512>(G, sketch, B, zhot, e_theta, estimate, grid, st);
+    case 1024: return launch_wpl<1024>(G, sketch, B, zhot, e_theta, estimate, grid, st);
+    case 2048: return launch_wpl<2048>(G, sketch, B, zhot, e_theta, estimate, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace ddhf

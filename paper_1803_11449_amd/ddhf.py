@@ -1,0 +1,274 @@
+"""Python binding of libddhf (include/ddhf.h), by ctypes.
+
+Argument marshalling only: every step of the sketch update and the restore
+runs in the HIP library. The functions keep the C names; ``Sketch`` wraps a
+handle for torch callers (pairs as a CUDA tensor, work on torch's current
+stream). There is no fallback: if libddhf.so is not built, loading fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libddhf.so")
+
+SKETCH_OK = 0
+SKETCH_E_INVAL = -1
+SKETCH_E_NOMEM = -2
+SKETCH_E_HIP = -3
+SKETCH_E_CAPACITY = -4
+SKETCH_E_SATURATED = -5
+
+DEFAULT_SEED = 0x1803114490000001
+
+EXPORTS = ("sketch_params_default", "sketch_params_check", "sketch_bytes",
+           "sketch_create", "sketch_destroy", "sketch_update", "sketch_restore",
+           "sketch_reset", "sketch_download", "sketch_upload",
+           "sketch_candidates", "sketch_last_error")
+
+c_u32, c_u64, c_i32, c_sz, c_dbl, c_vp = (ctypes.c_uint32, ctypes.c_uint64,
+                                          ctypes.c_int32, ctypes.c_size_t,
+                                          ctypes.c_double, ctypes.c_void_p)
+
+
+class sketch_params_t(ctypes.Structure):
+    _fields_ = [("g", c_u32), ("k", c_u32), ("r", c_u32), ("alpha", c_u32),
+                ("seed", c_u64), ("device", c_i32)]
+
+
+class sketch_sp_t(ctypes.Structure):
+    _fields_ = [("ip", c_u32), ("sz", c_u32), ("est", c_dbl)]
+
+
+class sketch_info_t(ctypes.Structure):
+    _fields_ = [("zr", c_u64 * 8), ("he_count", c_u32 * 8),
+                ("n_partials", c_u64 * 8), ("n_candidates", c_u64),
+                ("n_reported", c_u64), ("psi", c_dbl), ("d", c_dbl),
+                ("zmin", c_dbl), ("trep", c_dbl), ("zhot", c_u32),
+                ("szmax", c_u32)]
+
+
+SP_DTYPE = np.dtype([("ip", "<u4"), ("sz", "<u4"), ("est", "<f8")])
+assert SP_DTYPE.itemsize == ctypes.sizeof(sketch_sp_t) == 16
+
+
+class SketchError(RuntimeError):
+    def __init__(self, code: int, msg: str, n_needed: int | None = None):
+        super().__init__(f"libddhf status {code}: {msg}")
+        self.code = code
+        self.n_needed = n_needed
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library. Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it first (__graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        sig = {
+            "sketch_params_default": (None, [P(sketch_params_t)]),
+            "sketch_params_check": (c_i32, [P(sketch_params_t)]),
+            "sketch_bytes": (c_sz, [P(sketch_params_t)]),
+            "sketch_create": (c_i32, [P(sketch_params_t), P(c_vp)]),
+            "sketch_destroy": (None, [c_vp]),
+            "sketch_update": (c_i32, [c_vp, c_vp, c_sz, c_vp]),
+            "sketch_restore": (c_i32, [c_vp, c_dbl, c_vp, c_sz, P(c_sz),
+                                       P(sketch_info_t), c_vp]),
+            "sketch_reset": (c_i32, [c_vp, c_vp]),
+            "sketch_download": (c_i32, [c_vp, c_vp, c_sz, c_vp]),
+            "sketch_upload": (c_i32, [c_vp, c_vp, c_sz, c_vp]),
+            "sketch_candidates": (c_i32, [c_vp, c_dbl, c_vp, c_sz, P(c_sz), c_vp]),
+            "sketch_last_error": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().sketch_last_error().decode()
+
+
+def _check(rc: int, n_needed=None) -> None:
+    if rc != SKETCH_OK:
+        raise SketchError(rc, last_error(), n_needed)
+
+
+# --------------------------------------------------- C names, thin wrappers
+
+def sketch_params_default() -> sketch_params_t:
+    p = sketch_params_t()
+    lib().sketch_params_default(ctypes.byref(p))
+    return p
+
+
+def sketch_params_check(p: sketch_params_t) -> int:
+    return lib().sketch_params_check(ctypes.byref(p))
+
+
+def sketch_bytes(p: sketch_params_t) -> int:
+    return lib().sketch_bytes(ctypes.byref(p))
+
+
+def sketch_create(p: sketch_params_t) -> int:
+    h = c_vp()
+    _check(lib().sketch_create(ctypes.byref(p), ctypes.byref(h)))
+    return h.value
+
+
+def sketch_destroy(h: int) -> None:
+    lib().sketch_destroy(h)
+
+
+def sketch_update(h: int, d_pairs: int, n_pairs: int, stream: int = 0) -> None:
+    _check(lib().sketch_update(h, d_pairs, n_pairs, stream))
+
+
+def sketch_reset(h: int, stream: int = 0) -> None:
+    _check(lib().sketch_reset(h, stream))
+
+
+def sketch_restore(h: int, theta: float, cap: int, stream: int = 0):
+    """Returns (records[:n], info). Raises SketchError (with n_needed on
+    CAPACITY)."""
+    out = np.zeros(max(cap, 1), dtype=SP_DTYPE)
+    n = c_sz(0)
+    info = sketch_info_t()
+    rc = lib().sketch_restore(h, float(theta), out.ctypes.data, cap,
+                              ctypes.byref(n), ctypes.byref(info), stream)
+    if rc != SKETCH_OK:
+        err = SketchError(rc, last_error(), n.value)
+        err.info = info_dict(info)
+        raise err
+    return out[: n.value].copy(), info_dict(info)
+
+
+def sketch_candidates(h: int, theta: float, cap: int, stream: int = 0) -> np.ndarray:
+    out = np.zeros(max(cap, 1), dtype=np.uint32)
+    n = c_sz(0)
+    rc = lib().sketch_candidates(h, float(theta), out.ctypes.data, cap,
+                                 ctypes.byref(n), stream)
+    _check(rc, n.value)
+    return out[: n.value].copy()
+
+
+def sketch_download(h: int, n_words: int, stream: int = 0) -> np.ndarray:
+    out = np.zeros(n_words, dtype=np.uint32)
+    _check(lib().sketch_download(h, out.ctypes.data, n_words, stream))
+    return out
+
+
+def sketch_upload(h: int, words: np.ndarray, stream: int = 0) -> None:
+    words = np.ascontiguousarray(words, dtype=np.uint32)
+    _check(lib().sketch_upload(h, words.ctypes.data, words.size, stream))
+
+
+def info_dict(info: sketch_info_t) -> dict:
+    return {
+        "zr": list(info.zr), "he_count": list(info.he_count),
+        "n_partials": list(info.n_partials),
+        "n_candidates": info.n_candidates, "n_reported": info.n_reported,
+        "psi": info.psi, "d": info.d, "zmin": info.zmin, "trep": info.trep,
+        "zhot": info.zhot, "szmax": info.szmax,
+    }
+
+
+# ------------------------------------------------------------ torch facade
+
+def _stream_handle(stream, device) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+class Sketch:
+    """One DDHF sketch on a GPU (r rows of 2^k LEs of g bits)."""
+
+    def __init__(self, g=1024, k=14, r=5, alpha=6, seed=DEFAULT_SEED, device=None):
+        import torch
+        if device is None:
+            device = torch.cuda.current_device()
+        elif isinstance(device, torch.device):
+            device = device.index or 0
+        self.device = int(device)
+        self.params = sketch_params_t(g, k, r, alpha, seed, self.device)
+        self.words = sketch_bytes(self.params) // 4
+        self.handle = sketch_create(self.params)
+        self._cap = 1 << 12
+
+    # pairs: CUDA tensor of 2n 32-bit words (int32/uint32, [n,2] or [2n])
+    def update(self, pairs, stream=None) -> None:
+        import torch
+        if not isinstance(pairs, torch.Tensor) or not pairs.is_cuda:
+            raise TypeError("pairs must be a CUDA tensor")
+        if pairs.element_size() != 4 or not pairs.is_contiguous():
+            raise TypeError("pairs must be a contiguous 32-bit tensor")
+        if pairs.numel() % 2:
+            raise ValueError("pairs must hold an even number of words")
+        sketch_update(self.handle, pairs.data_ptr(), pairs.numel() // 2,
+                      _stream_handle(stream, pairs.device))
+
+    def update_ptr(self, d_pairs: int, n_pairs: int, stream: int = 0) -> None:
+        sketch_update(self.handle, d_pairs, n_pairs, stream)
+
+    def restore(self, theta: float, stream=None):
+        """(records ascending by ip, info dict)."""
+        s = _stream_handle(stream, self.device)
+        while True:
+            try:
+                recs, info = sketch_restore(self.handle, theta, self._cap, s)
+                return recs, info
+            except SketchError as e:
+                if e.code != SKETCH_E_CAPACITY:
+                    raise
+                self._cap = max(int(e.n_needed) + 64, 2 * self._cap)
+
+    def candidates(self, theta: float, stream=None) -> np.ndarray:
+        s = _stream_handle(stream, self.device)
+        cap = 1 << 14
+        while True:
+            try:
+                return sketch_candidates(self.handle, theta, cap, s)
+            except SketchError as e:
+                if e.code != SKETCH_E_CAPACITY:
+                    raise
+                cap = int(e.n_needed) + 64
+
+    def reset(self, stream=None) -> None:
+        sketch_reset(self.handle, _stream_handle(stream, self.device))
+
+    def download(self, stream=None) -> np.ndarray:
+        return sketch_download(self.handle, self.words, _stream_handle(stream, self.device))
+
+    def upload(self, words: np.ndarray, stream=None) -> None:
+        sketch_upload(self.handle, words, _stream_handle(stream, self.device))
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            sketch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,299 @@
+"""GPU path vs the CPU oracle, through the C ABI.
+
+Bar: the sketch bitmap, the candidate set and the reported super point list
+(addresses and SZ) are bit-identical to the oracle's; estimates agree to
+1e-6 relative (+inf == +inf). The report decision is an integer test on
+both sides of the same float64 threshold; a threshold within 1e-9 of an
+integer would make the decision rounding-sensitive, and the tests check
+that none is.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1803_11449_amd import ddhf, traffic as T
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+RTOL = 1e-6
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def host_words(pairs_t):
+    return pairs_t.cpu().numpy().view(np.uint32).reshape(-1)
+
+
+def make_sketch(p: oracle.Params):
+    return ddhf.Sketch(p.g, p.k, p.r, p.alpha, p.seed, device=0)
+
+
+def assert_not_boundary(info):
+    for v in (info["trep"], info["zmin"]):
+        assert abs(v - round(v)) > 1e-9, f"threshold {v} too close to an integer"
+
+
+def assert_spl_equal(recs, ip, sz, c):
+    assert np.array_equal(recs["ip"], ip), (len(recs), len(ip))
+    assert np.array_equal(recs["sz"], sz)
+    est = recs["est"]
+    inf_g, inf_o = np.isinf(est), np.isinf(c)
+    assert np.array_equal(inf_g, inf_o)
+    fin = ~inf_o
+    np.testing.assert_allclose(est[fin], c[fin], rtol=RTOL, atol=0)
+
+
+def rand_pairs(rng, n, n_src):
+    src = rng.integers(0, 2**32, size=n_src, dtype=np.uint64)[rng.integers(0, n_src, size=n)]
+    dst = rng.integers(0, 2**32, size=n, dtype=np.uint64)
+    return np.stack([src, dst], axis=1).astype(np.uint32)
+
+
+def planted(rng, hosts, card):
+    return [np.stack([np.full(card, h, dtype=np.uint32),
+                      rng.choice(2**32, size=card, replace=False).astype(np.uint32)], 1)
+            for h in hosts]
+
+
+def to_dev(pairs_np):
+    return torch.from_numpy(np.ascontiguousarray(pairs_np).view(np.int32)).to(DEV)
+
+
+# ------------------------------------------------------------------ update
+
+def test_generator_same_on_gpu_and_cpu():
+    spec = T.WindowSpec(n_pairs=200_000, n_sources=20_000, zipf_s=1.1,
+                        planted_card=[1200, 3000], n_scanners=2,
+                        scanner_len=1000, dup_frac=0.1)
+    a = T.generate(spec, 5, device="cpu").pairs
+    b = T.generate(spec, 5, device=DEV).pairs.cpu()
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 64, 255, 257, 4099, 100_003])
+def test_update_ragged_sizes(n):
+    say(f"update ragged n={n}")
+    p = oracle.Params()
+    rng = np.random.default_rng(n + 1)
+    pairs = rand_pairs(rng, n, max(1, n // 7)) if n else np.zeros((0, 2), np.uint32)
+    with make_sketch(p) as sk:
+        if n:
+            sk.update(to_dev(pairs))
+        else:
+            sk.update(torch.zeros((0, 2), dtype=torch.int32, device=DEV))
+        torch.cuda.synchronize()
+        got = sk.download()
+    assert np.array_equal(got, oracle.build_sketch(p, pairs))
+
+
+PARAMS = [oracle.Params(), oracle.Params(1024, 18, 5, 5), oracle.Params(1024, 16, 3, 16),
+          oracle.Params(256, 12, 6, 5), oracle.Params(512, 10, 8, 4),
+          oracle.Params(32, 14, 5, 6), oracle.Params(64, 14, 5, 6),
+          oracle.Params(4096, 14, 5, 6), oracle.Params(16384, 12, 5, 7)]
+
+
+@pytest.mark.parametrize("p", PARAMS, ids=lambda p: f"g{p.g}k{p.k}r{p.r}a{p.alpha}")
+def test_update_params_and_chunking(p):
+    say(f"update params g={p.g} k={p.k} r={p.r} alpha={p.alpha}")
+    rng = np.random.default_rng(p.g + p.k)
+    pairs = rand_pairs(rng, 60_001, 3000)
+    ref = oracle.build_sketch(p, pairs)
+    with make_sketch(p) as sk:
+        d = to_dev(pairs)
+        # uneven chunks, each 8-byte aligned
+        cuts = [0, 1, 1000, 1001, 33_333, 60_001]
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            sk.update(d[a:b])
+        torch.cuda.synchronize()
+        assert np.array_equal(sk.download(), ref)
+        # duplicates change nothing; reset clears
+        sk.update(d[::2].contiguous())
+        torch.cuda.synchronize()
+        assert np.array_equal(sk.download(), ref)
+        sk.reset()
+        torch.cuda.synchronize()
+        assert not sk.download().any()
+
+
+# ----------------------------------------------------------------- restore
+
+@pytest.fixture(scope="module")
+def cfg1():
+    say("config: single window 1M pairs, default sketch")
+    w = T.generate(T.spec_single_window_1m(), T.config_seed(1), device=DEV)
+    p = oracle.Params()
+    ref = oracle.build_sketch(p, host_words(w.pairs))
+    return w, p, ref
+
+
+def test_config1_sketch_candidates_and_spl(cfg1):
+    w, p, ref = cfg1
+    with make_sketch(p) as sk:
+        sk.update(w.pairs)
+        torch.cuda.synchronize()
+        assert np.array_equal(sk.download(), ref)
+        cand = sk.candidates(1024.0)
+        assert np.array_equal(cand, oracle.candidates(p, ref, 1024.0, "join"))
+        recs, info = sk.restore(1024.0)
+    ip, sz, c, sc = oracle.restore(p, ref, 1024.0)
+    assert_not_boundary(info)
+    assert_spl_equal(recs, ip, sz, c)
+    assert info["psi"] == pytest.approx(sc["psi"], rel=1e-12)
+    assert info["d"] == pytest.approx(sc["D"], rel=1e-12)
+    _, zr = oracle.zero_counts(p, ref)
+    assert info["zr"][:p.r] == [int(x) for x in zr]
+    he = oracle.hot_lists(p, ref, 1024.0)
+    assert info["he_count"][:p.r] == [len(h) for h in he]
+    assert set(w.planted_src.tolist()) <= set(recs["ip"].tolist())
+
+
+@pytest.mark.parametrize("theta", [300.0, 700.0, 1024.0, 2048.0, 5000.0])
+def test_config1_restore_thresholds_on_uploaded_sketch(cfg1, theta):
+    """Restore alone: the oracle's bitmap uploaded, so only restore is tested."""
+    _, p, ref = cfg1
+    with make_sketch(p) as sk:
+        sk.upload(ref)
+        recs, info = sk.restore(theta)
+        again, _ = sk.restore(theta)
+    ip, sz, c, _ = oracle.restore(p, ref, theta)
+    assert_not_boundary(info)
+    assert_spl_equal(recs, ip, sz, c)
+    assert np.array_equal(recs, again)
+
+
+@pytest.mark.parametrize("p", [oracle.Params(1024, 16, 3, 16), oracle.Params(256, 12, 6, 5),
+                               oracle.Params(512, 18, 5, 5), oracle.Params(2048, 14, 5, 6),
+                               oracle.Params(32, 16, 4, 8)],
+                         ids=lambda p: f"g{p.g}k{p.k}r{p.r}a{p.alpha}")
+def test_restore_other_params_vs_bruteforce(p):
+    say(f"restore params g={p.g} k={p.k} r={p.r} alpha={p.alpha}")
+    rng = np.random.default_rng(p.k * 7 + p.r)
+    hosts = rng.choice(2**32, size=12, replace=False).astype(np.uint32)
+    pairs = np.concatenate([rand_pairs(rng, 200_000, 20_000)] + planted(rng, hosts, 3000))
+    pairs = pairs[rng.permutation(len(pairs))]
+    theta = 0.7 * p.g if p.g >= 256 else 20.0
+    ref = oracle.build_sketch(p, pairs)
+    with make_sketch(p) as sk:
+        sk.update(to_dev(pairs))
+        torch.cuda.synchronize()
+        assert np.array_equal(sk.download(), ref)
+        cand = sk.candidates(theta)
+        recs, info = sk.restore(theta)
+    assert np.array_equal(cand, oracle.candidates(p, ref, theta, "brute"))
+    ip, sz, c, _ = oracle.restore(p, ref, theta, mode="brute")
+    assert_not_boundary(info)
+    assert_spl_equal(recs, ip, sz, c)
+
+
+def test_empty_and_saturated_sketch():
+    p = oracle.Params()
+    with make_sketch(p) as sk:
+        recs, info = sk.restore(1024.0)
+        assert len(recs) == 0 and info["psi"] == 0.0
+        assert info["he_count"][:5] == [0] * 5
+        words = np.zeros(p.words(), dtype=np.uint32)
+        row = p.words() // p.r
+        words[3 * row:4 * row] = 0xFFFFFFFF
+        sk.upload(words)
+        with pytest.raises(ddhf.SketchError) as e:
+            sk.restore(1024.0)
+        assert e.value.code == ddhf.SKETCH_E_SATURATED
+
+
+def test_capacity_two_call_pattern(cfg1):
+    _, p, ref = cfg1
+    with make_sketch(p) as sk:
+        sk.upload(ref)
+        with pytest.raises(ddhf.SketchError) as e:
+            ddhf.sketch_restore(sk.handle, 1024.0, 0)
+        assert e.value.code == ddhf.SKETCH_E_CAPACITY
+        need = e.value.n_needed
+        recs, _ = ddhf.sketch_restore(sk.handle, 1024.0, need)
+        assert len(recs) == need
+
+
+def test_single_isolated_host():
+    p = oracle.Params()
+    rng = np.random.default_rng(1)
+    host = np.uint32(0xDEADBEEF)
+    pairs = planted(rng, [host], 9000)[0]   # n >> g ln(2g): SZ is usually 0
+    with make_sketch(p) as sk:
+        sk.update(to_dev(pairs))
+        recs, info = sk.restore(1024.0)
+    ip, sz, c, _ = oracle.restore(p, oracle.build_sketch(p, pairs), 1024.0)
+    assert list(recs["ip"]) == [host]
+    assert_spl_equal(recs, ip, sz, c)
+
+
+# ------------------------------------------------------ full-size windows
+
+def sized_params(n_pairs):
+    """Smallest k >= 14 with load n/(g 2^k) <= 0.45; alpha = ceil((32-k)/(r-2))."""
+    k = 14
+    while n_pairs / (1024 * 2**k) > 0.45:
+        k += 1
+    return oracle.Params(1024, k, 5, math.ceil((32 - k) / 3))
+
+
+def test_config2_large_window_full_size():
+    """100M pairs (the benchmark's window) at k = 18: bitmap, candidates and
+    super point list against the oracle (candidates by the 2^32 brute
+    force, which is the oracle's definition of the set)."""
+    spec = T.spec_large_window_100m()
+    p = sized_params(spec.n_pairs)
+    assert (p.k, p.alpha) == (18, 5)
+    say("config: large window 100M pairs, k=18 alpha=5")
+    w = T.generate(spec, T.config_seed(2), device=DEV)
+    with make_sketch(p) as sk:
+        sk.update(w.pairs)
+        torch.cuda.synchronize()
+        got = sk.download()
+        recs, info = sk.restore(1024.0)
+        cand = sk.candidates(1024.0)
+    hp = host_words(w.pairs)
+    del w
+    say("  oracle update")
+    ref = oracle.build_sketch(p, hp)
+    assert np.array_equal(got, ref)
+    del got
+    say("  oracle restore (brute force)")
+    assert np.array_equal(cand, oracle.candidates(p, ref, 1024.0, "brute"))
+    ip, sz, c, sc = oracle.restore(p, ref, 1024.0, mode="brute")
+    assert_not_boundary(info)
+    assert_spl_equal(recs, ip, sz, c)
+    say(f"  {len(recs)} super points, {len(cand)} candidates, psi={info['psi']:.4f}, "
+        f"he={info['he_count'][:5]}, partials={info['n_partials'][:5]}")
+
+
+@pytest.mark.parametrize("window", [0, 59])
+def test_config3_stream_window_full_size(window):
+    """Windows of the sustained 117M-pair stream, with a reset between."""
+    spec = T.spec_stream_window(window)
+    p = sized_params(spec.n_pairs)
+    say(f"config: stream window {window}, 117M pairs, k={p.k} alpha={p.alpha}")
+    w = T.generate(spec, T.config_seed(3, window), device=DEV)
+    with make_sketch(p) as sk:
+        junk = T.generate(T.spec_single_window_1m(), 7, device=DEV)
+        sk.update(junk.pairs)
+        sk.reset()
+        sk.update(w.pairs)
+        torch.cuda.synchronize()
+        got = sk.download()
+        recs, info = sk.restore(1024.0)
+    hp = host_words(w.pairs)
+    planted_src = w.planted_src
+    del w
+    ref = oracle.build_sketch(p, hp)
+    assert np.array_equal(got, ref)
+    del got
+    ip, sz, c, _ = oracle.restore(p, ref, 1024.0, mode="brute")
+    assert_not_boundary(info)
+    assert_spl_equal(recs, ip, sz, c)
+    found = np.isin(planted_src, recs["ip"]).mean()
+    say(f"  {len(recs)} super points, planted recall {found:.3f}")

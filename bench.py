@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=100_000_000,
                     help="pairs of the window the oracle baseline processes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--update-path", type=int, default=0, choices=(0, 1, 2),
+                    help="0 = library's choice by size, 1 = direct, 2 = binned")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of this many MiB "
                          "(for scaling HBM counters)")
@@ -126,6 +128,8 @@ def main():
         del a, b
 
     sk = ddhf.Sketch(g, k, r, alpha, traffic.HASH_SEED, device=0)
+    if args.update_path:
+        sk.set_option(ddhf.SKETCH_OPT_UPDATE_PATH, args.update_path)
     stream = torch.cuda.current_stream(dev)
     n = spec.n_pairs
 

@@ -143,6 +143,31 @@ int sketch_restore(sketch_t *s, double theta, sketch_sp_t *out, size_t cap,
  * Asynchronous on hip_stream. */
 int sketch_reset(sketch_t *s, void *hip_stream);
 
+/* ---- tuning ---- */
+
+/* Options of sketch_set_option. The update has two kernels computing the
+ * same sketch: "direct" (each pair sets its r bits with a check-then-
+ * atomicOr in the sketch, Alg. 1 as written) and "binned" (the bit sets are
+ * grouped by 64 KiB slice of the sketch and applied in LDS, one workgroup
+ * per slice). */
+enum {
+  SKETCH_OPT_UPDATE_PATH = 1,       /* 0 = choose by size (default),
+                                       1 = direct, 2 = binned */
+  SKETCH_OPT_BINNED_MIN_PAIRS = 2,  /* "choose by size": binned at and above
+                                       this many pairs per call */
+  SKETCH_OPT_UPDATE_GRID = 3,       /* blocks of the direct kernel */
+  SKETCH_OPT_UPDATE_CHECK = 4,      /* direct kernel: 1 = test the bit before
+                                       the atomicOr (default), 0 = always OR */
+  SKETCH_OPT_BINNED_ROUND = 5       /* binned: pairs per round; the round's
+                                       codes take 4*r bytes per pair of device
+                                       memory, allocated on first use */
+};
+
+/* Set a tuning option; results never depend on it. Errors: INVAL (NULL
+ * handle, unknown option, value out of range, binned path on a sketch of
+ * more than 4096 slices). */
+int sketch_set_option(sketch_t *s, int option, int64_t value);
+
 /* ---- test and checkpoint hooks ---- */
 
 /* Copy the sketch to HOST memory host_words (n_words must equal

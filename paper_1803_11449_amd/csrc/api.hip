@@ -25,6 +25,11 @@ struct sketch {
   int grid = 0;          // blocks for grid-stride kernels
   int update_grid = 0;
   int update_variant = 1;
+  int update_path = 0;   // 0 auto, 1 direct, 2 binned
+  size_t binned_min_pairs = 0;
+  size_t binned_round = (size_t)1 << 27;  // pairs per binned round (codes < 2^32)
+  uint32_t nbins = 0;
+  BinBufs BB{};
 };
 
 namespace {
@@ -137,25 +142,58 @@ void free_all(sketch *s) {
   dev_free(B.bk_val);
   dev_free(B.part[0]);
   dev_free(B.part[1]);
+  dev_free(B.segc[0]);
+  dev_free(B.segc[1]);
   dev_free(B.cand);
   dev_free(B.cand_sorted);
+  dev_free(B.rank);
   dev_free(B.spl);
   dev_free(B.spl_sorted);
   if (s->h_state) (void)hipHostFree(s->h_state);
   s->h_state = nullptr;
+  BinBufs &BB = s->BB;
+  dev_free(BB.hist);
+  dev_free(BB.totals);
+  dev_free(BB.base);
+  dev_free(BB.item_start);
+  dev_free(BB.xslot);
+  dev_free(BB.n_items);
+  dev_free(BB.codes);
+  dev_free(BB.scratch);
+  BB.codes_cap = 0;
 }
 
-int grow_partials(sketch *s, size_t need) {
+// Codes buffer of the binned update for rounds of `pairs` pairs.
+int ensure_codes(sketch *s, size_t pairs, hipStream_t st) {
+  BinBufs &BB = s->BB;
+  const size_t need = pairs * s->p.r;
+  if (BB.codes_cap >= need) return SKETCH_OK;
+  HIP_OK(hipStreamSynchronize(st));
+  dev_free(BB.codes);
+  dev_free(BB.scratch);
+  BB.codes_cap = 0;
+  int rc = dev_alloc(&BB.codes, need, "update codes");
+  if (rc) return rc;
+  // a tile cut into j items needs j-1 scratch tiles; j-1 < codes/APPLY_ITEM
+  rc = dev_alloc(&BB.scratch, (need / APPLY_ITEM + 1) * (size_t)BIN_TILE_WORDS,
+                 "update scratch tiles");
+  if (rc) return rc;
+  BB.codes_cap = need;
+  return SKETCH_OK;
+}
+
+// Partial-address buffers: jblk segments of seg_cap entries each.
+int grow_partials(sketch *s, size_t seg_need) {
   RestoreBufs &B = s->B;
-  size_t cap = std::max(need + need / 2, B.part_cap[0] * 2);
+  const size_t cap = std::max(seg_need + seg_need / 2, B.seg_cap * 2);
   dev_free(B.part[0]);
   dev_free(B.part[1]);
-  B.part_cap[0] = B.part_cap[1] = 0;
-  int rc = dev_alloc(&B.part[0], cap, "partials");
+  B.seg_cap = 0;
+  int rc = dev_alloc(&B.part[0], cap * B.jblk, "partials");
   if (rc) return rc;
-  rc = dev_alloc(&B.part[1], cap, "partials");
+  rc = dev_alloc(&B.part[1], cap * B.jblk, "partials");
   if (rc) return rc;
-  B.part_cap[0] = B.part_cap[1] = cap;
+  B.seg_cap = cap;
   return SKETCH_OK;
 }
 
@@ -227,8 +265,8 @@ int run_restore(sketch *s, double theta, int estimate, hipStream_t st, double *z
     bool again = false;
     size_t need_part = 0;
     for (uint32_t i = 2; i + 1 < s->p.r; i++)
-      need_part = std::max<size_t>(need_part, h.n_out[i]);
-    if (need_part > s->B.part_cap[0]) {
+      need_part = std::max<size_t>(need_part, h.seg_max[i]);
+    if (need_part > s->B.seg_cap) {
       int rc = grow_partials(s, need_part);
       if (rc) return rc;
       again = true;
@@ -308,9 +346,26 @@ int sketch_create(const sketch_params_t *params, sketch_t **out) {
   if (!rc) rc = dev_alloc(&B.bk_off, (size_t)params->r * (nb + 1), "bucket offsets");
   if (!rc) rc = dev_alloc(&B.bk_cur, (size_t)params->r * nb, "bucket cursors");
   if (!rc) rc = dev_alloc(&B.bk_val, n_le, "bucket values");
-  if (!rc) rc = grow_partials(s, (size_t)1 << 20);
+  B.jblk = (uint32_t)(s->n_cu * 2);
+  if (!rc) rc = dev_alloc(&B.rank, 16384, "sort ranks");
+  if (!rc) rc = dev_alloc(&B.segc[0], B.jblk, "segment counts");
+  if (!rc) rc = dev_alloc(&B.segc[1], B.jblk, "segment counts");
+  if (!rc) rc = grow_partials(s, (size_t)1 << 12);
   if (!rc) rc = grow_cand(s, (size_t)1 << 16);
   if (!rc) rc = grow_spl(s, (size_t)1 << 16);
+  s->nbins = (uint32_t)((s->words + BIN_TILE_WORDS - 1) / BIN_TILE_WORDS);
+  s->BB.nblk = (uint32_t)std::min(1024, s->n_cu);
+  s->BB.apply_grid = (uint32_t)s->n_cu;
+  s->binned_min_pairs = std::max<size_t>(s->words / 8, 1 << 16);
+  if (s->nbins <= BIN_MAX) {
+    BinBufs &BB = s->BB;
+    if (!rc) rc = dev_alloc(&BB.hist, (size_t)s->nbins * BB.nblk, "tile counts");
+    if (!rc) rc = dev_alloc(&BB.totals, s->nbins, "tile totals");
+    if (!rc) rc = dev_alloc(&BB.base, s->nbins + 1, "tile runs");
+    if (!rc) rc = dev_alloc(&BB.item_start, s->nbins + 1, "tile items");
+    if (!rc) rc = dev_alloc(&BB.xslot, s->nbins + 1, "tile scratch slots");
+    if (!rc) rc = dev_alloc(&BB.n_items, 1, "tile item count");
+  }
   if (!rc && hipHostMalloc((void **)&s->h_state, sizeof(DevState)) != hipSuccess) {
     s->h_state = nullptr;
     rc = fail(SKETCH_E_NOMEM, "hipHostMalloc(state) failed");
@@ -344,9 +399,51 @@ int sketch_update(sketch_t *s, const uint32_t *d_pairs, size_t n_pairs, void *hi
   if (((uintptr_t)d_pairs) & 7u)
     return fail(SKETCH_E_INVAL, "sketch_update: pairs must be 8-byte aligned");
   DEVICE_GUARD(s->p.device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  const bool can_bin = s->nbins <= BIN_MAX;
+  const bool binned = can_bin && (s->update_path == 2 ||
+                                  (s->update_path == 0 && n_pairs >= s->binned_min_pairs));
+  if (binned) {
+    int rc = ensure_codes(s, std::min(n_pairs, s->binned_round), st);
+    if (rc) return rc;
+    HIP_OK(launch_update_binned(s->G, s->d_sketch, s->words, d_pairs, n_pairs, s->BB, st));
+    return SKETCH_OK;
+  }
   HIP_OK(launch_update(s->G, s->d_sketch, d_pairs, n_pairs, s->update_grid,
-                       s->update_variant, (hipStream_t)hip_stream));
+                       s->update_variant, st));
   return SKETCH_OK;
+}
+
+int sketch_set_option(sketch_t *s, int option, int64_t value) {
+  if (!s) return fail(SKETCH_E_INVAL, "sketch_set_option: NULL handle");
+  switch (option) {
+    case SKETCH_OPT_UPDATE_PATH:
+      if (value < 0 || value > 2) break;
+      if (value == 2 && s->nbins > BIN_MAX)
+        return fail(SKETCH_E_INVAL, "sketch_set_option: sketch too large for the binned update");
+      s->update_path = (int)value;
+      return SKETCH_OK;
+    case SKETCH_OPT_BINNED_MIN_PAIRS:
+      if (value < 0) break;
+      s->binned_min_pairs = (size_t)value;
+      return SKETCH_OK;
+    case SKETCH_OPT_UPDATE_GRID:
+      if (value < 1 || value > (1 << 20)) break;
+      s->update_grid = (int)value;
+      return SKETCH_OK;
+    case SKETCH_OPT_UPDATE_CHECK:
+      if (value < 0 || value > 1) break;
+      s->update_variant = (int)value;
+      return SKETCH_OK;
+    case SKETCH_OPT_BINNED_ROUND:
+      if (value < 1024 || (uint64_t)value * s->p.r >= (1ull << 32)) break;
+      s->binned_round = (size_t)value;
+      return SKETCH_OK;
+    default:
+      return fail(SKETCH_E_INVAL, "sketch_set_option: unknown option %d", option);
+  }
+  return fail(SKETCH_E_INVAL, "sketch_set_option: bad value %lld for option %d",
+              (long long)value, option);
 }
 
 int sketch_reset(sketch_t *s, void *hip_stream) {

@@ -49,6 +49,7 @@ struct DevState {
   double psi, d, trep;
   uint32_t szmax;
   uint32_t saturated;
+  uint32_t seg_max[8];               // largest block segment of join stage i
   uint32_t pad[2];
 };
 
@@ -60,17 +61,46 @@ struct RestoreBufs {
   uint32_t *bk_off;       // r * (nb+1): bucket offsets of row i (rows >= 2)
   uint32_t *bk_cur;       // r * nb: fill cursors
   uint32_t *bk_val;       // r * 2^k: row entries grouped by bucket
-  uint2 *part[2];         // ping-pong partial addresses (sub, c0)
-  size_t part_cap[2];
+  uint2 *part[2];         // ping-pong partial addresses (sub, c0): jblk
+                          // segments of seg_cap entries, one per join block
+  uint32_t *segc[2];      // entries written to each segment
+  size_t seg_cap;
+  uint32_t jblk;          // blocks of the join kernels
   uint32_t *cand;         // candidate addresses
   size_t cand_cap;
   uint4 *spl;             // records {ip, sz, est.lo, est.hi}, unsorted
   uint4 *spl_sorted;      // the same, ascending by ip
   size_t spl_cap;
   uint32_t *cand_sorted;
+  uint32_t *rank;         // sort ranks (16384 entries)
+};
+
+// Binned update (update.hip): the sketch is cut into 128 KiB tiles; a code
+// is the bit offset inside its tile.
+constexpr uint32_t BIN_TILE_LOG2 = 20;               // bits per tile = 2^20
+constexpr uint32_t BIN_TILE_WORDS = 1u << 15;        // 128 KiB
+constexpr uint32_t BIN_MAX = 2048;                   // tiles (sketch <= 256 MiB)
+constexpr uint32_t SPLIT_MIN = 1u << 20;             // tiles above this many codes
+constexpr uint32_t APPLY_ITEM = 1u << 19;            //   are cut into items of this many
+
+struct BinBufs {
+  uint32_t *hist;        // [tiles][nblk]: counts, then offsets inside the run
+  uint32_t *totals;      // [tiles]
+  uint32_t *base;        // [tiles + 1]: run starts
+  uint32_t *item_start;  // [tiles + 1]
+  uint32_t *xslot;       // [tiles + 1]: first scratch tile of each cut tile
+  uint32_t *n_items;     // [1]
+  uint32_t *codes;       // codes_cap entries
+  size_t codes_cap;      // a multiple of r; < 2^32
+  uint32_t *scratch;     // (codes_cap / APPLY_ITEM + 1) tiles for cut tiles
+  uint32_t nblk;         // blocks of the count and scatter passes (<= 1024)
+  uint32_t apply_grid;
 };
 
 // ---- launchers (update.hip) ----
+hipError_t launch_update_binned(const Geom &G, uint32_t *sketch, size_t words,
+                                const uint32_t *pairs, size_t n, const BinBufs &BB,
+                                hipStream_t st);
 hipError_t launch_update(const Geom &G, uint32_t *sketch, const uint32_t *pairs,
                          size_t n, int grid, int variant, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, size_t n_words, uint32_t value,

@@ -87,9 +87,10 @@ struct LeShape {
 
 // ----------------------------------------------------------- 0: state init
 
-__global__ void k_state_init(DevState *st) {
+__global__ void k_state_init(DevState *st, uint32_t *rank, uint32_t n_rank) {
   uint32_t *p = reinterpret_cast<uint32_t *>(st);
   for (uint32_t i = threadIdx.x; i < sizeof(DevState) / 4; i += blockDim.x) p[i] = 0;
+  for (uint32_t i = threadIdx.x; i < n_rank; i += blockDim.x) rank[i] = 0;
 }
 
 // -------------------------------------------------------------- 1: hot scan
@@ -263,16 +264,42 @@ __global__ void k_scalars(Geom G, DevState *st, double e_theta) {
 }
 
 // ------------------------------------------------------------------ 5: join
+//
+// Stage 1 (Alg. 3) takes every (CL_0, CL_1) of HE(0) x HE(1); stage i >= 3
+// (Alg. 4) takes every partial address of stage i-1. Each item probes the
+// bucket of HE(i) (i = 2 for stage 1) that holds exactly the entries whose
+// low k-alpha bits continue the overlap, and every entry of it that extends
+// the partial address is an output.
+//
+//  - The probed row's bucket table is copied into LDS when it fits: offsets
+//    as uint16, and per entry only its top alpha bits (the bucket index is
+//    the low k-alpha bits), as uint8 or uint16. Otherwise it is read from
+//    the global tables.
+//  - A wave expands its 64 items together: the bucket sizes are scanned, and
+//    each lane then takes one output slot and finds the item that owns it by
+//    a binary search over the scan, so uneven bucket sizes do not diverge.
+//  - Every block appends its outputs to its own segment of the next
+//    stage's buffer through an LDS counter (no global counter); stage i+1's
+//    block b reads segment b. Counts stay exact past a segment's capacity,
+//    so the host can grow it and run again.
+//  - The last stage keeps an address only if it is a 32-bit value and DH0
+//    of it is the CL_0 it was built from; those few are appended to the
+//    candidate list with a global counter.
 
-// Does bucket entry c (row i, 2 <= i <= r-1) extend partial address `sub`
-// built with CL_0 = c0? Writes the extended address. Bits of the address at
-// or above 32 must be 0 for a 32-bit host; such tuples are dropped here,
-// where they first appear, rather than at the last stage.
-__device__ __forceinline__ bool extend(const Geom &G, uint32_t i, uint32_t sub,
-                                       uint32_t c0, uint32_t c, uint32_t *out) {
-  const uint32_t blk = c0 ^ c;
-  const uint32_t top = blk >> (G.k - G.alpha);   // the alpha new bits
-  const uint32_t pos = G.k + (i - 2) * G.alpha;  // where they go
+constexpr int JOIN_THREADS = 512;
+
+// Orders this wave's LDS writes before its later LDS reads by other lanes.
+__device__ __forceinline__ void lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+}
+constexpr uint32_t TAB_OFF_MAX = 8193;          // bucket offsets held in LDS
+constexpr uint32_t TAB_VAL_BYTES = 32768;       // bucket entries held in LDS
+
+// Bits of the address from block i >= 2: alpha new bits at k + (i-2)*alpha.
+// top = the new bits; false if any lands at or above bit 32.
+__device__ __forceinline__ bool extend_top(const Geom &G, uint32_t i, uint32_t sub,
+                                           uint32_t top, uint32_t *out) {
+  const uint32_t pos = G.k + (i - 2) * G.alpha;
   if (pos >= 32) {
     *out = sub;
     return top == 0;
@@ -282,176 +309,163 @@ __device__ __forceinline__ bool extend(const Geom &G, uint32_t i, uint32_t sub,
   return (s2 >> 32) == 0;
 }
 
-// Join outputs are staged per wave in LDS and copied out in runs, so the
-// global list counter sees one atomic per STAGE_CAP outputs rather than one
-// per wave step (a single hot counter serialises otherwise).
-constexpr int STAGE_CAP = 1024;
-
-__device__ __forceinline__ void lds_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-}
-
-template <typename T>
-struct Stage {
-  T *buf;         // this wave's slice of LDS
-  uint32_t fill;  // wave-uniform
+struct JoinTable {
+  const uint16_t *off16;   // LDS
+  const uint8_t *hi8;      // LDS
+  const uint16_t *hi16;    // LDS
+  const uint32_t *off;     // global
+  const uint32_t *val;     // global
+  uint32_t shift;          // k - alpha
+  bool lds;
+  bool wide;               // alpha > 8
+  __device__ __forceinline__ uint32_t start(uint32_t key) const {
+    return lds ? (uint32_t)off16[key] : off[key];
+  }
+  __device__ __forceinline__ uint32_t top_bits(uint32_t j) const {
+    if (lds) return wide ? (uint32_t)hi16[j] : (uint32_t)hi8[j];
+    return val[j] >> shift;
+  }
 };
 
-template <typename T>
-__device__ __forceinline__ void stage_flush(Stage<T> &s, unsigned long long *counter,
-                                            T *out, size_t cap) {
-  if (s.fill == 0) return;
-  unsigned long long base = 0;
-  if (lane_id() == 0) base = atomicAdd(counter, (unsigned long long)s.fill);
-  base = __shfl(base, 0, 64);
-  lds_fence();
-  for (uint32_t i = lane_id(); i < s.fill; i += 64)
-    if (base + i < cap) out[base + i] = s.buf[i];
-  lds_fence();
-  s.fill = 0;
-}
-
-template <bool LAST>
-struct JoinOut {
-  using T = uint2;  // (partial address, CL_0)
-  static __device__ __forceinline__ T make(uint32_t a, uint32_t c0) { return make_uint2(a, c0); }
-};
-template <>
-struct JoinOut<true> {
-  using T = uint32_t;  // rebuilt address
-  static __device__ __forceinline__ T make(uint32_t a, uint32_t) { return a; }
-};
-
-// One wave step of a join stage: each lane holds a partial address `sub`
-// (with its CL_0) and the range [b0,b1) of bucket entries of row `row` whose
-// overlap bits match; every entry that extends it is emitted (after the
-// 32-bit and re-hash tests on the last stage). All 64 lanes must call.
-template <bool LAST>
-__device__ __forceinline__ void join_step(const Geom &G, uint32_t row, uint32_t sub,
-                                          uint32_t c0, uint32_t b0, uint32_t b1,
-                                          const uint32_t *__restrict__ val,
-                                          Stage<typename JoinOut<LAST>::T> &s,
-                                          unsigned long long *counter,
-                                          typename JoinOut<LAST>::T *out, size_t cap) {
-  using O = JoinOut<LAST>;
-  uint32_t nout = 0;
-  for (uint32_t j = b0; j < b1; j++) {
-    uint32_t a;
-    bool ok = extend(G, row, sub, c0, val[j], &a);
-    if (LAST) ok = ok && hash_dh0(G, a) == c0;
-    nout += ok;
-  }
-  const uint32_t incl = wave_incl_scan(nout);
-  const uint32_t total = __shfl(incl, 63, 64);
-  if (total == 0) return;
-  if (s.fill + total > (uint32_t)STAGE_CAP) stage_flush(s, counter, out, cap);
-  const uint32_t excl = incl - nout;
-  if (total > (uint32_t)STAGE_CAP) {
-    // larger than the stage: reserve in the global list directly
-    unsigned long long base = 0;
-    if (lane_id() == 0) base = atomicAdd(counter, (unsigned long long)total);
-    base = __shfl(base, 0, 64) + excl;
-    for (uint32_t j = b0; j < b1 && nout; j++) {
-      uint32_t a;
-      bool ok = extend(G, row, sub, c0, val[j], &a);
-      if (LAST) ok = ok && hash_dh0(G, a) == c0;
-      if (!ok) continue;
-      if (base < cap) out[base] = O::make(a, c0);
-      base++;
-    }
-    return;
-  }
-  uint32_t pos = s.fill + excl;
-  for (uint32_t j = b0; j < b1 && nout; j++) {
-    uint32_t a;
-    bool ok = extend(G, row, sub, c0, val[j], &a);
-    if (LAST) ok = ok && hash_dh0(G, a) == c0;
-    if (!ok) continue;
-    s.buf[pos++] = O::make(a, c0);
-  }
-  s.fill += total;
-}
-
-// Stage 1 (Alg. 3): every (CL_0, CL_1) of HE(0) x HE(1), probing HE(2)'s
-// bucket ((BL(1) >> alpha) xor CL_0) mod 2^(k-alpha). A wave takes one CL_0
-// (a scalar) and 64 consecutive CL_1.
-template <bool LAST>
-__global__ __launch_bounds__(256) void k_join_first(
-    Geom G, const uint32_t *__restrict__ he, const uint32_t *__restrict__ bk_off,
-    const uint32_t *__restrict__ bk_val, DevState *__restrict__ st,
-    typename JoinOut<LAST>::T *__restrict__ out, size_t cap) {
-  using T = typename JoinOut<LAST>::T;
-  __shared__ uint2 stage_mem[4 * STAGE_CAP];
-  if (st->saturated) return;
-  const uint32_t h0 = st->he_count[0], h1 = st->he_count[1];
-  if (h0 == 0 || h1 == 0) return;
-  const uint32_t nb = 1u << (G.k - G.alpha), M = nb - 1;
-  const uint32_t *HE0 = he, *HE1 = he + (1u << G.k);
-  const uint32_t *off = bk_off + 2 * (size_t)(nb + 1);
-  const uint32_t *val = bk_val + ((size_t)2 << G.k);
-  unsigned long long *counter = LAST ? &st->n_cand : &st->n_out[2];
-  Stage<T> s{reinterpret_cast<T *>(stage_mem) + (threadIdx.x >> 6) * STAGE_CAP, 0};
-
-  const uint32_t nch = (h1 + 63) >> 6;
-  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
-  const uint32_t dq = n_waves / nch, dr = n_waves % nch;
-  uint32_t x0 = wave / nch, ch = wave % nch;
-  while (x0 < h0) {
-    const uint32_t c0 = HE0[x0];
-    const uint32_t x1 = (ch << 6) + lane_id();
-    uint32_t blk1 = 0, b0 = 0, b1 = 0;
-    if (x1 < h1) {
-      blk1 = c0 ^ HE1[x1];
-      const uint32_t key = ((blk1 >> G.alpha) ^ c0) & M;
-      b0 = off[key];
-      b1 = off[key + 1];
-    }
-    join_step<LAST>(G, 2, blk1, c0, b0, b1, val, s, counter, out, cap);
-    x0 += dq;
-    ch += dr;
-    if (ch >= nch) {
-      ch -= nch;
-      x0++;
-    }
-  }
-  stage_flush(s, counter, out, cap);
-}
-
-// Stage i >= 3 (Alg. 4): every partial address of stage i-1, probing HE(i)'s
-// bucket ((partial >> (i-1)*alpha) xor CL_0) mod 2^(k-alpha).
-template <bool LAST>
-__global__ __launch_bounds__(256) void k_join_next(
-    Geom G, uint32_t row, const uint2 *__restrict__ in, size_t in_cap,
+template <bool FIRST, bool LAST>
+__global__ __launch_bounds__(JOIN_THREADS) void k_join(
+    Geom G, uint32_t row, const uint32_t *__restrict__ he,
+    const uint2 *__restrict__ in, const uint32_t *__restrict__ in_cnt,
     const uint32_t *__restrict__ bk_off, const uint32_t *__restrict__ bk_val,
-    DevState *__restrict__ st, typename JoinOut<LAST>::T *__restrict__ out, size_t cap) {
-  using T = typename JoinOut<LAST>::T;
-  __shared__ uint2 stage_mem[4 * STAGE_CAP];
+    DevState *__restrict__ st, uint2 *__restrict__ out, uint32_t *__restrict__ out_cnt,
+    size_t seg_cap, uint32_t *__restrict__ cand, size_t cand_cap) {
+  __shared__ uint16_t t_off[TAB_OFF_MAX];
+  __shared__ __attribute__((aligned(16))) uint8_t t_val[TAB_VAL_BYTES];
+  __shared__ uint32_t w_incl[JOIN_THREADS], w_sub[JOIN_THREADS], w_c0[JOIN_THREADS];
+  __shared__ int32_t w_base[JOIN_THREADS];
+  __shared__ uint32_t seg_fill;
   if (st->saturated) return;
-  const unsigned long long n_in_all = st->n_out[row - 1];
-  const uint64_t n_in = n_in_all < in_cap ? n_in_all : in_cap;
+
   const uint32_t nb = 1u << (G.k - G.alpha), M = nb - 1;
-  const uint32_t *off = bk_off + (size_t)row * (nb + 1);
-  const uint32_t *val = bk_val + ((size_t)row << G.k);
-  const uint32_t sh = G.shift[row];
-  unsigned long long *counter = LAST ? &st->n_cand : &st->n_out[row];
-  Stage<T> s{reinterpret_cast<T *>(stage_mem) + (threadIdx.x >> 6) * STAGE_CAP, 0};
-  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const uint64_t step = ((uint64_t)gridDim.x * blockDim.x) & ~63ull;
-  for (uint64_t base = wave << 6; base < n_in; base += step) {
-    const uint64_t t = base + lane_id();
-    uint32_t sub = 0, c0 = 0, b0 = 0, b1 = 0;
-    if (t < n_in) {
-      const uint2 p = in[t];
-      sub = p.x;
-      c0 = p.y;
-      const uint32_t key = ((uint32_t)((uint64_t)sub >> sh) ^ c0) & M;
-      b0 = off[key];
-      b1 = off[key + 1];
+  const uint32_t h = st->he_count[row];
+  const bool wide = G.alpha > 8;
+  const bool lds = nb + 1 <= TAB_OFF_MAX && h < 65536 && G.alpha <= 16 &&
+                   (size_t)h * (wide ? 2 : 1) <= TAB_VAL_BYTES;
+  const uint32_t *g_off = bk_off + (size_t)row * (nb + 1);
+  const uint32_t *g_val = bk_val + ((size_t)row << G.k);
+  if (threadIdx.x == 0) seg_fill = 0;
+  if (lds) {
+    for (uint32_t x = threadIdx.x; x <= nb; x += blockDim.x) t_off[x] = (uint16_t)g_off[x];
+    for (uint32_t x = threadIdx.x; x < h; x += blockDim.x) {
+      const uint32_t hi = g_val[x] >> (G.k - G.alpha);
+      if (wide) reinterpret_cast<uint16_t *>(t_val)[x] = (uint16_t)hi;
+      else t_val[x] = (uint8_t)hi;
     }
-    join_step<LAST>(G, row, sub, c0, b0, b1, val, s, counter, out, cap);
   }
-  stage_flush(s, counter, out, cap);
+  __syncthreads();
+  const JoinTable T{t_off, t_val, reinterpret_cast<const uint16_t *>(t_val), g_off, g_val,
+                    G.k - G.alpha, lds, wide};
+
+  const uint32_t lane = lane_id();
+  const uint32_t wib = threadIdx.x >> 6;                    // wave in block
+  const uint32_t wpb = blockDim.x >> 6;                     // waves per block
+  uint32_t *W_incl = w_incl + wib * 64, *W_sub = w_sub + wib * 64, *W_c0 = w_c0 + wib * 64;
+  int32_t *W_base = w_base + wib * 64;
+  const uint32_t sh = G.shift[row];
+  uint2 *seg = LAST ? nullptr : out + (size_t)blockIdx.x * seg_cap;
+
+  // this block's wave items
+  uint64_t w_lo, w_hi, nch = 1;
+  const uint32_t *HE0 = he, *HE1 = he + (1u << G.k);
+  uint32_t h1 = 0;
+  const uint2 *my_in = nullptr;
+  uint32_t n_in = 0;
+  if (FIRST) {
+    const uint32_t h0 = st->he_count[0];
+    h1 = st->he_count[1];
+    nch = (h1 + 63) >> 6;
+    const uint64_t W = (uint64_t)h0 * nch;
+    w_lo = W * blockIdx.x / gridDim.x;
+    w_hi = W * (blockIdx.x + 1) / gridDim.x;
+  } else {
+    const uint32_t c = in_cnt[blockIdx.x];
+    n_in = (uint32_t)(c < seg_cap ? c : seg_cap);
+    my_in = in + (size_t)blockIdx.x * seg_cap;
+    w_lo = 0;
+    w_hi = (n_in + 63) >> 6;
+  }
+
+  for (uint64_t w = w_lo + wib; w < w_hi; w += wpb) {
+    // ---- this lane's item
+    uint32_t sub = 0, c0 = 0, b0 = 0, cnt = 0;
+    bool valid;
+    if (FIRST) {
+      const uint32_t x0 = (uint32_t)(w / nch);
+      const uint32_t x1 = (uint32_t)(w - (uint64_t)x0 * nch) * 64 + lane;
+      valid = x1 < h1;
+      if (valid) {
+        c0 = HE0[x0];
+        sub = c0 ^ HE1[x1];                 // BL(1)
+      }
+    } else {
+      const uint32_t t = (uint32_t)w * 64 + lane;
+      valid = t < n_in;
+      if (valid) {
+        const uint2 p = my_in[t];
+        sub = p.x;
+        c0 = p.y;
+      }
+    }
+    if (valid) {
+      const uint32_t key = ((uint32_t)((uint64_t)sub >> sh) ^ c0) & M;
+      b0 = T.start(key);
+      cnt = T.start(key + 1) - b0;
+    }
+    const uint32_t incl = wave_incl_scan(cnt);
+    const uint32_t total = __shfl(incl, 63, 64);
+    if (total == 0) continue;
+    W_incl[lane] = incl;
+    W_base[lane] = (int32_t)b0 - (int32_t)(incl - cnt);
+    W_sub[lane] = sub;
+    W_c0[lane] = c0;
+    lds_fence();
+    // ---- expand: one output slot per lane per pass
+    for (uint32_t base = 0; base < total; base += 64) {
+      const uint32_t slot = base + lane;
+      bool ok = false;
+      uint32_t a = 0, oc0 = 0;
+      if (slot < total) {
+        uint32_t o = 0;
+#pragma unroll
+        for (uint32_t s = 32; s; s >>= 1)
+          if (W_incl[o + s - 1] <= slot) o += s;
+        const uint32_t j = (uint32_t)(W_base[o] + (int32_t)slot);
+        oc0 = W_c0[o];
+        const uint32_t top = (oc0 >> (G.k - G.alpha)) ^ T.top_bits(j);
+        ok = extend_top(G, row, W_sub[o], top, &a);
+        if (LAST) ok = ok && hash_dh0(G, a) == oc0;
+      }
+      const unsigned long long mask = __ballot(ok);
+      if (mask == 0) continue;
+      const uint32_t n_ok = __popcll(mask);
+      const uint32_t rank = __popcll(mask & ((1ull << lane) - 1));
+      if (LAST) {
+        unsigned long long gb = 0;
+        if (lane == 0) gb = atomicAdd(&st->n_cand, (unsigned long long)n_ok);
+        gb = __shfl(gb, 0, 64);
+        if (ok && gb + rank < cand_cap) cand[gb + rank] = a;
+      } else {
+        uint32_t lb = 0;
+        if (lane == 0) lb = atomicAdd(&seg_fill, n_ok);
+        lb = __shfl(lb, 0, 64);
+        if (ok && (size_t)lb + rank < seg_cap) seg[lb + rank] = make_uint2(a, oc0);
+      }
+    }
+    lds_fence();
+  }
+  if (!LAST) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      out_cnt[blockIdx.x] = seg_fill;
+      atomicAdd(&st->n_out[row], (unsigned long long)seg_fill);
+      atomicMax(&st->seg_max[row], seg_fill);
+    }
+  }
 }
 
 // ------------------------------------------------------------ 6: estimate
@@ -517,13 +531,16 @@ __global__ __launch_bounds__(256) void k_estimate(Geom G, const uint32_t *__rest
 }
 
 // ----------------------------------------------------------------- 7: sort
-
+//
 // Records with distinct 32-bit keys (the address in .x for uint4 records,
-// the value itself for uint32) are sorted ascending. Up to SMALL_SORT
-// entries: one workgroup, a bitonic network over (key << 32 | index) in LDS.
-// Beyond that: every element's rank is the number of smaller keys, counted
-// against LDS tiles of all keys, by as many blocks as the grid has.
-constexpr uint32_t SMALL_SORT = 8192;
+// the value itself for uint32) are sorted ascending by rank = the number
+// of smaller keys. Up to SMALL_SORT entries the ranks are counted by a
+// (SMALL_SORT/256) x RANK_SPLIT grid, block (x, y) comparing 256 elements
+// against the y-th slice of the keys and adding its counts to a zeroed rank
+// array; a second kernel places each record at its rank. Larger lists use
+// one kernel in which each element scans all keys.
+constexpr uint32_t SMALL_SORT = 16384;
+constexpr uint32_t RANK_SPLIT = 8;
 
 template <typename T>
 __device__ __forceinline__ uint32_t sort_key(const T &v);
@@ -533,34 +550,37 @@ template <>
 __device__ __forceinline__ uint32_t sort_key<uint32_t>(const uint32_t &v) { return v; }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_sort_small(const T *__restrict__ in,
-                                                     const unsigned long long *__restrict__ count,
-                                                     size_t cap, T *__restrict__ out) {
-  __shared__ unsigned long long key[SMALL_SORT];
+__global__ __launch_bounds__(256) void k_rank_count(const T *__restrict__ in,
+                                                    const unsigned long long *__restrict__ count,
+                                                    size_t cap, uint32_t *__restrict__ rank) {
+  __shared__ uint32_t keys[SMALL_SORT / RANK_SPLIT];
   const unsigned long long n_all = *count;
   const uint32_t n = (uint32_t)(n_all < cap ? n_all : cap);
-  if (n > SMALL_SORT || n == 0) return;
-  uint32_t N = 2;
-  while (N < n) N <<= 1;
-  for (uint32_t i = threadIdx.x; i < N; i += blockDim.x)
-    key[i] = i < n ? ((unsigned long long)sort_key<T>(in[i]) << 32) | i : ~0ull;
+  if (n > SMALL_SORT) return;
+  const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x * 256 >= n) return;
+  const uint32_t per = (n + RANK_SPLIT - 1) / RANK_SPLIT;
+  const uint32_t k0 = blockIdx.y * per, k1 = k0 + per < n ? k0 + per : n;
+  if (k0 >= k1) return;
+  for (uint32_t t = threadIdx.x; t < k1 - k0; t += blockDim.x) keys[t] = sort_key<T>(in[k0 + t]);
   __syncthreads();
-  for (uint32_t k = 2; k <= N; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) {
-        const uint32_t ixj = i ^ j;
-        if (ixj > i) {
-          const unsigned long long a = key[i], b = key[ixj];
-          if ((a > b) == ((i & k) == 0)) {
-            key[i] = b;
-            key[ixj] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) out[i] = in[(uint32_t)key[i]];
+  if (j >= n) return;
+  const uint32_t mine = sort_key<T>(in[j]);
+  uint32_t c = 0;
+  for (uint32_t t = 0; t < k1 - k0; t++) c += keys[t] < mine;
+  if (c) atomicAdd(&rank[j], c);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_rank_place(const T *__restrict__ in,
+                                                    const unsigned long long *__restrict__ count,
+                                                    size_t cap, const uint32_t *__restrict__ rank,
+                                                    T *__restrict__ out) {
+  const unsigned long long n_all = *count;
+  const uint32_t n = (uint32_t)(n_all < cap ? n_all : cap);
+  if (n > SMALL_SORT) return;
+  const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+  if (j < n) out[rank[j]] = in[j];
 }
 
 template <typename T>
@@ -593,10 +613,12 @@ __global__ __launch_bounds__(256) void k_rank_sort(const T *__restrict__ in,
   }
 }
 
+// rank must hold SMALL_SORT zeroed entries.
 template <typename T>
 static void launch_sort(const T *in, const unsigned long long *count, size_t cap, T *out,
-                        int grid, hipStream_t st) {
-  k_sort_small<T><<<1, 1024, 0, st>>>(in, count, cap, out);
+                        uint32_t *rank, int grid, hipStream_t st) {
+  k_rank_count<T><<<dim3(SMALL_SORT / 256, RANK_SPLIT), 256, 0, st>>>(in, count, cap, rank);
+  k_rank_place<T><<<SMALL_SORT / 256, 256, 0, st>>>(in, count, cap, rank, out);
   k_rank_sort<T><<<grid, 256, 0, st>>>(in, count, cap, out);
 }
 
@@ -609,7 +631,7 @@ static hipError_t launch_wpl(const Geom &G, const uint32_t *sketch, const Restor
   const uint32_t r = G.r, k = G.k;
   const size_t n_le = (size_t)r << k;
   // 0: clear state and the hot bitmap
-  k_state_init<<<1, 256, 0, st>>>(B.st);
+  k_state_init<<<1, 1024, 0, st>>>(B.st, B.rank, SMALL_SORT);
   hipError_t e = launch_fill_u32(B.hotmask, n_le / 32, 0u, grid, st);
   if (e != hipSuccess) return e;
   // 1: hot scan
@@ -629,33 +651,39 @@ static hipError_t launch_wpl(const Geom &G, const uint32_t *sketch, const Restor
   // 4: scalars
   k_scalars<<<1, 64, 0, st>>>(G, B.st, e_theta);
   // 5: join
-  if (r == 3) {
-    k_join_first<true><<<grid, 256, 0, st>>>(G, B.he, B.bk_off, B.bk_val, B.st, B.cand,
-                                             B.cand_cap);
-  } else {
-    k_join_first<false><<<grid, 256, 0, st>>>(G, B.he, B.bk_off, B.bk_val, B.st, B.part[0],
-                                              B.part_cap[0]);
-    for (uint32_t row = 3; row < r; row++) {
-      // stage 1 wrote part[0]; stage row reads part[(row-3)%2], writes the other
-      const int ib = (row - 3) & 1;
-      const int ob = ib ^ 1;
-      if (row + 1 == r)
-        k_join_next<true><<<grid, 256, 0, st>>>(G, row, B.part[ib], B.part_cap[ib], B.bk_off,
-                                                B.bk_val, B.st, B.cand, B.cand_cap);
-      else
-        k_join_next<false><<<grid, 256, 0, st>>>(G, row, B.part[ib], B.part_cap[ib], B.bk_off,
-                                                 B.bk_val, B.st, B.part[ob], B.part_cap[ob]);
+  {
+    const uint32_t jb = B.jblk;
+    if (r == 3) {
+      k_join<true, true><<<jb, JOIN_THREADS, 0, st>>>(G, 2, B.he, nullptr, nullptr, B.bk_off,
+                                                      B.bk_val, B.st, nullptr, nullptr, 0,
+                                                      B.cand, B.cand_cap);
+    } else {
+      k_join<true, false><<<jb, JOIN_THREADS, 0, st>>>(G, 2, B.he, nullptr, nullptr, B.bk_off,
+                                                       B.bk_val, B.st, B.part[0], B.segc[0],
+                                                       B.seg_cap, B.cand, B.cand_cap);
+      for (uint32_t row = 3; row < r; row++) {
+        // stage 1 wrote part[0]; stage `row` reads part[(row-3)%2], writes the other
+        const int ib = (row - 3) & 1, ob = ib ^ 1;
+        if (row + 1 == r)
+          k_join<false, true><<<jb, JOIN_THREADS, 0, st>>>(
+              G, row, B.he, B.part[ib], B.segc[ib], B.bk_off, B.bk_val, B.st, nullptr, nullptr,
+              B.seg_cap, B.cand, B.cand_cap);
+        else
+          k_join<false, false><<<jb, JOIN_THREADS, 0, st>>>(
+              G, row, B.he, B.part[ib], B.segc[ib], B.bk_off, B.bk_val, B.st, B.part[ob],
+              B.segc[ob], B.seg_cap, B.cand, B.cand_cap);
+      }
     }
   }
   if (!estimate) {
-    launch_sort<uint32_t>(B.cand, &B.st->n_cand, B.cand_cap, B.cand_sorted, grid, st);
+    launch_sort<uint32_t>(B.cand, &B.st->n_cand, B.cand_cap, B.cand_sorted, B.rank, grid, st);
     return hipGetLastError();
   }
   // 6: estimate and report
   k_estimate<WPL><<<grid, 256, 0, st>>>(G, sketch, B.cand, B.cand_cap, B.st, B.spl,
                                         B.spl_cap);
   // 7: sort
-  launch_sort<uint4>(B.spl, &B.st->n_spl, B.spl_cap, B.spl_sorted, grid, st);
+  launch_sort<uint4>(B.spl, &B.st->n_spl, B.spl_cap, B.spl_sorted, B.rank, grid, st);
   return hipGetLastError();
 }
 

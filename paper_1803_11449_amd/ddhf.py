@@ -27,7 +27,13 @@ DEFAULT_SEED = 0x1803114490000001
 EXPORTS = ("sketch_params_default", "sketch_params_check", "sketch_bytes",
            "sketch_create", "sketch_destroy", "sketch_update", "sketch_restore",
            "sketch_reset", "sketch_download", "sketch_upload",
-           "sketch_candidates", "sketch_last_error")
+           "sketch_candidates", "sketch_last_error", "sketch_set_option")
+
+SKETCH_OPT_UPDATE_PATH = 1
+SKETCH_OPT_BINNED_MIN_PAIRS = 2
+SKETCH_OPT_UPDATE_GRID = 3
+SKETCH_OPT_UPDATE_CHECK = 4
+SKETCH_OPT_BINNED_ROUND = 5
 
 c_u32, c_u64, c_i32, c_sz, c_dbl, c_vp = (ctypes.c_uint32, ctypes.c_uint64,
                                           ctypes.c_int32, ctypes.c_size_t,
@@ -88,6 +94,7 @@ def lib() -> ctypes.CDLL:
             "sketch_upload": (c_i32, [c_vp, c_vp, c_sz, c_vp]),
             "sketch_candidates": (c_i32, [c_vp, c_dbl, c_vp, c_sz, P(c_sz), c_vp]),
             "sketch_last_error": (ctypes.c_char_p, []),
+            "sketch_set_option": (c_i32, [c_vp, c_i32, ctypes.c_int64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -107,6 +114,10 @@ def _check(rc: int, n_needed=None) -> None:
 
 
 # --------------------------------------------------- C names, thin wrappers
+
+def sketch_set_option(h: int, option: int, value: int) -> None:
+    _check(lib().sketch_set_option(h, option, int(value)))
+
 
 def sketch_params_default() -> sketch_params_t:
     p = sketch_params_t()
@@ -220,6 +231,9 @@ class Sketch:
             raise ValueError("pairs must hold an even number of words")
         sketch_update(self.handle, pairs.data_ptr(), pairs.numel() // 2,
                       _stream_handle(stream, pairs.device))
+
+    def set_option(self, option: int, value: int) -> None:
+        sketch_set_option(self.handle, option, value)
 
     def update_ptr(self, d_pairs: int, n_pairs: int, stream: int = 0) -> None:
         sketch_update(self.handle, d_pairs, n_pairs, stream)

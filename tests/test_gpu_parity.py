@@ -30,8 +30,14 @@ def host_words(pairs_t):
     return pairs_t.cpu().numpy().view(np.uint32).reshape(-1)
 
 
-def make_sketch(p: oracle.Params):
-    return ddhf.Sketch(p.g, p.k, p.r, p.alpha, p.seed, device=0)
+def make_sketch(p: oracle.Params, path: int = 0):
+    sk = ddhf.Sketch(p.g, p.k, p.r, p.alpha, p.seed, device=0)
+    if path:
+        sk.set_option(ddhf.SKETCH_OPT_UPDATE_PATH, path)
+    return sk
+
+
+PATHS = pytest.mark.parametrize("path", [1, 2], ids=["direct", "binned"])
 
 
 def assert_not_boundary(info):
@@ -76,13 +82,14 @@ def test_generator_same_on_gpu_and_cpu():
     assert torch.equal(a, b)
 
 
+@PATHS
 @pytest.mark.parametrize("n", [0, 1, 63, 64, 255, 257, 4099, 100_003])
-def test_update_ragged_sizes(n):
-    say(f"update ragged n={n}")
+def test_update_ragged_sizes(n, path):
+    say(f"update ragged n={n} path={path}")
     p = oracle.Params()
     rng = np.random.default_rng(n + 1)
     pairs = rand_pairs(rng, n, max(1, n // 7)) if n else np.zeros((0, 2), np.uint32)
-    with make_sketch(p) as sk:
+    with make_sketch(p, path) as sk:
         if n:
             sk.update(to_dev(pairs))
         else:
@@ -95,16 +102,18 @@ def test_update_ragged_sizes(n):
 PARAMS = [oracle.Params(), oracle.Params(1024, 18, 5, 5), oracle.Params(1024, 16, 3, 16),
           oracle.Params(256, 12, 6, 5), oracle.Params(512, 10, 8, 4),
           oracle.Params(32, 14, 5, 6), oracle.Params(64, 14, 5, 6),
-          oracle.Params(4096, 14, 5, 6), oracle.Params(16384, 12, 5, 7)]
+          oracle.Params(4096, 14, 5, 6), oracle.Params(16384, 12, 5, 7),
+          oracle.Params(32, 5, 8, 5), oracle.Params(64, 8, 6, 7)]
 
 
+@PATHS
 @pytest.mark.parametrize("p", PARAMS, ids=lambda p: f"g{p.g}k{p.k}r{p.r}a{p.alpha}")
-def test_update_params_and_chunking(p):
-    say(f"update params g={p.g} k={p.k} r={p.r} alpha={p.alpha}")
+def test_update_params_and_chunking(p, path):
+    say(f"update params g={p.g} k={p.k} r={p.r} alpha={p.alpha} path={path}")
     rng = np.random.default_rng(p.g + p.k)
     pairs = rand_pairs(rng, 60_001, 3000)
     ref = oracle.build_sketch(p, pairs)
-    with make_sketch(p) as sk:
+    with make_sketch(p, path) as sk:
         d = to_dev(pairs)
         # uneven chunks, each 8-byte aligned
         cuts = [0, 1, 1000, 1001, 33_333, 60_001]
@@ -119,6 +128,34 @@ def test_update_params_and_chunking(p):
         sk.reset()
         torch.cuda.synchronize()
         assert not sk.download().any()
+
+
+def test_binned_rounds_and_split_tiles():
+    """Binned update with small rounds (several count/scatter/apply passes
+    per call) and a heavy source whose tile holds far more codes than one
+    apply item (the tile is split and merged with atomicOr)."""
+    p = oracle.Params(1024, 18, 5, 5)
+    rng = np.random.default_rng(21)
+    heavy = np.stack([np.full(1_500_000, 0x01020304, dtype=np.uint32),
+                      rng.integers(0, 2**32, size=1_500_000, dtype=np.uint64).astype(np.uint32)], 1)
+    pairs = np.concatenate([rand_pairs(rng, 700_000, 50_000), heavy])
+    pairs = pairs[rng.permutation(len(pairs))]
+    ref = oracle.build_sketch(p, pairs)
+    for rnd in (1 << 19, 1 << 27):
+        with make_sketch(p, 2) as sk:
+            sk.set_option(ddhf.SKETCH_OPT_BINNED_ROUND, rnd)
+            sk.update(to_dev(pairs))
+            torch.cuda.synchronize()
+            assert np.array_equal(sk.download(), ref), rnd
+
+
+def test_set_option_rejects_bad_values():
+    with make_sketch(oracle.Params()) as sk:
+        for opt, val in ((ddhf.SKETCH_OPT_UPDATE_PATH, 3), (ddhf.SKETCH_OPT_UPDATE_GRID, 0),
+                         (ddhf.SKETCH_OPT_BINNED_ROUND, 10), (99, 1)):
+            with pytest.raises(ddhf.SketchError) as e:
+                sk.set_option(opt, val)
+            assert e.value.code == ddhf.SKETCH_E_INVAL
 
 
 # ----------------------------------------------------------------- restore
@@ -169,7 +206,9 @@ def test_config1_restore_thresholds_on_uploaded_sketch(cfg1, theta):
 
 @pytest.mark.parametrize("p", [oracle.Params(1024, 16, 3, 16), oracle.Params(256, 12, 6, 5),
                                oracle.Params(512, 18, 5, 5), oracle.Params(2048, 14, 5, 6),
-                               oracle.Params(32, 16, 4, 8)],
+                               oracle.Params(32, 16, 4, 8),
+                               # 2^16 buckets: the join reads its tables from HBM
+                               oracle.Params(1024, 20, 5, 4)],
                          ids=lambda p: f"g{p.g}k{p.k}r{p.r}a{p.alpha}")
 def test_restore_other_params_vs_bruteforce(p):
     say(f"restore params g={p.g} k={p.k} r={p.r} alpha={p.alpha}")
@@ -187,6 +226,25 @@ def test_restore_other_params_vs_bruteforce(p):
         recs, info = sk.restore(theta)
     assert np.array_equal(cand, oracle.candidates(p, ref, theta, "brute"))
     ip, sz, c, _ = oracle.restore(p, ref, theta, mode="brute")
+    assert_not_boundary(info)
+    assert_spl_equal(recs, ip, sz, c)
+
+
+def test_more_super_points_than_the_small_sort():
+    """More than 16384 reported addresses: the large-list sort path."""
+    p = oracle.Params(1024, 18, 5, 5)
+    rng = np.random.default_rng(31)
+    hosts = rng.choice(2**32, size=20_000, replace=False).astype(np.uint32)
+    n_each = 1300
+    src = np.repeat(hosts, n_each)
+    dst = rng.integers(0, 2**32, size=src.size, dtype=np.uint64).astype(np.uint32)
+    pairs = np.stack([src, dst], 1)[rng.permutation(src.size)]
+    ref = oracle.build_sketch(p, pairs)
+    with make_sketch(p) as sk:
+        sk.update(to_dev(pairs))
+        recs, info = sk.restore(1024.0)
+    assert len(recs) > 16384
+    ip, sz, c, _ = oracle.restore(p, ref, 1024.0, mode="brute")
     assert_not_boundary(info)
     assert_spl_equal(recs, ip, sz, c)
 

@@ -125,6 +125,22 @@ void sketch_destroy(sketch_t *s);
 int sketch_update(sketch_t *s, const uint32_t *d_pairs, size_t n_pairs,
                   void *hip_stream);
 
+/* One sketch's share of a batched update. */
+typedef struct {
+  sketch_t *sketch;
+  const uint32_t *d_pairs;   /* DEVICE memory, as for sketch_update */
+  size_t n_pairs;
+} sketch_update_job_t;
+
+/* Alg. 1 for several sketches (links or windows of uneven size) in one set
+ * of launches: each kernel of the update takes every job, so the batch
+ * fills the GPU even when each job alone would not. The result is the same
+ * as sketch_update on each job in turn. All sketches must be on one device
+ * and distinct; pairs follow the rules of sketch_update. Asynchronous on
+ * hip_stream. Errors: INVAL (NULL job list or handle, sketches on different
+ * devices, a sketch twice, bad pairs pointer), NOMEM, HIP. */
+int sketch_update_batch(const sketch_update_job_t *jobs, size_t n_jobs, void *hip_stream);
+
 /* Alg. 2 (Sec. 3.3) computed as in Sec. 4.2: LEs with z0 < g*exp(-theta/g)
  * are hot; the join of Algs. 3-4 rebuilds every address whose r LEs are
  * all hot and which re-hashes to its own LE in row 0; each is reported iff
@@ -138,6 +154,29 @@ int sketch_update(sketch_t *s, const uint32_t *d_pairs, size_t n_pairs,
  * success, CAPACITY and SATURATED. */
 int sketch_restore(sketch_t *s, double theta, sketch_sp_t *out, size_t cap,
                    size_t *n_out, sketch_info_t *info, void *hip_stream);
+
+/* One sketch's share of a batched restore. Inputs: sketch, theta, out
+ * (HOST memory for cap records), cap, info (nullable). Outputs: n_out (the
+ * number of records, also on CAPACITY) and status (the sketch_restore code
+ * of this job). */
+typedef struct {
+  sketch_t *sketch;
+  double theta;
+  sketch_sp_t *out;
+  size_t cap;
+  sketch_info_t *info;
+  size_t n_out;
+  int status;
+} sketch_restore_job_t;
+
+/* sketch_restore for several distinct sketches on one device: every
+ * restore is enqueued on hip_stream before one wait, so windows that close
+ * together are reported together. Each job gets the result sketch_restore
+ * would give it. Synchronous. Returns SKETCH_OK if every job succeeded,
+ * else the first failing job's code (each job's status says which). Errors
+ * before any work (NULL list or handle, bad theta or out, a sketch twice,
+ * several devices): INVAL, with no job run. */
+int sketch_restore_batch(sketch_restore_job_t *jobs, size_t n_jobs, void *hip_stream);
 
 /* Start a new window: every bit of the sketch back to 0 (Sec. 4).
  * Asynchronous on hip_stream. */
@@ -158,9 +197,16 @@ enum {
   SKETCH_OPT_UPDATE_GRID = 3,       /* blocks of the direct kernel */
   SKETCH_OPT_UPDATE_CHECK = 4,      /* direct kernel: 1 = test the bit before
                                        the atomicOr (default), 0 = always OR */
-  SKETCH_OPT_BINNED_ROUND = 5       /* binned: pairs per round; the round's
+  SKETCH_OPT_BINNED_ROUND = 5,      /* binned: pairs per round; the round's
                                        codes take 4*r bytes per pair of device
                                        memory, allocated on first use */
+  SKETCH_OPT_SCATTER_PPT = 6,       /* binned: pairs per thread in one LDS
+                                       sorting batch: 2, 4 or 6 (default);
+                                       capped by LDS at 4 for r in 6..7 and
+                                       at 2 for r = 8 */
+  SKETCH_OPT_BINNED_BLOCKS = 7      /* binned: blocks of the count and
+                                       scatter passes, 1..1024 (default: one
+                                       per compute unit) */
 };
 
 /* Set a tuning option; results never depend on it. Errors: INVAL (NULL

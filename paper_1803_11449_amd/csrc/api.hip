@@ -7,12 +7,37 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "ddhf.h"
 #include "ddhf_internal.h"
 
 using namespace ddhf;
+
+namespace {
+
+// Per-device launch context shared by every handle on the device: a ring of
+// update job tables (pinned host staging + device copy + an event marking
+// when the launches that read a slot are done).
+struct DevCtx {
+  static constexpr int SLOTS = 16;
+  int dev = -1;
+  int refs = 0;
+  std::mutex mu;
+  UpdJob *h_jobs[SLOTS] = {};
+  UpdJob *d_jobs[SLOTS] = {};
+  uint32_t *d_total = nullptr;   // SLOTS words
+  hipEvent_t ev[SLOTS] = {};
+  bool armed[SLOTS] = {};
+  int next = 0;
+};
+
+std::mutex g_ctx_mu;
+DevCtx *g_ctx[256] = {};
+
+}  // namespace
 
 struct sketch {
   sketch_params_t p;
@@ -30,6 +55,7 @@ struct sketch {
   size_t binned_round = (size_t)1 << 27;  // pairs per binned round (codes < 2^32)
   uint32_t nbins = 0;
   BinBufs BB{};
+  DevCtx *ctx = nullptr;
 };
 
 namespace {
@@ -131,6 +157,8 @@ void dev_free(T *&p) {
   p = nullptr;
 }
 
+void ctx_release(DevCtx *c);
+
 void free_all(sketch *s) {
   dev_free(s->d_sketch);
   RestoreBufs &B = s->B;
@@ -161,6 +189,8 @@ void free_all(sketch *s) {
   dev_free(BB.codes);
   dev_free(BB.scratch);
   BB.codes_cap = 0;
+  ctx_release(s->ctx);
+  s->ctx = nullptr;
 }
 
 // Codes buffer of the binned update for rounds of `pairs` pairs.
@@ -194,6 +224,61 @@ int grow_partials(sketch *s, size_t seg_need) {
   rc = dev_alloc(&B.part[1], cap * B.jblk, "partials");
   if (rc) return rc;
   B.seg_cap = cap;
+  return SKETCH_OK;
+}
+
+// The device context of `dev` (created on first use; refcounted by handles).
+int ctx_acquire(int dev, DevCtx **out) {
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  if (dev < 0 || dev >= 256) return fail(SKETCH_E_INVAL, "device %d out of range", dev);
+  DevCtx *c = g_ctx[dev];
+  if (!c) {
+    c = new DevCtx();
+    c->dev = dev;
+    for (int i = 0; i < DevCtx::SLOTS; i++) {
+      if (hipHostMalloc((void **)&c->h_jobs[i], sizeof(UpdJob) * MAX_JOBS) != hipSuccess ||
+          hipMalloc((void **)&c->d_jobs[i], sizeof(UpdJob) * MAX_JOBS) != hipSuccess ||
+          hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming) != hipSuccess)
+        return fail(SKETCH_E_NOMEM, "device context: allocation failed");
+    }
+    if (hipMalloc((void **)&c->d_total, sizeof(uint32_t) * DevCtx::SLOTS) != hipSuccess)
+      return fail(SKETCH_E_NOMEM, "device context: allocation failed");
+    g_ctx[dev] = c;
+  }
+  c->refs++;
+  *out = c;
+  return SKETCH_OK;
+}
+
+void ctx_release(DevCtx *c) {
+  if (!c) return;
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  if (--c->refs > 0) return;
+  for (int i = 0; i < DevCtx::SLOTS; i++) {
+    if (c->armed[i]) (void)hipEventSynchronize(c->ev[i]);
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    if (c->h_jobs[i]) (void)hipHostFree(c->h_jobs[i]);
+    if (c->d_jobs[i]) (void)hipFree(c->d_jobs[i]);
+  }
+  if (c->d_total) (void)hipFree(c->d_total);
+  g_ctx[c->dev] = nullptr;
+  delete c;
+}
+
+// Copy n jobs into the next ring slot and launch them on st.
+int launch_jobs(DevCtx *c, const UpdJob *jobs, uint32_t n, bool binned, uint32_t r,
+                uint32_t ppt, uint32_t apply_grid, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(c->mu);
+  const int slot = c->next;
+  c->next = (c->next + 1) % DevCtx::SLOTS;
+  if (c->armed[slot]) HIP_OK(hipEventSynchronize(c->ev[slot]));
+  memcpy(c->h_jobs[slot], jobs, sizeof(UpdJob) * n);
+  HIP_OK(hipMemcpyAsync(c->d_jobs[slot], c->h_jobs[slot], sizeof(UpdJob) * n,
+                        hipMemcpyHostToDevice, st));
+  HIP_OK(launch_update_jobs(c->h_jobs[slot], c->d_jobs[slot], n, c->d_total + slot, binned, r,
+                            ppt, apply_grid, st));
+  HIP_OK(hipEventRecord(c->ev[slot], st));
+  c->armed[slot] = true;
   return SKETCH_OK;
 }
 
@@ -247,41 +332,70 @@ void fill_info(const sketch *s, const DevState &st, double zmin, uint32_t zhot,
 // Runs the restore pipeline until every buffer held its output (counts are
 // exact on the device even past capacity, so one rerun per grown stage at
 // most). Leaves the final state in s->h_state.
+// Thresholds that depend on theta only (host, float64).
+struct Thresholds {
+  double e_theta, zmin;
+  uint32_t zhot;
+};
+
+Thresholds thresholds(const sketch *s, double theta) {
+  Thresholds t;
+  t.e_theta = exp(-theta / (double)s->p.g);
+  t.zmin = (double)s->p.g * t.e_theta;
+  // hot <=> z0 < zmin <=> z0 <= ceil(zmin) - 1 for integer z0
+  const double zc = ceil(t.zmin) - 1.0;
+  t.zhot = zc < 0 ? 0u : (zc > (double)s->p.g ? s->p.g : (uint32_t)zc);
+  return t;
+}
+
+// Enqueue the restore kernels and the copy of the device state (no wait).
+int restore_launch(sketch *s, const Thresholds &t, int estimate, hipStream_t st) {
+  HIP_OK(launch_restore(s->G, s->d_sketch, s->B, t.zhot, t.e_theta, estimate, s->grid, st));
+  HIP_OK(hipMemcpyAsync(s->h_state, s->B.st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+  return SKETCH_OK;
+}
+
+// After the state copy has landed: grow any buffer that overflowed.
+// *again = a buffer grew, so the restore must run again.
+int restore_check(sketch *s, int estimate, bool *again) {
+  const DevState &h = *s->h_state;
+  *again = false;
+  if (h.saturated) return SKETCH_E_SATURATED;
+  size_t need_part = 0;
+  for (uint32_t i = 2; i + 1 < s->p.r; i++) need_part = std::max<size_t>(need_part, h.seg_max[i]);
+  if (need_part > s->B.seg_cap) {
+    int rc = grow_partials(s, need_part);
+    if (rc) return rc;
+    *again = true;
+  }
+  if (h.n_cand > s->B.cand_cap) {
+    int rc = grow_cand(s, h.n_cand);
+    if (rc) return rc;
+    *again = true;
+  }
+  if (estimate && h.n_spl > s->B.spl_cap) {
+    int rc = grow_spl(s, h.n_spl);
+    if (rc) return rc;
+    *again = true;
+  }
+  return SKETCH_OK;
+}
+
+// Runs the restore pipeline until every buffer held its output (counts are
+// exact on the device even past capacity, so one rerun per grown stage at
+// most). Leaves the final state in s->h_state.
 int run_restore(sketch *s, double theta, int estimate, hipStream_t st, double *zmin_out,
                 uint32_t *zhot_out) {
-  const double e_theta = exp(-theta / (double)s->p.g);
-  const double zmin = (double)s->p.g * e_theta;
-  // hot <=> z0 < zmin <=> z0 <= ceil(zmin) - 1 for integer z0
-  const double zc = ceil(zmin) - 1.0;
-  const uint32_t zhot = zc < 0 ? 0u : (zc > (double)s->p.g ? s->p.g : (uint32_t)zc);
-  *zmin_out = zmin;
-  *zhot_out = zhot;
+  const Thresholds t = thresholds(s, theta);
+  *zmin_out = t.zmin;
+  *zhot_out = t.zhot;
   for (int attempt = 0; attempt < 16; attempt++) {
-    HIP_OK(launch_restore(s->G, s->d_sketch, s->B, zhot, e_theta, estimate, s->grid, st));
-    HIP_OK(hipMemcpyAsync(s->h_state, s->B.st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+    int rc = restore_launch(s, t, estimate, st);
+    if (rc) return rc;
     HIP_OK(hipStreamSynchronize(st));
-    const DevState &h = *s->h_state;
-    if (h.saturated) return SKETCH_E_SATURATED;
-    bool again = false;
-    size_t need_part = 0;
-    for (uint32_t i = 2; i + 1 < s->p.r; i++)
-      need_part = std::max<size_t>(need_part, h.seg_max[i]);
-    if (need_part > s->B.seg_cap) {
-      int rc = grow_partials(s, need_part);
-      if (rc) return rc;
-      again = true;
-    }
-    if (h.n_cand > s->B.cand_cap) {
-      int rc = grow_cand(s, h.n_cand);
-      if (rc) return rc;
-      again = true;
-    }
-    if (estimate && h.n_spl > s->B.spl_cap) {
-      int rc = grow_spl(s, h.n_spl);
-      if (rc) return rc;
-      again = true;
-    }
-    if (!again) return SKETCH_OK;
+    bool again;
+    rc = restore_check(s, estimate, &again);
+    if (rc || !again) return rc;
   }
   return fail(SKETCH_E_HIP, "restore: capacities did not settle");
 }
@@ -356,16 +470,20 @@ int sketch_create(const sketch_params_t *params, sketch_t **out) {
   s->nbins = (uint32_t)((s->words + BIN_TILE_WORDS - 1) / BIN_TILE_WORDS);
   s->BB.nblk = (uint32_t)std::min(1024, s->n_cu);
   s->BB.apply_grid = (uint32_t)s->n_cu;
-  s->binned_min_pairs = std::max<size_t>(s->words / 8, 1 << 16);
+  s->BB.scatter_ppt = 6;
+  // measured crossover on MI355X (100M-pair Zipf window): the binned update
+  // wins from ~1e5 pairs at k = 14 and ~2e5 at k = 18
+  s->binned_min_pairs = std::max<size_t>(s->words / 256, 1 << 14);
   if (s->nbins <= BIN_MAX) {
     BinBufs &BB = s->BB;
-    if (!rc) rc = dev_alloc(&BB.hist, (size_t)s->nbins * BB.nblk, "tile counts");
+    if (!rc) rc = dev_alloc(&BB.hist, (size_t)s->nbins * BIN_BLOCKS_MAX, "tile counts");
     if (!rc) rc = dev_alloc(&BB.totals, s->nbins, "tile totals");
     if (!rc) rc = dev_alloc(&BB.base, s->nbins + 1, "tile runs");
     if (!rc) rc = dev_alloc(&BB.item_start, s->nbins + 1, "tile items");
     if (!rc) rc = dev_alloc(&BB.xslot, s->nbins + 1, "tile scratch slots");
     if (!rc) rc = dev_alloc(&BB.n_items, 1, "tile item count");
   }
+  if (!rc) rc = ctx_acquire(params->device, &s->ctx);
   if (!rc && hipHostMalloc((void **)&s->h_state, sizeof(DevState)) != hipSuccess) {
     s->h_state = nullptr;
     rc = fail(SKETCH_E_NOMEM, "hipHostMalloc(state) failed");
@@ -392,26 +510,170 @@ void sketch_destroy(sketch_t *s) {
   delete s;
 }
 
+// ------------------------------------------------------------ update
+
+namespace {
+
+UpdJob job_base(const sketch *s) {
+  UpdJob J{};
+  J.G = s->G;
+  J.sk = s->d_sketch;
+  J.words = s->words;
+  J.nbins = s->nbins;
+  J.hist = s->BB.hist;
+  J.totals = s->BB.totals;
+  J.base = s->BB.base;
+  J.item_start = s->BB.item_start;
+  J.xslot = s->BB.xslot;
+  J.n_items = s->BB.n_items;
+  J.codes = s->BB.codes;
+  J.scratch = s->BB.scratch;
+  J.check = (uint32_t)(s->update_variant & 1);
+  return J;
+}
+
+bool wants_binned(const sketch *s, size_t n) {
+  if (s->nbins > BIN_MAX) return false;
+  return s->update_path == 2 || (s->update_path == 0 && n >= s->binned_min_pairs);
+}
+
+// A launch group: jobs that share the kernels (same r, path, check flag).
+struct Group {
+  uint32_t r;
+  bool binned;
+  uint32_t check;
+  uint32_t ppt;
+  uint32_t apply_grid;
+  std::vector<UpdJob> jobs;
+};
+
+int flush_group(DevCtx *c, Group &g, hipStream_t st) {
+  for (size_t at = 0; at < g.jobs.size(); at += MAX_JOBS) {
+    const uint32_t n = (uint32_t)std::min<size_t>(MAX_JOBS, g.jobs.size() - at);
+    UpdJob *J = g.jobs.data() + at;
+    uint32_t blk = 0, tile = 0;
+    for (uint32_t j = 0; j < n; j++) {
+      J[j].blk0 = blk;
+      J[j].tile0 = tile;
+      blk += J[j].nblk;
+      tile += J[j].nbins;
+    }
+    int rc = launch_jobs(c, J, n, g.binned, g.r, g.ppt, g.apply_grid, st);
+    if (rc) return rc;
+  }
+  g.jobs.clear();
+  return SKETCH_OK;
+}
+
+void add_job(std::vector<Group> &groups, const sketch *s, UpdJob J, bool binned) {
+  const uint32_t ppt = s->BB.scatter_ppt;
+  for (Group &g : groups)
+    if (g.r == s->p.r && g.binned == binned && (binned || g.check == J.check) &&
+        (!binned || g.ppt == ppt)) {
+      g.apply_grid = std::max(g.apply_grid, s->BB.apply_grid);
+      g.jobs.push_back(J);
+      return;
+    }
+  groups.push_back(Group{s->p.r, binned, J.check, ppt, s->BB.apply_grid, {J}});
+}
+
+// The update of several distinct sketches on one device: every pair of every
+// job is applied; binned jobs run in rounds of at most their round size.
+int update_jobs(const sketch_update_job_t *jobs, size_t n_jobs, hipStream_t st) {
+  if (n_jobs == 0) return SKETCH_OK;
+  if (!jobs) return fail(SKETCH_E_INVAL, "sketch_update_batch: NULL jobs");
+  const int dev = jobs[0].sketch ? jobs[0].sketch->p.device : -1;
+  for (size_t j = 0; j < n_jobs; j++) {
+    const sketch *s = jobs[j].sketch;
+    if (!s) return fail(SKETCH_E_INVAL, "sketch_update: NULL handle (job %zu)", j);
+    if (s->p.device != dev)
+      return fail(SKETCH_E_INVAL, "sketch_update_batch: sketches on different devices");
+    if (jobs[j].n_pairs && !jobs[j].d_pairs)
+      return fail(SKETCH_E_INVAL, "sketch_update: NULL pairs (job %zu)", j);
+    if (((uintptr_t)jobs[j].d_pairs) & 7u)
+      return fail(SKETCH_E_INVAL, "sketch_update: pairs must be 8-byte aligned (job %zu)", j);
+    for (size_t i = 0; i < j; i++)
+      if (jobs[i].sketch == s)
+        return fail(SKETCH_E_INVAL, "sketch_update_batch: a sketch appears twice (jobs %zu, %zu)",
+                    i, j);
+  }
+  DEVICE_GUARD(dev);
+  DevCtx *c = jobs[0].sketch->ctx;
+  // per job: pairs left, binned or not
+  std::vector<const uint32_t *> ptr(n_jobs);
+  std::vector<size_t> left(n_jobs);
+  std::vector<char> binned(n_jobs);
+  std::vector<Group> groups;
+  for (size_t j = 0; j < n_jobs; j++) {
+    sketch *s = jobs[j].sketch;
+    ptr[j] = jobs[j].d_pairs;
+    left[j] = jobs[j].n_pairs;
+    binned[j] = left[j] && wants_binned(s, left[j]);
+    if (binned[j]) {
+      int rc = ensure_codes(s, std::min(left[j], s->binned_round), st);
+      if (rc) return rc;
+      if (((uintptr_t)ptr[j]) & 15u) {
+        // the count pass reads pairs 16 bytes at a time: the first pair
+        // goes through the direct kernel so the rest starts 16-byte aligned
+        UpdJob J = job_base(s);
+        J.pairs = reinterpret_cast<const uint2 *>(ptr[j]);
+        J.n = 1;
+        J.nblk = 1;
+        add_job(groups, s, J, false);
+        ptr[j] += 2;
+        left[j]--;
+      }
+    }
+  }
+  for (;;) {
+    bool any = false;
+    for (size_t j = 0; j < n_jobs; j++) {
+      if (!left[j]) continue;
+      sketch *s = jobs[j].sketch;
+      UpdJob J = job_base(s);
+      J.pairs = reinterpret_cast<const uint2 *>(ptr[j]);
+      if (binned[j]) {
+        const size_t m = std::min(left[j], s->binned_round);
+        J.n = m;
+        // about 32k pairs or more per block, at most the configured count
+        const size_t want = (m + 32767) / 32768;
+        J.nblk = (uint32_t)std::max<size_t>(1, std::min<size_t>(s->BB.nblk, want));
+        size_t chunk = (m + J.nblk - 1) / J.nblk;
+        chunk += chunk & 1;
+        J.chunk = chunk;
+        J.nblk = (uint32_t)((m + chunk - 1) / chunk);
+        add_job(groups, s, J, true);
+        ptr[j] += 2 * m;
+        left[j] -= m;
+      } else {
+        J.n = left[j];
+        J.nblk = (uint32_t)std::max<size_t>(
+            1, std::min<size_t>((size_t)s->update_grid, (left[j] + 255) / 256));
+        add_job(groups, s, J, false);
+        left[j] = 0;
+      }
+      any = true;
+    }
+    for (Group &g : groups) {
+      int rc = flush_group(c, g, st);
+      if (rc) return rc;
+    }
+    if (!any) break;
+  }
+  return SKETCH_OK;
+}
+
+}  // namespace
+
 int sketch_update(sketch_t *s, const uint32_t *d_pairs, size_t n_pairs, void *hip_stream) {
   if (!s) return fail(SKETCH_E_INVAL, "sketch_update: NULL handle");
   if (n_pairs == 0) return SKETCH_OK;
-  if (!d_pairs) return fail(SKETCH_E_INVAL, "sketch_update: NULL pairs");
-  if (((uintptr_t)d_pairs) & 7u)
-    return fail(SKETCH_E_INVAL, "sketch_update: pairs must be 8-byte aligned");
-  DEVICE_GUARD(s->p.device);
-  hipStream_t st = (hipStream_t)hip_stream;
-  const bool can_bin = s->nbins <= BIN_MAX;
-  const bool binned = can_bin && (s->update_path == 2 ||
-                                  (s->update_path == 0 && n_pairs >= s->binned_min_pairs));
-  if (binned) {
-    int rc = ensure_codes(s, std::min(n_pairs, s->binned_round), st);
-    if (rc) return rc;
-    HIP_OK(launch_update_binned(s->G, s->d_sketch, s->words, d_pairs, n_pairs, s->BB, st));
-    return SKETCH_OK;
-  }
-  HIP_OK(launch_update(s->G, s->d_sketch, d_pairs, n_pairs, s->update_grid,
-                       s->update_variant, st));
-  return SKETCH_OK;
+  const sketch_update_job_t job{s, d_pairs, n_pairs};
+  return update_jobs(&job, 1, (hipStream_t)hip_stream);
+}
+
+int sketch_update_batch(const sketch_update_job_t *jobs, size_t n_jobs, void *hip_stream) {
+  return update_jobs(jobs, n_jobs, (hipStream_t)hip_stream);
 }
 
 int sketch_set_option(sketch_t *s, int option, int64_t value) {
@@ -434,6 +696,14 @@ int sketch_set_option(sketch_t *s, int option, int64_t value) {
     case SKETCH_OPT_UPDATE_CHECK:
       if (value < 0 || value > 1) break;
       s->update_variant = (int)value;
+      return SKETCH_OK;
+    case SKETCH_OPT_SCATTER_PPT:
+      if (value != 2 && value != 4 && value != 6) break;
+      s->BB.scatter_ppt = (uint32_t)value;
+      return SKETCH_OK;
+    case SKETCH_OPT_BINNED_BLOCKS:
+      if (value < 1 || value > (int64_t)BIN_BLOCKS_MAX) break;
+      s->BB.nblk = (uint32_t)value;
       return SKETCH_OK;
     case SKETCH_OPT_BINNED_ROUND:
       if (value < 1024 || (uint64_t)value * s->p.r >= (1ull << 32)) break;
@@ -479,6 +749,64 @@ int sketch_restore(sketch_t *s, double theta, sketch_sp_t *out, size_t cap, size
     HIP_OK(hipMemcpyAsync(out, s->B.spl_sorted, h.n_spl * sizeof(uint4), hipMemcpyDeviceToHost,
                           st));
   HIP_OK(hipStreamSynchronize(st));
+  return SKETCH_OK;
+}
+
+int sketch_restore_batch(sketch_restore_job_t *jobs, size_t n_jobs, void *hip_stream) {
+  if (n_jobs == 0) return SKETCH_OK;
+  if (!jobs) return fail(SKETCH_E_INVAL, "sketch_restore_batch: NULL jobs");
+  const int dev = jobs[0].sketch ? jobs[0].sketch->p.device : -1;
+  for (size_t j = 0; j < n_jobs; j++) {
+    const sketch_restore_job_t &J = jobs[j];
+    if (!J.sketch) return fail(SKETCH_E_INVAL, "sketch_restore_batch: NULL handle (job %zu)", j);
+    if (J.sketch->p.device != dev)
+      return fail(SKETCH_E_INVAL, "sketch_restore_batch: sketches on different devices");
+    if (!(J.theta > 0.0) || !isfinite(J.theta))
+      return fail(SKETCH_E_INVAL, "sketch_restore_batch: theta must be finite and > 0 (job %zu)", j);
+    if (J.cap && !J.out)
+      return fail(SKETCH_E_INVAL, "sketch_restore_batch: NULL out with cap > 0 (job %zu)", j);
+    for (size_t i = 0; i < j; i++)
+      if (jobs[i].sketch == J.sketch)
+        return fail(SKETCH_E_INVAL, "sketch_restore_batch: a sketch appears twice (jobs %zu, %zu)",
+                    i, j);
+  }
+  DEVICE_GUARD(dev);
+  hipStream_t st = (hipStream_t)hip_stream;
+  std::vector<Thresholds> th(n_jobs);
+  // every restore enqueued, one wait
+  for (size_t j = 0; j < n_jobs; j++) {
+    th[j] = thresholds(jobs[j].sketch, jobs[j].theta);
+    int rc = restore_launch(jobs[j].sketch, th[j], 1, st);
+    if (rc) return rc;
+  }
+  HIP_OK(hipStreamSynchronize(st));
+  int first_err = SKETCH_OK;
+  for (size_t j = 0; j < n_jobs; j++) {
+    sketch_restore_job_t &J = jobs[j];
+    sketch *s = J.sketch;
+    bool again;
+    int rc = restore_check(s, 1, &again);
+    if (rc == SKETCH_OK && again) {
+      double zmin;
+      uint32_t zhot;
+      rc = run_restore(s, J.theta, 1, st, &zmin, &zhot);   // this job alone, to completion
+    }
+    const DevState h = *s->h_state;
+    if (rc == SKETCH_OK || rc == SKETCH_E_SATURATED) fill_info(s, h, th[j].zmin, th[j].zhot, J.info);
+    J.n_out = rc == SKETCH_OK ? (size_t)h.n_spl : 0;
+    if (rc == SKETCH_OK && h.n_spl > J.cap) rc = SKETCH_E_CAPACITY;
+    if (rc == SKETCH_OK && h.n_spl) {
+      rc = SKETCH_OK;
+      hipError_t e = hipMemcpyAsync(J.out, s->B.spl_sorted, h.n_spl * sizeof(uint4),
+                                    hipMemcpyDeviceToHost, st);
+      if (e != hipSuccess) rc = SKETCH_E_HIP;
+    }
+    J.status = rc;
+    if (rc && !first_err) first_err = rc;
+  }
+  HIP_OK(hipStreamSynchronize(st));
+  if (first_err)
+    return fail(first_err, "sketch_restore_batch: a job failed (see each job's status)");
   return SKETCH_OK;
 }
 

@@ -84,7 +84,7 @@ constexpr uint32_t SPLIT_MIN = 1u << 20;             // tiles above this many co
 constexpr uint32_t APPLY_ITEM = 1u << 19;            //   are cut into items of this many
 
 struct BinBufs {
-  uint32_t *hist;        // [tiles][nblk]: counts, then offsets inside the run
+  uint32_t *hist;        // [tiles][BIN_BLOCKS_MAX]: counts, then offsets inside the run
   uint32_t *totals;      // [tiles]
   uint32_t *base;        // [tiles + 1]: run starts
   uint32_t *item_start;  // [tiles + 1]
@@ -93,16 +93,43 @@ struct BinBufs {
   uint32_t *codes;       // codes_cap entries
   size_t codes_cap;      // a multiple of r; < 2^32
   uint32_t *scratch;     // (codes_cap / APPLY_ITEM + 1) tiles for cut tiles
-  uint32_t nblk;         // blocks of the count and scatter passes (<= 1024)
+  uint32_t nblk;         // blocks of the count and scatter passes (<= BIN_BLOCKS_MAX)
   uint32_t apply_grid;
+  uint32_t scatter_ppt;  // pairs per thread per scatter batch: 2, 4 or 6
 };
 
+constexpr uint32_t BIN_BLOCKS_MAX = 1024;
+
+// One sketch's share of an update launch. Kernels of a launch take a table
+// of these (device memory) and map each block, tile or work item to its
+// job by binary search over the prefix fields blk0 / tile0 / item0.
+struct UpdJob {
+  Geom G;
+  uint32_t *sk;
+  const uint2 *pairs;    // this launch's pairs of the job
+  uint64_t words;        // sketch words
+  uint64_t n;            // pairs
+  uint64_t chunk;        // pairs per block (even)
+  uint32_t nbins;        // tiles of the sketch
+  uint32_t nblk;         // blocks of this job (count / scatter / direct)
+  uint32_t blk0;         // first global block of this job
+  uint32_t tile0;        // first global tile of this job
+  uint32_t *hist, *totals, *base, *item_start, *xslot, *n_items;
+  uint32_t *codes, *scratch;
+  uint32_t item0;        // first global apply item (written on the device)
+  uint32_t check;        // direct kernel: test the bit before the atomicOr
+};
+
+constexpr uint32_t MAX_JOBS = 256;     // jobs per launch group
+
+// Launches one update round for n_jobs jobs that share r: `h_jobs` is the
+// host copy (blk0 / tile0 / nblk filled in), `d_jobs` its device copy
+// (already transferred), `d_total` one device word for the item count.
+hipError_t launch_update_jobs(const UpdJob *h_jobs, UpdJob *d_jobs, uint32_t n_jobs,
+                              uint32_t *d_total, bool binned, uint32_t r, uint32_t ppt,
+                              uint32_t apply_grid, hipStream_t st);
+
 // ---- launchers (update.hip) ----
-hipError_t launch_update_binned(const Geom &G, uint32_t *sketch, size_t words,
-                                const uint32_t *pairs, size_t n, const BinBufs &BB,
-                                hipStream_t st);
-hipError_t launch_update(const Geom &G, uint32_t *sketch, const uint32_t *pairs,
-                         size_t n, int grid, int variant, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, size_t n_words, uint32_t value,
                            int grid, hipStream_t st);
 

@@ -1,26 +1,83 @@
 // Sketch update (Alg. 1, Sec. 3.2 and 4.1) and the window reset (Sec. 4).
 //
-// One pass over the packed (a,b) pairs in HBM: each lane loads one 8-byte
-// pair (a wave reads 512 contiguous bytes), hashes it in registers (two
-// multiply-add-shifts and r-1 shift/xor), and sets one bit in one LE of each
-// row. The sketch (10 MiB at the paper's defaults, 160 MiB at k = 18) lives
-// in HBM but its hot working set sits in the L2s and the Infinity Cache; the
-// bit sets are non-returning atomicOr, which are order-free, so concurrent
-// setters never lose a bit. Alg. 1 skips the write when the bit is already
-// 1; that test is a plain load, and it turns the heavy hitters' updates
-// (whose LEs fill up early in a window) into cache reads instead of
-// serialised read-modify-writes on a handful of hot lines.
+// Every launch takes a table of jobs, one per sketch (UpdJob), so a batch of
+// links or windows of uneven size runs in one set of launches; a single
+// sketch's update is a batch of one. Blocks, tiles and work items are mapped
+// to their job by binary search over the jobs' prefix fields.
+//
+// Two kernels compute the same sketch:
+//
+// direct   Alg. 1 as written. Each lane loads one 8-byte pair, hashes it in
+//          registers (two multiply-add-shifts, r-1 shift/xor) and sets one
+//          bit in one LE of each row with a non-returning atomicOr, after a
+//          plain load shows the bit unset (Alg. 1 skips a bit already 1;
+//          that turns the heavy hitters' updates, whose LEs fill early, into
+//          cache reads). Bound by random accesses into the sketch: on MI355X
+//          a random 4-byte access to a 160 MiB buffer runs at ~60 G/s and a
+//          global atomicOr at ~27 G/s, whatever the buffer size. Used for
+//          small updates.
+//
+// binned   The bit sets are moved into LDS. Every (pair, row) gives the bit
+//          index B = ((row * 2^k + cell) * g) + bit of the sketch seen as
+//          one bit string; tile = B >> 20 names the 128 KiB slice it falls
+//          in and code = B mod 2^20 the bit inside it.
+//            count    each block counts its chunk's codes per tile (LDS)
+//            scan     per tile, the blocks' counts become write offsets;
+//                     over tiles, the totals become run starts; a tile with
+//                     many codes is cut into several apply items
+//            scatter  each block sorts a batch of pairs' codes by tile in
+//                     LDS and writes them into its part of each tile's run
+//            apply    one workgroup per item: the tile in LDS (up to 160 KiB
+//                     per workgroup on gfx950), ds_or per code. The first
+//                     item of a tile reads and writes the tile itself; the
+//                     other items of a cut tile write scratch tiles instead
+//            merge    each cut tile ORs its scratch tiles into the sketch
+//          Only the pairs, the code runs and whole tiles move through HBM.
 #include "ddhf_internal.h"
 
 namespace ddhf {
 
+// ------------------------------------------------------------ job lookup
+
+__device__ __forceinline__ uint32_t job_of_block(const UpdJob *jobs, uint32_t nj, uint32_t b) {
+  uint32_t lo = 0, hi = nj;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (jobs[mid].blk0 <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint32_t job_of_tile(const UpdJob *jobs, uint32_t nj, uint32_t t) {
+  uint32_t lo = 0, hi = nj;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (jobs[mid].tile0 <= t) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint32_t job_of_item(const UpdJob *jobs, uint32_t nj, uint32_t it) {
+  uint32_t lo = 0, hi = nj;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (jobs[mid].item0 <= it) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------- direct
+
 template <int R, bool CHECK>
-__global__ __launch_bounds__(256) void k_update(Geom G, uint32_t *__restrict__ sk,
-                                                const uint2 *__restrict__ pairs,
-                                                size_t n) {
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += stride) {
+__global__ __launch_bounds__(256) void k_update(const UpdJob *__restrict__ jobs, uint32_t nj) {
+  const uint32_t j = job_of_block(jobs, nj, blockIdx.x);
+  const UpdJob &J = jobs[j];
+  const Geom G = J.G;
+  uint32_t *__restrict__ sk = J.sk;
+  const uint2 *__restrict__ pairs = J.pairs;
+  const size_t n = J.n;
+  const size_t stride = (size_t)J.nblk * blockDim.x;
+  for (size_t i = (size_t)(blockIdx.x - J.blk0) * blockDim.x + threadIdx.x; i < n; i += stride) {
     const uint2 p = pairs[i];
     const uint32_t bit = hash_h1(G, p.y);
     const uint32_t c0 = hash_dh0(G, p.x);
@@ -36,56 +93,9 @@ __global__ __launch_bounds__(256) void k_update(Geom G, uint32_t *__restrict__ s
   }
 }
 
-template <bool CHECK>
-static hipError_t dispatch_update(const Geom &G, uint32_t *sk, const uint2 *pairs,
-                                  size_t n, int grid, hipStream_t st) {
-  switch (G.r) {
-    case 3: k_update<3, CHECK><<<grid, 256, 0, st>>>(G, sk, pairs, n); break;
-    case 4: k_update<4, CHECK><<<grid, 256, 0, st>>>(G, sk, pairs, n); break;
-    case 5: k_update<5, CHECK><<<grid, 256, 0, st>>>(G, sk, pairs, n); break;
-    case 6: k_update<6, CHECK><<<grid, 256, 0, st>>>(G, sk, pairs, n); break;
-    case 7: k_update<7, CHECK><<<grid, 256, 0, st>>>(G, sk, pairs, n); break;
-    case 8: k_update<8, CHECK><<<grid, 256, 0, st>>>(G, sk, pairs, n); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_update(const Geom &G, uint32_t *sketch, const uint32_t *pairs,
-                         size_t n, int grid, int variant, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  const size_t need = (n + 255) / 256;
-  if ((size_t)grid > need) grid = (int)need;
-  const uint2 *p2 = reinterpret_cast<const uint2 *>(pairs);
-  return (variant & 1) ? dispatch_update<true>(G, sketch, p2, n, grid, st)
-                       : dispatch_update<false>(G, sketch, p2, n, grid, st);
-}
-
-// ------------------------------------------------------- binned update
-//
-// For large updates the random read-modify-writes into the sketch are the
-// limit (on MI355X a random 4-byte access to a 160 MiB buffer runs at
-// ~60 G/s and a global atomicOr at ~27 G/s, whatever the buffer size), so
-// the bit sets are moved into LDS instead. Every (pair, row) gives the bit
-// index B = ((row * 2^k + cell) * g) + bit of the sketch seen as one bit
-// string; tile = B >> 20 names the 128 KiB slice it falls in and
-// code = B mod 2^20 the bit inside it.
-//   count    each block counts its chunk's codes per tile (LDS histogram)
-//   scan     per tile, the blocks' counts become write offsets; over tiles,
-//            the totals become run starts; a tile with many codes is cut
-//            into several apply items
-//   scatter  each block sorts a batch of 4096 pairs' codes by tile in LDS
-//            and writes them into its part of each tile's run, so stores
-//            go out in runs rather than one line per lane
-//   apply    one workgroup per item: the tile in LDS (144 KiB max per
-//            workgroup on gfx950), ds_or per code. The first item of a tile
-//            reads and writes the tile itself; the other items of a cut
-//            tile write their bits to a scratch tile instead
-//   merge    each cut tile ORs its scratch tiles into the sketch
-// Only the pairs, the code runs and whole tiles move through HBM.
+// ---------------------------------------------------------------- binned
 
 constexpr uint32_t CODE_MASK = (1u << BIN_TILE_LOG2) - 1;
-constexpr int PAIRS_PER_THREAD = 4;             // scatter batch: 4096 pairs
 
 template <int R>
 __device__ __forceinline__ void pair_codes(const Geom &G, uint2 p, uint32_t *B) {
@@ -94,13 +104,14 @@ __device__ __forceinline__ void pair_codes(const Geom &G, uint2 p, uint32_t *B) 
 #pragma unroll
   for (int row = 0; row < R; row++) {
     const uint32_t cell = row == 0 ? c0 : (bit_block(G, row, p.x) ^ c0);
-    // sketch bit index; < 2^32 since the sketch is at most 2^BIN_MAX tiles
+    // sketch bit index; < 2^31 since a binned sketch has at most BIN_MAX tiles
     B[row] = ((((uint32_t)row << G.k) | cell) << G.log2g) | bit;
   }
 }
 
 // Pairs are read as uint4 (two pairs per lane per load), COUNT_V4 loads in
-// flight per lane; a chunk starts on an even pair so the loads are aligned.
+// flight per lane; a job's pairs start 16-byte aligned and its chunks are
+// even, so every block's loads are aligned.
 constexpr int COUNT_V4 = 8;
 
 template <int R>
@@ -112,40 +123,38 @@ __device__ __forceinline__ void count_pair(const Geom &G, uint2 p, uint32_t *h) 
 }
 
 template <int R>
-__global__ __launch_bounds__(1024) void k_bin_count(Geom G, const uint2 *__restrict__ pairs,
-                                                    size_t n, size_t chunk, uint32_t nbins,
-                                                    uint32_t nblk,
-                                                    uint32_t *__restrict__ hist) {
+__global__ __launch_bounds__(1024) void k_bin_count(const UpdJob *__restrict__ jobs, uint32_t nj) {
   __shared__ uint32_t h[BIN_MAX];
+  const UpdJob &J = jobs[job_of_block(jobs, nj, blockIdx.x)];
+  const Geom G = J.G;
+  const uint32_t nbins = J.nbins, lb = blockIdx.x - J.blk0;
   for (uint32_t t = threadIdx.x; t < nbins; t += blockDim.x) h[t] = 0;
   __syncthreads();
-  const size_t p0 = (size_t)blockIdx.x * chunk;
-  const size_t p1 = p0 + chunk < n ? p0 + chunk : n;
+  const size_t p0 = (size_t)lb * J.chunk;
+  const size_t p1 = p0 + J.chunk < J.n ? p0 + J.chunk : J.n;
   if (p0 < p1) {
-    // p0 is even (chunk is even); pairs before the last even boundary go
-    // through uint4 loads, an odd last pair alone
-    const uint4 *q = reinterpret_cast<const uint4 *>(pairs + p0);
+    const uint4 *q = reinterpret_cast<const uint4 *>(J.pairs + p0);
     const size_t nq = (p1 - p0) / 2;
     for (size_t i0 = 0; i0 < nq; i0 += (size_t)blockDim.x * COUNT_V4) {
       uint4 v[COUNT_V4];
 #pragma unroll
-      for (int j = 0; j < COUNT_V4; j++) {
-        const size_t i = i0 + (size_t)j * blockDim.x + threadIdx.x;
-        v[j] = i < nq ? q[i] : make_uint4(0, 0, 0, 0);
+      for (int u = 0; u < COUNT_V4; u++) {
+        const size_t i = i0 + (size_t)u * blockDim.x + threadIdx.x;
+        v[u] = i < nq ? q[i] : make_uint4(0, 0, 0, 0);
       }
 #pragma unroll
-      for (int j = 0; j < COUNT_V4; j++) {
-        const size_t i = i0 + (size_t)j * blockDim.x + threadIdx.x;
+      for (int u = 0; u < COUNT_V4; u++) {
+        const size_t i = i0 + (size_t)u * blockDim.x + threadIdx.x;
         if (i >= nq) continue;
-        count_pair<R>(G, make_uint2(v[j].x, v[j].y), h);
-        count_pair<R>(G, make_uint2(v[j].z, v[j].w), h);
+        count_pair<R>(G, make_uint2(v[u].x, v[u].y), h);
+        count_pair<R>(G, make_uint2(v[u].z, v[u].w), h);
       }
     }
-    if (((p1 - p0) & 1) && threadIdx.x == 0) count_pair<R>(G, pairs[p1 - 1], h);
+    if (((p1 - p0) & 1) && threadIdx.x == 0) count_pair<R>(G, J.pairs[p1 - 1], h);
   }
   __syncthreads();
   for (uint32_t t = threadIdx.x; t < nbins; t += blockDim.x)
-    hist[(size_t)t * nblk + blockIdx.x] = h[t];
+    J.hist[(size_t)t * BIN_BLOCKS_MAX + lb] = h[t];
 }
 
 // Exclusive prefix sum over a workgroup of 1024 threads.
@@ -176,16 +185,17 @@ __device__ __forceinline__ uint32_t blk_scan_1024(uint32_t v, uint32_t *total, u
 }
 
 // Per tile: the blocks' counts -> exclusive offsets (in place); the total.
-__global__ __launch_bounds__(1024) void k_bin_scan_cols(uint32_t *__restrict__ hist,
-                                                        uint32_t nblk,
-                                                        uint32_t *__restrict__ totals) {
+__global__ __launch_bounds__(1024) void k_bin_scan_cols(const UpdJob *__restrict__ jobs,
+                                                        uint32_t nj) {
   __shared__ uint32_t sh[16];
-  uint32_t *col = hist + (size_t)blockIdx.x * nblk;
-  const uint32_t v = threadIdx.x < nblk ? col[threadIdx.x] : 0;
+  const UpdJob &J = jobs[job_of_tile(jobs, nj, blockIdx.x)];
+  const uint32_t t = blockIdx.x - J.tile0;
+  uint32_t *col = J.hist + (size_t)t * BIN_BLOCKS_MAX;
+  const uint32_t v = threadIdx.x < J.nblk ? col[threadIdx.x] : 0;
   uint32_t total;
   const uint32_t ex = blk_scan_1024(v, &total, sh);
-  if (threadIdx.x < nblk) col[threadIdx.x] = ex;
-  if (threadIdx.x == 0) totals[blockIdx.x] = total;
+  if (threadIdx.x < J.nblk) col[threadIdx.x] = ex;
+  if (threadIdx.x == 0) J.totals[t] = total;
 }
 
 // Apply items of a tile with v codes: one if v <= SPLIT_MIN, else one per
@@ -194,22 +204,20 @@ __device__ __forceinline__ uint32_t tile_items(uint32_t v) {
   return v == 0 ? 0u : (v <= SPLIT_MIN ? 1u : (v + APPLY_ITEM - 1) / APPLY_ITEM);
 }
 
-// Over tiles: run starts, apply-item starts, scratch-slot starts (a tile
-// cut into j items owns j-1 scratch tiles) and the item count.
-__global__ __launch_bounds__(1024) void k_bin_scan_tiles(const uint32_t *__restrict__ totals,
-                                                         uint32_t nbins,
-                                                         uint32_t *__restrict__ base,
-                                                         uint32_t *__restrict__ item_start,
-                                                         uint32_t *__restrict__ xslot,
-                                                         uint32_t *__restrict__ n_items) {
+// Over one job's tiles (block = job): run starts, apply-item starts,
+// scratch-slot starts (a tile cut into j items owns j-1 scratch tiles) and
+// the item count.
+__global__ __launch_bounds__(1024) void k_bin_scan_tiles(const UpdJob *__restrict__ jobs) {
   __shared__ uint32_t sh[16];
+  const UpdJob &J = jobs[blockIdx.x];
+  const uint32_t nbins = J.nbins;
   constexpr uint32_t PER = BIN_MAX / 1024;
   const uint32_t t0 = threadIdx.x * PER;
   uint32_t c = 0, it = 0, xs = 0;
 #pragma unroll
-  for (uint32_t j = 0; j < PER; j++) {
-    const uint32_t t = t0 + j;
-    const uint32_t v = t < nbins ? totals[t] : 0;
+  for (uint32_t k = 0; k < PER; k++) {
+    const uint32_t t = t0 + k;
+    const uint32_t v = t < nbins ? J.totals[t] : 0;
     const uint32_t ni = tile_items(v);
     c += v;
     it += ni;
@@ -220,148 +228,153 @@ __global__ __launch_bounds__(1024) void k_bin_scan_tiles(const uint32_t *__restr
   uint32_t ei = blk_scan_1024(it, &tot_it, sh);
   uint32_t ex = blk_scan_1024(xs, &tot_xs, sh);
 #pragma unroll
-  for (uint32_t j = 0; j < PER; j++) {
-    const uint32_t t = t0 + j;
+  for (uint32_t k = 0; k < PER; k++) {
+    const uint32_t t = t0 + k;
     if (t < nbins) {
-      const uint32_t v = totals[t];
+      const uint32_t v = J.totals[t];
       const uint32_t ni = tile_items(v);
-      base[t] = ec;
-      item_start[t] = ei;
-      xslot[t] = ex;
+      J.base[t] = ec;
+      J.item_start[t] = ei;
+      J.xslot[t] = ex;
       ec += v;
       ei += ni;
       ex += ni > 1 ? ni - 1 : 0;
     }
   }
   if (threadIdx.x == 0) {
-    base[nbins] = tot_c;
-    item_start[nbins] = tot_it;
-    xslot[nbins] = tot_xs;
-    *n_items = tot_it;
+    J.base[nbins] = tot_c;
+    J.item_start[nbins] = tot_it;
+    J.xslot[nbins] = tot_xs;
+    *J.n_items = tot_it;
   }
 }
 
-template <int R>
-__global__ __launch_bounds__(1024) void k_bin_scatter(Geom G, const uint2 *__restrict__ pairs,
-                                                      size_t n, size_t chunk, uint32_t nbins,
-                                                      uint32_t nblk,
-                                                      const uint32_t *__restrict__ hist,
-                                                      const uint32_t *__restrict__ base,
-                                                      uint32_t *__restrict__ codes) {
-  constexpr uint32_t BATCH = 1024 * PAIRS_PER_THREAD * R;
-  __shared__ uint32_t sorted[BATCH];   // (tile << 20 | code), grouped by tile
+// First global apply item of every job, and the total (one block).
+__global__ __launch_bounds__(1024) void k_item_offsets(UpdJob *__restrict__ jobs, uint32_t nj,
+                                                       uint32_t *__restrict__ total) {
+  __shared__ uint32_t sh[16];
+  const uint32_t v = threadIdx.x < nj ? *jobs[threadIdx.x].n_items : 0;
+  uint32_t tot;
+  const uint32_t ex = blk_scan_1024(v, &tot, sh);
+  if (threadIdx.x < nj) jobs[threadIdx.x].item0 = ex;
+  if (threadIdx.x == 0) *total = tot;
+}
+
+template <int R, int PPT>
+__global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__ jobs,
+                                                      uint32_t nj) {
+  constexpr uint32_t BATCH = 1024 * PPT * R;
+  __shared__ uint32_t sorted[BATCH];   // sketch bit index, grouped by tile
   __shared__ uint32_t cnt[BIN_MAX];    // codes per tile in this batch
   __shared__ uint32_t lofs[BIN_MAX];   // batch-local run starts
+  __shared__ uint32_t dst[BIN_MAX];    // global slot of batch entry e is dst[t] + e
   __shared__ uint32_t gcur[BIN_MAX];   // next global slot of this block per tile
   __shared__ uint32_t sh[16];
+  const UpdJob &J = jobs[job_of_block(jobs, nj, blockIdx.x)];
+  const Geom G = J.G;
+  const uint32_t nbins = J.nbins, lb = blockIdx.x - J.blk0;
+  const uint2 *__restrict__ pairs = J.pairs;
+  uint32_t *__restrict__ codes = J.codes;
   for (uint32_t t = threadIdx.x; t < BIN_MAX; t += blockDim.x) {
     cnt[t] = 0;
-    gcur[t] = t < nbins ? base[t] + hist[(size_t)t * nblk + blockIdx.x] : 0;
+    gcur[t] = t < nbins ? J.base[t] + J.hist[(size_t)t * BIN_BLOCKS_MAX + lb] : 0;
   }
   __syncthreads();
-  const size_t p0 = (size_t)blockIdx.x * chunk;
-  const size_t p1 = p0 + chunk < n ? p0 + chunk : n;
-  const size_t step = (size_t)blockDim.x * PAIRS_PER_THREAD;
+  const size_t p0 = (size_t)lb * J.chunk;
+  const size_t p1 = p0 + J.chunk < J.n ? p0 + J.chunk : J.n;
+  const size_t step = (size_t)blockDim.x * PPT;
   // the next batch's pairs are loaded while this batch is sorted and written
-  uint2 nxt[PAIRS_PER_THREAD];
+  uint2 nxt[PPT];
 #pragma unroll
-  for (int j = 0; j < PAIRS_PER_THREAD; j++) {
-    const size_t i = p0 + (size_t)j * blockDim.x + threadIdx.x;
-    nxt[j] = i < p1 ? pairs[i] : make_uint2(0, 0);
+  for (int k = 0; k < PPT; k++) {
+    const size_t i = p0 + (size_t)k * blockDim.x + threadIdx.x;
+    nxt[k] = i < p1 ? pairs[i] : make_uint2(0, 0);
   }
+  const uint32_t ta = threadIdx.x * 2, tb = ta + 1;   // tiles this thread keeps
   for (size_t i0 = p0; i0 < p1; i0 += step) {
-    uint32_t v[PAIRS_PER_THREAD * R], rk[PAIRS_PER_THREAD * R];
-    uint2 cur[PAIRS_PER_THREAD];
+    uint32_t v[PPT * R], rk[PPT * R];
+    uint2 cur[PPT];
 #pragma unroll
-    for (int j = 0; j < PAIRS_PER_THREAD; j++) {
-      cur[j] = nxt[j];
-      const size_t i = i0 + step + (size_t)j * blockDim.x + threadIdx.x;
-      nxt[j] = i < p1 ? pairs[i] : make_uint2(0, 0);
+    for (int k = 0; k < PPT; k++) {
+      cur[k] = nxt[k];
+      const size_t i = i0 + step + (size_t)k * blockDim.x + threadIdx.x;
+      nxt[k] = i < p1 ? pairs[i] : make_uint2(0, 0);
     }
+    // 1: codes and their rank inside their tile's run of this batch
 #pragma unroll
-    for (int j = 0; j < PAIRS_PER_THREAD; j++) {
-      const size_t i = i0 + (size_t)j * blockDim.x + threadIdx.x;
+    for (int k = 0; k < PPT; k++) {
+      const size_t i = i0 + (size_t)k * blockDim.x + threadIdx.x;
       if (i < p1) {
         uint32_t B[R];
-        pair_codes<R>(G, cur[j], B);
+        pair_codes<R>(G, cur[k], B);
 #pragma unroll
         for (int row = 0; row < R; row++) {
-          const uint32_t t = B[row] >> BIN_TILE_LOG2;
-          v[j * R + row] = B[row];
-          rk[j * R + row] = atomicAdd(&cnt[t], 1u);
+          v[k * R + row] = B[row];
+          rk[k * R + row] = atomicAdd(&cnt[B[row] >> BIN_TILE_LOG2], 1u);
         }
       } else {
 #pragma unroll
-        for (int row = 0; row < R; row++) v[j * R + row] = ~0u;
+        for (int row = 0; row < R; row++) v[k * R + row] = ~0u;
       }
     }
     __syncthreads();
-    // batch-local run starts (2 tiles per thread)
-    const uint32_t ta = threadIdx.x * 2, tb = ta + 1;
+    // 2: run starts; dst maps a sorted position to its global slot
     const uint32_t ca = cnt[ta], cb = cnt[tb];
     uint32_t total;
     const uint32_t ex = blk_scan_1024(ca + cb, &total, sh);
     lofs[ta] = ex;
     lofs[tb] = ex + ca;
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < PAIRS_PER_THREAD * R; q++)
-      if (v[q] != ~0u) sorted[lofs[v[q] >> BIN_TILE_LOG2] + rk[q]] = v[q];
-    __syncthreads();
-    for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
-      const uint32_t x = sorted[e];
-      const uint32_t t = x >> BIN_TILE_LOG2;
-      codes[gcur[t] + (e - lofs[t])] = x & CODE_MASK;
-    }
-    __syncthreads();
+    dst[ta] = gcur[ta] - ex;
+    dst[tb] = gcur[tb] - (ex + ca);
     gcur[ta] += ca;
     gcur[tb] += cb;
     cnt[ta] = 0;
     cnt[tb] = 0;
     __syncthreads();
+    // 3: group by tile in LDS
+#pragma unroll
+    for (int q = 0; q < PPT * R; q++)
+      if (v[q] != ~0u) sorted[lofs[v[q] >> BIN_TILE_LOG2] + rk[q]] = v[q];
+    __syncthreads();
+    // 4: write the runs
+    for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
+      const uint32_t x = sorted[e];
+      codes[dst[x >> BIN_TILE_LOG2] + e] = x & CODE_MASK;
+    }
+    __syncthreads();
   }
-}
-
-// Tile of an item: the largest t with item_start[t] <= it.
-__device__ __forceinline__ uint32_t item_tile(const uint32_t *item_start, uint32_t nbins,
-                                              uint32_t it) {
-  uint32_t lo = 0, hi = nbins;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (item_start[mid] <= it) lo = mid; else hi = mid;
-  }
-  return lo;
 }
 
 constexpr int APPLY_UNROLL = 4;
 
-__global__ __launch_bounds__(1024) void k_bin_apply(uint32_t *__restrict__ sk, size_t words,
-                                                    const uint32_t *__restrict__ codes,
-                                                    const uint32_t *__restrict__ base,
-                                                    const uint32_t *__restrict__ item_start,
-                                                    const uint32_t *__restrict__ xslot,
-                                                    const uint32_t *__restrict__ n_items_p,
-                                                    uint32_t nbins,
-                                                    uint32_t *__restrict__ scratch) {
+__global__ __launch_bounds__(1024) void k_bin_apply(const UpdJob *__restrict__ jobs, uint32_t nj,
+                                                    const uint32_t *__restrict__ n_items_p) {
   __shared__ uint32_t tile[BIN_TILE_WORDS];
   const uint32_t n_items = *n_items_p;
   for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
-    const uint32_t t = item_tile(item_start, nbins, it);
-    const uint32_t sub = it - item_start[t];
-    const uint32_t c_end = base[t + 1];
-    const uint32_t c0 = item_start[t + 1] - item_start[t] == 1 ? base[t]
-                                                               : base[t] + sub * APPLY_ITEM;
-    const uint32_t c1 = item_start[t + 1] - item_start[t] == 1
-                            ? c_end
-                            : (c_end - c0 > APPLY_ITEM ? c0 + APPLY_ITEM : c_end);
+    const UpdJob &J = jobs[job_of_item(jobs, nj, it)];
+    const uint32_t jit = it - J.item0;
+    // tile of this item: the largest t with item_start[t] <= jit
+    uint32_t lo = 0, hi = J.nbins;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (J.item_start[mid] <= jit) lo = mid; else hi = mid;
+    }
+    const uint32_t t = lo;
+    const uint32_t sub = jit - J.item_start[t];
+    const bool whole = J.item_start[t + 1] - J.item_start[t] == 1;
+    const uint32_t c_end = J.base[t + 1];
+    const uint32_t c0 = whole ? J.base[t] : J.base[t] + sub * APPLY_ITEM;
+    const uint32_t c1 = whole ? c_end : (c_end - c0 > APPLY_ITEM ? c0 + APPLY_ITEM : c_end);
     const size_t w0 = (size_t)t * BIN_TILE_WORDS;
-    const uint32_t tw = (uint32_t)(words - w0 < BIN_TILE_WORDS ? words - w0 : BIN_TILE_WORDS);
-    // the first item of a tile owns the tile; item j >= 1 of a cut tile
-    // writes scratch tile xslot[t] + j - 1
-    uint32_t *dst = sub == 0 ? sk + w0
-                             : scratch + (size_t)(xslot[t] + sub - 1) * BIN_TILE_WORDS;
+    const uint32_t tw = (uint32_t)(J.words - w0 < BIN_TILE_WORDS ? J.words - w0 : BIN_TILE_WORDS);
+    const uint32_t *__restrict__ codes = J.codes;
+    // the first item of a tile owns the tile; item s >= 1 of a cut tile
+    // writes scratch tile xslot[t] + s - 1
+    uint32_t *dstp = sub == 0 ? J.sk + w0
+                              : J.scratch + (size_t)(J.xslot[t] + sub - 1) * BIN_TILE_WORDS;
     if (sub == 0) {
-      for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) tile[w] = dst[w];
+      for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) tile[w] = dstp[w];
     } else {
       for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) tile[w] = 0;
     }
@@ -398,102 +411,95 @@ __global__ __launch_bounds__(1024) void k_bin_apply(uint32_t *__restrict__ sk, s
       atomicOr(&tile[x >> 5], 1u << (x & 31));
     }
     __syncthreads();
-    for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) dst[w] = tile[w];
+    for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) dstp[w] = tile[w];
     __syncthreads();
   }
 }
 
 // OR the scratch tiles of every cut tile into the sketch: block (t, y)
-// takes the y-th 4096-word slice of tile t.
+// takes the y-th MERGE_SLICE-word slice of global tile t.
 constexpr uint32_t MERGE_SLICE = 4096;
 
-__global__ __launch_bounds__(256) void k_bin_merge(uint32_t *__restrict__ sk, size_t words,
-                                                   const uint32_t *__restrict__ item_start,
-                                                   const uint32_t *__restrict__ xslot,
-                                                   uint32_t nbins,
-                                                   const uint32_t *__restrict__ scratch) {
-  const uint32_t t = blockIdx.x;
-  if (t >= nbins) return;
-  const uint32_t n = item_start[t + 1] - item_start[t];
+__global__ __launch_bounds__(256) void k_bin_merge(const UpdJob *__restrict__ jobs, uint32_t nj) {
+  const UpdJob &J = jobs[job_of_tile(jobs, nj, blockIdx.x)];
+  const uint32_t t = blockIdx.x - J.tile0;
+  const uint32_t n = J.item_start[t + 1] - J.item_start[t];
   if (n <= 1) return;
   const size_t w0 = (size_t)t * BIN_TILE_WORDS;
-  const uint32_t tw = (uint32_t)(words - w0 < BIN_TILE_WORDS ? words - w0 : BIN_TILE_WORDS);
+  const uint32_t tw = (uint32_t)(J.words - w0 < BIN_TILE_WORDS ? J.words - w0 : BIN_TILE_WORDS);
   const uint32_t s_lo = blockIdx.y * MERGE_SLICE;
   const uint32_t s_hi = s_lo + MERGE_SLICE < tw ? s_lo + MERGE_SLICE : tw;
-  const uint32_t *s0 = scratch + (size_t)xslot[t] * BIN_TILE_WORDS;
+  const uint32_t *s0 = J.scratch + (size_t)J.xslot[t] * BIN_TILE_WORDS;
+  uint32_t *sk = J.sk + w0;
   for (uint32_t w = s_lo + threadIdx.x * 4; w < s_hi; w += blockDim.x * 4) {
     if (w + 4 <= s_hi) {
-      uint4 v = *reinterpret_cast<const uint4 *>(sk + w0 + w);
-      for (uint32_t j = 1; j < n; j++) {
-        const uint4 x =
-            *reinterpret_cast<const uint4 *>(s0 + (size_t)(j - 1) * BIN_TILE_WORDS + w);
+      uint4 v = *reinterpret_cast<const uint4 *>(sk + w);
+      for (uint32_t k = 1; k < n; k++) {
+        const uint4 x = *reinterpret_cast<const uint4 *>(s0 + (size_t)(k - 1) * BIN_TILE_WORDS + w);
         v.x |= x.x; v.y |= x.y; v.z |= x.z; v.w |= x.w;
       }
-      *reinterpret_cast<uint4 *>(sk + w0 + w) = v;
+      *reinterpret_cast<uint4 *>(sk + w) = v;
     } else {
       for (uint32_t ww = w; ww < s_hi; ww++) {
-        uint32_t v = sk[w0 + ww];
-        for (uint32_t j = 1; j < n; j++) v |= s0[(size_t)(j - 1) * BIN_TILE_WORDS + ww];
-        sk[w0 + ww] = v;
+        uint32_t v = sk[ww];
+        for (uint32_t k = 1; k < n; k++) v |= s0[(size_t)(k - 1) * BIN_TILE_WORDS + ww];
+        sk[ww] = v;
       }
     }
   }
 }
 
+// ---------------------------------------------------------------- launch
+
 template <int R>
-static hipError_t binned_rounds(const Geom &G, uint32_t *sk, size_t words, const uint2 *pairs,
-                                size_t n, const BinBufs &BB, hipStream_t st) {
-  const uint32_t nbins = (uint32_t)((words + BIN_TILE_WORDS - 1) / BIN_TILE_WORDS);
-  const size_t round = BB.codes_cap / R;
-  for (size_t done = 0; done < n; done += round) {
-    const size_t m = n - done < round ? n - done : round;
-    const uint2 *pp = pairs + done;
-    size_t chunk = (m + BB.nblk - 1) / BB.nblk;
-    chunk += chunk & 1;  // even: count pass loads pairs two at a time
-    k_bin_count<R><<<BB.nblk, 1024, 0, st>>>(G, pp, m, chunk, nbins, BB.nblk, BB.hist);
-    k_bin_scan_cols<<<nbins, 1024, 0, st>>>(BB.hist, BB.nblk, BB.totals);
-    k_bin_scan_tiles<<<1, 1024, 0, st>>>(BB.totals, nbins, BB.base, BB.item_start, BB.xslot,
-                                         BB.n_items);
-    k_bin_scatter<R><<<BB.nblk, 1024, 0, st>>>(G, pp, m, chunk, nbins, BB.nblk, BB.hist, BB.base,
-                                               BB.codes);
-    k_bin_apply<<<BB.apply_grid, 1024, 0, st>>>(sk, words, BB.codes, BB.base, BB.item_start,
-                                                BB.xslot, BB.n_items, nbins, BB.scratch);
-    k_bin_merge<<<dim3(nbins, BIN_TILE_WORDS / MERGE_SLICE), 256, 0, st>>>(
-        sk, words, BB.item_start, BB.xslot, nbins, BB.scratch);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+static hipError_t launch_r(const UpdJob *h, UpdJob *d, uint32_t nj, uint32_t *d_total,
+                           bool binned, uint32_t ppt, uint32_t apply_grid, hipStream_t st) {
+  uint32_t blocks = 0, tiles = 0;
+  for (uint32_t j = 0; j < nj; j++) {
+    blocks += h[j].nblk;
+    tiles += h[j].nbins;
   }
-  return hipSuccess;
+  if (!binned) {
+    bool check = h[0].check != 0;
+    if (check) k_update<R, true><<<blocks, 256, 0, st>>>(d, nj);
+    else k_update<R, false><<<blocks, 256, 0, st>>>(d, nj);
+    return hipGetLastError();
+  }
+  k_bin_count<R><<<blocks, 1024, 0, st>>>(d, nj);
+  k_bin_scan_cols<<<tiles, 1024, 0, st>>>(d, nj);
+  k_bin_scan_tiles<<<nj, 1024, 0, st>>>(d);
+  // LDS: 4*1024*PPT*r bytes of sorted codes + 32 KiB of tile arrays <= 160 KiB
+  constexpr int P4 = R <= 7 ? 4 : 2;
+  constexpr int P6 = R <= 5 ? 6 : P4;
+  if (ppt == 2) k_bin_scatter<R, 2><<<blocks, 1024, 0, st>>>(d, nj);
+  else if (ppt == 6) k_bin_scatter<R, P6><<<blocks, 1024, 0, st>>>(d, nj);
+  else k_bin_scatter<R, P4><<<blocks, 1024, 0, st>>>(d, nj);
+  k_item_offsets<<<1, 1024, 0, st>>>(d, nj, d_total);
+  k_bin_apply<<<apply_grid, 1024, 0, st>>>(d, nj, d_total);
+  k_bin_merge<<<dim3(tiles, BIN_TILE_WORDS / MERGE_SLICE), 256, 0, st>>>(d, nj);
+  return hipGetLastError();
 }
 
-hipError_t launch_update_binned(const Geom &G, uint32_t *sketch, size_t words,
-                                const uint32_t *pairs, size_t n, const BinBufs &BB,
-                                hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  if (((uintptr_t)pairs) & 15u) {
-    // the count pass reads pairs 16 bytes at a time: take one pair through
-    // the direct kernel so the rest starts 16-byte aligned
-    hipError_t e = launch_update(G, sketch, pairs, 1, 1, 1, st);
-    if (e != hipSuccess) return e;
-    pairs += 2;
-    if (--n == 0) return hipSuccess;
-  }
-  const uint2 *p2 = reinterpret_cast<const uint2 *>(pairs);
-  switch (G.r) {
-    case 3: return binned_rounds<3>(G, sketch, words, p2, n, BB, st);
-    case 4: return binned_rounds<4>(G, sketch, words, p2, n, BB, st);
-    case 5: return binned_rounds<5>(G, sketch, words, p2, n, BB, st);
-    case 6: return binned_rounds<6>(G, sketch, words, p2, n, BB, st);
-    case 7: return binned_rounds<7>(G, sketch, words, p2, n, BB, st);
-    case 8: return binned_rounds<8>(G, sketch, words, p2, n, BB, st);
+hipError_t launch_update_jobs(const UpdJob *h_jobs, UpdJob *d_jobs, uint32_t n_jobs,
+                              uint32_t *d_total, bool binned, uint32_t r, uint32_t ppt,
+                              uint32_t apply_grid, hipStream_t st) {
+  if (n_jobs == 0) return hipSuccess;
+  switch (r) {
+    case 3: return launch_r<3>(h_jobs, d_jobs, n_jobs, d_total, binned, ppt, apply_grid, st);
+    case 4: return launch_r<4>(h_jobs, d_jobs, n_jobs, d_total, binned, ppt, apply_grid, st);
+    case 5: return launch_r<5>(h_jobs, d_jobs, n_jobs, d_total, binned, ppt, apply_grid, st);
+    case 6: return launch_r<6>(h_jobs, d_jobs, n_jobs, d_total, binned, ppt, apply_grid, st);
+    case 7: return launch_r<7>(h_jobs, d_jobs, n_jobs, d_total, binned, ppt, apply_grid, st);
+    case 8: return launch_r<8>(h_jobs, d_jobs, n_jobs, d_total, binned, ppt, apply_grid, st);
     default: return hipErrorInvalidValue;
   }
 }
 
+// ------------------------------------------------------------------ fill
+
 // Word fill with 16-byte stores (a kernel rather than hipMemsetAsync, so
-// the same launch sequence can later be captured into a graph).
-__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p,
-                                                  size_t n, uint32_t v) {
+// the launch sequences stay capturable into graphs).
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p, size_t n, uint32_t v) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t n4 = n / 4;

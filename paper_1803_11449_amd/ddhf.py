@@ -27,13 +27,16 @@ DEFAULT_SEED = 0x1803114490000001
 EXPORTS = ("sketch_params_default", "sketch_params_check", "sketch_bytes",
            "sketch_create", "sketch_destroy", "sketch_update", "sketch_restore",
            "sketch_reset", "sketch_download", "sketch_upload",
-           "sketch_candidates", "sketch_last_error", "sketch_set_option")
+           "sketch_candidates", "sketch_last_error", "sketch_set_option",
+           "sketch_update_batch", "sketch_restore_batch")
 
 SKETCH_OPT_UPDATE_PATH = 1
 SKETCH_OPT_BINNED_MIN_PAIRS = 2
 SKETCH_OPT_UPDATE_GRID = 3
 SKETCH_OPT_UPDATE_CHECK = 4
 SKETCH_OPT_BINNED_ROUND = 5
+SKETCH_OPT_SCATTER_PPT = 6
+SKETCH_OPT_BINNED_BLOCKS = 7
 
 c_u32, c_u64, c_i32, c_sz, c_dbl, c_vp = (ctypes.c_uint32, ctypes.c_uint64,
                                           ctypes.c_int32, ctypes.c_size_t,
@@ -55,6 +58,15 @@ class sketch_info_t(ctypes.Structure):
                 ("n_reported", c_u64), ("psi", c_dbl), ("d", c_dbl),
                 ("zmin", c_dbl), ("trep", c_dbl), ("zhot", c_u32),
                 ("szmax", c_u32)]
+
+
+class sketch_update_job_t(ctypes.Structure):
+    _fields_ = [("sketch", c_vp), ("d_pairs", c_vp), ("n_pairs", c_sz)]
+
+
+class sketch_restore_job_t(ctypes.Structure):
+    _fields_ = [("sketch", c_vp), ("theta", c_dbl), ("out", c_vp), ("cap", c_sz),
+                ("info", c_vp), ("n_out", c_sz), ("status", ctypes.c_int)]
 
 
 SP_DTYPE = np.dtype([("ip", "<u4"), ("sz", "<u4"), ("est", "<f8")])
@@ -95,6 +107,8 @@ def lib() -> ctypes.CDLL:
             "sketch_candidates": (c_i32, [c_vp, c_dbl, c_vp, c_sz, P(c_sz), c_vp]),
             "sketch_last_error": (ctypes.c_char_p, []),
             "sketch_set_option": (c_i32, [c_vp, c_i32, ctypes.c_int64]),
+            "sketch_update_batch": (c_i32, [c_vp, c_sz, c_vp]),
+            "sketch_restore_batch": (c_i32, [c_vp, c_sz, c_vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -147,6 +161,14 @@ def sketch_update(h: int, d_pairs: int, n_pairs: int, stream: int = 0) -> None:
     _check(lib().sketch_update(h, d_pairs, n_pairs, stream))
 
 
+def sketch_update_batch(jobs, stream: int = 0) -> None:
+    """jobs: sequence of (handle, d_pairs, n_pairs)."""
+    arr = (sketch_update_job_t * max(1, len(jobs)))()
+    for i, (h, ptr, n) in enumerate(jobs):
+        arr[i] = sketch_update_job_t(h, ptr, n)
+    _check(lib().sketch_update_batch(ctypes.cast(arr, c_vp), len(jobs), stream))
+
+
 def sketch_reset(h: int, stream: int = 0) -> None:
     _check(lib().sketch_reset(h, stream))
 
@@ -164,6 +186,30 @@ def sketch_restore(h: int, theta: float, cap: int, stream: int = 0):
         err.info = info_dict(info)
         raise err
     return out[: n.value].copy(), info_dict(info)
+
+
+def sketch_restore_batch(items, stream: int = 0):
+    """items: sequence of (handle, theta, cap). Returns a list of
+    (records, info, status, n_needed) per item, in order."""
+    n = len(items)
+    arr = (sketch_restore_job_t * max(1, n))()
+    outs, infos = [], []
+    for i, (h, theta, cap) in enumerate(items):
+        out = np.zeros(max(cap, 1), dtype=SP_DTYPE)
+        info = sketch_info_t()
+        outs.append(out)
+        infos.append(info)
+        arr[i] = sketch_restore_job_t(h, float(theta), out.ctypes.data, cap,
+                                      ctypes.addressof(info), 0, 0)
+    rc = lib().sketch_restore_batch(ctypes.cast(arr, c_vp), n, stream)
+    if rc == SKETCH_E_INVAL and all(arr[i].status == 0 for i in range(n)):
+        raise SketchError(rc, last_error())
+    res = []
+    for i in range(n):
+        st = arr[i].status
+        recs = outs[i][: arr[i].n_out].copy() if st == SKETCH_OK else outs[i][:0].copy()
+        res.append((recs, info_dict(infos[i]), st, arr[i].n_out))
+    return res
 
 
 def sketch_candidates(h: int, theta: float, cap: int, stream: int = 0) -> np.ndarray:
@@ -205,6 +251,53 @@ def _stream_handle(stream, device) -> int:
     return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
 
 
+def _check_pairs(pairs):
+    import torch
+    if not isinstance(pairs, torch.Tensor) or not pairs.is_cuda:
+        raise TypeError("pairs must be a CUDA tensor")
+    if pairs.element_size() != 4 or not pairs.is_contiguous():
+        raise TypeError("pairs must be a contiguous 32-bit tensor")
+    if pairs.numel() % 2:
+        raise ValueError("pairs must hold an even number of words")
+
+
+def update_batch(items, stream=None) -> None:
+    """items: sequence of (Sketch, pairs tensor). One batched update."""
+    if not items:
+        return
+    for _, t in items:
+        _check_pairs(t)
+    dev = items[0][0].device
+    sketch_update_batch([(sk.handle, t.data_ptr(), t.numel() // 2) for sk, t in items],
+                        _stream_handle(stream, dev))
+
+
+def restore_batch(items, stream=None):
+    """items: sequence of (Sketch, theta). One batched restore; returns
+    [(records, info)] in order. Raises SketchError for a failed job other
+    than CAPACITY; CAPACITY jobs are rerun in a second batch."""
+    if not items:
+        return []
+    dev = items[0][0].device
+    s = _stream_handle(stream, dev)
+    res = sketch_restore_batch([(sk.handle, th, sk._cap) for sk, th in items], s)
+    out = [None] * len(items)
+    retry = []
+    for i, ((sk, th), (recs, info, st, need)) in enumerate(zip(items, res)):
+        if st == SKETCH_OK:
+            out[i] = (recs, info)
+        elif st == SKETCH_E_CAPACITY:
+            sk._cap = max(int(need) + 64, 2 * sk._cap)
+            retry.append(i)
+        else:
+            raise SketchError(st, f"restore of batch item {i} failed")
+    if retry:
+        again = restore_batch([items[i] for i in retry], stream)
+        for i, r in zip(retry, again):
+            out[i] = r
+    return out
+
+
 class Sketch:
     """One DDHF sketch on a GPU (r rows of 2^k LEs of g bits)."""
 
@@ -222,13 +315,7 @@ class Sketch:
 
     # pairs: CUDA tensor of 2n 32-bit words (int32/uint32, [n,2] or [2n])
     def update(self, pairs, stream=None) -> None:
-        import torch
-        if not isinstance(pairs, torch.Tensor) or not pairs.is_cuda:
-            raise TypeError("pairs must be a CUDA tensor")
-        if pairs.element_size() != 4 or not pairs.is_contiguous():
-            raise TypeError("pairs must be a contiguous 32-bit tensor")
-        if pairs.numel() % 2:
-            raise ValueError("pairs must hold an even number of words")
+        _check_pairs(pairs)
         sketch_update(self.handle, pairs.data_ptr(), pairs.numel() // 2,
                       _stream_handle(stream, pairs.device))
 

@@ -149,6 +149,63 @@ def test_binned_rounds_and_split_tiles():
             assert np.array_equal(sk.download(), ref), rnd
 
 
+def test_update_batch_mixed_sketches():
+    """One batched update over sketches of different parameters and sizes
+    (direct and binned jobs, several r) equals the oracle for each."""
+    rng = np.random.default_rng(41)
+    specs = [(oracle.Params(), 500_000), (oracle.Params(1024, 18, 5, 5), 2_000_000),
+             (oracle.Params(), 3_000), (oracle.Params(256, 12, 6, 5), 400_000),
+             (oracle.Params(1024, 16, 3, 16), 1_000_000), (oracle.Params(), 0),
+             (oracle.Params(512, 14, 5, 6), 1_234_567)]
+    sketches, tensors, refs = [], [], []
+    for p, n in specs:
+        pairs = rand_pairs(rng, n, max(1, n // 20)) if n else np.zeros((0, 2), np.uint32)
+        refs.append(oracle.build_sketch(p, pairs))
+        sketches.append(make_sketch(p))
+        t = to_dev(pairs) if n else torch.zeros((0, 2), dtype=torch.int32, device=DEV)
+        tensors.append(t[1:].contiguous() if n > 10 else t)   # odd offset
+        if n > 10:
+            sketches[-1].update(t[:1])
+    ddhf.update_batch(list(zip(sketches, tensors)))
+    torch.cuda.synchronize()
+    for sk, ref in zip(sketches, refs):
+        assert np.array_equal(sk.download(), ref)
+        sk.close()
+
+
+def test_restore_batch_equals_single_restores():
+    """Batched restore of several windows (one needing bigger buffers, one
+    saturated-free empty sketch) gives each the single-restore result."""
+    rng = np.random.default_rng(43)
+    specs = [oracle.Params(), oracle.Params(1024, 18, 5, 5), oracle.Params(), oracle.Params(256, 12, 6, 5)]
+    sizes = [600_000, 3_000_000, 0, 300_000]
+    sks, refs = [], []
+    for p, n in zip(specs, sizes):
+        hosts = rng.choice(2**32, size=8, replace=False).astype(np.uint32)
+        parts = [rand_pairs(rng, n, max(1, n // 30))] if n else []
+        pairs = np.concatenate(parts + planted(rng, hosts, 2500)) if n else np.zeros((0, 2), np.uint32)
+        sk = make_sketch(p)
+        if n:
+            sk.update(to_dev(pairs))
+        sks.append(sk)
+        refs.append(oracle.restore(p, oracle.build_sketch(p, pairs), 0.7 * p.g))
+    res = ddhf.restore_batch([(sk, 0.7 * p.g) for sk, p in zip(sks, specs)])
+    for (recs, info), (ip, sz, c, _), sk, p in zip(res, refs, sks, specs):
+        assert_spl_equal(recs, ip, sz, c)
+        alone, _ = sk.restore(0.7 * p.g)
+        assert np.array_equal(alone, recs)
+        sk.close()
+
+
+def test_update_batch_rejects_duplicates():
+    p = oracle.Params()
+    with make_sketch(p) as sk:
+        t = to_dev(rand_pairs(np.random.default_rng(1), 1000, 10))
+        with pytest.raises(ddhf.SketchError) as e:
+            ddhf.update_batch([(sk, t), (sk, t)])
+        assert e.value.code == ddhf.SKETCH_E_INVAL
+
+
 def test_set_option_rejects_bad_values():
     with make_sketch(oracle.Params()) as sk:
         for opt, val in ((ddhf.SKETCH_OPT_UPDATE_PATH, 3), (ddhf.SKETCH_OPT_UPDATE_GRID, 0),

@@ -40,6 +40,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(ddhf.sketch_params_t) == 32
     assert ctypes.sizeof(ddhf.sketch_sp_t) == 16
     assert ctypes.sizeof(ddhf.sketch_info_t) == 216
+    assert ctypes.sizeof(ddhf.sketch_update_job_t) == 24
+    assert ctypes.sizeof(ddhf.sketch_restore_job_t) == 56
 
 
 def test_params_default_check_and_bytes(L):
@@ -72,5 +74,9 @@ def test_null_handle_errors(L):
                             None) == ddhf.SKETCH_E_INVAL
     assert L.sketch_download(None, None, 0, None) == ddhf.SKETCH_E_INVAL
     assert L.sketch_candidates(None, 1.0, None, 0, ctypes.byref(n), None) == ddhf.SKETCH_E_INVAL
+    assert L.sketch_update_batch(None, 1, None) == ddhf.SKETCH_E_INVAL
+    assert L.sketch_update_batch(None, 0, None) == ddhf.SKETCH_OK
+    assert L.sketch_restore_batch(None, 1, None) == ddhf.SKETCH_E_INVAL
+    assert L.sketch_set_option(None, 1, 0) == ddhf.SKETCH_E_INVAL
     L.sketch_destroy(None)
     assert "NULL" in ddhf.last_error()

@@ -40,6 +40,26 @@ def sized_k(n_pairs: int, g: int = 1024) -> tuple[int, int]:
     return k, math.ceil((32 - k) / 3)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "large_window_100m_hbm_traffic.md")
+UPDATE_SRC = os.path.join(ROOT, "paper_1803_11449_amd", "csrc", "update.hip")
+
+
+def measured_update_traffic():
+    """HBM bytes of one 100M-pair update from the committed counter profile,
+    or None if the update source changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src = hashlib.sha256(open(UPDATE_SRC, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line
+                and line.split(": ", 1)[0] in ("update_traffic_bytes", "update_source_sha256"))
+    if vals.get("update_source_sha256", "").strip() != src:
+        return None
+    return float(vals["update_traffic_bytes"])
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -170,6 +190,7 @@ def main():
     alg_bytes = n * PAIR_BYTES
     achieved = alg_bytes / (upd_mean / 1e3) / 1e9
     info = rec["info"]
+    traffic = measured_update_traffic() if n == 100_000_000 else None
 
     out = {
         "metric": METRIC,
@@ -199,11 +220,16 @@ def main():
         "candidates": info["n_candidates"],
         "he_count": info["he_count"][:r],
         "psi": round(info["psi"], 6),
-        "roofline": {"kernel": "k_update", "bound": "hbm",
+        "roofline": {"kernel": "sketch_update (k_bin_count, k_bin_scan_cols, "
+                               "k_bin_scan_tiles, k_bin_scatter, k_item_offsets, "
+                               "k_bin_apply, k_bin_merge)",
+                     "bound": "hbm",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": None},
+                     "traffic": traffic},
     }
+    if traffic:
+        out["roofline"]["traffic_gbs"] = round(traffic / (upd_mean / 1e3) / 1e9, 1)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         host = pairs.cpu().numpy().view(np.uint32).reshape(-1)

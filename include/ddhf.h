@@ -182,6 +182,15 @@ int sketch_restore_batch(sketch_restore_job_t *jobs, size_t n_jobs, void *hip_st
  * Asynchronous on hip_stream. */
 int sketch_reset(sketch_t *s, void *hip_stream);
 
+/* Merge the window of another monitor into this one: dst |= src, bit by bit
+ * (the router-merge step of Sec. 4.2). The paper writes the merge as a
+ * bit-wise AND; OR is what reproduces the sketch of the union of both pair
+ * streams (a bit is set iff some pair of either stream sets it), so the
+ * merged sketch equals the one a single monitor would have built. Both
+ * sketches must have the same g, k, r, alpha and seed and be on one device.
+ * Asynchronous on hip_stream; src is unchanged. Errors: INVAL, HIP. */
+int sketch_merge(sketch_t *dst, const sketch_t *src, void *hip_stream);
+
 /* ---- tuning ---- */
 
 /* Options of sketch_set_option. The update has two kernels computing the

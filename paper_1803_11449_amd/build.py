@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libddhf.so")
 ARCH = os.environ.get("DDHF_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "update.hip", "restore.hip"]
+SOURCES = ["api.hip", "update.hip", "restore.hip", "ops.hip"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

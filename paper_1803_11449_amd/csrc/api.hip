@@ -1,6 +1,15 @@
 // C ABI of libddhf (declared in include/ddhf.h): handle lifetime, argument
-// checks, device memory, and the host side of the restore (capacity growth
-// and the copies to the caller).
+// checks, device memory, batching, and the host side of the restore
+// (capacity growth and the copies to the caller).
+//
+// Memory. A handle owns what is tied to its sketch and must outlive a call:
+// the sketch, its per-row restore arrays (hot bitmap, hot lists, bucket
+// tables), its per-tile update arrays, its device state and its sorted
+// output. The large scratch buffers are shared by every handle on a device
+// (DevCtx): the update arena (codes and scratch tiles of one launch group)
+// and the restore pool (partial addresses, candidates, unsorted records,
+// sort ranks). Work that uses either waits on the event of the last work
+// that used them, so streams of different handles stay ordered on them.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -15,48 +24,6 @@
 #include "ddhf_internal.h"
 
 using namespace ddhf;
-
-namespace {
-
-// Per-device launch context shared by every handle on the device: a ring of
-// update job tables (pinned host staging + device copy + an event marking
-// when the launches that read a slot are done).
-struct DevCtx {
-  static constexpr int SLOTS = 16;
-  int dev = -1;
-  int refs = 0;
-  std::mutex mu;
-  UpdJob *h_jobs[SLOTS] = {};
-  UpdJob *d_jobs[SLOTS] = {};
-  uint32_t *d_total = nullptr;   // SLOTS words
-  hipEvent_t ev[SLOTS] = {};
-  bool armed[SLOTS] = {};
-  int next = 0;
-};
-
-std::mutex g_ctx_mu;
-DevCtx *g_ctx[256] = {};
-
-}  // namespace
-
-struct sketch {
-  sketch_params_t p;
-  Geom G;
-  uint32_t *d_sketch = nullptr;
-  size_t words = 0;
-  RestoreBufs B{};
-  DevState *h_state = nullptr;  // pinned host copy of the device state
-  int n_cu = 0;
-  int grid = 0;          // blocks for grid-stride kernels
-  int update_grid = 0;
-  int update_variant = 1;
-  int update_path = 0;   // 0 auto, 1 direct, 2 binned
-  size_t binned_min_pairs = 0;
-  size_t binned_round = (size_t)1 << 27;  // pairs per binned round (codes < 2^32)
-  uint32_t nbins = 0;
-  BinBufs BB{};
-  DevCtx *ctx = nullptr;
-};
 
 namespace {
 
@@ -82,7 +49,7 @@ int fail(int code, const char *fmt, ...) {
                   __LINE__);                                                     \
   } while (0)
 
-// Makes params.device current for the lifetime of the guard and puts the
+// Makes a device current for the lifetime of the guard and puts the
 // caller's device back afterwards.
 struct DeviceGuard {
   int prev = -1;
@@ -102,6 +69,231 @@ struct DeviceGuard {
   if (guard_.err != hipSuccess)                                                  \
     return fail(SKETCH_E_HIP, "hipSetDevice(%d): %s", (int)(dev),                \
                 hipGetErrorString(guard_.err));
+
+template <typename T>
+int dev_alloc(T **p, size_t count, const char *what) {
+  *p = nullptr;
+  hipError_t e = hipMalloc((void **)p, std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(e == hipErrorOutOfMemory ? SKETCH_E_NOMEM : SKETCH_E_HIP,
+                "hipMalloc(%s, %zu bytes): %s", what, count * sizeof(T), hipGetErrorString(e));
+  }
+  return SKETCH_OK;
+}
+
+template <typename T>
+void dev_free(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+// ---------------------------------------------------------- device context
+
+constexpr size_t ARENA_MAX_PAIRS = (size_t)1 << 27;   // pairs per binned launch group
+
+struct DevCtx {
+  static constexpr int SLOTS = 16;
+  int dev = -1;
+  int refs = 0;
+  int n_cu = 0;
+  std::mutex mu;
+  // ring of update job tables
+  UpdJob *h_jobs[SLOTS] = {};
+  UpdJob *d_jobs[SLOTS] = {};
+  uint32_t *d_total = nullptr;   // SLOTS words
+  hipEvent_t ev[SLOTS] = {};
+  bool armed[SLOTS] = {};
+  int next = 0;
+  // update arena
+  uint32_t *codes = nullptr;
+  size_t codes_cap = 0;          // words
+  uint32_t *scratch = nullptr;
+  size_t scratch_tiles = 0;
+  // restore pool
+  uint32_t jblk = 0;             // blocks of the join kernels
+  uint2 *part[2] = {};
+  uint32_t *segc[2] = {};
+  size_t seg_cap = 0;
+  uint32_t *cand = nullptr, *cand_sorted = nullptr;
+  size_t cand_cap = 0;
+  uint4 *spl = nullptr;
+  size_t spl_cap = 0;
+  uint32_t *rank = nullptr;
+  // last work that used the arena or the pool
+  hipEvent_t pool_ev = nullptr;
+  bool pool_armed = false;
+};
+
+std::mutex g_ctx_mu;
+DevCtx *g_ctx[256] = {};
+
+// Order work about to be enqueued on st after the last use of the pools.
+int pool_enter(DevCtx *c, hipStream_t st) {
+  if (c->pool_armed) HIP_OK(hipStreamWaitEvent(st, c->pool_ev, 0));
+  return SKETCH_OK;
+}
+
+int pool_leave(DevCtx *c, hipStream_t st) {
+  HIP_OK(hipEventRecord(c->pool_ev, st));
+  c->pool_armed = true;
+  return SKETCH_OK;
+}
+
+// Wait on the host until the pools are idle (before reallocating them).
+int pool_idle(DevCtx *c) {
+  if (c->pool_armed) HIP_OK(hipEventSynchronize(c->pool_ev));
+  return SKETCH_OK;
+}
+
+int grow_partials(DevCtx *c, size_t seg_need) {
+  int rc = pool_idle(c);
+  if (rc) return rc;
+  const size_t cap = std::max(seg_need + seg_need / 2, c->seg_cap * 2);
+  dev_free(c->part[0]);
+  dev_free(c->part[1]);
+  c->seg_cap = 0;
+  rc = dev_alloc(&c->part[0], cap * c->jblk, "partials");
+  if (!rc) rc = dev_alloc(&c->part[1], cap * c->jblk, "partials");
+  if (!rc) c->seg_cap = cap;
+  return rc;
+}
+
+int grow_cand(DevCtx *c, size_t need) {
+  int rc = pool_idle(c);
+  if (rc) return rc;
+  const size_t cap = std::max(need + need / 2, c->cand_cap * 2);
+  dev_free(c->cand);
+  dev_free(c->cand_sorted);
+  c->cand_cap = 0;
+  rc = dev_alloc(&c->cand, cap, "candidates");
+  if (!rc) rc = dev_alloc(&c->cand_sorted, cap, "candidates");
+  if (!rc) c->cand_cap = cap;
+  return rc;
+}
+
+int grow_pool_spl(DevCtx *c, size_t need) {
+  int rc = pool_idle(c);
+  if (rc) return rc;
+  const size_t cap = std::max(need + need / 2, c->spl_cap * 2);
+  dev_free(c->spl);
+  c->spl_cap = 0;
+  rc = dev_alloc(&c->spl, cap, "records");
+  if (!rc) c->spl_cap = cap;
+  return rc;
+}
+
+// Update arena for `words` code words and `tiles` scratch tiles.
+int ensure_arena(DevCtx *c, size_t words, size_t tiles) {
+  if (c->codes_cap >= words && c->scratch_tiles >= tiles) return SKETCH_OK;
+  int rc = pool_idle(c);
+  if (rc) return rc;
+  if (c->codes_cap < words) {
+    dev_free(c->codes);
+    c->codes_cap = 0;
+    const size_t cap = std::max(words, c->codes_cap + c->codes_cap / 2);
+    rc = dev_alloc(&c->codes, cap, "update codes");
+    if (rc) return rc;
+    c->codes_cap = cap;
+  }
+  if (c->scratch_tiles < tiles) {
+    dev_free(c->scratch);
+    c->scratch_tiles = 0;
+    rc = dev_alloc(&c->scratch, tiles * (size_t)BIN_TILE_WORDS, "update scratch tiles");
+    if (rc) return rc;
+    c->scratch_tiles = tiles;
+  }
+  return SKETCH_OK;
+}
+
+void ctx_free(DevCtx *c) {
+  for (int i = 0; i < DevCtx::SLOTS; i++) {
+    if (c->armed[i]) (void)hipEventSynchronize(c->ev[i]);
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+    if (c->h_jobs[i]) (void)hipHostFree(c->h_jobs[i]);
+    dev_free(c->d_jobs[i]);
+  }
+  (void)pool_idle(c);
+  if (c->pool_ev) (void)hipEventDestroy(c->pool_ev);
+  dev_free(c->d_total);
+  dev_free(c->codes);
+  dev_free(c->scratch);
+  dev_free(c->part[0]);
+  dev_free(c->part[1]);
+  dev_free(c->segc[0]);
+  dev_free(c->segc[1]);
+  dev_free(c->cand);
+  dev_free(c->cand_sorted);
+  dev_free(c->spl);
+  dev_free(c->rank);
+  delete c;
+}
+
+// The context of `dev` (created on first use; refcounted by handles).
+int ctx_acquire(int dev, int n_cu, DevCtx **out) {
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  if (dev < 0 || dev >= 256) return fail(SKETCH_E_INVAL, "device %d out of range", dev);
+  DevCtx *c = g_ctx[dev];
+  if (!c) {
+    c = new DevCtx();
+    c->dev = dev;
+    c->n_cu = n_cu;
+    c->jblk = (uint32_t)(n_cu * 2);
+    int rc = SKETCH_OK;
+    for (int i = 0; i < DevCtx::SLOTS && !rc; i++) {
+      if (hipHostMalloc((void **)&c->h_jobs[i], sizeof(UpdJob) * MAX_JOBS) != hipSuccess) {
+        c->h_jobs[i] = nullptr;
+        rc = fail(SKETCH_E_NOMEM, "device context: hipHostMalloc failed");
+        break;
+      }
+      rc = dev_alloc(&c->d_jobs[i], MAX_JOBS, "job tables");
+      if (!rc && hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming) != hipSuccess)
+        rc = fail(SKETCH_E_HIP, "device context: hipEventCreate failed");
+    }
+    if (!rc && hipEventCreateWithFlags(&c->pool_ev, hipEventDisableTiming) != hipSuccess)
+      rc = fail(SKETCH_E_HIP, "device context: hipEventCreate failed");
+    if (!rc) rc = dev_alloc(&c->d_total, DevCtx::SLOTS, "item totals");
+    if (!rc) rc = dev_alloc(&c->rank, 16384, "sort ranks");
+    if (!rc) rc = dev_alloc(&c->segc[0], c->jblk, "segment counts");
+    if (!rc) rc = dev_alloc(&c->segc[1], c->jblk, "segment counts");
+    if (!rc) rc = grow_partials(c, (size_t)1 << 12);
+    if (!rc) rc = grow_cand(c, (size_t)1 << 16);
+    if (!rc) rc = grow_pool_spl(c, (size_t)1 << 16);
+    if (rc) {
+      ctx_free(c);
+      return rc;
+    }
+    g_ctx[dev] = c;
+  }
+  c->refs++;
+  *out = c;
+  return SKETCH_OK;
+}
+
+void ctx_release(DevCtx *c) {
+  if (!c) return;
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  if (--c->refs > 0) return;
+  g_ctx[c->dev] = nullptr;
+  ctx_free(c);
+}
+
+// Copy n jobs into the next ring slot and launch them on st (caller holds
+// c->mu and has entered the pools).
+int launch_jobs(DevCtx *c, const UpdJob *jobs, uint32_t n, bool binned, uint32_t r,
+                uint32_t ppt, uint32_t apply_grid, hipStream_t st) {
+  const int slot = c->next;
+  c->next = (c->next + 1) % DevCtx::SLOTS;
+  if (c->armed[slot]) HIP_OK(hipEventSynchronize(c->ev[slot]));
+  memcpy(c->h_jobs[slot], jobs, sizeof(UpdJob) * n);
+  HIP_OK(hipMemcpyAsync(c->d_jobs[slot], c->h_jobs[slot], sizeof(UpdJob) * n,
+                        hipMemcpyHostToDevice, st));
+  HIP_OK(launch_update_jobs(c->h_jobs[slot], c->d_jobs[slot], n, c->d_total + slot, binned, r,
+                            ppt, apply_grid, st));
+  HIP_OK(hipEventRecord(c->ev[slot], st));
+  c->armed[slot] = true;
+  return SKETCH_OK;
+}
 
 uint64_t splitmix64_next(uint64_t &state) {
   // SplitMix64 (Steele, Lea and Flood 2014).
@@ -138,176 +330,94 @@ Geom make_geom(const sketch_params_t &p) {
   return G;
 }
 
-template <typename T>
-int dev_alloc(T **p, size_t count, const char *what) {
-  *p = nullptr;
-  hipError_t e = hipMalloc((void **)p, std::max<size_t>(count, 1) * sizeof(T));
-  if (e != hipSuccess) {
-    *p = nullptr;
-    return fail(e == hipErrorOutOfMemory ? SKETCH_E_NOMEM : SKETCH_E_HIP,
-                "hipMalloc(%s, %zu bytes): %s", what, count * sizeof(T),
-                hipGetErrorString(e));
-  }
-  return SKETCH_OK;
-}
+}  // namespace
 
-template <typename T>
-void dev_free(T *&p) {
-  if (p) (void)hipFree((void *)p);
-  p = nullptr;
-}
+// ------------------------------------------------------------------ handle
 
-void ctx_release(DevCtx *c);
+struct sketch {
+  sketch_params_t p;
+  Geom G;
+  DevCtx *ctx = nullptr;
+  int n_cu = 0;
+  int grid = 0;                 // blocks of grid-stride kernels
+  uint32_t *d_sketch = nullptr;
+  size_t words = 0;
+  // update
+  int update_grid = 0;          // blocks of the direct kernel
+  int update_check = 1;
+  int update_path = 0;          // 0 by size, 1 direct, 2 binned
+  size_t binned_min_pairs = 0;
+  size_t binned_round = ARENA_MAX_PAIRS;
+  uint32_t nbins = 0;
+  uint32_t bin_nblk = 0;        // count/scatter blocks per job (hist width)
+  uint32_t scatter_ppt = 6;
+  uint32_t apply_grid = 0;
+  uint32_t *hist = nullptr, *totals = nullptr, *base = nullptr, *item_start = nullptr,
+           *xslot = nullptr, *n_items = nullptr;
+  // restore
+  DevState *st = nullptr;
+  DevState *h_state = nullptr;  // pinned copy of the device state
+  uint32_t *hotmask = nullptr, *he = nullptr, *bk_off = nullptr, *bk_cur = nullptr,
+           *bk_val = nullptr;
+  uint4 *spl_sorted = nullptr;
+  size_t spl_sorted_cap = 0;
+};
 
-void free_all(sketch *s) {
+namespace {
+
+void free_sketch(sketch *s) {
   dev_free(s->d_sketch);
-  RestoreBufs &B = s->B;
-  dev_free(B.st);
-  dev_free(B.hotmask);
-  dev_free(B.he);
-  dev_free(B.bk_off);
-  dev_free(B.bk_cur);
-  dev_free(B.bk_val);
-  dev_free(B.part[0]);
-  dev_free(B.part[1]);
-  dev_free(B.segc[0]);
-  dev_free(B.segc[1]);
-  dev_free(B.cand);
-  dev_free(B.cand_sorted);
-  dev_free(B.rank);
-  dev_free(B.spl);
-  dev_free(B.spl_sorted);
+  dev_free(s->hist);
+  dev_free(s->totals);
+  dev_free(s->base);
+  dev_free(s->item_start);
+  dev_free(s->xslot);
+  dev_free(s->n_items);
+  dev_free(s->st);
+  dev_free(s->hotmask);
+  dev_free(s->he);
+  dev_free(s->bk_off);
+  dev_free(s->bk_cur);
+  dev_free(s->bk_val);
+  dev_free(s->spl_sorted);
   if (s->h_state) (void)hipHostFree(s->h_state);
   s->h_state = nullptr;
-  BinBufs &BB = s->BB;
-  dev_free(BB.hist);
-  dev_free(BB.totals);
-  dev_free(BB.base);
-  dev_free(BB.item_start);
-  dev_free(BB.xslot);
-  dev_free(BB.n_items);
-  dev_free(BB.codes);
-  dev_free(BB.scratch);
-  BB.codes_cap = 0;
   ctx_release(s->ctx);
   s->ctx = nullptr;
 }
 
-// Codes buffer of the binned update for rounds of `pairs` pairs.
-int ensure_codes(sketch *s, size_t pairs, hipStream_t st) {
-  BinBufs &BB = s->BB;
-  const size_t need = pairs * s->p.r;
-  if (BB.codes_cap >= need) return SKETCH_OK;
-  HIP_OK(hipStreamSynchronize(st));
-  dev_free(BB.codes);
-  dev_free(BB.scratch);
-  BB.codes_cap = 0;
-  int rc = dev_alloc(&BB.codes, need, "update codes");
-  if (rc) return rc;
-  // a tile cut into j items needs j-1 scratch tiles; j-1 < codes/APPLY_ITEM
-  rc = dev_alloc(&BB.scratch, (need / APPLY_ITEM + 1) * (size_t)BIN_TILE_WORDS,
-                 "update scratch tiles");
-  if (rc) return rc;
-  BB.codes_cap = need;
-  return SKETCH_OK;
+int grow_sorted(sketch *s, size_t need) {
+  const size_t cap = std::max(need + need / 2, s->spl_sorted_cap * 2);
+  dev_free(s->spl_sorted);
+  s->spl_sorted_cap = 0;
+  int rc = dev_alloc(&s->spl_sorted, cap, "sorted records");
+  if (!rc) s->spl_sorted_cap = cap;
+  return rc;
 }
 
-// Partial-address buffers: jblk segments of seg_cap entries each.
-int grow_partials(sketch *s, size_t seg_need) {
-  RestoreBufs &B = s->B;
-  const size_t cap = std::max(seg_need + seg_need / 2, B.seg_cap * 2);
-  dev_free(B.part[0]);
-  dev_free(B.part[1]);
-  B.seg_cap = 0;
-  int rc = dev_alloc(&B.part[0], cap * B.jblk, "partials");
-  if (rc) return rc;
-  rc = dev_alloc(&B.part[1], cap * B.jblk, "partials");
-  if (rc) return rc;
-  B.seg_cap = cap;
-  return SKETCH_OK;
-}
-
-// The device context of `dev` (created on first use; refcounted by handles).
-int ctx_acquire(int dev, DevCtx **out) {
-  std::lock_guard<std::mutex> lk(g_ctx_mu);
-  if (dev < 0 || dev >= 256) return fail(SKETCH_E_INVAL, "device %d out of range", dev);
-  DevCtx *c = g_ctx[dev];
-  if (!c) {
-    c = new DevCtx();
-    c->dev = dev;
-    for (int i = 0; i < DevCtx::SLOTS; i++) {
-      if (hipHostMalloc((void **)&c->h_jobs[i], sizeof(UpdJob) * MAX_JOBS) != hipSuccess ||
-          hipMalloc((void **)&c->d_jobs[i], sizeof(UpdJob) * MAX_JOBS) != hipSuccess ||
-          hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming) != hipSuccess)
-        return fail(SKETCH_E_NOMEM, "device context: allocation failed");
-    }
-    if (hipMalloc((void **)&c->d_total, sizeof(uint32_t) * DevCtx::SLOTS) != hipSuccess)
-      return fail(SKETCH_E_NOMEM, "device context: allocation failed");
-    g_ctx[dev] = c;
-  }
-  c->refs++;
-  *out = c;
-  return SKETCH_OK;
-}
-
-void ctx_release(DevCtx *c) {
-  if (!c) return;
-  std::lock_guard<std::mutex> lk(g_ctx_mu);
-  if (--c->refs > 0) return;
-  for (int i = 0; i < DevCtx::SLOTS; i++) {
-    if (c->armed[i]) (void)hipEventSynchronize(c->ev[i]);
-    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
-    if (c->h_jobs[i]) (void)hipHostFree(c->h_jobs[i]);
-    if (c->d_jobs[i]) (void)hipFree(c->d_jobs[i]);
-  }
-  if (c->d_total) (void)hipFree(c->d_total);
-  g_ctx[c->dev] = nullptr;
-  delete c;
-}
-
-// Copy n jobs into the next ring slot and launch them on st.
-int launch_jobs(DevCtx *c, const UpdJob *jobs, uint32_t n, bool binned, uint32_t r,
-                uint32_t ppt, uint32_t apply_grid, hipStream_t st) {
-  std::lock_guard<std::mutex> lk(c->mu);
-  const int slot = c->next;
-  c->next = (c->next + 1) % DevCtx::SLOTS;
-  if (c->armed[slot]) HIP_OK(hipEventSynchronize(c->ev[slot]));
-  memcpy(c->h_jobs[slot], jobs, sizeof(UpdJob) * n);
-  HIP_OK(hipMemcpyAsync(c->d_jobs[slot], c->h_jobs[slot], sizeof(UpdJob) * n,
-                        hipMemcpyHostToDevice, st));
-  HIP_OK(launch_update_jobs(c->h_jobs[slot], c->d_jobs[slot], n, c->d_total + slot, binned, r,
-                            ppt, apply_grid, st));
-  HIP_OK(hipEventRecord(c->ev[slot], st));
-  c->armed[slot] = true;
-  return SKETCH_OK;
-}
-
-int grow_cand(sketch *s, size_t need) {
-  RestoreBufs &B = s->B;
-  size_t cap = std::max(need + need / 2, B.cand_cap * 2);
-  dev_free(B.cand);
-  dev_free(B.cand_sorted);
-  B.cand_cap = 0;
-  int rc = dev_alloc(&B.cand, cap, "candidates");
-  if (rc) return rc;
-  rc = dev_alloc(&B.cand_sorted, cap, "candidates");
-  if (rc) return rc;
-  B.cand_cap = cap;
-  return SKETCH_OK;
-}
-
-int grow_spl(sketch *s, size_t need) {
-  RestoreBufs &B = s->B;
-  size_t cap = std::max(need + need / 2, B.spl_cap * 2);
-  dev_free(B.spl);
-  dev_free(B.spl_sorted);
-  B.spl_cap = 0;
-  int rc = dev_alloc(&B.spl, cap, "records");
-  if (rc) return rc;
-  rc = dev_alloc(&B.spl_sorted, cap, "records");
-  if (rc) return rc;
-  B.spl_cap = cap;
-  return SKETCH_OK;
+RestoreBufs restore_bufs(const sketch *s) {
+  const DevCtx *c = s->ctx;
+  RestoreBufs B{};
+  B.st = s->st;
+  B.hotmask = s->hotmask;
+  B.he = s->he;
+  B.bk_off = s->bk_off;
+  B.bk_cur = s->bk_cur;
+  B.bk_val = s->bk_val;
+  B.part[0] = c->part[0];
+  B.part[1] = c->part[1];
+  B.segc[0] = c->segc[0];
+  B.segc[1] = c->segc[1];
+  B.seg_cap = c->seg_cap;
+  B.jblk = c->jblk;
+  B.cand = c->cand;
+  B.cand_sorted = c->cand_sorted;
+  B.cand_cap = c->cand_cap;
+  B.spl = c->spl;
+  B.spl_sorted = s->spl_sorted;
+  B.spl_cap = std::min(c->spl_cap, s->spl_sorted_cap);
+  B.rank = c->rank;
+  return B;
 }
 
 void fill_info(const sketch *s, const DevState &st, double zmin, uint32_t zhot,
@@ -329,9 +439,6 @@ void fill_info(const sketch *s, const DevState &st, double zmin, uint32_t zhot,
   info->szmax = st.szmax;
 }
 
-// Runs the restore pipeline until every buffer held its output (counts are
-// exact on the device even past capacity, so one rerun per grown stage at
-// most). Leaves the final state in s->h_state.
 // Thresholds that depend on theta only (host, float64).
 struct Thresholds {
   double e_theta, zmin;
@@ -349,33 +456,45 @@ Thresholds thresholds(const sketch *s, double theta) {
 }
 
 // Enqueue the restore kernels and the copy of the device state (no wait).
+// Caller holds ctx->mu.
 int restore_launch(sketch *s, const Thresholds &t, int estimate, hipStream_t st) {
-  HIP_OK(launch_restore(s->G, s->d_sketch, s->B, t.zhot, t.e_theta, estimate, s->grid, st));
-  HIP_OK(hipMemcpyAsync(s->h_state, s->B.st, sizeof(DevState), hipMemcpyDeviceToHost, st));
-  return SKETCH_OK;
+  DevCtx *c = s->ctx;
+  int rc = pool_enter(c, st);
+  if (rc) return rc;
+  HIP_OK(launch_restore(s->G, s->d_sketch, restore_bufs(s), t.zhot, t.e_theta, estimate,
+                        s->grid, st));
+  HIP_OK(hipMemcpyAsync(s->h_state, s->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+  return pool_leave(c, st);
 }
 
 // After the state copy has landed: grow any buffer that overflowed.
-// *again = a buffer grew, so the restore must run again.
+// *again = a buffer grew, so the restore must run again. Caller holds ctx->mu.
 int restore_check(sketch *s, int estimate, bool *again) {
   const DevState &h = *s->h_state;
+  DevCtx *c = s->ctx;
   *again = false;
   if (h.saturated) return SKETCH_E_SATURATED;
   size_t need_part = 0;
   for (uint32_t i = 2; i + 1 < s->p.r; i++) need_part = std::max<size_t>(need_part, h.seg_max[i]);
-  if (need_part > s->B.seg_cap) {
-    int rc = grow_partials(s, need_part);
+  if (need_part > c->seg_cap) {
+    int rc = grow_partials(c, need_part);
     if (rc) return rc;
     *again = true;
   }
-  if (h.n_cand > s->B.cand_cap) {
-    int rc = grow_cand(s, h.n_cand);
+  if (h.n_cand > c->cand_cap) {
+    int rc = grow_cand(c, h.n_cand);
     if (rc) return rc;
     *again = true;
   }
-  if (estimate && h.n_spl > s->B.spl_cap) {
-    int rc = grow_spl(s, h.n_spl);
-    if (rc) return rc;
+  if (estimate && h.n_spl > std::min(c->spl_cap, s->spl_sorted_cap)) {
+    if (h.n_spl > c->spl_cap) {
+      int rc = grow_pool_spl(c, h.n_spl);
+      if (rc) return rc;
+    }
+    if (h.n_spl > s->spl_sorted_cap) {
+      int rc = grow_sorted(s, h.n_spl);
+      if (rc) return rc;
+    }
     *again = true;
   }
   return SKETCH_OK;
@@ -383,12 +502,8 @@ int restore_check(sketch *s, int estimate, bool *again) {
 
 // Runs the restore pipeline until every buffer held its output (counts are
 // exact on the device even past capacity, so one rerun per grown stage at
-// most). Leaves the final state in s->h_state.
-int run_restore(sketch *s, double theta, int estimate, hipStream_t st, double *zmin_out,
-                uint32_t *zhot_out) {
-  const Thresholds t = thresholds(s, theta);
-  *zmin_out = t.zmin;
-  *zhot_out = t.zhot;
+// most). Leaves the final state in s->h_state. Caller holds ctx->mu.
+int run_restore(sketch *s, const Thresholds &t, int estimate, hipStream_t st) {
   for (int attempt = 0; attempt < 16; attempt++) {
     int rc = restore_launch(s, t, estimate, st);
     if (rc) return rc;
@@ -400,7 +515,183 @@ int run_restore(sketch *s, double theta, int estimate, hipStream_t st, double *z
   return fail(SKETCH_E_HIP, "restore: capacities did not settle");
 }
 
+// ------------------------------------------------------------------ update
+
+UpdJob job_base(const sketch *s) {
+  UpdJob J{};
+  J.G = s->G;
+  J.sk = s->d_sketch;
+  J.words = s->words;
+  J.nbins = s->nbins;
+  J.hstride = s->bin_nblk;
+  J.hist = s->hist;
+  J.totals = s->totals;
+  J.base = s->base;
+  J.item_start = s->item_start;
+  J.xslot = s->xslot;
+  J.n_items = s->n_items;
+  J.check = (uint32_t)s->update_check;
+  return J;
+}
+
+bool wants_binned(const sketch *s, size_t n) {
+  if (s->nbins > BIN_MAX) return false;
+  return s->update_path == 2 || (s->update_path == 0 && n >= s->binned_min_pairs);
+}
+
+// A launch group: jobs that share the kernels (same r, path, check flag,
+// scatter batch).
+struct Group {
+  uint32_t r;
+  bool binned;
+  uint32_t check;
+  uint32_t ppt;
+  uint32_t apply_grid;
+  std::vector<UpdJob> jobs;
+};
+
+// Launch a group's jobs (caller holds c->mu). Binned jobs get their codes
+// and scratch tiles from the arena, packed one after another.
+int flush_group(DevCtx *c, Group &g, hipStream_t st) {
+  for (size_t at = 0; at < g.jobs.size(); at += MAX_JOBS) {
+    const uint32_t n = (uint32_t)std::min<size_t>(MAX_JOBS, g.jobs.size() - at);
+    UpdJob *J = g.jobs.data() + at;
+    uint32_t blk = 0, tile = 0;
+    size_t words = 0, tiles = 0;
+    for (uint32_t j = 0; j < n; j++) {
+      J[j].blk0 = blk;
+      J[j].tile0 = tile;
+      blk += J[j].nblk;
+      tile += J[j].nbins;
+      if (g.binned) {
+        const size_t w = (size_t)g.r * J[j].n;
+        words += (w + 3) & ~(size_t)3;        // keep every job's codes 16-byte aligned
+        tiles += w / APPLY_ITEM + 1;
+      }
+    }
+    if (g.binned) {
+      int rc = ensure_arena(c, words, tiles);
+      if (rc) return rc;
+      size_t wo = 0, to = 0;
+      for (uint32_t j = 0; j < n; j++) {
+        const size_t w = (size_t)g.r * J[j].n;
+        J[j].codes = c->codes + wo;
+        J[j].scratch = c->scratch + to * (size_t)BIN_TILE_WORDS;
+        wo += (w + 3) & ~(size_t)3;
+        to += w / APPLY_ITEM + 1;
+      }
+    }
+    int rc = pool_enter(c, st);
+    if (rc) return rc;
+    rc = launch_jobs(c, J, n, g.binned, g.r, g.ppt, g.apply_grid, st);
+    if (rc) return rc;
+    rc = pool_leave(c, st);
+    if (rc) return rc;
+  }
+  g.jobs.clear();
+  return SKETCH_OK;
+}
+
+void add_job(std::vector<Group> &groups, const sketch *s, const UpdJob &J, bool binned) {
+  for (Group &g : groups)
+    if (g.r == s->p.r && g.binned == binned && (binned ? g.ppt == s->scatter_ppt
+                                                       : g.check == J.check)) {
+      g.apply_grid = std::max(g.apply_grid, s->apply_grid);
+      g.jobs.push_back(J);
+      return;
+    }
+  groups.push_back(Group{s->p.r, binned, J.check, s->scatter_ppt, s->apply_grid, {J}});
+}
+
+// The update of several distinct sketches on one device: every pair of every
+// job is applied. Binned work runs in rounds of at most ARENA_MAX_PAIRS
+// pairs in total (and a job's binned_round each).
+int update_jobs(const sketch_update_job_t *jobs, size_t n_jobs, hipStream_t st) {
+  if (n_jobs == 0) return SKETCH_OK;
+  if (!jobs) return fail(SKETCH_E_INVAL, "sketch_update_batch: NULL jobs");
+  const int dev = jobs[0].sketch ? jobs[0].sketch->p.device : -1;
+  for (size_t j = 0; j < n_jobs; j++) {
+    const sketch *s = jobs[j].sketch;
+    if (!s) return fail(SKETCH_E_INVAL, "sketch_update: NULL handle (job %zu)", j);
+    if (s->p.device != dev)
+      return fail(SKETCH_E_INVAL, "sketch_update_batch: sketches on different devices");
+    if (jobs[j].n_pairs && !jobs[j].d_pairs)
+      return fail(SKETCH_E_INVAL, "sketch_update: NULL pairs (job %zu)", j);
+    if (((uintptr_t)jobs[j].d_pairs) & 7u)
+      return fail(SKETCH_E_INVAL, "sketch_update: pairs must be 8-byte aligned (job %zu)", j);
+    for (size_t i = 0; i < j; i++)
+      if (jobs[i].sketch == s)
+        return fail(SKETCH_E_INVAL, "sketch_update_batch: a sketch appears twice (jobs %zu, %zu)",
+                    i, j);
+  }
+  DEVICE_GUARD(dev);
+  DevCtx *c = jobs[0].sketch->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  std::vector<const uint32_t *> ptr(n_jobs);
+  std::vector<size_t> left(n_jobs);
+  std::vector<char> binned(n_jobs);
+  std::vector<Group> groups;
+  for (size_t j = 0; j < n_jobs; j++) {
+    sketch *s = jobs[j].sketch;
+    ptr[j] = jobs[j].d_pairs;
+    left[j] = jobs[j].n_pairs;
+    binned[j] = left[j] && wants_binned(s, left[j]);
+    if (binned[j] && (((uintptr_t)ptr[j]) & 15u)) {
+      // the count pass reads pairs 16 bytes at a time: the first pair goes
+      // through the direct kernel so the rest starts 16-byte aligned
+      UpdJob J = job_base(s);
+      J.pairs = reinterpret_cast<const uint2 *>(ptr[j]);
+      J.n = 1;
+      J.nblk = 1;
+      add_job(groups, s, J, false);
+      ptr[j] += 2;
+      left[j]--;
+    }
+  }
+  for (;;) {
+    bool any = false;
+    size_t room = ARENA_MAX_PAIRS;
+    for (size_t j = 0; j < n_jobs; j++) {
+      if (!left[j]) continue;
+      sketch *s = jobs[j].sketch;
+      UpdJob J = job_base(s);
+      J.pairs = reinterpret_cast<const uint2 *>(ptr[j]);
+      if (binned[j]) {
+        const size_t m = std::min({left[j], s->binned_round, room});
+        if (m == 0) continue;
+        room -= m;
+        J.n = m;
+        // about 32k pairs or more per block, at most the configured count
+        const size_t want = (m + 32767) / 32768;
+        J.nblk = (uint32_t)std::max<size_t>(1, std::min<size_t>(s->bin_nblk, want));
+        size_t chunk = (m + J.nblk - 1) / J.nblk;
+        chunk += chunk & 1;
+        J.chunk = chunk;
+        J.nblk = (uint32_t)((m + chunk - 1) / chunk);
+        add_job(groups, s, J, true);
+        ptr[j] += 2 * m;
+        left[j] -= m;
+      } else {
+        J.n = left[j];
+        J.nblk = (uint32_t)std::max<size_t>(
+            1, std::min<size_t>((size_t)s->update_grid, (left[j] + 255) / 256));
+        add_job(groups, s, J, false);
+        left[j] = 0;
+      }
+      any = true;
+    }
+    for (Group &g : groups) {
+      int rc = flush_group(c, g, st);
+      if (rc) return rc;
+    }
+    if (!any) break;
+  }
+  return SKETCH_OK;
+}
+
 }  // namespace
+
+// ===================================================================== ABI
 
 extern "C" {
 
@@ -435,55 +726,42 @@ int sketch_create(const sketch_params_t *params, sketch_t **out) {
   if (params->device < 0 || params->device >= ndev)
     return fail(SKETCH_E_INVAL, "sketch_create: device %d of %d", params->device, ndev);
   DEVICE_GUARD(params->device);
+  hipDeviceProp_t prop;
+  HIP_OK(hipGetDeviceProperties(&prop, params->device));
 
   sketch *s = new sketch();
   s->p = *params;
   s->G = make_geom(*params);
   s->words = sketch_bytes(params) / 4;
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, params->device) != hipSuccess) {
-    delete s;
-    return fail(SKETCH_E_HIP, "hipGetDeviceProperties failed");
-  }
   s->n_cu = prop.multiProcessorCount;
   s->grid = s->n_cu * 8;
   s->update_grid = s->n_cu * 8;
-
-  const size_t n_le = (size_t)params->r << params->k;
-  const size_t nb = (size_t)1 << (params->k - params->alpha);
-  RestoreBufs &B = s->B;
-  int rc = SKETCH_OK;
-  if (!rc) rc = dev_alloc(&s->d_sketch, s->words, "sketch");
-  if (!rc) rc = dev_alloc(&B.st, 1, "state");
-  if (!rc) rc = dev_alloc(&B.hotmask, n_le / 32, "hot bitmap");
-  if (!rc) rc = dev_alloc(&B.he, n_le, "hot lists");
-  if (!rc) rc = dev_alloc(&B.bk_off, (size_t)params->r * (nb + 1), "bucket offsets");
-  if (!rc) rc = dev_alloc(&B.bk_cur, (size_t)params->r * nb, "bucket cursors");
-  if (!rc) rc = dev_alloc(&B.bk_val, n_le, "bucket values");
-  B.jblk = (uint32_t)(s->n_cu * 2);
-  if (!rc) rc = dev_alloc(&B.rank, 16384, "sort ranks");
-  if (!rc) rc = dev_alloc(&B.segc[0], B.jblk, "segment counts");
-  if (!rc) rc = dev_alloc(&B.segc[1], B.jblk, "segment counts");
-  if (!rc) rc = grow_partials(s, (size_t)1 << 12);
-  if (!rc) rc = grow_cand(s, (size_t)1 << 16);
-  if (!rc) rc = grow_spl(s, (size_t)1 << 16);
   s->nbins = (uint32_t)((s->words + BIN_TILE_WORDS - 1) / BIN_TILE_WORDS);
-  s->BB.nblk = (uint32_t)std::min(1024, s->n_cu);
-  s->BB.apply_grid = (uint32_t)s->n_cu;
-  s->BB.scatter_ppt = 6;
+  s->bin_nblk = (uint32_t)std::min<int>((int)BIN_BLOCKS_MAX, s->n_cu);
+  s->apply_grid = (uint32_t)s->n_cu;
   // measured crossover on MI355X (100M-pair Zipf window): the binned update
   // wins from ~1e5 pairs at k = 14 and ~2e5 at k = 18
   s->binned_min_pairs = std::max<size_t>(s->words / 256, 1 << 14);
-  if (s->nbins <= BIN_MAX) {
-    BinBufs &BB = s->BB;
-    if (!rc) rc = dev_alloc(&BB.hist, (size_t)s->nbins * BIN_BLOCKS_MAX, "tile counts");
-    if (!rc) rc = dev_alloc(&BB.totals, s->nbins, "tile totals");
-    if (!rc) rc = dev_alloc(&BB.base, s->nbins + 1, "tile runs");
-    if (!rc) rc = dev_alloc(&BB.item_start, s->nbins + 1, "tile items");
-    if (!rc) rc = dev_alloc(&BB.xslot, s->nbins + 1, "tile scratch slots");
-    if (!rc) rc = dev_alloc(&BB.n_items, 1, "tile item count");
+
+  const size_t n_le = (size_t)params->r << params->k;
+  const size_t nb = (size_t)1 << (params->k - params->alpha);
+  int rc = ctx_acquire(params->device, s->n_cu, &s->ctx);
+  if (!rc) rc = dev_alloc(&s->d_sketch, s->words, "sketch");
+  if (!rc) rc = dev_alloc(&s->st, 1, "state");
+  if (!rc) rc = dev_alloc(&s->hotmask, n_le / 32, "hot bitmap");
+  if (!rc) rc = dev_alloc(&s->he, n_le, "hot lists");
+  if (!rc) rc = dev_alloc(&s->bk_off, (size_t)params->r * (nb + 1), "bucket offsets");
+  if (!rc) rc = dev_alloc(&s->bk_cur, (size_t)params->r * nb, "bucket cursors");
+  if (!rc) rc = dev_alloc(&s->bk_val, n_le, "bucket values");
+  if (!rc) rc = grow_sorted(s, (size_t)1 << 12);
+  if (!rc && s->nbins <= BIN_MAX) {
+    rc = dev_alloc(&s->hist, (size_t)s->nbins * s->bin_nblk, "tile counts");
+    if (!rc) rc = dev_alloc(&s->totals, s->nbins, "tile totals");
+    if (!rc) rc = dev_alloc(&s->base, s->nbins + 1, "tile runs");
+    if (!rc) rc = dev_alloc(&s->item_start, s->nbins + 1, "tile items");
+    if (!rc) rc = dev_alloc(&s->xslot, s->nbins + 1, "tile scratch slots");
+    if (!rc) rc = dev_alloc(&s->n_items, 1, "tile item count");
   }
-  if (!rc) rc = ctx_acquire(params->device, &s->ctx);
   if (!rc && hipHostMalloc((void **)&s->h_state, sizeof(DevState)) != hipSuccess) {
     s->h_state = nullptr;
     rc = fail(SKETCH_E_NOMEM, "hipHostMalloc(state) failed");
@@ -491,10 +769,11 @@ int sketch_create(const sketch_params_t *params, sketch_t **out) {
   if (!rc) {
     hipError_t e = launch_fill_u32(s->d_sketch, s->words, 0u, s->grid, nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
-    if (e != hipSuccess) rc = fail(SKETCH_E_HIP, "sketch_create: zero fill: %s", hipGetErrorString(e));
+    if (e != hipSuccess)
+      rc = fail(SKETCH_E_HIP, "sketch_create: zero fill: %s", hipGetErrorString(e));
   }
   if (rc) {
-    free_all(s);
+    free_sketch(s);
     delete s;
     return rc;
   }
@@ -506,164 +785,9 @@ void sketch_destroy(sketch_t *s) {
   if (!s) return;
   DeviceGuard guard(s->p.device);
   (void)hipDeviceSynchronize();
-  free_all(s);
+  free_sketch(s);
   delete s;
 }
-
-// ------------------------------------------------------------ update
-
-namespace {
-
-UpdJob job_base(const sketch *s) {
-  UpdJob J{};
-  J.G = s->G;
-  J.sk = s->d_sketch;
-  J.words = s->words;
-  J.nbins = s->nbins;
-  J.hist = s->BB.hist;
-  J.totals = s->BB.totals;
-  J.base = s->BB.base;
-  J.item_start = s->BB.item_start;
-  J.xslot = s->BB.xslot;
-  J.n_items = s->BB.n_items;
-  J.codes = s->BB.codes;
-  J.scratch = s->BB.scratch;
-  J.check = (uint32_t)(s->update_variant & 1);
-  return J;
-}
-
-bool wants_binned(const sketch *s, size_t n) {
-  if (s->nbins > BIN_MAX) return false;
-  return s->update_path == 2 || (s->update_path == 0 && n >= s->binned_min_pairs);
-}
-
-// A launch group: jobs that share the kernels (same r, path, check flag).
-struct Group {
-  uint32_t r;
-  bool binned;
-  uint32_t check;
-  uint32_t ppt;
-  uint32_t apply_grid;
-  std::vector<UpdJob> jobs;
-};
-
-int flush_group(DevCtx *c, Group &g, hipStream_t st) {
-  for (size_t at = 0; at < g.jobs.size(); at += MAX_JOBS) {
-    const uint32_t n = (uint32_t)std::min<size_t>(MAX_JOBS, g.jobs.size() - at);
-    UpdJob *J = g.jobs.data() + at;
-    uint32_t blk = 0, tile = 0;
-    for (uint32_t j = 0; j < n; j++) {
-      J[j].blk0 = blk;
-      J[j].tile0 = tile;
-      blk += J[j].nblk;
-      tile += J[j].nbins;
-    }
-    int rc = launch_jobs(c, J, n, g.binned, g.r, g.ppt, g.apply_grid, st);
-    if (rc) return rc;
-  }
-  g.jobs.clear();
-  return SKETCH_OK;
-}
-
-void add_job(std::vector<Group> &groups, const sketch *s, UpdJob J, bool binned) {
-  const uint32_t ppt = s->BB.scatter_ppt;
-  for (Group &g : groups)
-    if (g.r == s->p.r && g.binned == binned && (binned || g.check == J.check) &&
-        (!binned || g.ppt == ppt)) {
-      g.apply_grid = std::max(g.apply_grid, s->BB.apply_grid);
-      g.jobs.push_back(J);
-      return;
-    }
-  groups.push_back(Group{s->p.r, binned, J.check, ppt, s->BB.apply_grid, {J}});
-}
-
-// The update of several distinct sketches on one device: every pair of every
-// job is applied; binned jobs run in rounds of at most their round size.
-int update_jobs(const sketch_update_job_t *jobs, size_t n_jobs, hipStream_t st) {
-  if (n_jobs == 0) return SKETCH_OK;
-  if (!jobs) return fail(SKETCH_E_INVAL, "sketch_update_batch: NULL jobs");
-  const int dev = jobs[0].sketch ? jobs[0].sketch->p.device : -1;
-  for (size_t j = 0; j < n_jobs; j++) {
-    const sketch *s = jobs[j].sketch;
-    if (!s) return fail(SKETCH_E_INVAL, "sketch_update: NULL handle (job %zu)", j);
-    if (s->p.device != dev)
-      return fail(SKETCH_E_INVAL, "sketch_update_batch: sketches on different devices");
-    if (jobs[j].n_pairs && !jobs[j].d_pairs)
-      return fail(SKETCH_E_INVAL, "sketch_update: NULL pairs (job %zu)", j);
-    if (((uintptr_t)jobs[j].d_pairs) & 7u)
-      return fail(SKETCH_E_INVAL, "sketch_update: pairs must be 8-byte aligned (job %zu)", j);
-    for (size_t i = 0; i < j; i++)
-      if (jobs[i].sketch == s)
-        return fail(SKETCH_E_INVAL, "sketch_update_batch: a sketch appears twice (jobs %zu, %zu)",
-                    i, j);
-  }
-  DEVICE_GUARD(dev);
-  DevCtx *c = jobs[0].sketch->ctx;
-  // per job: pairs left, binned or not
-  std::vector<const uint32_t *> ptr(n_jobs);
-  std::vector<size_t> left(n_jobs);
-  std::vector<char> binned(n_jobs);
-  std::vector<Group> groups;
-  for (size_t j = 0; j < n_jobs; j++) {
-    sketch *s = jobs[j].sketch;
-    ptr[j] = jobs[j].d_pairs;
-    left[j] = jobs[j].n_pairs;
-    binned[j] = left[j] && wants_binned(s, left[j]);
-    if (binned[j]) {
-      int rc = ensure_codes(s, std::min(left[j], s->binned_round), st);
-      if (rc) return rc;
-      if (((uintptr_t)ptr[j]) & 15u) {
-        // the count pass reads pairs 16 bytes at a time: the first pair
-        // goes through the direct kernel so the rest starts 16-byte aligned
-        UpdJob J = job_base(s);
-        J.pairs = reinterpret_cast<const uint2 *>(ptr[j]);
-        J.n = 1;
-        J.nblk = 1;
-        add_job(groups, s, J, false);
-        ptr[j] += 2;
-        left[j]--;
-      }
-    }
-  }
-  for (;;) {
-    bool any = false;
-    for (size_t j = 0; j < n_jobs; j++) {
-      if (!left[j]) continue;
-      sketch *s = jobs[j].sketch;
-      UpdJob J = job_base(s);
-      J.pairs = reinterpret_cast<const uint2 *>(ptr[j]);
-      if (binned[j]) {
-        const size_t m = std::min(left[j], s->binned_round);
-        J.n = m;
-        // about 32k pairs or more per block, at most the configured count
-        const size_t want = (m + 32767) / 32768;
-        J.nblk = (uint32_t)std::max<size_t>(1, std::min<size_t>(s->BB.nblk, want));
-        size_t chunk = (m + J.nblk - 1) / J.nblk;
-        chunk += chunk & 1;
-        J.chunk = chunk;
-        J.nblk = (uint32_t)((m + chunk - 1) / chunk);
-        add_job(groups, s, J, true);
-        ptr[j] += 2 * m;
-        left[j] -= m;
-      } else {
-        J.n = left[j];
-        J.nblk = (uint32_t)std::max<size_t>(
-            1, std::min<size_t>((size_t)s->update_grid, (left[j] + 255) / 256));
-        add_job(groups, s, J, false);
-        left[j] = 0;
-      }
-      any = true;
-    }
-    for (Group &g : groups) {
-      int rc = flush_group(c, g, st);
-      if (rc) return rc;
-    }
-    if (!any) break;
-  }
-  return SKETCH_OK;
-}
-
-}  // namespace
 
 int sketch_update(sketch_t *s, const uint32_t *d_pairs, size_t n_pairs, void *hip_stream) {
   if (!s) return fail(SKETCH_E_INVAL, "sketch_update: NULL handle");
@@ -674,6 +798,139 @@ int sketch_update(sketch_t *s, const uint32_t *d_pairs, size_t n_pairs, void *hi
 
 int sketch_update_batch(const sketch_update_job_t *jobs, size_t n_jobs, void *hip_stream) {
   return update_jobs(jobs, n_jobs, (hipStream_t)hip_stream);
+}
+
+int sketch_reset(sketch_t *s, void *hip_stream) {
+  if (!s) return fail(SKETCH_E_INVAL, "sketch_reset: NULL handle");
+  DEVICE_GUARD(s->p.device);
+  HIP_OK(launch_fill_u32(s->d_sketch, s->words, 0u, s->grid * 4, (hipStream_t)hip_stream));
+  return SKETCH_OK;
+}
+
+int sketch_merge(sketch_t *dst, const sketch_t *src, void *hip_stream) {
+  if (!dst || !src) return fail(SKETCH_E_INVAL, "sketch_merge: NULL handle");
+  if (dst == src) return SKETCH_OK;
+  const sketch_params_t &a = dst->p, &b = src->p;
+  if (a.g != b.g || a.k != b.k || a.r != b.r || a.alpha != b.alpha || a.seed != b.seed)
+    return fail(SKETCH_E_INVAL, "sketch_merge: sketches differ in parameters or seed");
+  if (a.device != b.device)
+    return fail(SKETCH_E_INVAL, "sketch_merge: sketches on different devices");
+  DEVICE_GUARD(a.device);
+  HIP_OK(launch_or_u32(dst->d_sketch, src->d_sketch, dst->words, dst->grid * 4,
+                       (hipStream_t)hip_stream));
+  return SKETCH_OK;
+}
+
+int sketch_restore(sketch_t *s, double theta, sketch_sp_t *out, size_t cap, size_t *n_out,
+                   sketch_info_t *info, void *hip_stream) {
+  if (!s || !n_out) return fail(SKETCH_E_INVAL, "sketch_restore: NULL handle or n_out");
+  if (!(theta > 0.0) || !isfinite(theta))
+    return fail(SKETCH_E_INVAL, "sketch_restore: theta must be finite and > 0");
+  if (cap && !out) return fail(SKETCH_E_INVAL, "sketch_restore: NULL out with cap > 0");
+  DEVICE_GUARD(s->p.device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  std::lock_guard<std::mutex> lk(s->ctx->mu);
+  const Thresholds t = thresholds(s, theta);
+  int rc = run_restore(s, t, 1, st);
+  if (rc != SKETCH_OK && rc != SKETCH_E_SATURATED) return rc;
+  const DevState h = *s->h_state;
+  fill_info(s, h, t.zmin, t.zhot, info);
+  if (rc == SKETCH_E_SATURATED) {
+    *n_out = 0;
+    return fail(SKETCH_E_SATURATED, "sketch_restore: a row has no zero bit (psi = 1)");
+  }
+  *n_out = (size_t)h.n_spl;
+  if (h.n_spl > cap)
+    return fail(SKETCH_E_CAPACITY, "sketch_restore: %llu records, cap %zu", h.n_spl, cap);
+  static_assert(sizeof(sketch_sp_t) == sizeof(uint4), "record layout");
+  if (h.n_spl)
+    HIP_OK(hipMemcpyAsync(out, s->spl_sorted, h.n_spl * sizeof(uint4), hipMemcpyDeviceToHost,
+                          st));
+  HIP_OK(hipStreamSynchronize(st));
+  return SKETCH_OK;
+}
+
+int sketch_restore_batch(sketch_restore_job_t *jobs, size_t n_jobs, void *hip_stream) {
+  if (n_jobs == 0) return SKETCH_OK;
+  if (!jobs) return fail(SKETCH_E_INVAL, "sketch_restore_batch: NULL jobs");
+  const int dev = jobs[0].sketch ? jobs[0].sketch->p.device : -1;
+  for (size_t j = 0; j < n_jobs; j++) {
+    const sketch_restore_job_t &J = jobs[j];
+    if (!J.sketch) return fail(SKETCH_E_INVAL, "sketch_restore_batch: NULL handle (job %zu)", j);
+    if (J.sketch->p.device != dev)
+      return fail(SKETCH_E_INVAL, "sketch_restore_batch: sketches on different devices");
+    if (!(J.theta > 0.0) || !isfinite(J.theta))
+      return fail(SKETCH_E_INVAL, "sketch_restore_batch: theta must be finite and > 0 (job %zu)",
+                  j);
+    if (J.cap && !J.out)
+      return fail(SKETCH_E_INVAL, "sketch_restore_batch: NULL out with cap > 0 (job %zu)", j);
+    for (size_t i = 0; i < j; i++)
+      if (jobs[i].sketch == J.sketch)
+        return fail(SKETCH_E_INVAL, "sketch_restore_batch: a sketch appears twice (jobs %zu, %zu)",
+                    i, j);
+  }
+  DEVICE_GUARD(dev);
+  hipStream_t st = (hipStream_t)hip_stream;
+  DevCtx *c = jobs[0].sketch->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  std::vector<Thresholds> th(n_jobs);
+  // every restore enqueued, one wait
+  for (size_t j = 0; j < n_jobs; j++) {
+    th[j] = thresholds(jobs[j].sketch, jobs[j].theta);
+    int rc = restore_launch(jobs[j].sketch, th[j], 1, st);
+    if (rc) return rc;
+  }
+  HIP_OK(hipStreamSynchronize(st));
+  int first_err = SKETCH_OK;
+  for (size_t j = 0; j < n_jobs; j++) {
+    sketch_restore_job_t &J = jobs[j];
+    sketch *s = J.sketch;
+    bool again;
+    int rc = restore_check(s, 1, &again);
+    if (rc == SKETCH_OK && again) rc = run_restore(s, th[j], 1, st);  // this job alone
+    const DevState h = *s->h_state;
+    if (rc == SKETCH_OK || rc == SKETCH_E_SATURATED)
+      fill_info(s, h, th[j].zmin, th[j].zhot, J.info);
+    J.n_out = rc == SKETCH_OK ? (size_t)h.n_spl : 0;
+    if (rc == SKETCH_OK && h.n_spl > J.cap) rc = SKETCH_E_CAPACITY;
+    if (rc == SKETCH_OK && h.n_spl) {
+      hipError_t e = hipMemcpyAsync(J.out, s->spl_sorted, h.n_spl * sizeof(uint4),
+                                    hipMemcpyDeviceToHost, st);
+      if (e != hipSuccess) rc = SKETCH_E_HIP;
+    }
+    J.status = rc;
+    if (rc && !first_err) first_err = rc;
+  }
+  HIP_OK(hipStreamSynchronize(st));
+  if (first_err)
+    return fail(first_err, "sketch_restore_batch: a job failed (see each job's status)");
+  return SKETCH_OK;
+}
+
+int sketch_candidates(sketch_t *s, double theta, uint32_t *out, size_t cap, size_t *n_out,
+                      void *hip_stream) {
+  if (!s || !n_out) return fail(SKETCH_E_INVAL, "sketch_candidates: NULL handle or n_out");
+  if (!(theta > 0.0) || !isfinite(theta))
+    return fail(SKETCH_E_INVAL, "sketch_candidates: theta must be finite and > 0");
+  if (cap && !out) return fail(SKETCH_E_INVAL, "sketch_candidates: NULL out with cap > 0");
+  DEVICE_GUARD(s->p.device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  std::lock_guard<std::mutex> lk(s->ctx->mu);
+  int rc = run_restore(s, thresholds(s, theta), 0, st);
+  if (rc == SKETCH_E_SATURATED) {
+    *n_out = 0;
+    return fail(SKETCH_E_SATURATED, "sketch_candidates: a row has no zero bit (psi = 1)");
+  }
+  if (rc) return rc;
+  const DevState h = *s->h_state;
+  *n_out = (size_t)h.n_cand;
+  if (h.n_cand > cap)
+    return fail(SKETCH_E_CAPACITY, "sketch_candidates: %llu candidates, cap %zu", h.n_cand, cap);
+  if (h.n_cand)
+    HIP_OK(hipMemcpyAsync(out, s->ctx->cand_sorted, h.n_cand * sizeof(uint32_t),
+                          hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  return SKETCH_OK;
 }
 
 int sketch_set_option(sketch_t *s, int option, int64_t value) {
@@ -695,18 +952,27 @@ int sketch_set_option(sketch_t *s, int option, int64_t value) {
       return SKETCH_OK;
     case SKETCH_OPT_UPDATE_CHECK:
       if (value < 0 || value > 1) break;
-      s->update_variant = (int)value;
+      s->update_check = (int)value;
       return SKETCH_OK;
     case SKETCH_OPT_SCATTER_PPT:
       if (value != 2 && value != 4 && value != 6) break;
-      s->BB.scatter_ppt = (uint32_t)value;
+      s->scatter_ppt = (uint32_t)value;
       return SKETCH_OK;
-    case SKETCH_OPT_BINNED_BLOCKS:
+    case SKETCH_OPT_BINNED_BLOCKS: {
       if (value < 1 || value > (int64_t)BIN_BLOCKS_MAX) break;
-      s->BB.nblk = (uint32_t)value;
+      if (s->hist && (uint32_t)value > s->bin_nblk) {
+        // per-tile counts are [tiles][blocks]: widen (after pending work)
+        DEVICE_GUARD(s->p.device);
+        HIP_OK(hipDeviceSynchronize());
+        dev_free(s->hist);
+        int rc = dev_alloc(&s->hist, (size_t)s->nbins * (size_t)value, "tile counts");
+        if (rc) return rc;
+      }
+      s->bin_nblk = (uint32_t)value;
       return SKETCH_OK;
+    }
     case SKETCH_OPT_BINNED_ROUND:
-      if (value < 1024 || (uint64_t)value * s->p.r >= (1ull << 32)) break;
+      if (value < 1024 || (uint64_t)value > ARENA_MAX_PAIRS) break;
       s->binned_round = (size_t)value;
       return SKETCH_OK;
     default:
@@ -714,127 +980,6 @@ int sketch_set_option(sketch_t *s, int option, int64_t value) {
   }
   return fail(SKETCH_E_INVAL, "sketch_set_option: bad value %lld for option %d",
               (long long)value, option);
-}
-
-int sketch_reset(sketch_t *s, void *hip_stream) {
-  if (!s) return fail(SKETCH_E_INVAL, "sketch_reset: NULL handle");
-  DEVICE_GUARD(s->p.device);
-  HIP_OK(launch_fill_u32(s->d_sketch, s->words, 0u, s->grid * 4, (hipStream_t)hip_stream));
-  return SKETCH_OK;
-}
-
-int sketch_restore(sketch_t *s, double theta, sketch_sp_t *out, size_t cap, size_t *n_out,
-                   sketch_info_t *info, void *hip_stream) {
-  if (!s || !n_out) return fail(SKETCH_E_INVAL, "sketch_restore: NULL handle or n_out");
-  if (!(theta > 0.0) || !isfinite(theta))
-    return fail(SKETCH_E_INVAL, "sketch_restore: theta must be finite and > 0");
-  if (cap && !out) return fail(SKETCH_E_INVAL, "sketch_restore: NULL out with cap > 0");
-  DEVICE_GUARD(s->p.device);
-  hipStream_t st = (hipStream_t)hip_stream;
-  double zmin;
-  uint32_t zhot;
-  int rc = run_restore(s, theta, 1, st, &zmin, &zhot);
-  if (rc != SKETCH_OK && rc != SKETCH_E_SATURATED) return rc;
-  const DevState h = *s->h_state;
-  fill_info(s, h, zmin, zhot, info);
-  if (rc == SKETCH_E_SATURATED) {
-    *n_out = 0;
-    return fail(SKETCH_E_SATURATED, "sketch_restore: a row has no zero bit (psi = 1)");
-  }
-  *n_out = (size_t)h.n_spl;
-  if (h.n_spl > cap)
-    return fail(SKETCH_E_CAPACITY, "sketch_restore: %llu records, cap %zu", h.n_spl, cap);
-  static_assert(sizeof(sketch_sp_t) == sizeof(uint4), "record layout");
-  if (h.n_spl)
-    HIP_OK(hipMemcpyAsync(out, s->B.spl_sorted, h.n_spl * sizeof(uint4), hipMemcpyDeviceToHost,
-                          st));
-  HIP_OK(hipStreamSynchronize(st));
-  return SKETCH_OK;
-}
-
-int sketch_restore_batch(sketch_restore_job_t *jobs, size_t n_jobs, void *hip_stream) {
-  if (n_jobs == 0) return SKETCH_OK;
-  if (!jobs) return fail(SKETCH_E_INVAL, "sketch_restore_batch: NULL jobs");
-  const int dev = jobs[0].sketch ? jobs[0].sketch->p.device : -1;
-  for (size_t j = 0; j < n_jobs; j++) {
-    const sketch_restore_job_t &J = jobs[j];
-    if (!J.sketch) return fail(SKETCH_E_INVAL, "sketch_restore_batch: NULL handle (job %zu)", j);
-    if (J.sketch->p.device != dev)
-      return fail(SKETCH_E_INVAL, "sketch_restore_batch: sketches on different devices");
-    if (!(J.theta > 0.0) || !isfinite(J.theta))
-      return fail(SKETCH_E_INVAL, "sketch_restore_batch: theta must be finite and > 0 (job %zu)", j);
-    if (J.cap && !J.out)
-      return fail(SKETCH_E_INVAL, "sketch_restore_batch: NULL out with cap > 0 (job %zu)", j);
-    for (size_t i = 0; i < j; i++)
-      if (jobs[i].sketch == J.sketch)
-        return fail(SKETCH_E_INVAL, "sketch_restore_batch: a sketch appears twice (jobs %zu, %zu)",
-                    i, j);
-  }
-  DEVICE_GUARD(dev);
-  hipStream_t st = (hipStream_t)hip_stream;
-  std::vector<Thresholds> th(n_jobs);
-  // every restore enqueued, one wait
-  for (size_t j = 0; j < n_jobs; j++) {
-    th[j] = thresholds(jobs[j].sketch, jobs[j].theta);
-    int rc = restore_launch(jobs[j].sketch, th[j], 1, st);
-    if (rc) return rc;
-  }
-  HIP_OK(hipStreamSynchronize(st));
-  int first_err = SKETCH_OK;
-  for (size_t j = 0; j < n_jobs; j++) {
-    sketch_restore_job_t &J = jobs[j];
-    sketch *s = J.sketch;
-    bool again;
-    int rc = restore_check(s, 1, &again);
-    if (rc == SKETCH_OK && again) {
-      double zmin;
-      uint32_t zhot;
-      rc = run_restore(s, J.theta, 1, st, &zmin, &zhot);   // this job alone, to completion
-    }
-    const DevState h = *s->h_state;
-    if (rc == SKETCH_OK || rc == SKETCH_E_SATURATED) fill_info(s, h, th[j].zmin, th[j].zhot, J.info);
-    J.n_out = rc == SKETCH_OK ? (size_t)h.n_spl : 0;
-    if (rc == SKETCH_OK && h.n_spl > J.cap) rc = SKETCH_E_CAPACITY;
-    if (rc == SKETCH_OK && h.n_spl) {
-      rc = SKETCH_OK;
-      hipError_t e = hipMemcpyAsync(J.out, s->B.spl_sorted, h.n_spl * sizeof(uint4),
-                                    hipMemcpyDeviceToHost, st);
-      if (e != hipSuccess) rc = SKETCH_E_HIP;
-    }
-    J.status = rc;
-    if (rc && !first_err) first_err = rc;
-  }
-  HIP_OK(hipStreamSynchronize(st));
-  if (first_err)
-    return fail(first_err, "sketch_restore_batch: a job failed (see each job's status)");
-  return SKETCH_OK;
-}
-
-int sketch_candidates(sketch_t *s, double theta, uint32_t *out, size_t cap, size_t *n_out,
-                      void *hip_stream) {
-  if (!s || !n_out) return fail(SKETCH_E_INVAL, "sketch_candidates: NULL handle or n_out");
-  if (!(theta > 0.0) || !isfinite(theta))
-    return fail(SKETCH_E_INVAL, "sketch_candidates: theta must be finite and > 0");
-  if (cap && !out) return fail(SKETCH_E_INVAL, "sketch_candidates: NULL out with cap > 0");
-  DEVICE_GUARD(s->p.device);
-  hipStream_t st = (hipStream_t)hip_stream;
-  double zmin;
-  uint32_t zhot;
-  int rc = run_restore(s, theta, 0, st, &zmin, &zhot);
-  if (rc == SKETCH_E_SATURATED) {
-    *n_out = 0;
-    return fail(SKETCH_E_SATURATED, "sketch_candidates: a row has no zero bit (psi = 1)");
-  }
-  if (rc) return rc;
-  const DevState h = *s->h_state;
-  *n_out = (size_t)h.n_cand;
-  if (h.n_cand > cap)
-    return fail(SKETCH_E_CAPACITY, "sketch_candidates: %llu candidates, cap %zu", h.n_cand, cap);
-  if (h.n_cand)
-    HIP_OK(hipMemcpyAsync(out, s->B.cand_sorted, h.n_cand * sizeof(uint32_t),
-                          hipMemcpyDeviceToHost, st));
-  HIP_OK(hipStreamSynchronize(st));
-  return SKETCH_OK;
 }
 
 int sketch_download(const sketch_t *s, uint32_t *host_words, size_t n_words, void *hip_stream) {

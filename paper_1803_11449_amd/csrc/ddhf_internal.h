@@ -83,21 +83,6 @@ constexpr uint32_t BIN_MAX = 2048;                   // tiles (sketch <= 256 MiB
 constexpr uint32_t SPLIT_MIN = 1u << 20;             // tiles above this many codes
 constexpr uint32_t APPLY_ITEM = 1u << 19;            //   are cut into items of this many
 
-struct BinBufs {
-  uint32_t *hist;        // [tiles][BIN_BLOCKS_MAX]: counts, then offsets inside the run
-  uint32_t *totals;      // [tiles]
-  uint32_t *base;        // [tiles + 1]: run starts
-  uint32_t *item_start;  // [tiles + 1]
-  uint32_t *xslot;       // [tiles + 1]: first scratch tile of each cut tile
-  uint32_t *n_items;     // [1]
-  uint32_t *codes;       // codes_cap entries
-  size_t codes_cap;      // a multiple of r; < 2^32
-  uint32_t *scratch;     // (codes_cap / APPLY_ITEM + 1) tiles for cut tiles
-  uint32_t nblk;         // blocks of the count and scatter passes (<= BIN_BLOCKS_MAX)
-  uint32_t apply_grid;
-  uint32_t scatter_ppt;  // pairs per thread per scatter batch: 2, 4 or 6
-};
-
 constexpr uint32_t BIN_BLOCKS_MAX = 1024;
 
 // One sketch's share of an update launch. Kernels of a launch take a table
@@ -114,6 +99,8 @@ struct UpdJob {
   uint32_t nblk;         // blocks of this job (count / scatter / direct)
   uint32_t blk0;         // first global block of this job
   uint32_t tile0;        // first global tile of this job
+  uint32_t hstride;      // row stride of hist (>= nblk)
+  uint32_t pad0;
   uint32_t *hist, *totals, *base, *item_start, *xslot, *n_items;
   uint32_t *codes, *scratch;
   uint32_t item0;        // first global apply item (written on the device)
@@ -132,6 +119,8 @@ hipError_t launch_update_jobs(const UpdJob *h_jobs, UpdJob *d_jobs, uint32_t n_j
 // ---- launchers (update.hip) ----
 hipError_t launch_fill_u32(uint32_t *p, size_t n_words, uint32_t value,
                            int grid, hipStream_t st);
+hipError_t launch_or_u32(uint32_t *dst, const uint32_t *src, size_t n_words, int grid,
+                         hipStream_t st);
 
 // ---- launchers (restore.hip) ----
 // Runs every restore step up to and including the candidate list (and, when

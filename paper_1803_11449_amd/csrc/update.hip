@@ -154,7 +154,7 @@ __global__ __launch_bounds__(1024) void k_bin_count(const UpdJob *__restrict__ j
   }
   __syncthreads();
   for (uint32_t t = threadIdx.x; t < nbins; t += blockDim.x)
-    J.hist[(size_t)t * BIN_BLOCKS_MAX + lb] = h[t];
+    J.hist[(size_t)t * J.hstride + lb] = h[t];
 }
 
 // Exclusive prefix sum over a workgroup of 1024 threads.
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(1024) void k_bin_scan_cols(const UpdJob *__restrict
   __shared__ uint32_t sh[16];
   const UpdJob &J = jobs[job_of_tile(jobs, nj, blockIdx.x)];
   const uint32_t t = blockIdx.x - J.tile0;
-  uint32_t *col = J.hist + (size_t)t * BIN_BLOCKS_MAX;
+  uint32_t *col = J.hist + (size_t)t * J.hstride;
   const uint32_t v = threadIdx.x < J.nblk ? col[threadIdx.x] : 0;
   uint32_t total;
   const uint32_t ex = blk_scan_1024(v, &total, sh);
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
   uint32_t *__restrict__ codes = J.codes;
   for (uint32_t t = threadIdx.x; t < BIN_MAX; t += blockDim.x) {
     cnt[t] = 0;
-    gcur[t] = t < nbins ? J.base[t] + J.hist[(size_t)t * BIN_BLOCKS_MAX + lb] : 0;
+    gcur[t] = t < nbins ? J.base[t] + J.hist[(size_t)t * J.hstride + lb] : 0;
   }
   __syncthreads();
   const size_t p0 = (size_t)lb * J.chunk;
@@ -493,29 +493,6 @@ hipError_t launch_update_jobs(const UpdJob *h_jobs, UpdJob *d_jobs, uint32_t n_j
     case 8: return launch_r<8>(h_jobs, d_jobs, n_jobs, d_total, binned, ppt, apply_grid, st);
     default: return hipErrorInvalidValue;
   }
-}
-
-// ------------------------------------------------------------------ fill
-
-// Word fill with 16-byte stores (a kernel rather than hipMemsetAsync, so
-// the launch sequences stay capturable into graphs).
-__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p, size_t n, uint32_t v) {
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t n4 = n / 4;
-  uint4 *p4 = reinterpret_cast<uint4 *>(p);
-  const uint4 q = make_uint4(v, v, v, v);
-  for (size_t i = tid; i < n4; i += stride) p4[i] = q;
-  for (size_t i = n4 * 4 + tid; i < n; i += stride) p[i] = v;
-}
-
-hipError_t launch_fill_u32(uint32_t *p, size_t n_words, uint32_t value, int grid,
-                           hipStream_t st) {
-  if (n_words == 0) return hipSuccess;
-  const size_t need = (n_words / 4 + 255) / 256 + 1;
-  if ((size_t)grid > need) grid = (int)need;
-  k_fill_u32<<<grid, 256, 0, st>>>(p, n_words, value);
-  return hipGetLastError();
 }
 
 }  // namespace ddhf

@@ -28,7 +28,7 @@ EXPORTS = ("sketch_params_default", "sketch_params_check", "sketch_bytes",
            "sketch_create", "sketch_destroy", "sketch_update", "sketch_restore",
            "sketch_reset", "sketch_download", "sketch_upload",
            "sketch_candidates", "sketch_last_error", "sketch_set_option",
-           "sketch_update_batch", "sketch_restore_batch")
+           "sketch_update_batch", "sketch_restore_batch", "sketch_merge")
 
 SKETCH_OPT_UPDATE_PATH = 1
 SKETCH_OPT_BINNED_MIN_PAIRS = 2
@@ -109,6 +109,7 @@ def lib() -> ctypes.CDLL:
             "sketch_set_option": (c_i32, [c_vp, c_i32, ctypes.c_int64]),
             "sketch_update_batch": (c_i32, [c_vp, c_sz, c_vp]),
             "sketch_restore_batch": (c_i32, [c_vp, c_sz, c_vp]),
+            "sketch_merge": (c_i32, [c_vp, c_vp, c_vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -219,6 +220,10 @@ def sketch_candidates(h: int, theta: float, cap: int, stream: int = 0) -> np.nda
                                  ctypes.byref(n), stream)
     _check(rc, n.value)
     return out[: n.value].copy()
+
+
+def sketch_merge(dst: int, src: int, stream: int = 0) -> None:
+    _check(lib().sketch_merge(dst, src, stream))
 
 
 def sketch_download(h: int, n_words: int, stream: int = 0) -> np.ndarray:
@@ -356,6 +361,26 @@ class Sketch:
 
     def upload(self, words: np.ndarray, stream=None) -> None:
         sketch_upload(self.handle, words, _stream_handle(stream, self.device))
+
+    def merge(self, other: "Sketch", stream=None) -> None:
+        """OR another monitor's sketch of the same window into this one."""
+        sketch_merge(self.handle, other.handle, _stream_handle(stream, self.device))
+
+    def save(self, path: str) -> None:
+        """Snapshot: the sketch words and parameters to an .npz file."""
+        p = self.params
+        np.savez(path, words=self.download(),
+                 params=np.array([p.g, p.k, p.r, p.alpha], dtype=np.uint32),
+                 seed=np.array([p.seed], dtype=np.uint64))
+
+    @classmethod
+    def load(cls, path: str, device=None) -> "Sketch":
+        """A sketch restored from a snapshot written by save()."""
+        with np.load(path, allow_pickle=False) as z:
+            g, k, r, alpha = (int(x) for x in z["params"])
+            sk = cls(g, k, r, alpha, int(z["seed"][0]), device=device)
+            sk.upload(z["words"])
+        return sk
 
     def close(self) -> None:
         if getattr(self, "handle", None):

@@ -206,6 +206,37 @@ def test_update_batch_rejects_duplicates():
         assert e.value.code == ddhf.SKETCH_E_INVAL
 
 
+def test_merge_of_two_monitors_equals_union_and_snapshot_roundtrip(tmp_path):
+    """Two monitors see disjoint halves of a window; OR-merging their
+    sketches gives the oracle's sketch of the whole window, and the merged
+    sketch restores to the oracle's list. A saved snapshot loads back
+    bit for bit."""
+    p = oracle.Params(1024, 18, 5, 5)
+    rng = np.random.default_rng(47)
+    hosts = rng.choice(2**32, size=10, replace=False).astype(np.uint32)
+    pairs = np.concatenate([rand_pairs(rng, 3_000_000, 200_000)] + planted(rng, hosts, 3000))
+    pairs = pairs[rng.permutation(len(pairs))]
+    half = len(pairs) // 2
+    with make_sketch(p) as a, make_sketch(p) as b:
+        a.update(to_dev(pairs[:half]))
+        b.update(to_dev(pairs[half:]))
+        a.merge(b)
+        torch.cuda.synchronize()
+        ref = oracle.build_sketch(p, pairs)
+        assert np.array_equal(a.download(), ref)
+        recs, _ = a.restore(1024.0)
+        ip, sz, c, _ = oracle.restore(p, ref, 1024.0, mode="brute")
+        assert_spl_equal(recs, ip, sz, c)
+        path = str(tmp_path / "snap.npz")
+        a.save(path)
+        with ddhf.Sketch.load(path, device=0) as back:
+            assert np.array_equal(back.download(), ref)
+        other = make_sketch(oracle.Params())
+        with pytest.raises(ddhf.SketchError):
+            a.merge(other)
+        other.close()
+
+
 def test_set_option_rejects_bad_values():
     with make_sketch(oracle.Params()) as sk:
         for opt, val in ((ddhf.SKETCH_OPT_UPDATE_PATH, 3), (ddhf.SKETCH_OPT_UPDATE_GRID, 0),

@@ -77,6 +77,7 @@ def test_null_handle_errors(L):
     assert L.sketch_update_batch(None, 1, None) == ddhf.SKETCH_E_INVAL
     assert L.sketch_update_batch(None, 0, None) == ddhf.SKETCH_OK
     assert L.sketch_restore_batch(None, 1, None) == ddhf.SKETCH_E_INVAL
+    assert L.sketch_merge(None, None, None) == ddhf.SKETCH_E_INVAL
     assert L.sketch_set_option(None, 1, 0) == ddhf.SKETCH_E_INVAL
     L.sketch_destroy(None)
     assert "NULL" in ddhf.last_error()

@@ -114,6 +114,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--update-path", type=int, default=0, choices=(0, 1, 2),
                     help="0 = library's choice by size, 1 = direct, 2 = binned")
+    ap.add_argument("--workload", default="large_window_100m",
+                    choices=("large_window_100m", "batched_64_links", "serving_256_links"),
+                    help="large_window_100m (default, the headline); batched_64_links: 64 "
+                         "links of uneven windows in one batched launch vs one launch per "
+                         "window; serving_256_links: Poisson window closes from 256 links, "
+                         "continuous batching vs one window at a time")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of this many MiB "
                          "(for scaling HBM counters)")
@@ -129,6 +135,11 @@ def main():
     import torch
 
     from paper_1803_11449_amd import ddhf, traffic
+
+    if args.workload == "batched_64_links":
+        return run_batched(args)
+    if args.workload == "serving_256_links":
+        return run_serving(args)
 
     dev = torch.device("cuda:0")
     spec = traffic.spec_large_window_100m(args.pairs)
@@ -240,6 +251,116 @@ def main():
                                for kk, v in cb.items()}
     sk.close()
     print(json.dumps(out), flush=True)
+
+
+def _line(metric_value, steps, warmup, ms_per_step, config, extra):
+    out = {"metric": METRIC, "value": round(metric_value, 3), "unit": "Mpps", "n_gpus": 1,
+           "steps": steps, "warmup": warmup, "ms_per_step": round(ms_per_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+           "data": "synthetic", "config": config}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def run_batched(args):
+    """64 links, each with its own sketch and one window: sizes log-uniform
+    in [1M, 200M] pairs, Zipf exponent uniform in [0.8, 1.3] (three source
+    pools at 0.8, 1.05, 1.3), theta 512 or 1024, per-link sizing rule with
+    k <= 19. A step resets every sketch, updates all windows in one batched
+    update and restores all in one batched restore; the comparison is one
+    reset/update/restore per window in turn."""
+    import math as _m
+    import numpy as np
+    import torch
+    from paper_1803_11449_amd import ddhf, serving, traffic
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(0x640)
+    exps = (0.8, 1.05, 1.3)
+    print("bench: generating 3 pools of 2^28 pairs", file=sys.stderr, flush=True)
+    pools = [serving.pair_pool(1 << 28, s, traffic.config_seed(4, i), dev)
+             for i, s in enumerate(exps)]
+    links = []
+    for _ in range(64):
+        n = int(_m.exp(rng.uniform(_m.log(1e6), _m.log(2e8))))
+        s = rng.uniform(0.8, 1.3)
+        pool = pools[int(np.argmin([abs(s - e) for e in exps]))]
+        off = int(rng.integers(0, pool.shape[0] - n + 1))
+        theta = float(rng.choice([512.0, 1024.0]))
+        k, alpha = serving.sized_params(n, k_max=19)
+        links.append((ddhf.Sketch(1024, k, 5, alpha, traffic.HASH_SEED, device=0),
+                      pool[off:off + n], theta))
+    total = sum(p.shape[0] for _, p, _ in links)
+
+    def batched():
+        for sk, _, _ in links:
+            sk.reset()
+        ddhf.update_batch([(sk, p) for sk, p, _ in links])
+        return ddhf.restore_batch([(sk, th) for sk, _, th in links])
+
+    def plain():
+        res = []
+        for sk, p, th in links:
+            sk.reset()
+            sk.update(p)
+            res.append(sk.restore(th))
+        return res
+
+    print("bench: warmup", file=sys.stderr, flush=True)
+    for _ in range(max(1, args.warmup)):
+        rb = batched()
+        rp = plain()
+    differ = sum(not np.array_equal(a[0], b[0]) for a, b in zip(rb, rp))
+    steps = max(1, min(args.steps, 5))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batched()
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plain()
+    torch.cuda.synchronize()
+    tp = (time.perf_counter() - t0) / steps
+    _line(total / tb / 1e6, steps, args.warmup, tb * 1e3,
+          {"workload": "batched_64_links", "links": 64, "pairs": total,
+           "window_pairs": "log-uniform [1e6, 2e8]", "zipf_s": "U[0.8, 1.3]",
+           "theta": "512 or 1024", "k_max": 19},
+          {"plain_mpps": round(total / tp / 1e6, 2), "plain_ms_per_step": round(tp * 1e3, 3),
+           "speedup_vs_plain": round(tp / tb, 3), "windows_differing_from_plain": differ,
+           "super_points": int(sum(len(r[0]) for r in rb))})
+    for sk, _, _ in links:
+        sk.close()
+
+
+def run_serving(args):
+    """256 links whose windows close at Poisson times: sizes log-uniform in
+    [1e5, 5e7] pairs, Zipf(1.0) sources with 0.05% planted, theta 1024, 64 GB
+    HBM budget for resident sketches. Runs at the nominal aggregate rate of
+    150 Mpps and at an overload of 20 G pairs/s; for each, continuous
+    batching and one window at a time, with close-to-report latency."""
+    import numpy as np
+    import torch
+    from paper_1803_11449_amd import serving, traffic
+    dev = torch.device("cuda:0")
+    print("bench: generating 2 pools of 2^27 pairs", file=sys.stderr, flush=True)
+    pools = [serving.pair_pool(1 << 27, 1.0, traffic.config_seed(5, i), dev) for i in range(2)]
+    res = {}
+    for name, rate, dur in (("nominal_150mpps", 1.5e8, 3.0), ("overload_20gpps", 2e10, 0.25)):
+        reqs = serving.poisson_windows(pools, 256, rate, dur, 100_000, 50_000_000,
+                                       seed=0x256, theta=(1024.0,))
+        for mode, cls in (("continuous", serving.ContinuousServer), ("plain", serving.PlainServer)):
+            print(f"bench: {name} {mode}: {len(reqs)} windows", file=sys.stderr, flush=True)
+            with cls(budget_bytes=64 << 30) as srv:
+                srv.links.prewarm(reqs)
+                out = srv.serve(reqs)
+            res[f"{name}_{mode}"] = serving.latency_summary(out)
+    ov = res["overload_20gpps_continuous"]
+    _line(ov["served_mpps"], 1, 0, ov["span_s"] * 1e3,
+          {"workload": "serving_256_links", "links": 256,
+           "window_pairs": "log-uniform [1e5, 5e7]", "hbm_budget_gb": 64, "theta": 1024},
+          {"latency_ms_p50": ov["latency_ms_p50"], "latency_ms_p99": ov["latency_ms_p99"],
+           "runs": res})
 
 
 if __name__ == "__main__":

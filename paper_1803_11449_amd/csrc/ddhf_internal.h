@@ -79,7 +79,8 @@ struct RestoreBufs {
 // is the bit offset inside its tile.
 constexpr uint32_t BIN_TILE_LOG2 = 20;               // bits per tile = 2^20
 constexpr uint32_t BIN_TILE_WORDS = 1u << 15;        // 128 KiB
-constexpr uint32_t BIN_MAX = 2048;                   // tiles (sketch <= 256 MiB)
+constexpr uint32_t BIN_MAX = 4095;                   // tiles (sketch < 512 MiB); the
+                                                     // bit index of a code stays < 2^32 - 1
 constexpr uint32_t SPLIT_MIN = 1u << 20;             // tiles above this many codes
 constexpr uint32_t APPLY_ITEM = 1u << 19;            //   are cut into items of this many
 

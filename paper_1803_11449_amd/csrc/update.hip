@@ -124,7 +124,7 @@ __device__ __forceinline__ void count_pair(const Geom &G, uint2 p, uint32_t *h) 
 
 template <int R>
 __global__ __launch_bounds__(1024) void k_bin_count(const UpdJob *__restrict__ jobs, uint32_t nj) {
-  __shared__ uint32_t h[BIN_MAX];
+  __shared__ uint32_t h[BIN_MAX + 1];
   const UpdJob &J = jobs[job_of_block(jobs, nj, blockIdx.x)];
   const Geom G = J.G;
   const uint32_t nbins = J.nbins, lb = blockIdx.x - J.blk0;
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(1024) void k_bin_scan_tiles(const UpdJob *__restric
   __shared__ uint32_t sh[16];
   const UpdJob &J = jobs[blockIdx.x];
   const uint32_t nbins = J.nbins;
-  constexpr uint32_t PER = BIN_MAX / 1024;
+  constexpr uint32_t PER = (BIN_MAX + 1) / 1024;
   const uint32_t t0 = threadIdx.x * PER;
   uint32_t c = 0, it = 0, xs = 0;
 #pragma unroll
@@ -260,22 +260,24 @@ __global__ __launch_bounds__(1024) void k_item_offsets(UpdJob *__restrict__ jobs
   if (threadIdx.x == 0) *total = tot;
 }
 
-template <int R, int PPT>
+// TMAX: tiles the LDS arrays hold (2048 or 4096), at least the jobs' tiles.
+template <int R, int PPT, int TMAX>
 __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__ jobs,
                                                       uint32_t nj) {
   constexpr uint32_t BATCH = 1024 * PPT * R;
+  constexpr uint32_t TPT = TMAX / 1024;                // tiles per thread
   __shared__ uint32_t sorted[BATCH];   // sketch bit index, grouped by tile
-  __shared__ uint32_t cnt[BIN_MAX];    // codes per tile in this batch
-  __shared__ uint32_t lofs[BIN_MAX];   // batch-local run starts
-  __shared__ uint32_t dst[BIN_MAX];    // global slot of batch entry e is dst[t] + e
-  __shared__ uint32_t gcur[BIN_MAX];   // next global slot of this block per tile
+  __shared__ uint32_t cnt[TMAX];       // codes per tile in this batch
+  __shared__ uint32_t lofs[TMAX];      // batch-local run starts
+  __shared__ uint32_t dst[TMAX];       // global slot of batch entry e is dst[t] + e
+  __shared__ uint32_t gcur[TMAX];      // next global slot of this block per tile
   __shared__ uint32_t sh[16];
   const UpdJob &J = jobs[job_of_block(jobs, nj, blockIdx.x)];
   const Geom G = J.G;
   const uint32_t nbins = J.nbins, lb = blockIdx.x - J.blk0;
   const uint2 *__restrict__ pairs = J.pairs;
   uint32_t *__restrict__ codes = J.codes;
-  for (uint32_t t = threadIdx.x; t < BIN_MAX; t += blockDim.x) {
+  for (uint32_t t = threadIdx.x; t < TMAX; t += blockDim.x) {
     cnt[t] = 0;
     gcur[t] = t < nbins ? J.base[t] + J.hist[(size_t)t * J.hstride + lb] : 0;
   }
@@ -290,7 +292,7 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
     const size_t i = p0 + (size_t)k * blockDim.x + threadIdx.x;
     nxt[k] = i < p1 ? pairs[i] : make_uint2(0, 0);
   }
-  const uint32_t ta = threadIdx.x * 2, tb = ta + 1;   // tiles this thread keeps
+  const uint32_t t0 = threadIdx.x * TPT;              // tiles this thread keeps
   for (size_t i0 = p0; i0 < p1; i0 += step) {
     uint32_t v[PPT * R], rk[PPT * R];
     uint2 cur[PPT];
@@ -319,17 +321,23 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
     }
     __syncthreads();
     // 2: run starts; dst maps a sorted position to its global slot
-    const uint32_t ca = cnt[ta], cb = cnt[tb];
+    uint32_t c[TPT], sum = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < TPT; u++) {
+      c[u] = cnt[t0 + u];
+      sum += c[u];
+    }
     uint32_t total;
-    const uint32_t ex = blk_scan_1024(ca + cb, &total, sh);
-    lofs[ta] = ex;
-    lofs[tb] = ex + ca;
-    dst[ta] = gcur[ta] - ex;
-    dst[tb] = gcur[tb] - (ex + ca);
-    gcur[ta] += ca;
-    gcur[tb] += cb;
-    cnt[ta] = 0;
-    cnt[tb] = 0;
+    uint32_t ex = blk_scan_1024(sum, &total, sh);
+#pragma unroll
+    for (uint32_t u = 0; u < TPT; u++) {
+      const uint32_t t = t0 + u;
+      lofs[t] = ex;
+      dst[t] = gcur[t] - ex;
+      gcur[t] += c[u];
+      cnt[t] = 0;
+      ex += c[u];
+    }
     __syncthreads();
     // 3: group by tile in LDS
 #pragma unroll
@@ -468,12 +476,22 @@ static hipError_t launch_r(const UpdJob *h, UpdJob *d, uint32_t nj, uint32_t *d_
   k_bin_count<R><<<blocks, 1024, 0, st>>>(d, nj);
   k_bin_scan_cols<<<tiles, 1024, 0, st>>>(d, nj);
   k_bin_scan_tiles<<<nj, 1024, 0, st>>>(d);
-  // LDS: 4*1024*PPT*r bytes of sorted codes + 32 KiB of tile arrays <= 160 KiB
-  constexpr int P4 = R <= 7 ? 4 : 2;
-  constexpr int P6 = R <= 5 ? 6 : P4;
-  if (ppt == 2) k_bin_scatter<R, 2><<<blocks, 1024, 0, st>>>(d, nj);
-  else if (ppt == 6) k_bin_scatter<R, P6><<<blocks, 1024, 0, st>>>(d, nj);
-  else k_bin_scatter<R, P4><<<blocks, 1024, 0, st>>>(d, nj);
+  // LDS: 4*1024*PPT*r bytes of sorted codes + 16*TMAX bytes of tile arrays
+  // <= 160 KiB. Up to 2048 tiles: 6 pairs per thread for r <= 5, 4 for
+  // r <= 7, else 2. Up to 4095 tiles: 4 for r <= 5, else 2.
+  uint32_t max_tiles = 0;
+  for (uint32_t j = 0; j < nj; j++) max_tiles = max_tiles > h[j].nbins ? max_tiles : h[j].nbins;
+  if (max_tiles <= 2048) {
+    constexpr int P4 = R <= 7 ? 4 : 2;
+    constexpr int P6 = R <= 5 ? 6 : P4;
+    if (ppt == 2) k_bin_scatter<R, 2, 2048><<<blocks, 1024, 0, st>>>(d, nj);
+    else if (ppt == 6) k_bin_scatter<R, P6, 2048><<<blocks, 1024, 0, st>>>(d, nj);
+    else k_bin_scatter<R, P4, 2048><<<blocks, 1024, 0, st>>>(d, nj);
+  } else {
+    constexpr int P4 = R <= 5 ? 4 : 2;
+    if (ppt == 2) k_bin_scatter<R, 2, 4096><<<blocks, 1024, 0, st>>>(d, nj);
+    else k_bin_scatter<R, P4, 4096><<<blocks, 1024, 0, st>>>(d, nj);
+  }
   k_item_offsets<<<1, 1024, 0, st>>>(d, nj, d_total);
   k_bin_apply<<<apply_grid, 1024, 0, st>>>(d, nj, d_total);
   k_bin_merge<<<dim3(tiles, BIN_TILE_WORDS / MERGE_SLICE), 256, 0, st>>>(d, nj);

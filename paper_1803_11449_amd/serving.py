@@ -1,0 +1,298 @@
+"""Serving closing windows of many monitored links on one GPU.
+
+A request is the close of one window of one link: its (src,dst) pairs are
+already in device memory; the response is the window's super point list
+(Alg. 2 restore after Alg. 1 update). Each link keeps a sketch resident on
+the device, sized for its windows by the sizing rule (smallest k >= 14 with
+n / (g 2^k) <= 0.45, alpha = ceil((32 - k) / (r - 2))).
+
+ContinuousServer batches continuously: every loop iteration admits all
+requests that have arrived, one per link and as long as the resident
+sketches fit the HBM budget, and runs their updates as one batched update
+and their restores as one batched restore. Requests that arrive while a
+batch is on the GPU wait for the next iteration, so the batch size follows
+the load. PlainServer handles one request at a time in arrival order (the
+per-window launch). Both report every request's close-to-report latency.
+
+The scheduling is host code over the batched C ABI; every step of the
+update and the restore runs in the HIP library.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from collections import OrderedDict
+
+import numpy as np
+import torch
+
+from . import ddhf, traffic
+
+
+def sized_params(n_pairs: int, g: int = 1024, r: int = 5, k_min: int = 14,
+                 k_max: int = 20, load: float = 0.45):
+    """(k, alpha) of the sizing rule for a window of n_pairs pairs."""
+    k = k_min
+    while k < k_max and n_pairs / (g * 2 ** k) > load:
+        k += 1
+    return k, math.ceil((32 - k) / (r - 2))
+
+
+def resident_bytes(g: int, k: int, r: int, alpha: int) -> int:
+    """Device memory a resident link costs: the sketch plus its per-row
+    restore arrays and per-tile update arrays (the large scratch is shared)."""
+    n_le = r << k
+    sketch = n_le * g // 8
+    rows = n_le // 8 + 3 * 4 * n_le + 8 * r * (1 << (k - alpha))
+    tiles = max(1, sketch // (128 << 10)) * 4 * (256 + 4)
+    return sketch + rows + tiles + (1 << 16)
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    link: int
+    arrival: float            # seconds after the start of serving
+    pairs: torch.Tensor       # int32 [n, 2] on the device
+    theta: float = 1024.0
+
+    @property
+    def n_pairs(self) -> int:
+        return self.pairs.shape[0]
+
+
+@dataclasses.dataclass
+class Response:
+    rid: int
+    link: int
+    records: np.ndarray       # sketch records, ascending by address
+    info: dict
+    arrival: float
+    done: float               # seconds after the start of serving
+    batch: int                # requests served in the same batch
+    n_pairs: int = 0
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class _Links:
+    """Resident sketches, one per (link, k), under an HBM budget; the least
+    recently used ones not in the current batch are evicted first."""
+
+    def __init__(self, budget_bytes: int, g: int, r: int, device: int):
+        self.budget = budget_bytes
+        self.g, self.r, self.device = g, r, device
+        self.sk: OrderedDict = OrderedDict()    # (link, k) -> (Sketch, bytes)
+        self.used = 0
+
+    def _key(self, link: int, n_pairs: int):
+        k, alpha = sized_params(n_pairs, self.g, self.r)
+        return (link, k), alpha
+
+    def need(self, link: int, n_pairs: int) -> int:
+        """Bytes a request's sketch still has to take (0 if resident)."""
+        key, alpha = self._key(link, n_pairs)
+        return 0 if key in self.sk else resident_bytes(self.g, key[1], self.r, alpha)
+
+    def fits(self, need: int, pinned: set, pending: int = 0) -> bool:
+        """Whether `need` more bytes fit next to `pending` bytes already
+        promised to this batch, evicting sketches of links not in `pinned`."""
+        free = self.budget - self.used - pending
+        free += sum(b for kk, (_, b) in self.sk.items() if kk[0] not in pinned)
+        return need <= free
+
+    def get(self, link: int, n_pairs: int, pinned: set) -> ddhf.Sketch:
+        key, alpha = self._key(link, n_pairs)
+        cur = self.sk.get(key)
+        if cur is not None:
+            self.sk.move_to_end(key)
+            return cur[0]
+        need = resident_bytes(self.g, key[1], self.r, alpha)
+        for kk in list(self.sk):
+            if self.used + need <= self.budget:
+                break
+            if kk[0] not in pinned:
+                self._drop(kk)
+        if self.used + need > self.budget:
+            raise MemoryError("link sketches exceed the HBM budget")
+        sk = ddhf.Sketch(self.g, key[1], self.r, alpha, traffic.HASH_SEED, device=self.device)
+        self.sk[key] = (sk, need)
+        self.used += need
+        return sk
+
+    def prewarm(self, requests):
+        """Create the sketches a list of requests will use (as fits)."""
+        for q in requests:
+            if self.fits(self.need(q.link, q.n_pairs), set()):
+                self.get(q.link, q.n_pairs, set())
+
+    def _drop(self, key):
+        sk, b = self.sk.pop(key)
+        sk.close()
+        self.used -= b
+
+    def close(self):
+        for kk in list(self.sk):
+            self._drop(kk)
+
+
+class _Server:
+    def __init__(self, budget_bytes: int = 64 << 30, g: int = 1024, r: int = 5,
+                 device: int = 0):
+        self.links = _Links(budget_bytes, g, r, device)
+        self.dev = torch.device("cuda", device)
+
+    def close(self):
+        self.links.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @staticmethod
+    def _wait_until(t0: float, t: float):
+        while True:
+            now = time.perf_counter() - t0
+            if now >= t:
+                return
+            if t - now > 2e-3:
+                time.sleep((t - now) / 2)
+
+
+class ContinuousServer(_Server):
+    """Continuous batching: see the module docstring."""
+
+    def __init__(self, budget_bytes: int = 64 << 30, g: int = 1024, r: int = 5,
+                 device: int = 0, max_batch: int = 64):
+        super().__init__(budget_bytes, g, r, device)
+        self.max_batch = max_batch
+
+    def serve(self, requests) -> list:
+        reqs = sorted(requests, key=lambda q: q.arrival)
+        out, waiting, nxt = [], [], 0
+        t0 = time.perf_counter()
+        while nxt < len(reqs) or waiting:
+            now = time.perf_counter() - t0
+            while nxt < len(reqs) and reqs[nxt].arrival <= now:
+                waiting.append(reqs[nxt])
+                nxt += 1
+            if not waiting:
+                self._wait_until(t0, reqs[nxt].arrival)
+                continue
+            # admit in arrival order: one request per link, within the budget
+            batch, links, pending = [], set(), 0
+            for q in waiting:
+                if len(batch) == self.max_batch:
+                    break
+                if q.link in links:
+                    continue
+                need = self.links.need(q.link, q.n_pairs)
+                if not self.links.fits(need, links | {q.link}, pending):
+                    continue
+                batch.append(q)
+                links.add(q.link)
+                pending += need
+            if not batch:          # the oldest request alone may evict anything
+                batch, links = [waiting[0]], {waiting[0].link}
+            taken = {id(q) for q in batch}
+            waiting = [q for q in waiting if id(q) not in taken]
+            sks = [self.links.get(q.link, q.n_pairs, links) for q in batch]
+            for sk in sks:
+                sk.reset()
+            ddhf.update_batch([(sk, q.pairs) for sk, q in zip(sks, batch)])
+            res = ddhf.restore_batch([(sk, q.theta) for sk, q in zip(sks, batch)])
+            done = time.perf_counter() - t0
+            for q, (recs, info) in zip(batch, res):
+                out.append(Response(q.rid, q.link, recs, info, q.arrival, done, len(batch),
+                                    q.n_pairs))
+        return sorted(out, key=lambda r: r.rid)
+
+
+class PlainServer(_Server):
+    """One request at a time, in arrival order: reset, update, restore."""
+
+    def serve(self, requests) -> list:
+        reqs = sorted(requests, key=lambda q: q.arrival)
+        out = []
+        t0 = time.perf_counter()
+        for q in reqs:
+            self._wait_until(t0, q.arrival)
+            sk = self.links.get(q.link, q.n_pairs, {q.link})
+            sk.reset()
+            sk.update(q.pairs)
+            recs, info = sk.restore(q.theta)
+            out.append(Response(q.rid, q.link, recs, info, q.arrival,
+                                time.perf_counter() - t0, 1, q.n_pairs))
+        return sorted(out, key=lambda r: r.rid)
+
+
+def serve_alone(requests, device: int = 0, g: int = 1024, r: int = 5) -> list:
+    """Every request on its own fresh sketch, no timing: the reference
+    results a served request must reproduce."""
+    out = []
+    for q in requests:
+        k, alpha = sized_params(q.n_pairs, g, r)
+        with ddhf.Sketch(g, k, r, alpha, traffic.HASH_SEED, device=device) as sk:
+            sk.update(q.pairs)
+            recs, info = sk.restore(q.theta)
+        out.append(Response(q.rid, q.link, recs, info, q.arrival, 0.0, 1, q.n_pairs))
+    return out
+
+
+# ------------------------------------------------------------------ loads
+
+def pair_pool(n_pairs: int, zipf_s: float, seed: int, device) -> torch.Tensor:
+    """A long stream of synthetic pairs that windows are cut from: Zipf(s)
+    sources over n/32 hosts with uniform destinations, 0.05% of the hosts
+    planted as super points with log-uniform cardinalities in
+    [1024, 50000] (capped at 30% of the pool)."""
+    n_src = max(1000, n_pairs // 32)
+    n_planted = max(1, int(0.0005 * n_src))
+    card = traffic._loguniform_ints(traffic.stream_key(seed, 17), n_planted, 1024, 50000)
+    while sum(card) > 0.3 * n_pairs and len(card) > 1:
+        card = card[:-1]
+    spec = traffic.WindowSpec(n_pairs=n_pairs, n_sources=n_src, zipf_s=zipf_s,
+                              planted_card=card, name="pool")
+    return traffic.generate(spec, seed, device=device).pairs
+
+
+def poisson_windows(pools, n_links: int, rate_pps: float, duration_s: float,
+                    lo: int, hi: int, seed: int, theta=(1024.0,)) -> list:
+    """Closing windows of n_links links: Poisson arrivals whose sizes are
+    log-uniform in [lo, hi] pairs, at an aggregate rate_pps pairs per second,
+    over duration_s seconds. Window pairs are slices of the given pools."""
+    rng = np.random.default_rng(seed)
+    mean = (hi - lo) / math.log(hi / lo)
+    lam = rate_pps / mean                       # windows per second
+    reqs, t, rid = [], 0.0, 0
+    while True:
+        t += rng.exponential(1.0 / lam)
+        if t > duration_s:
+            break
+        n = int(math.exp(rng.uniform(math.log(lo), math.log(hi))))
+        pool = pools[rng.integers(len(pools))]
+        off = int(rng.integers(0, pool.shape[0] - n + 1))
+        reqs.append(Request(rid, int(rng.integers(n_links)), t, pool[off:off + n],
+                            float(theta[rng.integers(len(theta))])))
+        rid += 1
+    return reqs
+
+
+def latency_summary(resps) -> dict:
+    """Close-to-report latency percentiles and the served pair rate."""
+    if not resps:
+        return {}
+    lat = np.array([r.latency for r in resps]) * 1e3
+    span = max(r.done for r in resps) - min(r.arrival for r in resps)
+    pairs = sum(r.n_pairs for r in resps)
+    return {"requests": len(resps), "pairs": pairs,
+            "latency_ms_p50": round(float(np.percentile(lat, 50)), 4),
+            "latency_ms_p99": round(float(np.percentile(lat, 99)), 4),
+            "latency_ms_max": round(float(lat.max()), 4),
+            "span_s": round(span, 4), "served_mpps": round(pairs / span / 1e6, 2),
+            "mean_batch": round(float(np.mean([r.batch for r in resps])), 2)}

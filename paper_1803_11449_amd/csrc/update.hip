@@ -37,6 +37,33 @@
 
 namespace ddhf {
 
+// Pointers read from a job table are generic to the compiler, which then
+// emits flat loads and stores; those count against the LDS wait counter too,
+// so every wait for an LDS result would also wait for all memory traffic in
+// flight. Every job buffer is device global memory: say so.
+#define GMEM __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GMEM T *gmem(T *p) {
+  return (GMEM T *)p;
+}
+// HIP's vector structs cannot be copied out of a qualified pointer: 8- and
+// 16-byte accesses go through the compiler's own vector types.
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint2 ld2(const GMEM uint2 *p) {
+  const v2u v = *reinterpret_cast<const GMEM v2u *>(p);
+  return make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ uint4 ld4(const GMEM uint4 *p) {
+  const v4u v = *reinterpret_cast<const GMEM v4u *>(p);
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st4(GMEM uint4 *p, uint4 x) {
+  v4u v;
+  v.x = x.x; v.y = x.y; v.z = x.z; v.w = x.w;
+  *reinterpret_cast<GMEM v4u *>(p) = v;
+}
+
 // ------------------------------------------------------------ job lookup
 
 __device__ __forceinline__ uint32_t job_of_block(const UpdJob *jobs, uint32_t nj, uint32_t b) {
@@ -73,12 +100,12 @@ __global__ __launch_bounds__(256) void k_update(const UpdJob *__restrict__ jobs,
   const uint32_t j = job_of_block(jobs, nj, blockIdx.x);
   const UpdJob &J = jobs[j];
   const Geom G = J.G;
-  uint32_t *__restrict__ sk = J.sk;
-  const uint2 *__restrict__ pairs = J.pairs;
+  GMEM uint32_t *__restrict__ sk = gmem(J.sk);
+  const GMEM uint2 *__restrict__ pairs = gmem(J.pairs);
   const size_t n = J.n;
   const size_t stride = (size_t)J.nblk * blockDim.x;
   for (size_t i = (size_t)(blockIdx.x - J.blk0) * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const uint2 p = pairs[i];
+    const uint2 p = ld2(pairs + i);
     const uint32_t bit = hash_h1(G, p.y);
     const uint32_t c0 = hash_dh0(G, p.x);
     const uint32_t mask = 1u << (bit & 31);
@@ -86,9 +113,9 @@ __global__ __launch_bounds__(256) void k_update(const UpdJob *__restrict__ jobs,
 #pragma unroll
     for (int row = 0; row < R; row++) {
       const uint32_t cell = row == 0 ? c0 : (bit_block(G, row, p.x) ^ c0);
-      uint32_t *w = sk + ((size_t)(((uint32_t)row << G.k) | cell) * G.wpl + wofs);
+      GMEM uint32_t *w = sk + ((size_t)(((uint32_t)row << G.k) | cell) * G.wpl + wofs);
       if (CHECK && (*w & mask)) continue;
-      atomicOr(w, mask);
+      atomicOr((uint32_t *)w, mask);    // stays a global atomic after inlining
     }
   }
 }
@@ -133,28 +160,37 @@ __global__ __launch_bounds__(1024) void k_bin_count(const UpdJob *__restrict__ j
   const size_t p0 = (size_t)lb * J.chunk;
   const size_t p1 = p0 + J.chunk < J.n ? p0 + J.chunk : J.n;
   if (p0 < p1) {
-    const uint4 *q = reinterpret_cast<const uint4 *>(J.pairs + p0);
+    const GMEM uint4 *q = gmem(reinterpret_cast<const uint4 *>(J.pairs + p0));
     const size_t nq = (p1 - p0) / 2;
     for (size_t i0 = 0; i0 < nq; i0 += (size_t)blockDim.x * COUNT_V4) {
+      // loads past the end re-read the last uint4 (no branch around them)
       uint4 v[COUNT_V4];
 #pragma unroll
       for (int u = 0; u < COUNT_V4; u++) {
         const size_t i = i0 + (size_t)u * blockDim.x + threadIdx.x;
-        v[u] = i < nq ? q[i] : make_uint4(0, 0, 0, 0);
+        v[u] = ld4(q + (i < nq ? i : nq - 1));
       }
+      if (i0 + (size_t)blockDim.x * COUNT_V4 <= nq) {
 #pragma unroll
-      for (int u = 0; u < COUNT_V4; u++) {
-        const size_t i = i0 + (size_t)u * blockDim.x + threadIdx.x;
-        if (i >= nq) continue;
-        count_pair<R>(G, make_uint2(v[u].x, v[u].y), h);
-        count_pair<R>(G, make_uint2(v[u].z, v[u].w), h);
+        for (int u = 0; u < COUNT_V4; u++) {
+          count_pair<R>(G, make_uint2(v[u].x, v[u].y), h);
+          count_pair<R>(G, make_uint2(v[u].z, v[u].w), h);
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < COUNT_V4; u++) {
+          const size_t i = i0 + (size_t)u * blockDim.x + threadIdx.x;
+          if (i >= nq) continue;
+          count_pair<R>(G, make_uint2(v[u].x, v[u].y), h);
+          count_pair<R>(G, make_uint2(v[u].z, v[u].w), h);
+        }
       }
     }
-    if (((p1 - p0) & 1) && threadIdx.x == 0) count_pair<R>(G, J.pairs[p1 - 1], h);
+    if (((p1 - p0) & 1) && threadIdx.x == 0) count_pair<R>(G, ld2(gmem(J.pairs) + (p1 - 1)), h);
   }
   __syncthreads();
-  for (uint32_t t = threadIdx.x; t < nbins; t += blockDim.x)
-    J.hist[(size_t)t * J.hstride + lb] = h[t];
+  GMEM uint32_t *hist = gmem(J.hist);
+  for (uint32_t t = threadIdx.x; t < nbins; t += blockDim.x) hist[(size_t)t * J.hstride + lb] = h[t];
 }
 
 // Exclusive prefix sum over a workgroup of 1024 threads.
@@ -190,12 +226,12 @@ __global__ __launch_bounds__(1024) void k_bin_scan_cols(const UpdJob *__restrict
   __shared__ uint32_t sh[16];
   const UpdJob &J = jobs[job_of_tile(jobs, nj, blockIdx.x)];
   const uint32_t t = blockIdx.x - J.tile0;
-  uint32_t *col = J.hist + (size_t)t * J.hstride;
+  GMEM uint32_t *col = gmem(J.hist) + (size_t)t * J.hstride;
   const uint32_t v = threadIdx.x < J.nblk ? col[threadIdx.x] : 0;
   uint32_t total;
   const uint32_t ex = blk_scan_1024(v, &total, sh);
   if (threadIdx.x < J.nblk) col[threadIdx.x] = ex;
-  if (threadIdx.x == 0) J.totals[t] = total;
+  if (threadIdx.x == 0) gmem(J.totals)[t] = total;
 }
 
 // Apply items of a tile with v codes: one if v <= SPLIT_MIN, else one per
@@ -211,13 +247,15 @@ __global__ __launch_bounds__(1024) void k_bin_scan_tiles(const UpdJob *__restric
   __shared__ uint32_t sh[16];
   const UpdJob &J = jobs[blockIdx.x];
   const uint32_t nbins = J.nbins;
+  const GMEM uint32_t *totals = gmem(J.totals);
+  GMEM uint32_t *base = gmem(J.base), *item_start = gmem(J.item_start), *xslot = gmem(J.xslot);
   constexpr uint32_t PER = (BIN_MAX + 1) / 1024;
   const uint32_t t0 = threadIdx.x * PER;
   uint32_t c = 0, it = 0, xs = 0;
 #pragma unroll
   for (uint32_t k = 0; k < PER; k++) {
     const uint32_t t = t0 + k;
-    const uint32_t v = t < nbins ? J.totals[t] : 0;
+    const uint32_t v = t < nbins ? totals[t] : 0;
     const uint32_t ni = tile_items(v);
     c += v;
     it += ni;
@@ -231,21 +269,21 @@ __global__ __launch_bounds__(1024) void k_bin_scan_tiles(const UpdJob *__restric
   for (uint32_t k = 0; k < PER; k++) {
     const uint32_t t = t0 + k;
     if (t < nbins) {
-      const uint32_t v = J.totals[t];
+      const uint32_t v = totals[t];
       const uint32_t ni = tile_items(v);
-      J.base[t] = ec;
-      J.item_start[t] = ei;
-      J.xslot[t] = ex;
+      base[t] = ec;
+      item_start[t] = ei;
+      xslot[t] = ex;
       ec += v;
       ei += ni;
       ex += ni > 1 ? ni - 1 : 0;
     }
   }
   if (threadIdx.x == 0) {
-    J.base[nbins] = tot_c;
-    J.item_start[nbins] = tot_it;
-    J.xslot[nbins] = tot_xs;
-    *J.n_items = tot_it;
+    base[nbins] = tot_c;
+    item_start[nbins] = tot_it;
+    xslot[nbins] = tot_xs;
+    *gmem(J.n_items) = tot_it;
   }
 }
 
@@ -253,11 +291,22 @@ __global__ __launch_bounds__(1024) void k_bin_scan_tiles(const UpdJob *__restric
 __global__ __launch_bounds__(1024) void k_item_offsets(UpdJob *__restrict__ jobs, uint32_t nj,
                                                        uint32_t *__restrict__ total) {
   __shared__ uint32_t sh[16];
-  const uint32_t v = threadIdx.x < nj ? *jobs[threadIdx.x].n_items : 0;
+  const uint32_t v = threadIdx.x < nj ? *gmem(jobs[threadIdx.x].n_items) : 0;
   uint32_t tot;
   const uint32_t ex = blk_scan_1024(v, &tot, sh);
   if (threadIdx.x < nj) jobs[threadIdx.x].item0 = ex;
   if (threadIdx.x == 0) *total = tot;
+}
+
+constexpr int SCATTER_UNROLL = 4;
+
+// Two 16-bit ranks per register (q is a compile-time index after unrolling).
+__device__ __forceinline__ void put_rank(uint32_t *rk2, int q, uint32_t r) {
+  if (q & 1) rk2[q >> 1] |= r << 16;
+  else rk2[q >> 1] = r;
+}
+__device__ __forceinline__ uint32_t get_rank(const uint32_t *rk2, int q) {
+  return (q & 1) ? rk2[q >> 1] >> 16 : rk2[q >> 1] & 0xFFFFu;
 }
 
 // TMAX: tiles the LDS arrays hold (2048 or 4096), at least the jobs' tiles.
@@ -275,48 +324,70 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
   const UpdJob &J = jobs[job_of_block(jobs, nj, blockIdx.x)];
   const Geom G = J.G;
   const uint32_t nbins = J.nbins, lb = blockIdx.x - J.blk0;
-  const uint2 *__restrict__ pairs = J.pairs;
-  uint32_t *__restrict__ codes = J.codes;
+  const GMEM uint2 *__restrict__ pairs = gmem(J.pairs);
+  GMEM uint32_t *__restrict__ codes = gmem(J.codes);
+  const GMEM uint32_t *base = gmem(J.base), *hist = gmem(J.hist);
   for (uint32_t t = threadIdx.x; t < TMAX; t += blockDim.x) {
     cnt[t] = 0;
-    gcur[t] = t < nbins ? J.base[t] + J.hist[(size_t)t * J.hstride + lb] : 0;
+    gcur[t] = t < nbins ? base[t] + hist[(size_t)t * J.hstride + lb] : 0;
   }
   __syncthreads();
   const size_t p0 = (size_t)lb * J.chunk;
   const size_t p1 = p0 + J.chunk < J.n ? p0 + J.chunk : J.n;
+  if (p0 >= p1) return;                                // uniform over the block
   const size_t step = (size_t)blockDim.x * PPT;
-  // the next batch's pairs are loaded while this batch is sorted and written
+  // The next batch's pairs are loaded while this batch is sorted and
+  // written. Loads past the chunk re-read its last pair (their lanes are
+  // masked later): with no branch around them the compiler can wait for
+  // the older batch alone instead of for every load in flight.
   uint2 nxt[PPT];
 #pragma unroll
   for (int k = 0; k < PPT; k++) {
     const size_t i = p0 + (size_t)k * blockDim.x + threadIdx.x;
-    nxt[k] = i < p1 ? pairs[i] : make_uint2(0, 0);
+    nxt[k] = ld2(pairs + (i < p1 ? i : p1 - 1));
   }
   const uint32_t t0 = threadIdx.x * TPT;              // tiles this thread keeps
   for (size_t i0 = p0; i0 < p1; i0 += step) {
-    uint32_t v[PPT * R], rk[PPT * R];
+    // ranks are < BATCH <= 2^15: two per register
+    uint32_t v[PPT * R], rk2[(PPT * R + 1) / 2];
     uint2 cur[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; k++) {
       cur[k] = nxt[k];
       const size_t i = i0 + step + (size_t)k * blockDim.x + threadIdx.x;
-      nxt[k] = i < p1 ? pairs[i] : make_uint2(0, 0);
+      nxt[k] = ld2(pairs + (i < p1 ? i : p1 - 1));
     }
-    // 1: codes and their rank inside their tile's run of this batch
+    // 1: codes and their rank inside their tile's run of this batch (a full
+    // batch takes no per-pair bounds test; only a chunk's last batch can be
+    // partial, and its missing pairs get the code ~0)
+    const bool full = i0 + step <= p1;
+    if (full) {
 #pragma unroll
-    for (int k = 0; k < PPT; k++) {
-      const size_t i = i0 + (size_t)k * blockDim.x + threadIdx.x;
-      if (i < p1) {
+      for (int k = 0; k < PPT; k++) {
         uint32_t B[R];
         pair_codes<R>(G, cur[k], B);
 #pragma unroll
         for (int row = 0; row < R; row++) {
           v[k * R + row] = B[row];
-          rk[k * R + row] = atomicAdd(&cnt[B[row] >> BIN_TILE_LOG2], 1u);
+          put_rank(rk2, k * R + row, atomicAdd(&cnt[B[row] >> BIN_TILE_LOG2], 1u));
         }
-      } else {
+      }
+    } else {
 #pragma unroll
-        for (int row = 0; row < R; row++) v[k * R + row] = ~0u;
+      for (int k = 0; k < PPT; k++) {
+        const size_t i = i0 + (size_t)k * blockDim.x + threadIdx.x;
+        if (i < p1) {
+          uint32_t B[R];
+          pair_codes<R>(G, cur[k], B);
+#pragma unroll
+          for (int row = 0; row < R; row++) {
+            v[k * R + row] = B[row];
+            put_rank(rk2, k * R + row, atomicAdd(&cnt[B[row] >> BIN_TILE_LOG2], 1u));
+          }
+        } else {
+#pragma unroll
+          for (int row = 0; row < R; row++) v[k * R + row] = ~0u;
+        }
       }
     }
     __syncthreads();
@@ -340,12 +411,29 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
     }
     __syncthreads();
     // 3: group by tile in LDS
+    if (full) {
 #pragma unroll
-    for (int q = 0; q < PPT * R; q++)
-      if (v[q] != ~0u) sorted[lofs[v[q] >> BIN_TILE_LOG2] + rk[q]] = v[q];
+      for (int q = 0; q < PPT * R; q++)
+        sorted[lofs[v[q] >> BIN_TILE_LOG2] + get_rank(rk2, q)] = v[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < PPT * R; q++)
+        if (v[q] != ~0u) sorted[lofs[v[q] >> BIN_TILE_LOG2] + get_rank(rk2, q)] = v[q];
+    }
     __syncthreads();
-    // 4: write the runs
-    for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
+    // 4: write the runs, SCATTER_UNROLL entries per thread at a time so
+    // their LDS reads overlap
+    uint32_t e = threadIdx.x;
+    for (; e + (SCATTER_UNROLL - 1) * 1024 < total; e += SCATTER_UNROLL * 1024) {
+      uint32_t x[SCATTER_UNROLL], d[SCATTER_UNROLL];
+#pragma unroll
+      for (int u = 0; u < SCATTER_UNROLL; u++) x[u] = sorted[e + u * 1024];
+#pragma unroll
+      for (int u = 0; u < SCATTER_UNROLL; u++) d[u] = dst[x[u] >> BIN_TILE_LOG2];
+#pragma unroll
+      for (int u = 0; u < SCATTER_UNROLL; u++) codes[d[u] + e + u * 1024] = x[u] & CODE_MASK;
+    }
+    for (; e < total; e += 1024) {
       const uint32_t x = sorted[e];
       codes[dst[x >> BIN_TILE_LOG2] + e] = x & CODE_MASK;
     }
@@ -362,25 +450,27 @@ __global__ __launch_bounds__(1024) void k_bin_apply(const UpdJob *__restrict__ j
   for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const UpdJob &J = jobs[job_of_item(jobs, nj, it)];
     const uint32_t jit = it - J.item0;
+    const GMEM uint32_t *item_start = gmem(J.item_start), *base = gmem(J.base);
     // tile of this item: the largest t with item_start[t] <= jit
     uint32_t lo = 0, hi = J.nbins;
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) >> 1;
-      if (J.item_start[mid] <= jit) lo = mid; else hi = mid;
+      if (item_start[mid] <= jit) lo = mid; else hi = mid;
     }
     const uint32_t t = lo;
-    const uint32_t sub = jit - J.item_start[t];
-    const bool whole = J.item_start[t + 1] - J.item_start[t] == 1;
-    const uint32_t c_end = J.base[t + 1];
-    const uint32_t c0 = whole ? J.base[t] : J.base[t] + sub * APPLY_ITEM;
+    const uint32_t sub = jit - item_start[t];
+    const bool whole = item_start[t + 1] - item_start[t] == 1;
+    const uint32_t c_end = base[t + 1];
+    const uint32_t c0 = whole ? base[t] : base[t] + sub * APPLY_ITEM;
     const uint32_t c1 = whole ? c_end : (c_end - c0 > APPLY_ITEM ? c0 + APPLY_ITEM : c_end);
     const size_t w0 = (size_t)t * BIN_TILE_WORDS;
     const uint32_t tw = (uint32_t)(J.words - w0 < BIN_TILE_WORDS ? J.words - w0 : BIN_TILE_WORDS);
-    const uint32_t *__restrict__ codes = J.codes;
+    const GMEM uint32_t *__restrict__ codes = gmem(J.codes);
     // the first item of a tile owns the tile; item s >= 1 of a cut tile
     // writes scratch tile xslot[t] + s - 1
-    uint32_t *dstp = sub == 0 ? J.sk + w0
-                              : J.scratch + (size_t)(J.xslot[t] + sub - 1) * BIN_TILE_WORDS;
+    GMEM uint32_t *dstp =
+        sub == 0 ? gmem(J.sk) + w0
+                 : gmem(J.scratch) + (size_t)(gmem(J.xslot)[t] + sub - 1) * BIN_TILE_WORDS;
     if (sub == 0) {
       for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) tile[w] = dstp[w];
     } else {
@@ -396,23 +486,29 @@ __global__ __launch_bounds__(1024) void k_bin_apply(const UpdJob *__restrict__ j
       const uint32_t x = codes[c];
       atomicOr(&tile[x >> 5], 1u << (x & 31));
     }
-    const uint4 *q = reinterpret_cast<const uint4 *>(codes + a0);
+    const GMEM uint4 *q = reinterpret_cast<const GMEM uint4 *>(codes + a0);
     const uint32_t nq = (a1 - a0) / 4;
-    for (uint32_t i = threadIdx.x; i < nq; i += blockDim.x * APPLY_UNROLL) {
+    // whole rounds of APPLY_UNROLL uint4 per thread with no bounds test,
+    // then the rest one uint4 at a time
+    uint32_t i = threadIdx.x;
+    for (; i + (APPLY_UNROLL - 1) * blockDim.x < nq; i += blockDim.x * APPLY_UNROLL) {
       uint4 x[APPLY_UNROLL];
 #pragma unroll
-      for (int u = 0; u < APPLY_UNROLL; u++) {
-        const uint32_t iu = i + u * blockDim.x;
-        x[u] = iu < nq ? q[iu] : make_uint4(~0u, ~0u, ~0u, ~0u);
-      }
+      for (int u = 0; u < APPLY_UNROLL; u++) x[u] = ld4(q + i + u * blockDim.x);
 #pragma unroll
       for (int u = 0; u < APPLY_UNROLL; u++) {
-        if (x[u].x == ~0u) continue;
         atomicOr(&tile[x[u].x >> 5], 1u << (x[u].x & 31));
         atomicOr(&tile[x[u].y >> 5], 1u << (x[u].y & 31));
         atomicOr(&tile[x[u].z >> 5], 1u << (x[u].z & 31));
         atomicOr(&tile[x[u].w >> 5], 1u << (x[u].w & 31));
       }
+    }
+    for (; i < nq; i += blockDim.x) {
+      const uint4 x = ld4(q + i);
+      atomicOr(&tile[x.x >> 5], 1u << (x.x & 31));
+      atomicOr(&tile[x.y >> 5], 1u << (x.y & 31));
+      atomicOr(&tile[x.z >> 5], 1u << (x.z & 31));
+      atomicOr(&tile[x.w >> 5], 1u << (x.w & 31));
     }
     for (uint32_t c = a1 + threadIdx.x; c < c1; c += blockDim.x) {
       const uint32_t x = codes[c];
@@ -431,22 +527,24 @@ constexpr uint32_t MERGE_SLICE = 4096;
 __global__ __launch_bounds__(256) void k_bin_merge(const UpdJob *__restrict__ jobs, uint32_t nj) {
   const UpdJob &J = jobs[job_of_tile(jobs, nj, blockIdx.x)];
   const uint32_t t = blockIdx.x - J.tile0;
-  const uint32_t n = J.item_start[t + 1] - J.item_start[t];
+  const GMEM uint32_t *item_start = gmem(J.item_start);
+  const uint32_t n = item_start[t + 1] - item_start[t];
   if (n <= 1) return;
   const size_t w0 = (size_t)t * BIN_TILE_WORDS;
   const uint32_t tw = (uint32_t)(J.words - w0 < BIN_TILE_WORDS ? J.words - w0 : BIN_TILE_WORDS);
   const uint32_t s_lo = blockIdx.y * MERGE_SLICE;
   const uint32_t s_hi = s_lo + MERGE_SLICE < tw ? s_lo + MERGE_SLICE : tw;
-  const uint32_t *s0 = J.scratch + (size_t)J.xslot[t] * BIN_TILE_WORDS;
-  uint32_t *sk = J.sk + w0;
+  const GMEM uint32_t *s0 = gmem(J.scratch) + (size_t)gmem(J.xslot)[t] * BIN_TILE_WORDS;
+  GMEM uint32_t *sk = gmem(J.sk) + w0;
   for (uint32_t w = s_lo + threadIdx.x * 4; w < s_hi; w += blockDim.x * 4) {
     if (w + 4 <= s_hi) {
-      uint4 v = *reinterpret_cast<const uint4 *>(sk + w);
+      uint4 v = ld4(reinterpret_cast<const GMEM uint4 *>(sk + w));
       for (uint32_t k = 1; k < n; k++) {
-        const uint4 x = *reinterpret_cast<const uint4 *>(s0 + (size_t)(k - 1) * BIN_TILE_WORDS + w);
+        const uint4 x =
+            ld4(reinterpret_cast<const GMEM uint4 *>(s0 + (size_t)(k - 1) * BIN_TILE_WORDS + w));
         v.x |= x.x; v.y |= x.y; v.z |= x.z; v.w |= x.w;
       }
-      *reinterpret_cast<uint4 *>(sk + w) = v;
+      st4(reinterpret_cast<GMEM uint4 *>(sk + w), v);
     } else {
       for (uint32_t ww = w; ww < s_hi; ww++) {
         uint32_t v = sk[ww];

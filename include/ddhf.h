@@ -178,6 +178,60 @@ typedef struct {
  * several devices): INVAL, with no job run. */
 int sketch_restore_batch(sketch_restore_job_t *jobs, size_t n_jobs, void *hip_stream);
 
+/* ---- plans: one window cycle of a fixed batch, replayed as a HIP graph ----
+ *
+ * The per-window cycle of Sec. 4 (reset the sketch, Alg. 1 over the
+ * window's pairs, Alg. 2 at the window's end) for a fixed set of distinct
+ * sketches whose pairs sit at fixed device addresses with fixed counts,
+ * such as monitored links with one staging buffer each. The launches are
+ * planned once (the same launches sketch_update_batch and
+ * sketch_restore_batch would make) and captured into one HIP graph, so a
+ * run is a single graph launch whatever the number of links and rounds.
+ *
+ * The plan owns its job tables, update arena, restore buffers and outputs
+ * and reads the sketches it was made with: destroy the plan before them,
+ * keep every job's pairs valid while the plan is used, and order a run
+ * against other work on the same sketches (same stream). Options set on a
+ * sketch after sketch_plan_create do not apply to the plan. */
+typedef struct sketch_plan sketch_plan_t;
+
+typedef struct {
+  sketch_t *sketch;
+  const uint32_t *d_pairs;   /* DEVICE memory, as for sketch_update */
+  size_t n_pairs;
+  double theta;              /* restore threshold, > 0 with SKETCH_PLAN_RESTORE */
+} sketch_plan_job_t;
+
+enum {
+  SKETCH_PLAN_RESET = 1,     /* a run starts with sketch_reset of every job */
+  SKETCH_PLAN_RESTORE = 2    /* a run ends with the restore of every job */
+};
+
+/* Plans and captures. flags: SKETCH_PLAN_* bits. Synchronous (uploads the
+ * job tables, allocates). Errors: INVAL (as sketch_update_batch, bad theta
+ * or flags, no jobs), NOMEM, HIP. */
+int sketch_plan_create(const sketch_plan_job_t *jobs, size_t n_jobs, int flags,
+                       sketch_plan_t **out);
+
+/* One run: one graph launch on hip_stream, asynchronous. */
+int sketch_plan_run(sketch_plan_t *plan, void *hip_stream);
+
+/* The last run's restore results, one slot per job in creation order
+ * (out[j].sketch must be job j's sketch; out, cap and info as in
+ * sketch_restore_batch; theta is written back). Waits for hip_stream. A
+ * job whose output overflowed the plan's buffers is restored again on its
+ * own and the buffers grow (the graph is rebuilt before the next run), so
+ * every job gets exactly what sketch_restore would give. Returns SKETCH_OK
+ * if every job succeeded, else the first failing job's code. */
+int sketch_plan_results(sketch_plan_t *plan, sketch_restore_job_t *out, size_t n_out,
+                        void *hip_stream);
+
+/* Update launches in one run (each a set of kernels over many jobs). */
+size_t sketch_plan_launches(const sketch_plan_t *plan);
+
+/* Waits for the device, frees the plan. NULL is a no-op. */
+void sketch_plan_destroy(sketch_plan_t *plan);
+
 /* Start a new window: every bit of the sketch back to 0 (Sec. 4).
  * Asynchronous on hip_stream. */
 int sketch_reset(sketch_t *s, void *hip_stream);
@@ -213,9 +267,16 @@ enum {
                                        sorting batch: 2, 4 or 6 (default);
                                        capped by LDS at 4 for r in 6..7 and
                                        at 2 for r = 8 */
-  SKETCH_OPT_BINNED_BLOCKS = 7      /* binned: blocks of the count and
+  SKETCH_OPT_BINNED_BLOCKS = 7,     /* binned: blocks of the count and
                                        scatter passes, 1..1024 (default: one
                                        per compute unit) */
+  SKETCH_OPT_TRIM_POOLS = 8         /* device-wide, acts at once: waits for
+                                       pending work on the shared buffers,
+                                       frees the update arena and reallocates
+                                       the restore pool at `value` entries per
+                                       buffer, 0..2^24 (0 = the initial sizes);
+                                       both grow again on demand. Frees device
+                                       memory for callers under a budget */
 };
 
 /* Set a tuning option; results never depend on it. Errors: INVAL (NULL

@@ -146,10 +146,10 @@ int pool_idle(DevCtx *c) {
   return SKETCH_OK;
 }
 
-int grow_partials(DevCtx *c, size_t seg_need) {
+// Restore pool buffers at exactly `cap` entries (after the pools are idle).
+int alloc_partials(DevCtx *c, size_t cap) {
   int rc = pool_idle(c);
   if (rc) return rc;
-  const size_t cap = std::max(seg_need + seg_need / 2, c->seg_cap * 2);
   dev_free(c->part[0]);
   dev_free(c->part[1]);
   c->seg_cap = 0;
@@ -159,10 +159,9 @@ int grow_partials(DevCtx *c, size_t seg_need) {
   return rc;
 }
 
-int grow_cand(DevCtx *c, size_t need) {
+int alloc_cand(DevCtx *c, size_t cap) {
   int rc = pool_idle(c);
   if (rc) return rc;
-  const size_t cap = std::max(need + need / 2, c->cand_cap * 2);
   dev_free(c->cand);
   dev_free(c->cand_sorted);
   c->cand_cap = 0;
@@ -172,16 +171,25 @@ int grow_cand(DevCtx *c, size_t need) {
   return rc;
 }
 
-int grow_pool_spl(DevCtx *c, size_t need) {
+int alloc_pool_spl(DevCtx *c, size_t cap) {
   int rc = pool_idle(c);
   if (rc) return rc;
-  const size_t cap = std::max(need + need / 2, c->spl_cap * 2);
   dev_free(c->spl);
   c->spl_cap = 0;
   rc = dev_alloc(&c->spl, cap, "records");
   if (!rc) c->spl_cap = cap;
   return rc;
 }
+
+// Growth by at least half of what was asked, at least doubling.
+size_t grown(size_t need, size_t cap) { return std::max(need + need / 2, cap * 2); }
+int grow_partials(DevCtx *c, size_t need) { return alloc_partials(c, grown(need, c->seg_cap)); }
+int grow_cand(DevCtx *c, size_t need) { return alloc_cand(c, grown(need, c->cand_cap)); }
+int grow_pool_spl(DevCtx *c, size_t need) { return alloc_pool_spl(c, grown(need, c->spl_cap)); }
+
+// Initial restore pool: partial addresses per join block, candidates, records.
+constexpr size_t POOL_SEG0 = (size_t)1 << 12, POOL_CAND0 = (size_t)1 << 16,
+                 POOL_SPL0 = (size_t)1 << 16;
 
 // Update arena for `words` code words and `tiles` scratch tiles.
 int ensure_arena(DevCtx *c, size_t words, size_t tiles) {
@@ -204,6 +212,21 @@ int ensure_arena(DevCtx *c, size_t words, size_t tiles) {
     c->scratch_tiles = tiles;
   }
   return SKETCH_OK;
+}
+
+// Free the update arena and reallocate the restore pool at `entries` per
+// buffer (0: the initial sizes). Caller holds c->mu.
+int trim_pools(DevCtx *c, size_t entries) {
+  int rc = pool_idle(c);
+  if (rc) return rc;
+  dev_free(c->codes);
+  c->codes_cap = 0;
+  dev_free(c->scratch);
+  c->scratch_tiles = 0;
+  rc = alloc_partials(c, entries ? entries : POOL_SEG0);
+  if (!rc) rc = alloc_cand(c, entries ? entries : POOL_CAND0);
+  if (!rc) rc = alloc_pool_spl(c, entries ? entries : POOL_SPL0);
+  return rc;
 }
 
 void ctx_free(DevCtx *c) {
@@ -256,9 +279,9 @@ int ctx_acquire(int dev, int n_cu, DevCtx **out) {
     if (!rc) rc = dev_alloc(&c->rank, 16384, "sort ranks");
     if (!rc) rc = dev_alloc(&c->segc[0], c->jblk, "segment counts");
     if (!rc) rc = dev_alloc(&c->segc[1], c->jblk, "segment counts");
-    if (!rc) rc = grow_partials(c, (size_t)1 << 12);
-    if (!rc) rc = grow_cand(c, (size_t)1 << 16);
-    if (!rc) rc = grow_pool_spl(c, (size_t)1 << 16);
+    if (!rc) rc = alloc_partials(c, POOL_SEG0);
+    if (!rc) rc = alloc_cand(c, POOL_CAND0);
+    if (!rc) rc = alloc_pool_spl(c, POOL_SPL0);
     if (rc) {
       ctx_free(c);
       return rc;
@@ -361,6 +384,9 @@ struct sketch {
            *bk_val = nullptr;
   uint4 *spl_sorted = nullptr;
   size_t spl_sorted_cap = 0;
+  // capacities the last enqueued restore ran with (the pools may grow
+  // between its launch and its check when restores are batched)
+  size_t ran_seg_cap = 0, ran_cand_cap = 0, ran_spl_cap = 0;
 };
 
 namespace {
@@ -461,8 +487,11 @@ int restore_launch(sketch *s, const Thresholds &t, int estimate, hipStream_t st)
   DevCtx *c = s->ctx;
   int rc = pool_enter(c, st);
   if (rc) return rc;
-  HIP_OK(launch_restore(s->G, s->d_sketch, restore_bufs(s), t.zhot, t.e_theta, estimate,
-                        s->grid, st));
+  const RestoreBufs B = restore_bufs(s);
+  s->ran_seg_cap = B.seg_cap;
+  s->ran_cand_cap = B.cand_cap;
+  s->ran_spl_cap = B.spl_cap;
+  HIP_OK(launch_restore(s->G, s->d_sketch, B, t.zhot, t.e_theta, estimate, s->grid, st));
   HIP_OK(hipMemcpyAsync(s->h_state, s->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
   return pool_leave(c, st);
 }
@@ -474,19 +503,25 @@ int restore_check(sketch *s, int estimate, bool *again) {
   DevCtx *c = s->ctx;
   *again = false;
   if (h.saturated) return SKETCH_E_SATURATED;
+  // a stage overflowed if its count passed the capacity the run had; the
+  // buffer grows only if it has not grown enough since
   size_t need_part = 0;
   for (uint32_t i = 2; i + 1 < s->p.r; i++) need_part = std::max<size_t>(need_part, h.seg_max[i]);
-  if (need_part > c->seg_cap) {
-    int rc = grow_partials(c, need_part);
-    if (rc) return rc;
+  if (need_part > s->ran_seg_cap) {
+    if (need_part > c->seg_cap) {
+      int rc = grow_partials(c, need_part);
+      if (rc) return rc;
+    }
     *again = true;
   }
-  if (h.n_cand > c->cand_cap) {
-    int rc = grow_cand(c, h.n_cand);
-    if (rc) return rc;
+  if (h.n_cand > s->ran_cand_cap) {
+    if (h.n_cand > c->cand_cap) {
+      int rc = grow_cand(c, h.n_cand);
+      if (rc) return rc;
+    }
     *again = true;
   }
-  if (estimate && h.n_spl > std::min(c->spl_cap, s->spl_sorted_cap)) {
+  if (estimate && h.n_spl > s->ran_spl_cap) {
     if (h.n_spl > c->spl_cap) {
       int rc = grow_pool_spl(c, h.n_spl);
       if (rc) return rc;
@@ -550,36 +585,50 @@ struct Group {
   std::vector<UpdJob> jobs;
 };
 
-// Launch a group's jobs (caller holds c->mu). Binned jobs get their codes
-// and scratch tiles from the arena, packed one after another.
+// Block and tile prefixes of one launch's jobs; for a binned launch, the
+// code words and scratch tiles its jobs take from an arena.
+void layout_launch(UpdJob *J, uint32_t n, bool binned, uint32_t r, size_t *words,
+                   size_t *tiles) {
+  uint32_t blk = 0, tile = 0;
+  *words = 0;
+  *tiles = 0;
+  for (uint32_t j = 0; j < n; j++) {
+    J[j].blk0 = blk;
+    J[j].tile0 = tile;
+    blk += J[j].nblk;
+    tile += J[j].nbins;
+    if (binned) {
+      const size_t w = (size_t)r * J[j].n;
+      *words += (w + 3) & ~(size_t)3;        // keep every job's codes 16-byte aligned
+      *tiles += w / APPLY_ITEM + 1;
+    }
+  }
+}
+
+// Binned jobs' codes and scratch tiles, packed one after another.
+void place_arena(UpdJob *J, uint32_t n, uint32_t r, uint32_t *codes, uint32_t *scratch) {
+  size_t wo = 0, to = 0;
+  for (uint32_t j = 0; j < n; j++) {
+    const size_t w = (size_t)r * J[j].n;
+    J[j].codes = codes + wo;
+    J[j].scratch = scratch + to * (size_t)BIN_TILE_WORDS;
+    wo += (w + 3) & ~(size_t)3;
+    to += w / APPLY_ITEM + 1;
+  }
+}
+
+// Launch a group's jobs now (caller holds c->mu), at most MAX_JOBS per
+// launch; binned jobs take the device's shared arena.
 int flush_group(DevCtx *c, Group &g, hipStream_t st) {
   for (size_t at = 0; at < g.jobs.size(); at += MAX_JOBS) {
     const uint32_t n = (uint32_t)std::min<size_t>(MAX_JOBS, g.jobs.size() - at);
     UpdJob *J = g.jobs.data() + at;
-    uint32_t blk = 0, tile = 0;
-    size_t words = 0, tiles = 0;
-    for (uint32_t j = 0; j < n; j++) {
-      J[j].blk0 = blk;
-      J[j].tile0 = tile;
-      blk += J[j].nblk;
-      tile += J[j].nbins;
-      if (g.binned) {
-        const size_t w = (size_t)g.r * J[j].n;
-        words += (w + 3) & ~(size_t)3;        // keep every job's codes 16-byte aligned
-        tiles += w / APPLY_ITEM + 1;
-      }
-    }
+    size_t words, tiles;
+    layout_launch(J, n, g.binned, g.r, &words, &tiles);
     if (g.binned) {
       int rc = ensure_arena(c, words, tiles);
       if (rc) return rc;
-      size_t wo = 0, to = 0;
-      for (uint32_t j = 0; j < n; j++) {
-        const size_t w = (size_t)g.r * J[j].n;
-        J[j].codes = c->codes + wo;
-        J[j].scratch = c->scratch + to * (size_t)BIN_TILE_WORDS;
-        wo += (w + 3) & ~(size_t)3;
-        to += w / APPLY_ITEM + 1;
-      }
+      place_arena(J, n, g.r, c->codes, c->scratch);
     }
     int rc = pool_enter(c, st);
     if (rc) return rc;
@@ -603,30 +652,31 @@ void add_job(std::vector<Group> &groups, const sketch *s, const UpdJob &J, bool 
   groups.push_back(Group{s->p.r, binned, J.check, s->scatter_ppt, s->apply_grid, {J}});
 }
 
-// The update of several distinct sketches on one device: every pair of every
-// job is applied. Binned work runs in rounds of at most ARENA_MAX_PAIRS
-// pairs in total (and a job's binned_round each).
-int update_jobs(const sketch_update_job_t *jobs, size_t n_jobs, hipStream_t st) {
-  if (n_jobs == 0) return SKETCH_OK;
-  if (!jobs) return fail(SKETCH_E_INVAL, "sketch_update_batch: NULL jobs");
+// Checks the jobs of an update of several sketches on one device.
+int check_update_jobs(const sketch_update_job_t *jobs, size_t n_jobs, const char *who) {
+  if (!jobs) return fail(SKETCH_E_INVAL, "%s: NULL jobs", who);
   const int dev = jobs[0].sketch ? jobs[0].sketch->p.device : -1;
   for (size_t j = 0; j < n_jobs; j++) {
     const sketch *s = jobs[j].sketch;
-    if (!s) return fail(SKETCH_E_INVAL, "sketch_update: NULL handle (job %zu)", j);
-    if (s->p.device != dev)
-      return fail(SKETCH_E_INVAL, "sketch_update_batch: sketches on different devices");
+    if (!s) return fail(SKETCH_E_INVAL, "%s: NULL handle (job %zu)", who, j);
+    if (s->p.device != dev) return fail(SKETCH_E_INVAL, "%s: sketches on different devices", who);
     if (jobs[j].n_pairs && !jobs[j].d_pairs)
-      return fail(SKETCH_E_INVAL, "sketch_update: NULL pairs (job %zu)", j);
+      return fail(SKETCH_E_INVAL, "%s: NULL pairs (job %zu)", who, j);
     if (((uintptr_t)jobs[j].d_pairs) & 7u)
-      return fail(SKETCH_E_INVAL, "sketch_update: pairs must be 8-byte aligned (job %zu)", j);
+      return fail(SKETCH_E_INVAL, "%s: pairs must be 8-byte aligned (job %zu)", who, j);
     for (size_t i = 0; i < j; i++)
       if (jobs[i].sketch == s)
-        return fail(SKETCH_E_INVAL, "sketch_update_batch: a sketch appears twice (jobs %zu, %zu)",
-                    i, j);
+        return fail(SKETCH_E_INVAL, "%s: a sketch appears twice (jobs %zu, %zu)", who, i, j);
   }
-  DEVICE_GUARD(dev);
-  DevCtx *c = jobs[0].sketch->ctx;
-  std::lock_guard<std::mutex> lk(c->mu);
+  return SKETCH_OK;
+}
+
+// Splits the update of several distinct sketches into launch groups and
+// hands them, in order, to flush(Group&). Binned work runs in rounds of at
+// most ARENA_MAX_PAIRS pairs in total (and a job's binned_round each); job
+// j's per-sketch arrays come from base(j).
+template <class Base, class Flush>
+int schedule_update(const sketch_update_job_t *jobs, size_t n_jobs, Base base, Flush flush) {
   std::vector<const uint32_t *> ptr(n_jobs);
   std::vector<size_t> left(n_jobs);
   std::vector<char> binned(n_jobs);
@@ -639,7 +689,7 @@ int update_jobs(const sketch_update_job_t *jobs, size_t n_jobs, hipStream_t st) 
     if (binned[j] && (((uintptr_t)ptr[j]) & 15u)) {
       // the count pass reads pairs 16 bytes at a time: the first pair goes
       // through the direct kernel so the rest starts 16-byte aligned
-      UpdJob J = job_base(s);
+      UpdJob J = base(j);
       J.pairs = reinterpret_cast<const uint2 *>(ptr[j]);
       J.n = 1;
       J.nblk = 1;
@@ -654,7 +704,7 @@ int update_jobs(const sketch_update_job_t *jobs, size_t n_jobs, hipStream_t st) 
     for (size_t j = 0; j < n_jobs; j++) {
       if (!left[j]) continue;
       sketch *s = jobs[j].sketch;
-      UpdJob J = job_base(s);
+      UpdJob J = base(j);
       J.pairs = reinterpret_cast<const uint2 *>(ptr[j]);
       if (binned[j]) {
         const size_t m = std::min({left[j], s->binned_round, room});
@@ -681,11 +731,231 @@ int update_jobs(const sketch_update_job_t *jobs, size_t n_jobs, hipStream_t st) 
       any = true;
     }
     for (Group &g : groups) {
-      int rc = flush_group(c, g, st);
+      if (g.jobs.empty()) continue;
+      int rc = flush(g);
       if (rc) return rc;
+      g.jobs.clear();
     }
     if (!any) break;
   }
+  return SKETCH_OK;
+}
+
+// The update of several distinct sketches on one device: every pair of every
+// job is applied.
+int update_jobs(const sketch_update_job_t *jobs, size_t n_jobs, hipStream_t st) {
+  if (n_jobs == 0) return SKETCH_OK;
+  int rc = check_update_jobs(jobs, n_jobs, "sketch_update");
+  if (rc) return rc;
+  DEVICE_GUARD(jobs[0].sketch->p.device);
+  DevCtx *c = jobs[0].sketch->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  return schedule_update(
+      jobs, n_jobs, [&](size_t j) { return job_base(jobs[j].sketch); },
+      [&](Group &g) { return flush_group(c, g, st); });
+}
+
+
+// ------------------------------------------------------------------ plans
+
+}  // namespace
+
+// A fixed batch captured once into a HIP graph (see sketch_plan_create).
+// The graph references only memory that lives as long as the plan: the
+// sketches (fixed at creation), their per-row restore arrays (fixed), and
+// the plan's own job tables, update arrays, arena, restore pool, device
+// states and sorted outputs. Growing a buffer rebuilds the graph.
+struct PlanJob {
+  sketch *s = nullptr;
+  const uint32_t *pairs = nullptr;
+  size_t n = 0;
+  double theta = 0;
+  Thresholds t{};
+  uint32_t *hist = nullptr, *totals = nullptr, *base = nullptr, *item_start = nullptr,
+           *xslot = nullptr, *n_items = nullptr;
+  DevState *st = nullptr;
+  DevState *h_state = nullptr;  // pinned
+  uint4 *sorted = nullptr;
+  size_t sorted_cap = 0;
+  size_t ran_spl_cap = 0;       // record capacity the graph's restore runs with
+  bool eager = false;           // this result comes from an eager rerun
+};
+
+struct PlanLaunch {
+  std::vector<UpdJob> h;
+  UpdJob *d = nullptr;
+  uint32_t *d_total = nullptr;
+  bool binned = false;
+  uint32_t r = 0, ppt = 0, apply_grid = 0;
+};
+
+struct sketch_plan {
+  int dev = -1;
+  int flags = 0;
+  DevCtx *ctx = nullptr;
+  std::vector<PlanJob> jobs;
+  std::vector<PlanLaunch> launches;
+  uint32_t *codes = nullptr, *scratch = nullptr;
+  // restore pool
+  uint32_t jblk = 0;
+  uint2 *part[2] = {};
+  uint32_t *segc[2] = {};
+  size_t seg_cap = 0;
+  uint32_t *cand = nullptr, *cand_sorted = nullptr;
+  size_t cand_cap = 0;
+  uint4 *spl = nullptr;
+  size_t spl_cap = 0;
+  uint32_t *rank = nullptr;
+  // the graph
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool dirty = true;            // buffers changed since the graph was built
+  bool ran = false;             // the graph has run at least once
+  hipStream_t run_stream = nullptr;
+  size_t ran_seg_cap = 0, ran_cand_cap = 0;   // capacities the graph runs with
+};
+
+namespace {
+
+void plan_free_graph(sketch_plan *P) {
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  P->exec = nullptr;
+  P->graph = nullptr;
+  P->dirty = true;
+}
+
+void plan_free(sketch_plan *P) {
+  plan_free_graph(P);
+  if (P->cap) (void)hipStreamDestroy(P->cap);
+  for (PlanJob &j : P->jobs) {
+    dev_free(j.hist);
+    dev_free(j.totals);
+    dev_free(j.base);
+    dev_free(j.item_start);
+    dev_free(j.xslot);
+    dev_free(j.n_items);
+    dev_free(j.st);
+    dev_free(j.sorted);
+    if (j.h_state) (void)hipHostFree(j.h_state);
+  }
+  for (PlanLaunch &L : P->launches) {
+    dev_free(L.d);
+    dev_free(L.d_total);
+  }
+  dev_free(P->codes);
+  dev_free(P->scratch);
+  dev_free(P->part[0]);
+  dev_free(P->part[1]);
+  dev_free(P->segc[0]);
+  dev_free(P->segc[1]);
+  dev_free(P->cand);
+  dev_free(P->cand_sorted);
+  dev_free(P->spl);
+  dev_free(P->rank);
+  ctx_release(P->ctx);
+  P->ctx = nullptr;
+}
+
+int plan_alloc_partials(sketch_plan *P, size_t cap) {
+  dev_free(P->part[0]);
+  dev_free(P->part[1]);
+  P->seg_cap = 0;
+  int rc = dev_alloc(&P->part[0], cap * P->jblk, "plan partials");
+  if (!rc) rc = dev_alloc(&P->part[1], cap * P->jblk, "plan partials");
+  if (!rc) P->seg_cap = cap;
+  return rc;
+}
+
+int plan_alloc_cand(sketch_plan *P, size_t cap) {
+  dev_free(P->cand);
+  dev_free(P->cand_sorted);
+  P->cand_cap = 0;
+  int rc = dev_alloc(&P->cand, cap, "plan candidates");
+  if (!rc) rc = dev_alloc(&P->cand_sorted, cap, "plan candidates");
+  if (!rc) P->cand_cap = cap;
+  return rc;
+}
+
+int plan_alloc_spl(sketch_plan *P, size_t cap) {
+  dev_free(P->spl);
+  P->spl_cap = 0;
+  int rc = dev_alloc(&P->spl, cap, "plan records");
+  if (!rc) P->spl_cap = cap;
+  return rc;
+}
+
+int plan_alloc_sorted(PlanJob &j, size_t cap) {
+  dev_free(j.sorted);
+  j.sorted_cap = 0;
+  int rc = dev_alloc(&j.sorted, cap, "plan sorted records");
+  if (!rc) j.sorted_cap = cap;
+  return rc;
+}
+
+RestoreBufs plan_restore_bufs(const sketch_plan *P, const PlanJob &j) {
+  const sketch *s = j.s;
+  RestoreBufs B{};
+  B.st = j.st;
+  B.hotmask = s->hotmask;
+  B.he = s->he;
+  B.bk_off = s->bk_off;
+  B.bk_cur = s->bk_cur;
+  B.bk_val = s->bk_val;
+  B.part[0] = P->part[0];
+  B.part[1] = P->part[1];
+  B.segc[0] = P->segc[0];
+  B.segc[1] = P->segc[1];
+  B.seg_cap = P->seg_cap;
+  B.jblk = P->jblk;
+  B.cand = P->cand;
+  B.cand_sorted = P->cand_sorted;
+  B.cand_cap = P->cand_cap;
+  B.spl = P->spl;
+  B.spl_sorted = j.sorted;
+  B.spl_cap = std::min(P->spl_cap, j.sorted_cap);
+  B.rank = P->rank;
+  return B;
+}
+
+// Enqueue one whole run on st: resets, update launches, restores and the
+// copies of the device states (only plan-owned or fixed memory).
+int plan_enqueue(sketch_plan *P, hipStream_t st) {
+  if (P->flags & SKETCH_PLAN_RESET)
+    for (PlanJob &j : P->jobs)
+      HIP_OK(launch_fill_u32(j.s->d_sketch, j.s->words, 0u, j.s->grid * 4, st));
+  for (PlanLaunch &L : P->launches)
+    HIP_OK(launch_update_jobs(L.h.data(), L.d, (uint32_t)L.h.size(), L.d_total, L.binned, L.r,
+                              L.ppt, L.apply_grid, st));
+  if (P->flags & SKETCH_PLAN_RESTORE)
+    for (PlanJob &j : P->jobs) {
+      HIP_OK(launch_restore(j.s->G, j.s->d_sketch, plan_restore_bufs(P, j), j.t.zhot,
+                            j.t.e_theta, 1, j.s->grid, st));
+      HIP_OK(hipMemcpyAsync(j.h_state, j.st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+    }
+  return SKETCH_OK;
+}
+
+// (Re)capture the graph of a run.
+int plan_build_graph(sketch_plan *P) {
+  plan_free_graph(P);
+  HIP_OK(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
+  int rc = plan_enqueue(P, P->cap);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(P->cap, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess)
+    return fail(SKETCH_E_HIP, "plan: capture failed: %s", hipGetErrorString(e));
+  P->graph = g;
+  HIP_OK(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
+  P->ran_seg_cap = P->seg_cap;
+  P->ran_cand_cap = P->cand_cap;
+  for (PlanJob &j : P->jobs) j.ran_spl_cap = std::min(P->spl_cap, j.sorted_cap);
+  P->dirty = false;
   return SKETCH_OK;
 }
 
@@ -975,6 +1245,12 @@ int sketch_set_option(sketch_t *s, int option, int64_t value) {
       if (value < 1024 || (uint64_t)value > ARENA_MAX_PAIRS) break;
       s->binned_round = (size_t)value;
       return SKETCH_OK;
+    case SKETCH_OPT_TRIM_POOLS: {
+      if (value < 0 || value > (1 << 24)) break;
+      DEVICE_GUARD(s->p.device);
+      std::lock_guard<std::mutex> lk(s->ctx->mu);
+      return trim_pools(s->ctx, (size_t)value);
+    }
     default:
       return fail(SKETCH_E_INVAL, "sketch_set_option: unknown option %d", option);
   }
@@ -1002,6 +1278,230 @@ int sketch_upload(sketch_t *s, const uint32_t *host_words, size_t n_words, void 
   HIP_OK(hipMemcpyAsync(s->d_sketch, host_words, n_words * 4, hipMemcpyHostToDevice, st));
   HIP_OK(hipStreamSynchronize(st));
   return SKETCH_OK;
+}
+
+
+// ------------------------------------------------------------------ plans
+
+int sketch_plan_create(const sketch_plan_job_t *jobs, size_t n_jobs, int flags,
+                       sketch_plan_t **out) {
+  if (!out) return fail(SKETCH_E_INVAL, "sketch_plan_create: out is NULL");
+  *out = nullptr;
+  if (n_jobs == 0 || !jobs) return fail(SKETCH_E_INVAL, "sketch_plan_create: no jobs");
+  if (flags & ~(SKETCH_PLAN_RESET | SKETCH_PLAN_RESTORE))
+    return fail(SKETCH_E_INVAL, "sketch_plan_create: unknown flags 0x%x", flags);
+  std::vector<sketch_update_job_t> uj(n_jobs);
+  for (size_t j = 0; j < n_jobs; j++) {
+    uj[j] = sketch_update_job_t{jobs[j].sketch, jobs[j].d_pairs, jobs[j].n_pairs};
+    if ((flags & SKETCH_PLAN_RESTORE) && (!(jobs[j].theta > 0.0) || !isfinite(jobs[j].theta)))
+      return fail(SKETCH_E_INVAL, "sketch_plan_create: theta must be finite and > 0 (job %zu)",
+                  j);
+  }
+  int rc = check_update_jobs(uj.data(), n_jobs, "sketch_plan_create");
+  if (rc) return rc;
+  const int dev = jobs[0].sketch->p.device;
+  DEVICE_GUARD(dev);
+  DevCtx *c = jobs[0].sketch->ctx;
+  sketch_plan *P = new sketch_plan();
+  P->dev = dev;
+  P->flags = flags;
+  {
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
+    c->refs++;
+  }
+  P->ctx = c;
+  P->jblk = c->jblk;
+  P->jobs.resize(n_jobs);
+  for (size_t j = 0; j < n_jobs && !rc; j++) {
+    PlanJob &pj = P->jobs[j];
+    sketch *s = jobs[j].sketch;
+    pj.s = s;
+    pj.pairs = jobs[j].d_pairs;
+    pj.n = jobs[j].n_pairs;
+    pj.theta = jobs[j].theta;
+    pj.t = thresholds(s, pj.theta > 0 ? pj.theta : 1.0);
+    if (s->nbins <= BIN_MAX) {
+      rc = dev_alloc(&pj.hist, (size_t)s->nbins * s->bin_nblk, "plan tile counts");
+      if (!rc) rc = dev_alloc(&pj.totals, s->nbins, "plan tile totals");
+      if (!rc) rc = dev_alloc(&pj.base, s->nbins + 1, "plan tile runs");
+      if (!rc) rc = dev_alloc(&pj.item_start, s->nbins + 1, "plan tile items");
+      if (!rc) rc = dev_alloc(&pj.xslot, s->nbins + 1, "plan tile scratch slots");
+      if (!rc) rc = dev_alloc(&pj.n_items, 1, "plan tile item count");
+    }
+    if (!rc) rc = dev_alloc(&pj.st, 1, "plan state");
+    if (!rc) rc = plan_alloc_sorted(pj, std::max<size_t>(s->spl_sorted_cap, (size_t)1 << 12));
+    if (!rc && hipHostMalloc((void **)&pj.h_state, sizeof(DevState)) != hipSuccess) {
+      pj.h_state = nullptr;
+      rc = fail(SKETCH_E_NOMEM, "hipHostMalloc(plan state) failed");
+    }
+  }
+  // the update launches, with this plan's per-job arrays
+  size_t max_words = 0, max_tiles = 0;
+  if (!rc) {
+    std::lock_guard<std::mutex> lk(c->mu);
+    rc = schedule_update(
+        uj.data(), n_jobs,
+        [&](size_t j) {
+          UpdJob J = job_base(uj[j].sketch);
+          const PlanJob &pj = P->jobs[j];
+          J.hist = pj.hist;
+          J.totals = pj.totals;
+          J.base = pj.base;
+          J.item_start = pj.item_start;
+          J.xslot = pj.xslot;
+          J.n_items = pj.n_items;
+          return J;
+        },
+        [&](Group &g) {
+          for (size_t at = 0; at < g.jobs.size(); at += MAX_JOBS) {
+            const uint32_t n = (uint32_t)std::min<size_t>(MAX_JOBS, g.jobs.size() - at);
+            PlanLaunch L;
+            L.h.assign(g.jobs.begin() + at, g.jobs.begin() + at + n);
+            size_t words, tiles;
+            layout_launch(L.h.data(), n, g.binned, g.r, &words, &tiles);
+            max_words = std::max(max_words, words);
+            max_tiles = std::max(max_tiles, tiles);
+            L.binned = g.binned;
+            L.r = g.r;
+            L.ppt = g.ppt;
+            L.apply_grid = g.apply_grid;
+            P->launches.push_back(std::move(L));
+          }
+          return SKETCH_OK;
+        });
+  }
+  if (!rc && max_words) rc = dev_alloc(&P->codes, max_words, "plan update codes");
+  if (!rc && max_tiles)
+    rc = dev_alloc(&P->scratch, max_tiles * (size_t)BIN_TILE_WORDS, "plan scratch tiles");
+  for (size_t i = 0; i < P->launches.size() && !rc; i++) {
+    PlanLaunch &L = P->launches[i];
+    if (L.binned) place_arena(L.h.data(), (uint32_t)L.h.size(), L.r, P->codes, P->scratch);
+    rc = dev_alloc(&L.d, L.h.size(), "plan job table");
+    if (!rc) rc = dev_alloc(&L.d_total, 1, "plan item total");
+    if (!rc) {
+      hipError_t e = hipMemcpy(L.d, L.h.data(), sizeof(UpdJob) * L.h.size(),
+                               hipMemcpyHostToDevice);
+      if (e != hipSuccess) rc = fail(SKETCH_E_HIP, "plan: job table upload: %s",
+                                     hipGetErrorString(e));
+    }
+  }
+  if (!rc) rc = dev_alloc(&P->rank, 16384, "plan sort ranks");
+  if (!rc) rc = dev_alloc(&P->segc[0], P->jblk, "plan segment counts");
+  if (!rc) rc = dev_alloc(&P->segc[1], P->jblk, "plan segment counts");
+  if (!rc) rc = plan_alloc_partials(P, std::max<size_t>(c->seg_cap, 16));
+  if (!rc) rc = plan_alloc_cand(P, std::max<size_t>(c->cand_cap, 16));
+  if (!rc) rc = plan_alloc_spl(P, std::max<size_t>(c->spl_cap, 16));
+  if (!rc && hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking) != hipSuccess) {
+    P->cap = nullptr;
+    rc = fail(SKETCH_E_HIP, "plan: hipStreamCreate failed");
+  }
+  if (!rc) rc = plan_build_graph(P);
+  if (rc) {
+    plan_free(P);
+    delete P;
+    return rc;
+  }
+  *out = P;
+  return SKETCH_OK;
+}
+
+int sketch_plan_run(sketch_plan_t *P, void *hip_stream) {
+  if (!P) return fail(SKETCH_E_INVAL, "sketch_plan_run: NULL plan");
+  DEVICE_GUARD(P->dev);
+  if (P->dirty) {
+    if (P->ran) HIP_OK(hipStreamSynchronize(P->run_stream));   // the old graph is done
+    int rc = plan_build_graph(P);
+    if (rc) return rc;
+  }
+  HIP_OK(hipGraphLaunch(P->exec, (hipStream_t)hip_stream));
+  P->ran = true;
+  P->run_stream = (hipStream_t)hip_stream;
+  return SKETCH_OK;
+}
+
+int sketch_plan_results(sketch_plan_t *P, sketch_restore_job_t *out, size_t n_out,
+                        void *hip_stream) {
+  if (!P) return fail(SKETCH_E_INVAL, "sketch_plan_results: NULL plan");
+  if (!(P->flags & SKETCH_PLAN_RESTORE))
+    return fail(SKETCH_E_INVAL, "sketch_plan_results: the plan has no restore");
+  if (n_out != P->jobs.size() || !out)
+    return fail(SKETCH_E_INVAL, "sketch_plan_results: need %zu result slots", P->jobs.size());
+  for (size_t j = 0; j < n_out; j++) {
+    if (out[j].sketch != P->jobs[j].s)
+      return fail(SKETCH_E_INVAL, "sketch_plan_results: slot %zu is for another sketch", j);
+    if (out[j].cap && !out[j].out)
+      return fail(SKETCH_E_INVAL, "sketch_plan_results: NULL out with cap > 0 (slot %zu)", j);
+  }
+  if (!P->ran) return fail(SKETCH_E_INVAL, "sketch_plan_results: the plan has not run");
+  DEVICE_GUARD(P->dev);
+  hipStream_t st = (hipStream_t)hip_stream;
+  HIP_OK(hipStreamSynchronize(P->run_stream));
+  HIP_OK(hipStreamSynchronize(st));
+  std::lock_guard<std::mutex> lk(P->ctx->mu);
+  int first_err = SKETCH_OK;
+  for (size_t j = 0; j < n_out; j++) {
+    PlanJob &pj = P->jobs[j];
+    sketch *s = pj.s;
+    sketch_restore_job_t &J = out[j];
+    J.theta = pj.theta;
+    const DevState *h = pj.h_state;
+    const uint4 *src = pj.sorted;
+    int rc = SKETCH_OK;
+    pj.eager = false;
+    if (h->saturated) {
+      rc = SKETCH_E_SATURATED;
+    } else {
+      size_t need_part = 0;
+      for (uint32_t i = 2; i + 1 < s->p.r; i++)
+        need_part = std::max<size_t>(need_part, h->seg_max[i]);
+      // a stage overflowed if its count passed the capacity the graph ran
+      // with; buffers grow (for the next runs) only if not grown enough yet
+      const bool over_part = need_part > P->ran_seg_cap, over_cand = h->n_cand > P->ran_cand_cap,
+                 over_spl = h->n_spl > pj.ran_spl_cap;
+      if (over_part || over_cand || over_spl) {
+        int g = SKETCH_OK;
+        if (need_part > P->seg_cap) g = plan_alloc_partials(P, grown(need_part, P->seg_cap));
+        if (!g && h->n_cand > P->cand_cap) g = plan_alloc_cand(P, grown(h->n_cand, P->cand_cap));
+        if (!g && h->n_spl > P->spl_cap) g = plan_alloc_spl(P, grown(h->n_spl, P->spl_cap));
+        if (!g && h->n_spl > pj.sorted_cap)
+          g = plan_alloc_sorted(pj, grown(h->n_spl, pj.sorted_cap));
+        if (P->seg_cap != P->ran_seg_cap || P->cand_cap != P->ran_cand_cap ||
+            std::min(P->spl_cap, pj.sorted_cap) != pj.ran_spl_cap)
+          P->dirty = true;
+        // this run's result: the job restored again on its own
+        rc = g ? g : run_restore(s, pj.t, 1, st);
+        h = s->h_state;
+        src = s->spl_sorted;
+        pj.eager = true;
+      }
+    }
+    if (rc == SKETCH_OK || rc == SKETCH_E_SATURATED) fill_info(s, *h, pj.t.zmin, pj.t.zhot, J.info);
+    J.n_out = rc == SKETCH_OK ? (size_t)h->n_spl : 0;
+    if (rc == SKETCH_OK && h->n_spl > J.cap) rc = SKETCH_E_CAPACITY;
+    if (rc == SKETCH_OK && h->n_spl) {
+      hipError_t e = hipMemcpyAsync(J.out, src, h->n_spl * sizeof(uint4), hipMemcpyDeviceToHost,
+                                    st);
+      // an eager rerun's output is the sketch's own buffer: copy it out now
+      if (e == hipSuccess && pj.eager) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) rc = SKETCH_E_HIP;
+    }
+    J.status = rc;
+    if (rc && !first_err) first_err = rc;
+  }
+  HIP_OK(hipStreamSynchronize(st));
+  if (first_err)
+    return fail(first_err, "sketch_plan_results: a job failed (see each job's status)");
+  return SKETCH_OK;
+}
+
+size_t sketch_plan_launches(const sketch_plan_t *P) { return P ? P->launches.size() : 0; }
+
+void sketch_plan_destroy(sketch_plan_t *P) {
+  if (!P) return;
+  DeviceGuard guard(P->dev);
+  (void)hipDeviceSynchronize();
+  plan_free(P);
+  delete P;
 }
 
 const char *sketch_last_error(void) { return g_err.c_str(); }

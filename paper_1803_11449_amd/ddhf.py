@@ -28,7 +28,12 @@ EXPORTS = ("sketch_params_default", "sketch_params_check", "sketch_bytes",
            "sketch_create", "sketch_destroy", "sketch_update", "sketch_restore",
            "sketch_reset", "sketch_download", "sketch_upload",
            "sketch_candidates", "sketch_last_error", "sketch_set_option",
-           "sketch_update_batch", "sketch_restore_batch", "sketch_merge")
+           "sketch_update_batch", "sketch_restore_batch", "sketch_merge",
+           "sketch_plan_create", "sketch_plan_run", "sketch_plan_results",
+           "sketch_plan_launches", "sketch_plan_destroy")
+
+SKETCH_PLAN_RESET = 1
+SKETCH_PLAN_RESTORE = 2
 
 SKETCH_OPT_UPDATE_PATH = 1
 SKETCH_OPT_BINNED_MIN_PAIRS = 2
@@ -37,6 +42,7 @@ SKETCH_OPT_UPDATE_CHECK = 4
 SKETCH_OPT_BINNED_ROUND = 5
 SKETCH_OPT_SCATTER_PPT = 6
 SKETCH_OPT_BINNED_BLOCKS = 7
+SKETCH_OPT_TRIM_POOLS = 8
 
 c_u32, c_u64, c_i32, c_sz, c_dbl, c_vp = (ctypes.c_uint32, ctypes.c_uint64,
                                           ctypes.c_int32, ctypes.c_size_t,
@@ -62,6 +68,10 @@ class sketch_info_t(ctypes.Structure):
 
 class sketch_update_job_t(ctypes.Structure):
     _fields_ = [("sketch", c_vp), ("d_pairs", c_vp), ("n_pairs", c_sz)]
+
+
+class sketch_plan_job_t(ctypes.Structure):
+    _fields_ = [("sketch", c_vp), ("d_pairs", c_vp), ("n_pairs", c_sz), ("theta", c_dbl)]
 
 
 class sketch_restore_job_t(ctypes.Structure):
@@ -110,6 +120,11 @@ def lib() -> ctypes.CDLL:
             "sketch_update_batch": (c_i32, [c_vp, c_sz, c_vp]),
             "sketch_restore_batch": (c_i32, [c_vp, c_sz, c_vp]),
             "sketch_merge": (c_i32, [c_vp, c_vp, c_vp]),
+            "sketch_plan_create": (c_i32, [c_vp, c_sz, c_i32, P(c_vp)]),
+            "sketch_plan_run": (c_i32, [c_vp, c_vp]),
+            "sketch_plan_results": (c_i32, [c_vp, c_vp, c_sz, c_vp]),
+            "sketch_plan_launches": (c_sz, [c_vp]),
+            "sketch_plan_destroy": (None, [c_vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -213,6 +228,44 @@ def sketch_restore_batch(items, stream: int = 0):
     return res
 
 
+def sketch_plan_create(jobs, flags: int) -> int:
+    """jobs: sequence of (handle, d_pairs, n_pairs, theta). Returns the plan."""
+    arr = (sketch_plan_job_t * max(1, len(jobs)))()
+    for i, (h, ptr, n, theta) in enumerate(jobs):
+        arr[i] = sketch_plan_job_t(h, ptr, n, float(theta))
+    out = c_vp()
+    _check(lib().sketch_plan_create(ctypes.cast(arr, c_vp), len(jobs), flags,
+                                    ctypes.byref(out)))
+    return out.value
+
+
+def sketch_plan_run(plan: int, stream: int = 0) -> None:
+    _check(lib().sketch_plan_run(plan, stream))
+
+
+def sketch_plan_results(plan: int, items, stream: int = 0):
+    """items: sequence of (handle, cap) in job order. Returns a list of
+    (records, info, status, n_needed)."""
+    n = len(items)
+    arr = (sketch_restore_job_t * max(1, n))()
+    outs, infos = [], []
+    for i, (h, cap) in enumerate(items):
+        out = np.zeros(max(cap, 1), dtype=SP_DTYPE)
+        info = sketch_info_t()
+        outs.append(out)
+        infos.append(info)
+        arr[i] = sketch_restore_job_t(h, 0.0, out.ctypes.data, cap, ctypes.addressof(info), 0, 0)
+    rc = lib().sketch_plan_results(plan, ctypes.cast(arr, c_vp), n, stream)
+    if rc == SKETCH_E_INVAL and all(arr[i].status == 0 for i in range(n)):
+        raise SketchError(rc, last_error())
+    res = []
+    for i in range(n):
+        st = arr[i].status
+        recs = outs[i][: arr[i].n_out].copy() if st == SKETCH_OK else outs[i][:0].copy()
+        res.append((recs, info_dict(infos[i]), st, arr[i].n_out))
+    return res
+
+
 def sketch_candidates(h: int, theta: float, cap: int, stream: int = 0) -> np.ndarray:
     out = np.zeros(max(cap, 1), dtype=np.uint32)
     n = c_sz(0)
@@ -301,6 +354,67 @@ def restore_batch(items, stream=None):
         for i, r in zip(retry, again):
             out[i] = r
     return out
+
+
+class Plan:
+    """A fixed batch's window cycle as one HIP graph (sketch_plan_*).
+
+    items: sequence of (Sketch, pairs tensor, theta). The tensors must stay
+    alive and in place while the plan is used; close the plan before its
+    sketches."""
+
+    def __init__(self, items, reset: bool = True, restore: bool = True):
+        for _, t, _ in items:
+            _check_pairs(t)
+        self.items = list(items)
+        self.device = self.items[0][0].device
+        flags = (SKETCH_PLAN_RESET if reset else 0) | (SKETCH_PLAN_RESTORE if restore else 0)
+        self.handle = sketch_plan_create(
+            [(sk.handle, t.data_ptr(), t.numel() // 2, th) for sk, t, th in self.items], flags)
+
+    @property
+    def launches(self) -> int:
+        return lib().sketch_plan_launches(self.handle)
+
+    def run(self, stream=None) -> None:
+        sketch_plan_run(self.handle, _stream_handle(stream, self.device))
+
+    def results(self, stream=None):
+        """[(records, info)] of the last run, in item order."""
+        s = _stream_handle(stream, self.device)
+        while True:
+            res = sketch_plan_results(self.handle, [(sk.handle, sk._cap)
+                                                    for sk, _, _ in self.items], s)
+            retry = False
+            for (sk, _, _), (_, _, st, need) in zip(self.items, res):
+                if st == SKETCH_E_CAPACITY:
+                    sk._cap = max(int(need) + 64, 2 * sk._cap)
+                    retry = True
+                elif st != SKETCH_OK:
+                    raise SketchError(st, "plan result failed")
+            if not retry:
+                return [(recs, info) for recs, info, _, _ in res]
+
+    def close(self) -> None:
+        if self.handle:
+            sketch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sketch_plan_destroy(plan: int) -> None:
+    lib().sketch_plan_destroy(plan)
 
 
 class Sketch:

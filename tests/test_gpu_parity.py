@@ -197,6 +197,33 @@ def test_restore_batch_equals_single_restores():
         sk.close()
 
 
+def test_restore_batch_after_pools_grow_midway():
+    """Batched restores against tiny shared buffers: an earlier job grows
+    them, so a later job that overflowed the size it ran with must run again
+    (and match the oracle) rather than be judged by the grown size."""
+    p = oracle.Params()
+    rng = np.random.default_rng(53)
+    sks, refs = [], []
+    for m in (6, 12, 18, 22, 26, 30, 40):
+        hosts = rng.choice(2**32, size=m, replace=False).astype(np.uint32)
+        pairs = np.concatenate([rand_pairs(rng, 400_000, 20_000)] + planted(rng, hosts, 2500))
+        sk = make_sketch(p)
+        sk.update(to_dev(pairs))
+        sks.append(sk)
+        refs.append(oracle.restore(p, oracle.build_sketch(p, pairs), 0.7 * p.g))
+    say("restore batch of 7 windows, pools trimmed to 16 entries")
+    sks[0].set_option(ddhf.SKETCH_OPT_TRIM_POOLS, 16)
+    try:
+        res = ddhf.restore_batch([(sk, 0.7 * p.g) for sk in sks])
+        for (recs, info), (ip, sz, c, _) in zip(res, refs):
+            assert len(ip) >= 6
+            assert_spl_equal(recs, ip, sz, c)
+    finally:
+        sks[0].set_option(ddhf.SKETCH_OPT_TRIM_POOLS, 0)
+        for sk in sks:
+            sk.close()
+
+
 def test_update_batch_rejects_duplicates():
     p = oracle.Params()
     with make_sketch(p) as sk:
@@ -240,7 +267,8 @@ def test_merge_of_two_monitors_equals_union_and_snapshot_roundtrip(tmp_path):
 def test_set_option_rejects_bad_values():
     with make_sketch(oracle.Params()) as sk:
         for opt, val in ((ddhf.SKETCH_OPT_UPDATE_PATH, 3), (ddhf.SKETCH_OPT_UPDATE_GRID, 0),
-                         (ddhf.SKETCH_OPT_BINNED_ROUND, 10), (99, 1)):
+                         (ddhf.SKETCH_OPT_BINNED_ROUND, 10),
+                         (ddhf.SKETCH_OPT_TRIM_POOLS, -1), (99, 1)):
             with pytest.raises(ddhf.SketchError) as e:
                 sk.set_option(opt, val)
             assert e.value.code == ddhf.SKETCH_E_INVAL

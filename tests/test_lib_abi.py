@@ -42,6 +42,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(ddhf.sketch_info_t) == 216
     assert ctypes.sizeof(ddhf.sketch_update_job_t) == 24
     assert ctypes.sizeof(ddhf.sketch_restore_job_t) == 56
+    assert ctypes.sizeof(ddhf.sketch_plan_job_t) == 32
 
 
 def test_params_default_check_and_bytes(L):
@@ -81,3 +82,10 @@ def test_null_handle_errors(L):
     assert L.sketch_set_option(None, 1, 0) == ddhf.SKETCH_E_INVAL
     L.sketch_destroy(None)
     assert "NULL" in ddhf.last_error()
+    out = ctypes.c_void_p()
+    assert L.sketch_plan_create(None, 0, 3, ctypes.byref(out)) == ddhf.SKETCH_E_INVAL
+    assert L.sketch_plan_create(None, 1, 3, None) == ddhf.SKETCH_E_INVAL
+    assert L.sketch_plan_run(None, None) == ddhf.SKETCH_E_INVAL
+    assert L.sketch_plan_results(None, None, 0, None) == ddhf.SKETCH_E_INVAL
+    assert L.sketch_plan_launches(None) == 0
+    L.sketch_plan_destroy(None)

@@ -262,74 +262,105 @@ def _line(metric_value, steps, warmup, ms_per_step, config, extra):
     print(json.dumps(out), flush=True)
 
 
-def run_batched(args):
-    """64 links, each with its own sketch and one window: sizes log-uniform
-    in [1M, 200M] pairs, Zipf exponent uniform in [0.8, 1.3] (three source
-    pools at 0.8, 1.05, 1.3), theta 512 or 1024, per-link sizing rule with
-    k <= 19. A step resets every sketch, updates all windows in one batched
-    update and restores all in one batched restore; the comparison is one
-    reset/update/restore per window in turn."""
+def batched_links(dev, n_links=64, seed=0x640):
+    """The links of the batched workload: (n_pairs, zipf_s, n_planted, theta,
+    pairs tensor) each, windows log-uniform in [1e6, 2e8] pairs."""
     import math as _m
     import numpy as np
-    import torch
-    from paper_1803_11449_amd import ddhf, serving, traffic
-    dev = torch.device("cuda:0")
-    rng = np.random.default_rng(0x640)
-    exps = (0.8, 1.05, 1.3)
-    print("bench: generating 3 pools of 2^28 pairs", file=sys.stderr, flush=True)
-    pools = [serving.pair_pool(1 << 28, s, traffic.config_seed(4, i), dev)
-             for i, s in enumerate(exps)]
-    links = []
-    for _ in range(64):
+    from paper_1803_11449_amd import traffic
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_links):
         n = int(_m.exp(rng.uniform(_m.log(1e6), _m.log(2e8))))
-        s = rng.uniform(0.8, 1.3)
-        pool = pools[int(np.argmin([abs(s - e) for e in exps]))]
-        off = int(rng.integers(0, pool.shape[0] - n + 1))
+        s = float(rng.uniform(0.8, 1.3))
+        planted = int(rng.integers(10, 501))
         theta = float(rng.choice([512.0, 1024.0]))
+        key = traffic.config_seed(4, i)
+        spec = traffic.spec_link_window(n, s, planted, key)
+        out.append((n, s, planted, theta, traffic.generate(spec, key, device=dev).pairs))
+    return out
+
+
+def run_batched(args):
+    """64 links, each with its own sketch and one window (sizes log-uniform
+    in [1M, 200M] pairs, Zipf exponent uniform in [0.8, 1.3], 10..500
+    planted super points, theta 512 or 1024, sizing rule with k <= 19).
+    Update options per (sketch shape, size class) come from the autotuner.
+    A step is one window cycle of every link: reset, update, restore. The
+    value is the plan's rate (the whole cycle as one HIP graph); the same
+    cycle as eager batched calls and as one reset/update/restore per window
+    in turn are timed beside it, and all three must agree."""
+    import numpy as np
+    import torch
+    from paper_1803_11449_amd import ddhf, serving, traffic, tune
+    dev = torch.device("cuda:0")
+    print("bench: generating 64 link windows", file=sys.stderr, flush=True)
+    links = batched_links(dev)
+    total = sum(x[0] for x in links)
+    sks, tuned = [], {}
+    for n, s, planted, theta, pairs in links:
         k, alpha = serving.sized_params(n, k_max=19)
-        links.append((ddhf.Sketch(1024, k, 5, alpha, traffic.HASH_SEED, device=0),
-                      pool[off:off + n], theta))
-    total = sum(p.shape[0] for _, p, _ in links)
+        key = (k, tune.size_class(n))
+        if key not in tuned:
+            print(f"bench: tuning k={k} n~2^{key[1]}", file=sys.stderr, flush=True)
+            tuned[key] = tune.tune(1024, k, 5, alpha, pairs, traffic.HASH_SEED, use_cache=False)
+        sk = ddhf.Sketch(1024, k, 5, alpha, traffic.HASH_SEED, device=0)
+        tune.apply(sk, tuned[key])
+        sks.append(sk)
+    items = [(sk, x[4], x[3]) for sk, x in zip(sks, links)]
 
     def batched():
-        for sk, _, _ in links:
+        for sk in sks:
             sk.reset()
-        ddhf.update_batch([(sk, p) for sk, p, _ in links])
-        return ddhf.restore_batch([(sk, th) for sk, _, th in links])
+        ddhf.update_batch([(sk, p) for sk, p, _ in items])
+        return ddhf.restore_batch([(sk, th) for sk, _, th in items])
 
     def plain():
         res = []
-        for sk, p, th in links:
+        for sk, p, th in items:
             sk.reset()
             sk.update(p)
             res.append(sk.restore(th))
         return res
 
+    plan = ddhf.Plan(items)
+
+    def planned():
+        plan.run()
+        return plan.results()
+
     print("bench: warmup", file=sys.stderr, flush=True)
     for _ in range(max(1, args.warmup)):
+        rg = planned()
         rb = batched()
         rp = plain()
-    differ = sum(not np.array_equal(a[0], b[0]) for a, b in zip(rb, rp))
+    differ = sum(not (np.array_equal(a[0], b[0]) and np.array_equal(a[0], c[0]))
+                 for a, b, c in zip(rg, rb, rp))
     steps = max(1, min(args.steps, 5))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        batched()
-    torch.cuda.synchronize()
-    tb = (time.perf_counter() - t0) / steps
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        plain()
-    torch.cuda.synchronize()
-    tp = (time.perf_counter() - t0) / steps
-    _line(total / tb / 1e6, steps, args.warmup, tb * 1e3,
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    tg, tb, tp = timed(planned), timed(batched), timed(plain)
+    _line(total / tg / 1e6, steps, args.warmup, tg * 1e3,
           {"workload": "batched_64_links", "links": 64, "pairs": total,
            "window_pairs": "log-uniform [1e6, 2e8]", "zipf_s": "U[0.8, 1.3]",
-           "theta": "512 or 1024", "k_max": 19},
-          {"plain_mpps": round(total / tp / 1e6, 2), "plain_ms_per_step": round(tp * 1e3, 3),
-           "speedup_vs_plain": round(tp / tb, 3), "windows_differing_from_plain": differ,
-           "super_points": int(sum(len(r[0]) for r in rb))})
-    for sk, _, _ in links:
+           "planted": "U{10..500}", "theta": "512 or 1024", "k_max": 19},
+          {"plan_update_launches": plan.launches,
+           "eager_batched_mpps": round(total / tb / 1e6, 2),
+           "eager_batched_ms_per_step": round(tb * 1e3, 3),
+           "plain_mpps": round(total / tp / 1e6, 2), "plain_ms_per_step": round(tp * 1e3, 3),
+           "speedup_vs_plain": round(tp / tg, 3),
+           "windows_differing": differ,
+           "super_points": int(sum(len(r[0]) for r in rg)),
+           "tuned": {f"k{k}_n2^{c}": v for (k, c), v in sorted(tuned.items())}})
+    plan.close()
+    for sk in sks:
         sk.close()
 
 

@@ -256,5 +256,17 @@ def spec_stream_window(w: int, n_pairs: int = 117_000_000,
                       name=f"stream_window_{w}")
 
 
+def spec_link_window(n_pairs: int, zipf_s: float, n_planted: int, key: int) -> WindowSpec:
+    """One link's window in a batch of monitored links: Zipf(s) over
+    n_pairs/25 sources with uniform destinations, n_planted planted sources
+    with cardinalities log-uniform in [1024, 50000] (the list is cut while
+    the planted pairs exceed 30% of the window)."""
+    card = _loguniform_ints(stream_key(key, 13), n_planted, 1024, 50000)
+    while len(card) > 1 and sum(card) > 0.3 * n_pairs:
+        card = card[:-1]
+    return WindowSpec(n_pairs=n_pairs, n_sources=max(1000, n_pairs // 25), zipf_s=zipf_s,
+                      planted_card=card, name="link_window")
+
+
 def config_seed(config_id: int, window: int = 0) -> int:
     return TRAFFIC_SEED + config_id + (window << 32)

@@ -102,6 +102,19 @@ def run_cpu_baseline(pairs_host, p, theta, n_sample):
     }
 
 
+def cpu_baseline_leg(pairs, shape, theta, n_sample):
+    """The cpu_baseline object of the JSON line: the oracle on the host over
+    the first n_sample pairs of the window (pairs: int32 [n, 2] tensor)."""
+    import numpy as np
+    import oracle
+    from paper_1803_11449_amd import traffic
+    host = pairs.cpu().numpy().view(np.uint32).reshape(-1)
+    g, k, r, alpha = shape
+    cb = run_cpu_baseline(host, oracle.Params(g, k, r, alpha, traffic.HASH_SEED), theta,
+                          n_sample)
+    return {kk: (round(v, 3) if isinstance(v, float) else v) for kk, v in cb.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,7 +214,7 @@ def main():
     alg_bytes = n * PAIR_BYTES
     achieved = alg_bytes / (upd_mean / 1e3) / 1e9
     info = rec["info"]
-    traffic = measured_update_traffic() if n == 100_000_000 else None
+    hbm_traffic = measured_update_traffic() if n == 100_000_000 else None
 
     out = {
         "metric": METRIC,
@@ -237,18 +250,14 @@ def main():
                      "bound": "hbm",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": traffic},
+                     "traffic": hbm_traffic},
     }
-    if traffic:
-        out["roofline"]["traffic_gbs"] = round(traffic / (upd_mean / 1e3) / 1e9, 1)
+    if hbm_traffic:
+        out["roofline"]["traffic_gbs"] = round(hbm_traffic / (upd_mean / 1e3) / 1e9, 1)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
-        host = pairs.cpu().numpy().view(np.uint32).reshape(-1)
-        import oracle
-        cb = run_cpu_baseline(host, oracle.Params(g, k, r, alpha, traffic.HASH_SEED),
-                              args.theta, min(args.cpu_sample, n))
-        out["cpu_baseline"] = {kk: (round(v, 3) if isinstance(v, float) else v)
-                               for kk, v in cb.items()}
+        out["cpu_baseline"] = cpu_baseline_leg(pairs, (g, k, r, alpha), args.theta,
+                                               min(args.cpu_sample, n))
     sk.close()
     print(json.dumps(out), flush=True)
 
@@ -329,11 +338,22 @@ def run_batched(args):
         plan.run()
         return plan.results()
 
+    # the eager calls grow the shared buffers to this batch's needs; the plan
+    # runs last so that its graph is captured against the grown buffers once
     print("bench: warmup", file=sys.stderr, flush=True)
     for _ in range(max(1, args.warmup)):
-        rg = planned()
         rb = batched()
         rp = plain()
+        rg = planned()
+    rg = planned()
+    for (n, s, planted, theta, _), sk, (recs, info) in zip(links, sks, rg):
+        print(f"bench: link n={n} s={s:.2f} planted={planted} theta={theta:g} "
+              f"k={sk.params.k} he={info['he_count'][:5]} partials={info['n_partials'][2:4]} "
+              f"cand={info['n_candidates']} spl={len(recs)} psi={info['psi']:.3f}",
+              file=sys.stderr, flush=True)
+    free, tot = torch.cuda.mem_get_info()
+    print(f"bench: device memory free {free / 2**30:.1f} of {tot / 2**30:.1f} GiB, torch "
+          f"reserved {torch.cuda.memory_reserved() / 2**30:.1f} GiB", file=sys.stderr, flush=True)
     differ = sum(not (np.array_equal(a[0], b[0]) and np.array_equal(a[0], c[0]))
                  for a, b, c in zip(rg, rb, rp))
     steps = max(1, min(args.steps, 5))

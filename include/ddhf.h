@@ -188,11 +188,13 @@ int sketch_restore_batch(sketch_restore_job_t *jobs, size_t n_jobs, void *hip_st
  * sketch_restore_batch would make) and captured into one HIP graph, so a
  * run is a single graph launch whatever the number of links and rounds.
  *
- * The plan owns its job tables, update arena, restore buffers and outputs
- * and reads the sketches it was made with: destroy the plan before them,
- * keep every job's pairs valid while the plan is used, and order a run
- * against other work on the same sketches (same stream). Options set on a
- * sketch after sketch_plan_create do not apply to the plan. */
+ * The plan owns its job tables, per-job update arrays and outputs, and
+ * shares the device's update arena and restore buffers with every other
+ * call (it captures again when another call has moved them). It reads the
+ * sketches it was made with: destroy the plan before them, keep every
+ * job's pairs valid while the plan is used, and order a run against other
+ * work on the same sketches (same stream). Options set on a sketch after
+ * sketch_plan_create do not apply to the plan. */
 typedef struct sketch_plan sketch_plan_t;
 
 typedef struct {

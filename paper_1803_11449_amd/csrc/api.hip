@@ -123,6 +123,7 @@ struct DevCtx {
   // last work that used the arena or the pool
   hipEvent_t pool_ev = nullptr;
   bool pool_armed = false;
+  uint64_t gen = 0;              // bumped whenever the arena or the pool moves
 };
 
 std::mutex g_ctx_mu;
@@ -150,6 +151,7 @@ int pool_idle(DevCtx *c) {
 int alloc_partials(DevCtx *c, size_t cap) {
   int rc = pool_idle(c);
   if (rc) return rc;
+  c->gen++;
   dev_free(c->part[0]);
   dev_free(c->part[1]);
   c->seg_cap = 0;
@@ -162,6 +164,7 @@ int alloc_partials(DevCtx *c, size_t cap) {
 int alloc_cand(DevCtx *c, size_t cap) {
   int rc = pool_idle(c);
   if (rc) return rc;
+  c->gen++;
   dev_free(c->cand);
   dev_free(c->cand_sorted);
   c->cand_cap = 0;
@@ -174,6 +177,7 @@ int alloc_cand(DevCtx *c, size_t cap) {
 int alloc_pool_spl(DevCtx *c, size_t cap) {
   int rc = pool_idle(c);
   if (rc) return rc;
+  c->gen++;
   dev_free(c->spl);
   c->spl_cap = 0;
   rc = dev_alloc(&c->spl, cap, "records");
@@ -196,6 +200,7 @@ int ensure_arena(DevCtx *c, size_t words, size_t tiles) {
   if (c->codes_cap >= words && c->scratch_tiles >= tiles) return SKETCH_OK;
   int rc = pool_idle(c);
   if (rc) return rc;
+  c->gen++;
   if (c->codes_cap < words) {
     dev_free(c->codes);
     c->codes_cap = 0;
@@ -219,6 +224,7 @@ int ensure_arena(DevCtx *c, size_t words, size_t tiles) {
 int trim_pools(DevCtx *c, size_t entries) {
   int rc = pool_idle(c);
   if (rc) return rc;
+  c->gen++;
   dev_free(c->codes);
   c->codes_cap = 0;
   dev_free(c->scratch);
@@ -761,10 +767,13 @@ int update_jobs(const sketch_update_job_t *jobs, size_t n_jobs, hipStream_t st) 
 }  // namespace
 
 // A fixed batch captured once into a HIP graph (see sketch_plan_create).
-// The graph references only memory that lives as long as the plan: the
-// sketches (fixed at creation), their per-row restore arrays (fixed), and
-// the plan's own job tables, update arrays, arena, restore pool, device
-// states and sorted outputs. Growing a buffer rebuilds the graph.
+// The graph references the sketches and their per-row restore arrays
+// (fixed for a handle's life), the plan's own job tables, per-job update
+// arrays, device states and sorted outputs, and the device's shared update
+// arena and restore pool. The shared buffers can move (another call grows
+// them): the plan notes the device context's generation when it captures
+// and captures again when it has changed. Launches are ordered against
+// other users of the shared buffers by the pool event, outside the graph.
 struct PlanJob {
   sketch *s = nullptr;
   const uint32_t *pairs = nullptr;
@@ -777,7 +786,7 @@ struct PlanJob {
   DevState *h_state = nullptr;  // pinned
   uint4 *sorted = nullptr;
   size_t sorted_cap = 0;
-  size_t ran_spl_cap = 0;       // record capacity the graph's restore runs with
+  size_t ran_spl_cap = 0;       // record capacity the captured restore has
   bool eager = false;           // this result comes from an eager rerun
 };
 
@@ -795,25 +804,15 @@ struct sketch_plan {
   DevCtx *ctx = nullptr;
   std::vector<PlanJob> jobs;
   std::vector<PlanLaunch> launches;
-  uint32_t *codes = nullptr, *scratch = nullptr;
-  // restore pool
-  uint32_t jblk = 0;
-  uint2 *part[2] = {};
-  uint32_t *segc[2] = {};
-  size_t seg_cap = 0;
-  uint32_t *cand = nullptr, *cand_sorted = nullptr;
-  size_t cand_cap = 0;
-  uint4 *spl = nullptr;
-  size_t spl_cap = 0;
-  uint32_t *rank = nullptr;
-  // the graph
+  size_t arena_words = 0, arena_tiles = 0;   // largest launch's arena needs
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  bool dirty = true;            // buffers changed since the graph was built
+  bool dirty = true;            // a plan-owned buffer changed since the capture
+  uint64_t gen = ~0ull;         // device context generation at the capture
   bool ran = false;             // the graph has run at least once
   hipStream_t run_stream = nullptr;
-  size_t ran_seg_cap = 0, ran_cand_cap = 0;   // capacities the graph runs with
+  size_t ran_seg_cap = 0, ran_cand_cap = 0;   // pool capacities of the capture
 };
 
 namespace {
@@ -844,46 +843,8 @@ void plan_free(sketch_plan *P) {
     dev_free(L.d);
     dev_free(L.d_total);
   }
-  dev_free(P->codes);
-  dev_free(P->scratch);
-  dev_free(P->part[0]);
-  dev_free(P->part[1]);
-  dev_free(P->segc[0]);
-  dev_free(P->segc[1]);
-  dev_free(P->cand);
-  dev_free(P->cand_sorted);
-  dev_free(P->spl);
-  dev_free(P->rank);
   ctx_release(P->ctx);
   P->ctx = nullptr;
-}
-
-int plan_alloc_partials(sketch_plan *P, size_t cap) {
-  dev_free(P->part[0]);
-  dev_free(P->part[1]);
-  P->seg_cap = 0;
-  int rc = dev_alloc(&P->part[0], cap * P->jblk, "plan partials");
-  if (!rc) rc = dev_alloc(&P->part[1], cap * P->jblk, "plan partials");
-  if (!rc) P->seg_cap = cap;
-  return rc;
-}
-
-int plan_alloc_cand(sketch_plan *P, size_t cap) {
-  dev_free(P->cand);
-  dev_free(P->cand_sorted);
-  P->cand_cap = 0;
-  int rc = dev_alloc(&P->cand, cap, "plan candidates");
-  if (!rc) rc = dev_alloc(&P->cand_sorted, cap, "plan candidates");
-  if (!rc) P->cand_cap = cap;
-  return rc;
-}
-
-int plan_alloc_spl(sketch_plan *P, size_t cap) {
-  dev_free(P->spl);
-  P->spl_cap = 0;
-  int rc = dev_alloc(&P->spl, cap, "plan records");
-  if (!rc) P->spl_cap = cap;
-  return rc;
 }
 
 int plan_alloc_sorted(PlanJob &j, size_t cap) {
@@ -895,32 +856,15 @@ int plan_alloc_sorted(PlanJob &j, size_t cap) {
 }
 
 RestoreBufs plan_restore_bufs(const sketch_plan *P, const PlanJob &j) {
-  const sketch *s = j.s;
-  RestoreBufs B{};
+  RestoreBufs B = restore_bufs(j.s);      // the sketch's rows, the shared pool
   B.st = j.st;
-  B.hotmask = s->hotmask;
-  B.he = s->he;
-  B.bk_off = s->bk_off;
-  B.bk_cur = s->bk_cur;
-  B.bk_val = s->bk_val;
-  B.part[0] = P->part[0];
-  B.part[1] = P->part[1];
-  B.segc[0] = P->segc[0];
-  B.segc[1] = P->segc[1];
-  B.seg_cap = P->seg_cap;
-  B.jblk = P->jblk;
-  B.cand = P->cand;
-  B.cand_sorted = P->cand_sorted;
-  B.cand_cap = P->cand_cap;
-  B.spl = P->spl;
   B.spl_sorted = j.sorted;
-  B.spl_cap = std::min(P->spl_cap, j.sorted_cap);
-  B.rank = P->rank;
+  B.spl_cap = std::min(P->ctx->spl_cap, j.sorted_cap);
   return B;
 }
 
 // Enqueue one whole run on st: resets, update launches, restores and the
-// copies of the device states (only plan-owned or fixed memory).
+// copies of the device states.
 int plan_enqueue(sketch_plan *P, hipStream_t st) {
   if (P->flags & SKETCH_PLAN_RESET)
     for (PlanJob &j : P->jobs)
@@ -937,11 +881,20 @@ int plan_enqueue(sketch_plan *P, hipStream_t st) {
   return SKETCH_OK;
 }
 
-// (Re)capture the graph of a run.
+// (Re)capture the graph of a run against the shared buffers as they are
+// now. Caller holds ctx->mu; no run of the plan is in flight.
 int plan_build_graph(sketch_plan *P) {
+  DevCtx *c = P->ctx;
   plan_free_graph(P);
+  int rc = ensure_arena(c, P->arena_words, P->arena_tiles);
+  if (rc) return rc;
+  for (PlanLaunch &L : P->launches) {
+    if (!L.binned) continue;
+    place_arena(L.h.data(), (uint32_t)L.h.size(), L.r, c->codes, c->scratch);
+    HIP_OK(hipMemcpy(L.d, L.h.data(), sizeof(UpdJob) * L.h.size(), hipMemcpyHostToDevice));
+  }
   HIP_OK(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
-  int rc = plan_enqueue(P, P->cap);
+  rc = plan_enqueue(P, P->cap);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(P->cap, &g);
   if (rc) {
@@ -952,9 +905,10 @@ int plan_build_graph(sketch_plan *P) {
     return fail(SKETCH_E_HIP, "plan: capture failed: %s", hipGetErrorString(e));
   P->graph = g;
   HIP_OK(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
-  P->ran_seg_cap = P->seg_cap;
-  P->ran_cand_cap = P->cand_cap;
-  for (PlanJob &j : P->jobs) j.ran_spl_cap = std::min(P->spl_cap, j.sorted_cap);
+  P->ran_seg_cap = c->seg_cap;
+  P->ran_cand_cap = c->cand_cap;
+  for (PlanJob &j : P->jobs) j.ran_spl_cap = std::min(c->spl_cap, j.sorted_cap);
+  P->gen = c->gen;
   P->dirty = false;
   return SKETCH_OK;
 }
@@ -1310,7 +1264,6 @@ int sketch_plan_create(const sketch_plan_job_t *jobs, size_t n_jobs, int flags,
     c->refs++;
   }
   P->ctx = c;
-  P->jblk = c->jblk;
   P->jobs.resize(n_jobs);
   for (size_t j = 0; j < n_jobs && !rc; j++) {
     PlanJob &pj = P->jobs[j];
@@ -1335,10 +1288,13 @@ int sketch_plan_create(const sketch_plan_job_t *jobs, size_t n_jobs, int flags,
       rc = fail(SKETCH_E_NOMEM, "hipHostMalloc(plan state) failed");
     }
   }
-  // the update launches, with this plan's per-job arrays
-  size_t max_words = 0, max_tiles = 0;
+  if (!rc && hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking) != hipSuccess) {
+    P->cap = nullptr;
+    rc = fail(SKETCH_E_HIP, "plan: hipStreamCreate failed");
+  }
   if (!rc) {
     std::lock_guard<std::mutex> lk(c->mu);
+    // the update launches, with this plan's per-job arrays
     rc = schedule_update(
         uj.data(), n_jobs,
         [&](size_t j) {
@@ -1359,8 +1315,8 @@ int sketch_plan_create(const sketch_plan_job_t *jobs, size_t n_jobs, int flags,
             L.h.assign(g.jobs.begin() + at, g.jobs.begin() + at + n);
             size_t words, tiles;
             layout_launch(L.h.data(), n, g.binned, g.r, &words, &tiles);
-            max_words = std::max(max_words, words);
-            max_tiles = std::max(max_tiles, tiles);
+            P->arena_words = std::max(P->arena_words, words);
+            P->arena_tiles = std::max(P->arena_tiles, tiles);
             L.binned = g.binned;
             L.r = g.r;
             L.ppt = g.ppt;
@@ -1369,33 +1325,20 @@ int sketch_plan_create(const sketch_plan_job_t *jobs, size_t n_jobs, int flags,
           }
           return SKETCH_OK;
         });
-  }
-  if (!rc && max_words) rc = dev_alloc(&P->codes, max_words, "plan update codes");
-  if (!rc && max_tiles)
-    rc = dev_alloc(&P->scratch, max_tiles * (size_t)BIN_TILE_WORDS, "plan scratch tiles");
-  for (size_t i = 0; i < P->launches.size() && !rc; i++) {
-    PlanLaunch &L = P->launches[i];
-    if (L.binned) place_arena(L.h.data(), (uint32_t)L.h.size(), L.r, P->codes, P->scratch);
-    rc = dev_alloc(&L.d, L.h.size(), "plan job table");
-    if (!rc) rc = dev_alloc(&L.d_total, 1, "plan item total");
-    if (!rc) {
-      hipError_t e = hipMemcpy(L.d, L.h.data(), sizeof(UpdJob) * L.h.size(),
-                               hipMemcpyHostToDevice);
-      if (e != hipSuccess) rc = fail(SKETCH_E_HIP, "plan: job table upload: %s",
-                                     hipGetErrorString(e));
+    for (size_t i = 0; i < P->launches.size() && !rc; i++) {
+      PlanLaunch &L = P->launches[i];
+      rc = dev_alloc(&L.d, L.h.size(), "plan job table");
+      if (!rc) rc = dev_alloc(&L.d_total, 1, "plan item total");
+      if (!rc) {
+        hipError_t e = hipMemcpy(L.d, L.h.data(), sizeof(UpdJob) * L.h.size(),
+                                 hipMemcpyHostToDevice);
+        if (e != hipSuccess)
+          rc = fail(SKETCH_E_HIP, "plan: job table upload: %s", hipGetErrorString(e));
+      }
     }
+    if (!rc) rc = pool_idle(c);           // nothing else uses the shared buffers now
+    if (!rc) rc = plan_build_graph(P);
   }
-  if (!rc) rc = dev_alloc(&P->rank, 16384, "plan sort ranks");
-  if (!rc) rc = dev_alloc(&P->segc[0], P->jblk, "plan segment counts");
-  if (!rc) rc = dev_alloc(&P->segc[1], P->jblk, "plan segment counts");
-  if (!rc) rc = plan_alloc_partials(P, std::max<size_t>(c->seg_cap, 16));
-  if (!rc) rc = plan_alloc_cand(P, std::max<size_t>(c->cand_cap, 16));
-  if (!rc) rc = plan_alloc_spl(P, std::max<size_t>(c->spl_cap, 16));
-  if (!rc && hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking) != hipSuccess) {
-    P->cap = nullptr;
-    rc = fail(SKETCH_E_HIP, "plan: hipStreamCreate failed");
-  }
-  if (!rc) rc = plan_build_graph(P);
   if (rc) {
     plan_free(P);
     delete P;
@@ -1408,14 +1351,23 @@ int sketch_plan_create(const sketch_plan_job_t *jobs, size_t n_jobs, int flags,
 int sketch_plan_run(sketch_plan_t *P, void *hip_stream) {
   if (!P) return fail(SKETCH_E_INVAL, "sketch_plan_run: NULL plan");
   DEVICE_GUARD(P->dev);
-  if (P->dirty) {
+  DevCtx *c = P->ctx;
+  hipStream_t st = (hipStream_t)hip_stream;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (P->dirty || P->gen != c->gen ||
+      c->codes_cap < P->arena_words || c->scratch_tiles < P->arena_tiles) {
     if (P->ran) HIP_OK(hipStreamSynchronize(P->run_stream));   // the old graph is done
-    int rc = plan_build_graph(P);
+    int rc = pool_idle(c);
+    if (!rc) rc = plan_build_graph(P);
     if (rc) return rc;
   }
-  HIP_OK(hipGraphLaunch(P->exec, (hipStream_t)hip_stream));
+  int rc = pool_enter(c, st);
+  if (rc) return rc;
+  HIP_OK(hipGraphLaunch(P->exec, st));
+  rc = pool_leave(c, st);
+  if (rc) return rc;
   P->ran = true;
-  P->run_stream = (hipStream_t)hip_stream;
+  P->run_stream = st;
   return SKETCH_OK;
 }
 
@@ -1437,7 +1389,8 @@ int sketch_plan_results(sketch_plan_t *P, sketch_restore_job_t *out, size_t n_ou
   hipStream_t st = (hipStream_t)hip_stream;
   HIP_OK(hipStreamSynchronize(P->run_stream));
   HIP_OK(hipStreamSynchronize(st));
-  std::lock_guard<std::mutex> lk(P->ctx->mu);
+  DevCtx *c = P->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
   int first_err = SKETCH_OK;
   for (size_t j = 0; j < n_out; j++) {
     PlanJob &pj = P->jobs[j];
@@ -1455,27 +1408,22 @@ int sketch_plan_results(sketch_plan_t *P, sketch_restore_job_t *out, size_t n_ou
       for (uint32_t i = 2; i + 1 < s->p.r; i++)
         need_part = std::max<size_t>(need_part, h->seg_max[i]);
       // a stage overflowed if its count passed the capacity the graph ran
-      // with; buffers grow (for the next runs) only if not grown enough yet
-      const bool over_part = need_part > P->ran_seg_cap, over_cand = h->n_cand > P->ran_cand_cap,
-                 over_spl = h->n_spl > pj.ran_spl_cap;
-      if (over_part || over_cand || over_spl) {
-        int g = SKETCH_OK;
-        if (need_part > P->seg_cap) g = plan_alloc_partials(P, grown(need_part, P->seg_cap));
-        if (!g && h->n_cand > P->cand_cap) g = plan_alloc_cand(P, grown(h->n_cand, P->cand_cap));
-        if (!g && h->n_spl > P->spl_cap) g = plan_alloc_spl(P, grown(h->n_spl, P->spl_cap));
-        if (!g && h->n_spl > pj.sorted_cap)
-          g = plan_alloc_sorted(pj, grown(h->n_spl, pj.sorted_cap));
-        if (P->seg_cap != P->ran_seg_cap || P->cand_cap != P->ran_cand_cap ||
-            std::min(P->spl_cap, pj.sorted_cap) != pj.ran_spl_cap)
+      // with; the shared buffers grow as for an eager restore (which moves
+      // them, so the next run captures again) and this job runs again alone
+      if (need_part > P->ran_seg_cap || h->n_cand > P->ran_cand_cap ||
+          h->n_spl > pj.ran_spl_cap) {
+        if (h->n_spl > pj.sorted_cap) {
+          rc = plan_alloc_sorted(pj, grown(h->n_spl, pj.sorted_cap));
           P->dirty = true;
-        // this run's result: the job restored again on its own
-        rc = g ? g : run_restore(s, pj.t, 1, st);
+        }
+        if (!rc) rc = run_restore(s, pj.t, 1, st);
         h = s->h_state;
         src = s->spl_sorted;
         pj.eager = true;
       }
     }
-    if (rc == SKETCH_OK || rc == SKETCH_E_SATURATED) fill_info(s, *h, pj.t.zmin, pj.t.zhot, J.info);
+    if (rc == SKETCH_OK || rc == SKETCH_E_SATURATED)
+      fill_info(s, *h, pj.t.zmin, pj.t.zhot, J.info);
     J.n_out = rc == SKETCH_OK ? (size_t)h->n_spl : 0;
     if (rc == SKETCH_OK && h->n_spl > J.cap) rc = SKETCH_E_CAPACITY;
     if (rc == SKETCH_OK && h->n_spl) {

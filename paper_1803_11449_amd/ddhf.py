@@ -348,7 +348,7 @@ def restore_batch(items, stream=None):
             sk._cap = max(int(need) + 64, 2 * sk._cap)
             retry.append(i)
         else:
-            raise SketchError(st, f"restore of batch item {i} failed")
+            raise SketchError(st, f"restore of batch item {i} failed: {last_error()}")
     if retry:
         again = restore_batch([items[i] for i in retry], stream)
         for i, r in zip(retry, again):
@@ -391,7 +391,7 @@ class Plan:
                     sk._cap = max(int(need) + 64, 2 * sk._cap)
                     retry = True
                 elif st != SKETCH_OK:
-                    raise SketchError(st, "plan result failed")
+                    raise SketchError(st, f"plan result failed: {last_error()}")
             if not retry:
                 return [(recs, info) for recs, info, _, _ in res]
 

@@ -272,13 +272,17 @@ enum {
   SKETCH_OPT_BINNED_BLOCKS = 7,     /* binned: blocks of the count and
                                        scatter passes, 1..1024 (default: one
                                        per compute unit) */
-  SKETCH_OPT_TRIM_POOLS = 8         /* device-wide, acts at once: waits for
+  SKETCH_OPT_TRIM_POOLS = 8,        /* device-wide, acts at once: waits for
                                        pending work on the shared buffers,
                                        frees the update arena and reallocates
                                        the restore pool at `value` entries per
                                        buffer, 0..2^24 (0 = the initial sizes);
                                        both grow again on demand. Frees device
                                        memory for callers under a budget */
+  SKETCH_OPT_APPLY_BLOCKS = 9       /* binned: blocks of the apply pass;
+                                       0 = one per apply item (the dispatcher
+                                       balances uneven tiles), else that many
+                                       blocks striding over the items */
 };
 
 /* Set a tuning option; results never depend on it. Errors: INVAL (NULL

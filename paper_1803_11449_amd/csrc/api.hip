@@ -380,7 +380,7 @@ struct sketch {
   uint32_t nbins = 0;
   uint32_t bin_nblk = 0;        // count/scatter blocks per job (hist width)
   uint32_t scatter_ppt = 6;
-  uint32_t apply_grid = 0;
+  uint32_t apply_grid = 0;     // blocks of the apply pass (0: one per item)
   uint32_t *hist = nullptr, *totals = nullptr, *base = nullptr, *item_start = nullptr,
            *xslot = nullptr, *n_items = nullptr;
   // restore
@@ -651,7 +651,8 @@ void add_job(std::vector<Group> &groups, const sketch *s, const UpdJob &J, bool 
   for (Group &g : groups)
     if (g.r == s->p.r && g.binned == binned && (binned ? g.ppt == s->scatter_ppt
                                                        : g.check == J.check)) {
-      g.apply_grid = std::max(g.apply_grid, s->apply_grid);
+      g.apply_grid = (g.apply_grid == 0 || s->apply_grid == 0)
+                         ? 0u : std::max(g.apply_grid, s->apply_grid);
       g.jobs.push_back(J);
       return;
     }
@@ -1195,6 +1196,10 @@ int sketch_set_option(sketch_t *s, int option, int64_t value) {
       s->bin_nblk = (uint32_t)value;
       return SKETCH_OK;
     }
+    case SKETCH_OPT_APPLY_BLOCKS:
+      if (value < 0 || value > (1 << 20)) break;
+      s->apply_grid = (uint32_t)value;
+      return SKETCH_OK;
     case SKETCH_OPT_BINNED_ROUND:
       if (value < 1024 || (uint64_t)value > ARENA_MAX_PAIRS) break;
       s->binned_round = (size_t)value;

@@ -85,6 +85,14 @@ struct LeShape {
   static constexpr int VPL = WPL >= 4 ? V4 / LPL : 0;
 };
 
+// LDS arrays handed to a device function keep their address space (a plain
+// pointer would make every access a flat one).
+#define LDSP __attribute__((address_space(3)))
+template <typename T>
+__device__ __forceinline__ LDSP T *lds_ptr(T *p) {
+  return (LDSP T *)p;
+}
+
 // ----------------------------------------------------------- 0: state init
 
 __global__ void k_state_init(DevState *st, uint32_t *rank, uint32_t n_rank) {
@@ -196,23 +204,22 @@ __global__ __launch_bounds__(1024) void k_he_compact(Geom G,
 
 // --------------------------------------------------------------- 3: buckets
 
-__global__ __launch_bounds__(1024) void k_buckets(Geom G, const uint32_t *__restrict__ he,
-                                                  uint32_t *__restrict__ bk_off,
-                                                  uint32_t *__restrict__ bk_cur,
-                                                  uint32_t *__restrict__ bk_val,
-                                                  const DevState *__restrict__ st) {
-  __shared__ uint32_t sh[17];
-  const uint32_t row = blockIdx.x + 2;
+
+
+// One block per row i in 2..r-1: HE(i) grouped by its low k-alpha bits
+// (the bucket a probe of stage i looks up). Counts and cursors live in LDS
+// when the table fits (2^(k-alpha) <= BK_LDS buckets), else in bk_cur.
+constexpr uint32_t BK_LDS = 8192;
+
+template <typename CurPtr>
+__device__ __forceinline__ void bucket_rows(const Geom &G, uint32_t row, const uint32_t *h,
+                                            uint32_t n, uint32_t *off, CurPtr cur,
+                                            uint32_t *val, uint32_t *sh) {
   const uint32_t nb = 1u << (G.k - G.alpha), M = nb - 1;
-  uint32_t *off = bk_off + (size_t)row * (nb + 1);
-  uint32_t *cur = bk_cur + (size_t)row * nb;
-  const uint32_t *h = he + ((size_t)row << G.k);
-  uint32_t *val = bk_val + ((size_t)row << G.k);
-  const uint32_t n = st->he_count[row];
   const uint32_t tid = threadIdx.x, bs = blockDim.x;
   for (uint32_t b = tid; b < nb; b += bs) cur[b] = 0;
   __syncthreads();
-  for (uint32_t x = tid; x < n; x += bs) atomicAdd(&cur[h[x] & M], 1u);
+  for (uint32_t x = tid; x < n; x += bs) atomicAdd((uint32_t *)&cur[h[x] & M], 1u);
   __syncthreads();
   const uint32_t per = (nb + bs - 1) / bs;
   const uint32_t b0 = min(tid * per, nb), b1 = min(b0 + per, nb);
@@ -230,9 +237,26 @@ __global__ __launch_bounds__(1024) void k_buckets(Geom G, const uint32_t *__rest
   __syncthreads();
   for (uint32_t x = tid; x < n; x += bs) {
     const uint32_t c = h[x];
-    const uint32_t pos = atomicAdd(&cur[c & M], 1u);
+    const uint32_t pos = atomicAdd((uint32_t *)&cur[c & M], 1u);
     val[pos] = c;
   }
+}
+
+__global__ __launch_bounds__(1024) void k_buckets(Geom G, const uint32_t *__restrict__ he,
+                                                  uint32_t *__restrict__ bk_off,
+                                                  uint32_t *__restrict__ bk_cur,
+                                                  uint32_t *__restrict__ bk_val,
+                                                  const DevState *__restrict__ st) {
+  __shared__ uint32_t sh[17];
+  __shared__ uint32_t lcur[BK_LDS];
+  const uint32_t row = blockIdx.x + 2;
+  const uint32_t nb = 1u << (G.k - G.alpha);
+  uint32_t *off = bk_off + (size_t)row * (nb + 1);
+  const uint32_t *h = he + ((size_t)row << G.k);
+  uint32_t *val = bk_val + ((size_t)row << G.k);
+  const uint32_t n = st->he_count[row];
+  if (nb <= BK_LDS) bucket_rows(G, row, h, n, off, lds_ptr(lcur), val, sh);
+  else bucket_rows(G, row, h, n, off, bk_cur + (size_t)row * nb, val, sh);
 }
 
 // --------------------------------------------------------------- 4: scalars
@@ -293,6 +317,7 @@ __device__ __forceinline__ void lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
 }
 constexpr uint32_t TAB_OFF_MAX = 8193;          // bucket offsets held in LDS
+constexpr uint32_t OWN_MAX = 512;               // output slots per wave pass set
 constexpr uint32_t TAB_VAL_BYTES = 32768;       // bucket entries held in LDS
 
 // Bits of the address from block i >= 2: alpha new bits at k + (i-2)*alpha.
@@ -309,63 +334,46 @@ __device__ __forceinline__ bool extend_top(const Geom &G, uint32_t i, uint32_t s
   return (s2 >> 32) == 0;
 }
 
+// The probed row's bucket table: in LDS (offsets as uint16, entries as
+// their top alpha bits) or in the global tables. Which one is a template
+// parameter, so a loop over an LDS table issues no global loads that a
+// wait for prefetched data would have to cover.
+template <bool TLDS>
 struct JoinTable {
-  const uint16_t *off16;   // LDS
-  const uint8_t *hi8;      // LDS
-  const uint16_t *hi16;    // LDS
+  const LDSP uint16_t *off16;
+  const LDSP uint8_t *hi8;
+  const LDSP uint16_t *hi16;
   const uint32_t *off;     // global
   const uint32_t *val;     // global
   uint32_t shift;          // k - alpha
-  bool lds;
   bool wide;               // alpha > 8
   __device__ __forceinline__ uint32_t start(uint32_t key) const {
-    return lds ? (uint32_t)off16[key] : off[key];
+    if constexpr (TLDS) return (uint32_t)off16[key];
+    else return off[key];
   }
   __device__ __forceinline__ uint32_t top_bits(uint32_t j) const {
-    if (lds) return wide ? (uint32_t)hi16[j] : (uint32_t)hi8[j];
-    return val[j] >> shift;
+    if constexpr (TLDS) return wide ? (uint32_t)hi16[j] : (uint32_t)hi8[j];
+    else return val[j] >> shift;
   }
 };
 
-template <bool FIRST, bool LAST>
-__global__ __launch_bounds__(JOIN_THREADS) void k_join(
-    Geom G, uint32_t row, const uint32_t *__restrict__ he,
+// The wave items of one join block (see k_join).
+template <bool FIRST, bool LAST, bool TLDS>
+__device__ __forceinline__ void join_items(
+    const Geom &G, uint32_t row, const uint32_t *__restrict__ he,
     const uint2 *__restrict__ in, const uint32_t *__restrict__ in_cnt,
-    const uint32_t *__restrict__ bk_off, const uint32_t *__restrict__ bk_val,
-    DevState *__restrict__ st, uint2 *__restrict__ out, uint32_t *__restrict__ out_cnt,
-    size_t seg_cap, uint32_t *__restrict__ cand, size_t cand_cap) {
-  __shared__ uint16_t t_off[TAB_OFF_MAX];
-  __shared__ __attribute__((aligned(16))) uint8_t t_val[TAB_VAL_BYTES];
-  __shared__ uint32_t w_incl[JOIN_THREADS], w_sub[JOIN_THREADS], w_c0[JOIN_THREADS];
-  __shared__ int32_t w_base[JOIN_THREADS];
-  __shared__ uint32_t seg_fill;
-  if (st->saturated) return;
-
-  const uint32_t nb = 1u << (G.k - G.alpha), M = nb - 1;
-  const uint32_t h = st->he_count[row];
-  const bool wide = G.alpha > 8;
-  const bool lds = nb + 1 <= TAB_OFF_MAX && h < 65536 && G.alpha <= 16 &&
-                   (size_t)h * (wide ? 2 : 1) <= TAB_VAL_BYTES;
-  const uint32_t *g_off = bk_off + (size_t)row * (nb + 1);
-  const uint32_t *g_val = bk_val + ((size_t)row << G.k);
-  if (threadIdx.x == 0) seg_fill = 0;
-  if (lds) {
-    for (uint32_t x = threadIdx.x; x <= nb; x += blockDim.x) t_off[x] = (uint16_t)g_off[x];
-    for (uint32_t x = threadIdx.x; x < h; x += blockDim.x) {
-      const uint32_t hi = g_val[x] >> (G.k - G.alpha);
-      if (wide) reinterpret_cast<uint16_t *>(t_val)[x] = (uint16_t)hi;
-      else t_val[x] = (uint8_t)hi;
-    }
-  }
-  __syncthreads();
-  const JoinTable T{t_off, t_val, reinterpret_cast<const uint16_t *>(t_val), g_off, g_val,
-                    G.k - G.alpha, lds, wide};
-
+    const JoinTable<TLDS> &T, DevState *__restrict__ st, uint2 *__restrict__ out,
+    size_t seg_cap, uint32_t *__restrict__ cand, size_t cand_cap, uint32_t M,
+    LDSP uint32_t *w_incl, LDSP uint32_t *w_sub, LDSP uint32_t *w_c0, LDSP int32_t *w_base,
+    LDSP uint16_t *w_own, LDSP uint32_t *seg_fill_p) {
+  LDSP uint32_t &seg_fill = *seg_fill_p;
   const uint32_t lane = lane_id();
   const uint32_t wib = threadIdx.x >> 6;                    // wave in block
   const uint32_t wpb = blockDim.x >> 6;                     // waves per block
-  uint32_t *W_incl = w_incl + wib * 64, *W_sub = w_sub + wib * 64, *W_c0 = w_c0 + wib * 64;
-  int32_t *W_base = w_base + wib * 64;
+  LDSP uint32_t *W_incl = w_incl + wib * 64, *W_sub = w_sub + wib * 64,
+                *W_c0 = w_c0 + wib * 64;
+  LDSP int32_t *W_base = w_base + wib * 64;
+  LDSP uint16_t *W_own = w_own + wib * OWN_MAX;
   const uint32_t sh = G.shift[row];
   uint2 *seg = LAST ? nullptr : out + (size_t)blockIdx.x * seg_cap;
 
@@ -390,26 +398,55 @@ __global__ __launch_bounds__(JOIN_THREADS) void k_join(
     w_hi = (n_in + 63) >> 6;
   }
 
-  for (uint64_t w = w_lo + wib; w < w_hi; w += wpb) {
-    // ---- this lane's item
-    uint32_t sub = 0, c0 = 0, b0 = 0, cnt = 0;
-    bool valid;
+  // A wave's items are w_lo + wib, + wpb, ...; stage 1's item w is
+  // (x0, xc) = (w / nch, w % nch), stepped without dividing. The next
+  // item's inputs are loaded before the current one is expanded (indices
+  // past the end are clamped: the loads need no branch and stay in bounds).
+  uint64_t w = w_lo + wib;
+  uint32_t x0 = 0, xc = 0;
+  if (FIRST && w < w_hi) {
+    x0 = (uint32_t)(w / nch);
+    xc = (uint32_t)(w - (uint64_t)x0 * nch);
+  }
+  auto load_item = [&](uint64_t wi, uint32_t a0, uint32_t ac, uint32_t &sub_o, uint32_t &c0_o,
+                       bool &valid_o) {
     if (FIRST) {
-      const uint32_t x0 = (uint32_t)(w / nch);
-      const uint32_t x1 = (uint32_t)(w - (uint64_t)x0 * nch) * 64 + lane;
-      valid = x1 < h1;
-      if (valid) {
-        c0 = HE0[x0];
-        sub = c0 ^ HE1[x1];                 // BL(1)
-      }
+      const uint32_t x1 = ac * 64 + lane;
+      valid_o = wi < w_hi && x1 < h1;
+      const uint32_t c0v = HE0[a0];
+      c0_o = c0v;
+      sub_o = c0v ^ HE1[x1 < h1 ? x1 : h1 - 1];     // BL(1)
     } else {
-      const uint32_t t = (uint32_t)w * 64 + lane;
-      valid = t < n_in;
-      if (valid) {
-        const uint2 p = my_in[t];
-        sub = p.x;
-        c0 = p.y;
+      const uint32_t t = (uint32_t)wi * 64 + lane;
+      valid_o = wi < w_hi && t < n_in;
+      const uint2 p = my_in[t < n_in ? t : n_in - 1];
+      sub_o = p.x;
+      c0_o = p.y;
+    }
+  };
+  uint32_t n_sub = 0, n_c0 = 0;
+  bool n_valid = false;
+  if (w < w_hi) load_item(w, x0, xc, n_sub, n_c0, n_valid);
+
+  for (; w < w_hi; w += wpb) {
+    // ---- this lane's item; the next one's loads go out now
+    uint32_t sub = n_sub, c0 = n_c0, b0 = 0, cnt = 0;
+    const bool valid = n_valid;
+    {
+      const uint64_t wn = w + wpb;
+      const uint32_t cx0 = x0, cxc = xc;                   // this item's (x0, xc)
+      if (FIRST) {
+        xc += wpb;
+        while (xc >= nch) {
+          xc -= (uint32_t)nch;
+          x0++;
+        }
       }
+      // past the last item: this item's inputs again (in bounds), unused
+      const bool more = wn < w_hi;
+      if (FIRST) load_item(more ? wn : w, more ? x0 : cx0, more ? xc : cxc, n_sub, n_c0, n_valid);
+      else load_item(more ? wn : w, 0, 0, n_sub, n_c0, n_valid);
+      if (!more) n_valid = false;
     }
     if (valid) {
       const uint32_t key = ((uint32_t)((uint64_t)sub >> sh) ^ c0) & M;
@@ -419,7 +456,15 @@ __global__ __launch_bounds__(JOIN_THREADS) void k_join(
     const uint32_t incl = wave_incl_scan(cnt);
     const uint32_t total = __shfl(incl, 63, 64);
     if (total == 0) continue;
-    W_incl[lane] = incl;
+    // each item writes its own index into its output slots when they fit,
+    // so a slot finds its item with one LDS read; otherwise by a binary
+    // search over the inclusive scan
+    const bool own = total <= OWN_MAX;                 // uniform over the wave
+    if (own) {
+      for (uint32_t q = incl - cnt; q < incl; q++) W_own[q] = (uint16_t)lane;
+    } else {
+      W_incl[lane] = incl;
+    }
     W_base[lane] = (int32_t)b0 - (int32_t)(incl - cnt);
     W_sub[lane] = sub;
     W_c0[lane] = c0;
@@ -431,9 +476,13 @@ __global__ __launch_bounds__(JOIN_THREADS) void k_join(
       uint32_t a = 0, oc0 = 0;
       if (slot < total) {
         uint32_t o = 0;
+        if (own) {
+          o = W_own[slot];
+        } else {
 #pragma unroll
-        for (uint32_t s = 32; s; s >>= 1)
-          if (W_incl[o + s - 1] <= slot) o += s;
+          for (uint32_t s = 32; s; s >>= 1)
+            if (W_incl[o + s - 1] <= slot) o += s;
+        }
         const uint32_t j = (uint32_t)(W_base[o] + (int32_t)slot);
         oc0 = W_c0[o];
         const uint32_t top = (oc0 >> (G.k - G.alpha)) ^ T.top_bits(j);
@@ -451,12 +500,62 @@ __global__ __launch_bounds__(JOIN_THREADS) void k_join(
         if (ok && gb + rank < cand_cap) cand[gb + rank] = a;
       } else {
         uint32_t lb = 0;
-        if (lane == 0) lb = atomicAdd(&seg_fill, n_ok);
+        if (lane == 0) lb = atomicAdd((uint32_t *)&seg_fill, n_ok);   // an LDS atomic after inlining
         lb = __shfl(lb, 0, 64);
         if (ok && (size_t)lb + rank < seg_cap) seg[lb + rank] = make_uint2(a, oc0);
       }
     }
     lds_fence();
+  }
+}
+
+template <bool FIRST, bool LAST>
+__global__ __launch_bounds__(JOIN_THREADS) void k_join(
+    Geom G, uint32_t row, const uint32_t *__restrict__ he,
+    const uint2 *__restrict__ in, const uint32_t *__restrict__ in_cnt,
+    const uint32_t *__restrict__ bk_off, const uint32_t *__restrict__ bk_val,
+    DevState *__restrict__ st, uint2 *__restrict__ out, uint32_t *__restrict__ out_cnt,
+    size_t seg_cap, uint32_t *__restrict__ cand, size_t cand_cap) {
+  __shared__ uint16_t t_off[TAB_OFF_MAX];
+  __shared__ __attribute__((aligned(16))) uint8_t t_val[TAB_VAL_BYTES];
+  __shared__ uint32_t w_incl[JOIN_THREADS], w_sub[JOIN_THREADS], w_c0[JOIN_THREADS];
+  __shared__ int32_t w_base[JOIN_THREADS];
+  __shared__ uint16_t w_own[(JOIN_THREADS / 64) * OWN_MAX];
+  __shared__ uint32_t seg_fill;
+  if (st->saturated) return;
+
+  const uint32_t nb = 1u << (G.k - G.alpha), M = nb - 1;
+  const uint32_t h = st->he_count[row];
+  const bool wide = G.alpha > 8;
+  const bool lds = nb + 1 <= TAB_OFF_MAX && h < 65536 && G.alpha <= 16 &&
+                   (size_t)h * (wide ? 2 : 1) <= TAB_VAL_BYTES;
+  const uint32_t *g_off = bk_off + (size_t)row * (nb + 1);
+  const uint32_t *g_val = bk_val + ((size_t)row << G.k);
+  if (threadIdx.x == 0) seg_fill = 0;
+  if (lds) {
+    for (uint32_t x = threadIdx.x; x <= nb; x += blockDim.x) t_off[x] = (uint16_t)g_off[x];
+    for (uint32_t x = threadIdx.x; x < h; x += blockDim.x) {
+      const uint32_t hi = g_val[x] >> (G.k - G.alpha);
+      if (wide) reinterpret_cast<uint16_t *>(t_val)[x] = (uint16_t)hi;
+      else t_val[x] = (uint8_t)hi;
+    }
+  }
+  __syncthreads();
+  const bool wide_t = wide;
+  if (lds) {
+    const JoinTable<true> T{lds_ptr(t_off), lds_ptr(t_val),
+                            lds_ptr(reinterpret_cast<uint16_t *>(t_val)), g_off, g_val,
+                            G.k - G.alpha, wide_t};
+    join_items<FIRST, LAST, true>(G, row, he, in, in_cnt, T, st, out, seg_cap, cand, cand_cap,
+                                  M, lds_ptr(w_incl), lds_ptr(w_sub), lds_ptr(w_c0),
+                                  lds_ptr(w_base), lds_ptr(w_own), lds_ptr(&seg_fill));
+  } else {
+    const JoinTable<false> T{lds_ptr(t_off), lds_ptr(t_val),
+                             lds_ptr(reinterpret_cast<uint16_t *>(t_val)), g_off, g_val,
+                             G.k - G.alpha, wide_t};
+    join_items<FIRST, LAST, false>(G, row, he, in, in_cnt, T, st, out, seg_cap, cand,
+                                   cand_cap, M, lds_ptr(w_incl), lds_ptr(w_sub), lds_ptr(w_c0),
+                                   lds_ptr(w_base), lds_ptr(w_own), lds_ptr(&seg_fill));
   }
   if (!LAST) {
     __syncthreads();

@@ -591,7 +591,14 @@ static hipError_t launch_r(const UpdJob *h, UpdJob *d, uint32_t nj, uint32_t *d_
     else k_bin_scatter<R, P4, 4096><<<blocks, 1024, 0, st>>>(d, nj);
   }
   k_item_offsets<<<1, 1024, 0, st>>>(d, nj, d_total);
-  k_bin_apply<<<apply_grid, 1024, 0, st>>>(d, nj, d_total);
+  // apply_grid 0: one workgroup per apply item (an upper bound of the
+  // items: a tile with v codes makes at most 1 + v / APPLY_ITEM of them), so
+  // the dispatcher hands items to compute units as they free up
+  uint64_t grid = apply_grid;
+  if (grid == 0)
+    for (uint32_t j = 0; j < nj; j++) grid += h[j].nbins + (uint64_t)R * h[j].n / APPLY_ITEM + 1;
+  if (grid > 0x7FFFFFFFull) grid = 0x7FFFFFFFull;
+  k_bin_apply<<<(uint32_t)grid, 1024, 0, st>>>(d, nj, d_total);
   k_bin_merge<<<dim3(tiles, BIN_TILE_WORDS / MERGE_SLICE), 256, 0, st>>>(d, nj);
   return hipGetLastError();
 }

@@ -43,6 +43,7 @@ SKETCH_OPT_BINNED_ROUND = 5
 SKETCH_OPT_SCATTER_PPT = 6
 SKETCH_OPT_BINNED_BLOCKS = 7
 SKETCH_OPT_TRIM_POOLS = 8
+SKETCH_OPT_APPLY_BLOCKS = 9
 
 c_u32, c_u64, c_i32, c_sz, c_dbl, c_vp = (ctypes.c_uint32, ctypes.c_uint64,
                                           ctypes.c_int32, ctypes.c_size_t,

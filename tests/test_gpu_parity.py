@@ -268,7 +268,8 @@ def test_set_option_rejects_bad_values():
     with make_sketch(oracle.Params()) as sk:
         for opt, val in ((ddhf.SKETCH_OPT_UPDATE_PATH, 3), (ddhf.SKETCH_OPT_UPDATE_GRID, 0),
                          (ddhf.SKETCH_OPT_BINNED_ROUND, 10),
-                         (ddhf.SKETCH_OPT_TRIM_POOLS, -1), (99, 1)):
+                         (ddhf.SKETCH_OPT_TRIM_POOLS, -1), (ddhf.SKETCH_OPT_APPLY_BLOCKS, -1),
+                         (99, 1)):
             with pytest.raises(ddhf.SketchError) as e:
                 sk.set_option(opt, val)
             assert e.value.code == ddhf.SKETCH_E_INVAL

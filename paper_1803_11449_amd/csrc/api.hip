@@ -90,7 +90,7 @@ void dev_free(T *&p) {
 
 // ---------------------------------------------------------- device context
 
-constexpr size_t ARENA_MAX_PAIRS = (size_t)1 << 27;   // pairs per binned launch group
+constexpr size_t ARENA_MAX_PAIRS = MAX_ROUND_PAIRS;   // pairs per binned launch group
 
 struct DevCtx {
   static constexpr int SLOTS = 16;
@@ -382,7 +382,7 @@ struct sketch {
   uint32_t scatter_ppt = 6;
   uint32_t apply_grid = 0;     // blocks of the apply pass (0: one per item)
   uint32_t *hist = nullptr, *totals = nullptr, *base = nullptr, *item_start = nullptr,
-           *xslot = nullptr, *n_items = nullptr;
+           *xslot = nullptr, *n_items = nullptr, *item_tile = nullptr;
   // restore
   DevState *st = nullptr;
   DevState *h_state = nullptr;  // pinned copy of the device state
@@ -405,6 +405,7 @@ void free_sketch(sketch *s) {
   dev_free(s->item_start);
   dev_free(s->xslot);
   dev_free(s->n_items);
+  dev_free(s->item_tile);
   dev_free(s->st);
   dev_free(s->hotmask);
   dev_free(s->he);
@@ -570,6 +571,7 @@ UpdJob job_base(const sketch *s) {
   J.base = s->base;
   J.item_start = s->item_start;
   J.xslot = s->xslot;
+  J.item_tile = s->item_tile;
   J.n_items = s->n_items;
   J.check = (uint32_t)s->update_check;
   return J;
@@ -782,7 +784,7 @@ struct PlanJob {
   double theta = 0;
   Thresholds t{};
   uint32_t *hist = nullptr, *totals = nullptr, *base = nullptr, *item_start = nullptr,
-           *xslot = nullptr, *n_items = nullptr;
+           *xslot = nullptr, *n_items = nullptr, *item_tile = nullptr;
   DevState *st = nullptr;
   DevState *h_state = nullptr;  // pinned
   uint4 *sorted = nullptr;
@@ -836,6 +838,7 @@ void plan_free(sketch_plan *P) {
     dev_free(j.item_start);
     dev_free(j.xslot);
     dev_free(j.n_items);
+    dev_free(j.item_tile);
     dev_free(j.st);
     dev_free(j.sorted);
     if (j.h_state) (void)hipHostFree(j.h_state);
@@ -985,6 +988,7 @@ int sketch_create(const sketch_params_t *params, sketch_t **out) {
     if (!rc) rc = dev_alloc(&s->base, s->nbins + 1, "tile runs");
     if (!rc) rc = dev_alloc(&s->item_start, s->nbins + 1, "tile items");
     if (!rc) rc = dev_alloc(&s->xslot, s->nbins + 1, "tile scratch slots");
+    if (!rc) rc = dev_alloc(&s->item_tile, ITEM_TILE_SLOTS(s->nbins), "item tiles");
     if (!rc) rc = dev_alloc(&s->n_items, 1, "tile item count");
   }
   if (!rc && hipHostMalloc((void **)&s->h_state, sizeof(DevState)) != hipSuccess) {
@@ -1284,6 +1288,7 @@ int sketch_plan_create(const sketch_plan_job_t *jobs, size_t n_jobs, int flags,
       if (!rc) rc = dev_alloc(&pj.base, s->nbins + 1, "plan tile runs");
       if (!rc) rc = dev_alloc(&pj.item_start, s->nbins + 1, "plan tile items");
       if (!rc) rc = dev_alloc(&pj.xslot, s->nbins + 1, "plan tile scratch slots");
+      if (!rc) rc = dev_alloc(&pj.item_tile, ITEM_TILE_SLOTS(s->nbins), "plan item tiles");
       if (!rc) rc = dev_alloc(&pj.n_items, 1, "plan tile item count");
     }
     if (!rc) rc = dev_alloc(&pj.st, 1, "plan state");
@@ -1311,6 +1316,7 @@ int sketch_plan_create(const sketch_plan_job_t *jobs, size_t n_jobs, int flags,
           J.item_start = pj.item_start;
           J.xslot = pj.xslot;
           J.n_items = pj.n_items;
+          J.item_tile = pj.item_tile;
           return J;
         },
         [&](Group &g) {

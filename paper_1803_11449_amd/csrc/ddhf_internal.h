@@ -103,12 +103,21 @@ struct UpdJob {
   uint32_t hstride;      // row stride of hist (>= nblk)
   uint32_t pad0;
   uint32_t *hist, *totals, *base, *item_start, *xslot, *n_items;
+  uint32_t *item_tile;   // tile of each apply item (ITEM_TILE_SLOTS(nbins) entries)
   uint32_t *codes, *scratch;
   uint32_t item0;        // first global apply item (written on the device)
   uint32_t check;        // direct kernel: test the bit before the atomicOr
 };
 
 constexpr uint32_t MAX_JOBS = 256;     // jobs per launch group
+
+// Pairs of one job in one binned round, at most; it bounds the apply items
+// of a job: a tile with v codes makes at most 1 + v / APPLY_ITEM of them,
+// and a round has at most 8 * MAX_ROUND_PAIRS codes.
+constexpr uint64_t MAX_ROUND_PAIRS = (uint64_t)1 << 27;
+constexpr uint64_t ITEM_TILE_SLOTS(uint32_t nbins) {
+  return (uint64_t)nbins + 8 * MAX_ROUND_PAIRS / APPLY_ITEM + 1;
+}
 
 // Launches one update round for n_jobs jobs that share r: `h_jobs` is the
 // host copy (blk0 / tile0 / nblk filled in), `d_jobs` its device copy

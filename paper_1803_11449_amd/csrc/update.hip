@@ -249,6 +249,7 @@ __global__ __launch_bounds__(1024) void k_bin_scan_tiles(const UpdJob *__restric
   const uint32_t nbins = J.nbins;
   const GMEM uint32_t *totals = gmem(J.totals);
   GMEM uint32_t *base = gmem(J.base), *item_start = gmem(J.item_start), *xslot = gmem(J.xslot);
+  GMEM uint32_t *item_tile = gmem(J.item_tile);
   constexpr uint32_t PER = (BIN_MAX + 1) / 1024;
   const uint32_t t0 = threadIdx.x * PER;
   uint32_t c = 0, it = 0, xs = 0;
@@ -274,6 +275,7 @@ __global__ __launch_bounds__(1024) void k_bin_scan_tiles(const UpdJob *__restric
       base[t] = ec;
       item_start[t] = ei;
       xslot[t] = ex;
+      for (uint32_t q = 0; q < ni; q++) item_tile[ei + q] = t;
       ec += v;
       ei += ni;
       ex += ni > 1 ? ni - 1 : 0;
@@ -445,19 +447,15 @@ constexpr int APPLY_UNROLL = 4;
 
 __global__ __launch_bounds__(1024) void k_bin_apply(const UpdJob *__restrict__ jobs, uint32_t nj,
                                                     const uint32_t *__restrict__ n_items_p) {
-  __shared__ uint32_t tile[BIN_TILE_WORDS];
+  __shared__ __attribute__((aligned(16))) uint32_t tile[BIN_TILE_WORDS];
+  constexpr uint32_t TV4 = BIN_TILE_WORDS / 4 / 1024;      // uint4 per thread per tile
+  uint4 *tile4 = reinterpret_cast<uint4 *>(tile);
   const uint32_t n_items = *n_items_p;
   for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const UpdJob &J = jobs[job_of_item(jobs, nj, it)];
     const uint32_t jit = it - J.item0;
     const GMEM uint32_t *item_start = gmem(J.item_start), *base = gmem(J.base);
-    // tile of this item: the largest t with item_start[t] <= jit
-    uint32_t lo = 0, hi = J.nbins;
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (item_start[mid] <= jit) lo = mid; else hi = mid;
-    }
-    const uint32_t t = lo;
+    const uint32_t t = gmem(J.item_tile)[jit];                // tile of this item
     const uint32_t sub = jit - item_start[t];
     const bool whole = item_start[t + 1] - item_start[t] == 1;
     const uint32_t c_end = base[t + 1];
@@ -471,10 +469,19 @@ __global__ __launch_bounds__(1024) void k_bin_apply(const UpdJob *__restrict__ j
     GMEM uint32_t *dstp =
         sub == 0 ? gmem(J.sk) + w0
                  : gmem(J.scratch) + (size_t)(gmem(J.xslot)[t] + sub - 1) * BIN_TILE_WORDS;
-    if (sub == 0) {
-      for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) tile[w] = dstp[w];
-    } else {
+    // the tile in: a whole tile as 16-byte loads, all in flight before the
+    // LDS writes (tiles and scratch tiles are 128 KiB aligned)
+    if (sub != 0) {
       for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) tile[w] = 0;
+    } else if (tw == BIN_TILE_WORDS) {
+      const GMEM uint4 *src = reinterpret_cast<const GMEM uint4 *>(dstp);
+      uint4 v[TV4];
+#pragma unroll
+      for (uint32_t u = 0; u < TV4; u++) v[u] = ld4(src + threadIdx.x + u * 1024);
+#pragma unroll
+      for (uint32_t u = 0; u < TV4; u++) tile4[threadIdx.x + u * 1024] = v[u];
+    } else {
+      for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) tile[w] = dstp[w];
     }
     __syncthreads();
     // codes [c0,c1): a scalar head up to a 4-aligned index, uint4 body,
@@ -515,7 +522,16 @@ __global__ __launch_bounds__(1024) void k_bin_apply(const UpdJob *__restrict__ j
       atomicOr(&tile[x >> 5], 1u << (x & 31));
     }
     __syncthreads();
-    for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) dstp[w] = tile[w];
+    if (tw == BIN_TILE_WORDS) {
+      GMEM uint4 *d4 = reinterpret_cast<GMEM uint4 *>(dstp);
+      uint4 v[TV4];
+#pragma unroll
+      for (uint32_t u = 0; u < TV4; u++) v[u] = tile4[threadIdx.x + u * 1024];
+#pragma unroll
+      for (uint32_t u = 0; u < TV4; u++) st4(d4 + threadIdx.x + u * 1024, v[u]);
+    } else {
+      for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) dstp[w] = tile[w];
+    }
     __syncthreads();
   }
 }

@@ -280,9 +280,10 @@ enum {
                                        both grow again on demand. Frees device
                                        memory for callers under a budget */
   SKETCH_OPT_APPLY_BLOCKS = 9       /* binned: blocks of the apply pass;
-                                       0 = one per apply item (the dispatcher
-                                       balances uneven tiles), else that many
-                                       blocks striding over the items */
+                                       0 = one per apply item (default: the
+                                       dispatcher balances uneven tiles), else
+                                       that many blocks striding over the
+                                       items */
 };
 
 /* Set a tuning option; results never depend on it. Errors: INVAL (NULL

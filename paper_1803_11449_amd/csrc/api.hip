@@ -88,6 +88,30 @@ void dev_free(T *&p) {
   p = nullptr;
 }
 
+// Pinned host memory for `count` T and the address kernels write it at.
+template <typename T>
+int pinned_alloc(T **h, T **d, size_t count, const char *what) {
+  *h = nullptr;
+  *d = nullptr;
+  if (hipHostMalloc((void **)h, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
+    *h = nullptr;
+    return fail(SKETCH_E_NOMEM, "hipHostMalloc(%s, %zu bytes) failed", what, count * sizeof(T));
+  }
+  if (hipHostGetDevicePointer((void **)d, *h, 0) != hipSuccess) {
+    (void)hipHostFree(*h);
+    *h = nullptr;
+    return fail(SKETCH_E_HIP, "hipHostGetDevicePointer(%s) failed", what);
+  }
+  return SKETCH_OK;
+}
+
+template <typename T>
+void pinned_free(T *&h, T *&d) {
+  if (h) (void)hipHostFree((void *)h);
+  h = nullptr;
+  d = nullptr;
+}
+
 // ---------------------------------------------------------- device context
 
 constexpr size_t ARENA_MAX_PAIRS = MAX_ROUND_PAIRS;   // pairs per binned launch group
@@ -385,14 +409,16 @@ struct sketch {
            *xslot = nullptr, *n_items = nullptr, *item_tile = nullptr;
   // restore
   DevState *st = nullptr;
-  DevState *h_state = nullptr;  // pinned copy of the device state
+  DevState *h_state = nullptr, *d_h_state = nullptr;   // pinned copy of the device state
+  uint4 *h_recs = nullptr, *d_h_recs = nullptr;         // pinned copy of the records
+  size_t h_recs_cap = 0;
   uint32_t *hotmask = nullptr, *he = nullptr, *bk_off = nullptr, *bk_cur = nullptr,
            *bk_val = nullptr;
   uint4 *spl_sorted = nullptr;
   size_t spl_sorted_cap = 0;
   // capacities the last enqueued restore ran with (the pools may grow
   // between its launch and its check when restores are batched)
-  size_t ran_seg_cap = 0, ran_cand_cap = 0, ran_spl_cap = 0;
+  size_t ran_seg_cap = 0, ran_cand_cap = 0, ran_spl_cap = 0, ran_h_recs_cap = 0;
 };
 
 namespace {
@@ -413,8 +439,9 @@ void free_sketch(sketch *s) {
   dev_free(s->bk_cur);
   dev_free(s->bk_val);
   dev_free(s->spl_sorted);
-  if (s->h_state) (void)hipHostFree(s->h_state);
-  s->h_state = nullptr;
+  pinned_free(s->h_state, s->d_h_state);
+  pinned_free(s->h_recs, s->d_h_recs);
+  s->h_recs_cap = 0;
   ctx_release(s->ctx);
   s->ctx = nullptr;
 }
@@ -450,7 +477,30 @@ RestoreBufs restore_bufs(const sketch *s) {
   B.spl_sorted = s->spl_sorted;
   B.spl_cap = std::min(c->spl_cap, s->spl_sorted_cap);
   B.rank = c->rank;
+  B.h_state = s->d_h_state;
+  B.h_recs = s->d_h_recs;
+  B.h_recs_cap = s->h_recs_cap;
   return B;
+}
+
+// The records of the restore that just finished into host memory `out`:
+// from the pinned copy the restore wrote when it fit, else from the device
+// (and the pinned buffer grows for the next restore). Caller holds ctx->mu.
+int copy_records(sketch *s, sketch_sp_t *out, size_t n, size_t published_cap, hipStream_t st) {
+  static_assert(sizeof(sketch_sp_t) == sizeof(uint4), "record layout");
+  if (n == 0) return SKETCH_OK;
+  if (n <= published_cap) {
+    memcpy(out, s->h_recs, n * sizeof(uint4));
+    return SKETCH_OK;
+  }
+  HIP_OK(hipMemcpyAsync(out, s->spl_sorted, n * sizeof(uint4), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  pinned_free(s->h_recs, s->d_h_recs);
+  s->h_recs_cap = 0;
+  const size_t cap = n + n / 2;
+  int rc = pinned_alloc(&s->h_recs, &s->d_h_recs, cap, "records");
+  if (!rc) s->h_recs_cap = cap;
+  return rc;
 }
 
 void fill_info(const sketch *s, const DevState &st, double zmin, uint32_t zhot,
@@ -498,8 +548,8 @@ int restore_launch(sketch *s, const Thresholds &t, int estimate, hipStream_t st)
   s->ran_seg_cap = B.seg_cap;
   s->ran_cand_cap = B.cand_cap;
   s->ran_spl_cap = B.spl_cap;
+  s->ran_h_recs_cap = B.h_recs_cap;
   HIP_OK(launch_restore(s->G, s->d_sketch, B, t.zhot, t.e_theta, estimate, s->grid, st));
-  HIP_OK(hipMemcpyAsync(s->h_state, s->st, sizeof(DevState), hipMemcpyDeviceToHost, st));
   return pool_leave(c, st);
 }
 
@@ -786,7 +836,9 @@ struct PlanJob {
   uint32_t *hist = nullptr, *totals = nullptr, *base = nullptr, *item_start = nullptr,
            *xslot = nullptr, *n_items = nullptr, *item_tile = nullptr;
   DevState *st = nullptr;
-  DevState *h_state = nullptr;  // pinned
+  DevState *h_state = nullptr, *d_h_state = nullptr;   // pinned
+  uint4 *h_recs = nullptr, *d_h_recs = nullptr;         // pinned
+  size_t h_recs_cap = 0, ran_h_recs_cap = 0;
   uint4 *sorted = nullptr;
   size_t sorted_cap = 0;
   size_t ran_spl_cap = 0;       // record capacity the captured restore has
@@ -841,7 +893,8 @@ void plan_free(sketch_plan *P) {
     dev_free(j.item_tile);
     dev_free(j.st);
     dev_free(j.sorted);
-    if (j.h_state) (void)hipHostFree(j.h_state);
+    pinned_free(j.h_state, j.d_h_state);
+    pinned_free(j.h_recs, j.d_h_recs);
   }
   for (PlanLaunch &L : P->launches) {
     dev_free(L.d);
@@ -864,6 +917,9 @@ RestoreBufs plan_restore_bufs(const sketch_plan *P, const PlanJob &j) {
   B.st = j.st;
   B.spl_sorted = j.sorted;
   B.spl_cap = std::min(P->ctx->spl_cap, j.sorted_cap);
+  B.h_state = j.d_h_state;
+  B.h_recs = j.d_h_recs;
+  B.h_recs_cap = j.h_recs_cap;
   return B;
 }
 
@@ -880,7 +936,6 @@ int plan_enqueue(sketch_plan *P, hipStream_t st) {
     for (PlanJob &j : P->jobs) {
       HIP_OK(launch_restore(j.s->G, j.s->d_sketch, plan_restore_bufs(P, j), j.t.zhot,
                             j.t.e_theta, 1, j.s->grid, st));
-      HIP_OK(hipMemcpyAsync(j.h_state, j.st, sizeof(DevState), hipMemcpyDeviceToHost, st));
     }
   return SKETCH_OK;
 }
@@ -911,7 +966,10 @@ int plan_build_graph(sketch_plan *P) {
   HIP_OK(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
   P->ran_seg_cap = c->seg_cap;
   P->ran_cand_cap = c->cand_cap;
-  for (PlanJob &j : P->jobs) j.ran_spl_cap = std::min(c->spl_cap, j.sorted_cap);
+  for (PlanJob &j : P->jobs) {
+    j.ran_spl_cap = std::min(c->spl_cap, j.sorted_cap);
+    j.ran_h_recs_cap = j.h_recs_cap;
+  }
   P->gen = c->gen;
   P->dirty = false;
   return SKETCH_OK;
@@ -993,10 +1051,9 @@ int sketch_create(const sketch_params_t *params, sketch_t **out) {
     if (!rc) rc = dev_alloc(&s->item_tile, ITEM_TILE_SLOTS(s->nbins), "item tiles");
     if (!rc) rc = dev_alloc(&s->n_items, 1, "tile item count");
   }
-  if (!rc && hipHostMalloc((void **)&s->h_state, sizeof(DevState)) != hipSuccess) {
-    s->h_state = nullptr;
-    rc = fail(SKETCH_E_NOMEM, "hipHostMalloc(state) failed");
-  }
+  if (!rc) rc = pinned_alloc(&s->h_state, &s->d_h_state, 1, "state");
+  if (!rc) rc = pinned_alloc(&s->h_recs, &s->d_h_recs, (size_t)1 << 12, "records");
+  if (!rc) s->h_recs_cap = (size_t)1 << 12;
   if (!rc) {
     hipError_t e = launch_fill_u32(s->d_sketch, s->words, 0u, s->grid, nullptr);
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
@@ -1073,12 +1130,7 @@ int sketch_restore(sketch_t *s, double theta, sketch_sp_t *out, size_t cap, size
   *n_out = (size_t)h.n_spl;
   if (h.n_spl > cap)
     return fail(SKETCH_E_CAPACITY, "sketch_restore: %llu records, cap %zu", h.n_spl, cap);
-  static_assert(sizeof(sketch_sp_t) == sizeof(uint4), "record layout");
-  if (h.n_spl)
-    HIP_OK(hipMemcpyAsync(out, s->spl_sorted, h.n_spl * sizeof(uint4), hipMemcpyDeviceToHost,
-                          st));
-  HIP_OK(hipStreamSynchronize(st));
-  return SKETCH_OK;
+  return copy_records(s, out, (size_t)h.n_spl, s->ran_h_recs_cap, st);
 }
 
 int sketch_restore_batch(sketch_restore_job_t *jobs, size_t n_jobs, void *hip_stream) {
@@ -1124,15 +1176,11 @@ int sketch_restore_batch(sketch_restore_job_t *jobs, size_t n_jobs, void *hip_st
       fill_info(s, h, th[j].zmin, th[j].zhot, J.info);
     J.n_out = rc == SKETCH_OK ? (size_t)h.n_spl : 0;
     if (rc == SKETCH_OK && h.n_spl > J.cap) rc = SKETCH_E_CAPACITY;
-    if (rc == SKETCH_OK && h.n_spl) {
-      hipError_t e = hipMemcpyAsync(J.out, s->spl_sorted, h.n_spl * sizeof(uint4),
-                                    hipMemcpyDeviceToHost, st);
-      if (e != hipSuccess) rc = SKETCH_E_HIP;
-    }
+    if (rc == SKETCH_OK)
+      rc = copy_records(s, J.out, (size_t)h.n_spl, s->ran_h_recs_cap, st);
     J.status = rc;
     if (rc && !first_err) first_err = rc;
   }
-  HIP_OK(hipStreamSynchronize(st));
   if (first_err)
     return fail(first_err, "sketch_restore_batch: a job failed (see each job's status)");
   return SKETCH_OK;
@@ -1295,10 +1343,9 @@ int sketch_plan_create(const sketch_plan_job_t *jobs, size_t n_jobs, int flags,
     }
     if (!rc) rc = dev_alloc(&pj.st, 1, "plan state");
     if (!rc) rc = plan_alloc_sorted(pj, std::max<size_t>(s->spl_sorted_cap, (size_t)1 << 12));
-    if (!rc && hipHostMalloc((void **)&pj.h_state, sizeof(DevState)) != hipSuccess) {
-      pj.h_state = nullptr;
-      rc = fail(SKETCH_E_NOMEM, "hipHostMalloc(plan state) failed");
-    }
+    if (!rc) rc = pinned_alloc(&pj.h_state, &pj.d_h_state, 1, "plan state");
+    if (!rc) rc = pinned_alloc(&pj.h_recs, &pj.d_h_recs, pj.sorted_cap, "plan records");
+    if (!rc) pj.h_recs_cap = pj.sorted_cap;
   }
   if (!rc && hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking) != hipSuccess) {
     P->cap = nullptr;
@@ -1437,14 +1484,28 @@ int sketch_plan_results(sketch_plan_t *P, sketch_restore_job_t *out, size_t n_ou
     }
     if (rc == SKETCH_OK || rc == SKETCH_E_SATURATED)
       fill_info(s, *h, pj.t.zmin, pj.t.zhot, J.info);
-    J.n_out = rc == SKETCH_OK ? (size_t)h->n_spl : 0;
-    if (rc == SKETCH_OK && h->n_spl > J.cap) rc = SKETCH_E_CAPACITY;
-    if (rc == SKETCH_OK && h->n_spl) {
-      hipError_t e = hipMemcpyAsync(J.out, src, h->n_spl * sizeof(uint4), hipMemcpyDeviceToHost,
-                                    st);
-      // an eager rerun's output is the sketch's own buffer: copy it out now
-      if (e == hipSuccess && pj.eager) e = hipStreamSynchronize(st);
-      if (e != hipSuccess) rc = SKETCH_E_HIP;
+    const size_t n = rc == SKETCH_OK ? (size_t)h->n_spl : 0;
+    J.n_out = n;
+    if (rc == SKETCH_OK && n > J.cap) rc = SKETCH_E_CAPACITY;
+    if (rc == SKETCH_OK && n) {
+      if (pj.eager) {
+        rc = copy_records(s, J.out, n, s->ran_h_recs_cap, st);   // the sketch's own copy
+      } else if (n <= pj.ran_h_recs_cap) {
+        memcpy(J.out, pj.h_recs, n * sizeof(uint4));
+      } else {
+        // more records than the pinned copy holds: from the device, and a
+        // larger pinned copy for the next runs (the graph is captured again)
+        hipError_t e = hipMemcpyAsync(J.out, src, n * sizeof(uint4), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = SKETCH_E_HIP;
+        if (!rc && n > pj.h_recs_cap) {
+          pinned_free(pj.h_recs, pj.d_h_recs);
+          pj.h_recs_cap = 0;
+          rc = pinned_alloc(&pj.h_recs, &pj.d_h_recs, n + n / 2, "plan records");
+          if (!rc) pj.h_recs_cap = n + n / 2;
+          P->dirty = true;
+        }
+      }
     }
     J.status = rc;
     if (rc && !first_err) first_err = rc;

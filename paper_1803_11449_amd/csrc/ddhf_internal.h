@@ -73,6 +73,11 @@ struct RestoreBufs {
   size_t spl_cap;
   uint32_t *cand_sorted;
   uint32_t *rank;         // sort ranks (16384 entries)
+  // pinned host memory (device-side addresses) the last step writes: the
+  // device state and the first min(n, h_recs_cap) sorted records
+  DevState *h_state;
+  uint4 *h_recs;          // may be null (no records published)
+  size_t h_recs_cap;
 };
 
 // Binned update (update.hip): the sketch is cut into 128 KiB tiles; a code

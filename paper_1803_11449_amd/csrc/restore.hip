@@ -721,6 +721,28 @@ static void launch_sort(const T *in, const unsigned long long *count, size_t cap
   k_rank_sort<T><<<grid, 256, 0, st>>>(in, count, cap, out);
 }
 
+// ---------------------------------------------------------------- 8: publish
+
+// The device state and the first min(n, cap) sorted records written straight
+// into pinned host memory, so the caller waits once for the whole restore.
+__global__ __launch_bounds__(256) void k_publish(const DevState *__restrict__ st,
+                                                 const uint4 *__restrict__ recs, size_t recs_cap,
+                                                 DevState *h_state, uint4 *h_recs,
+                                                 size_t h_cap) {
+  if (blockIdx.x == 0) {
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(st);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(h_state);
+    for (uint32_t i = threadIdx.x; i < sizeof(DevState) / 4; i += blockDim.x) dst[i] = src[i];
+  }
+  if (!h_recs) return;
+  uint64_t n = st->saturated ? 0 : st->n_spl;
+  if (n > recs_cap) n = recs_cap;
+  if (n > h_cap) n = h_cap;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    h_recs[i] = recs[i];
+}
+
 // ------------------------------------------------------------ orchestration
 
 template <int WPL>
@@ -776,6 +798,7 @@ static hipError_t launch_wpl(const Geom &G, const uint32_t *sketch, const Restor
   }
   if (!estimate) {
     launch_sort<uint32_t>(B.cand, &B.st->n_cand, B.cand_cap, B.cand_sorted, B.rank, grid, st);
+    k_publish<<<1, 256, 0, st>>>(B.st, nullptr, 0, B.h_state, nullptr, 0);
     return hipGetLastError();
   }
   // 6: estimate and report
@@ -783,6 +806,9 @@ static hipError_t launch_wpl(const Geom &G, const uint32_t *sketch, const Restor
                                         B.spl_cap);
   // 7: sort
   launch_sort<uint4>(B.spl, &B.st->n_spl, B.spl_cap, B.spl_sorted, B.rank, grid, st);
+  // 8: state and records to the host
+  k_publish<<<16, 256, 0, st>>>(B.st, B.spl_sorted, B.spl_cap, B.h_state, B.h_recs,
+                                B.h_recs_cap);
   return hipGetLastError();
 }
 

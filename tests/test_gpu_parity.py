@@ -360,10 +360,14 @@ def test_more_super_points_than_the_small_sort():
     with make_sketch(p) as sk:
         sk.update(to_dev(pairs))
         recs, info = sk.restore(1024.0)
+        # the first list outgrew the pinned host copy (it came from the
+        # device); the second comes through the grown pinned copy
+        again, _ = sk.restore(1024.0)
     assert len(recs) > 16384
     ip, sz, c, _ = oracle.restore(p, ref, 1024.0, mode="brute")
     assert_not_boundary(info)
     assert_spl_equal(recs, ip, sz, c)
+    assert np.array_equal(again, recs)
 
 
 def test_empty_and_saturated_sketch():

@@ -318,7 +318,7 @@ __device__ __forceinline__ void lds_fence() {
 }
 constexpr uint32_t TAB_OFF_MAX = 8193;          // bucket offsets held in LDS
 constexpr uint32_t OWN_MAX = 512;               // output slots per wave pass set
-constexpr uint32_t TAB_VAL_BYTES = 32768;       // bucket entries held in LDS
+constexpr uint32_t TAB_VAL_BYTES = 16384;       // bucket entries held in LDS (3 blocks per CU)
 
 // Bits of the address from block i >= 2: alpha new bits at k + (i-2)*alpha.
 // top = the new bits; false if any lands at or above bit 32.

@@ -147,6 +147,7 @@ struct DevCtx {
   // last work that used the arena or the pool
   hipEvent_t pool_ev = nullptr;
   bool pool_armed = false;
+  hipStream_t pool_stream = nullptr;   // stream of that work
   uint64_t gen = 0;              // bumped whenever the arena or the pool moves
 };
 
@@ -155,13 +156,15 @@ DevCtx *g_ctx[256] = {};
 
 // Order work about to be enqueued on st after the last use of the pools.
 int pool_enter(DevCtx *c, hipStream_t st) {
-  if (c->pool_armed) HIP_OK(hipStreamWaitEvent(st, c->pool_ev, 0));
+  // work on the stream that used the pools last is ordered after it anyway
+  if (c->pool_armed && st != c->pool_stream) HIP_OK(hipStreamWaitEvent(st, c->pool_ev, 0));
   return SKETCH_OK;
 }
 
 int pool_leave(DevCtx *c, hipStream_t st) {
   HIP_OK(hipEventRecord(c->pool_ev, st));
   c->pool_armed = true;
+  c->pool_stream = st;
   return SKETCH_OK;
 }
 

@@ -95,10 +95,19 @@ __device__ __forceinline__ LDSP T *lds_ptr(T *p) {
 
 // ----------------------------------------------------------- 0: state init
 
-__global__ void k_state_init(DevState *st, uint32_t *rank, uint32_t n_rank) {
-  uint32_t *p = reinterpret_cast<uint32_t *>(st);
-  for (uint32_t i = threadIdx.x; i < sizeof(DevState) / 4; i += blockDim.x) p[i] = 0;
-  for (uint32_t i = threadIdx.x; i < n_rank; i += blockDim.x) rank[i] = 0;
+// The device state, the sort ranks and the hot bitmap back to zero, in one
+// launch.
+__global__ __launch_bounds__(256) void k_restore_init(DevState *st, uint32_t *rank,
+                                                      uint32_t n_rank, uint32_t *hotmask,
+                                                      size_t n_hm) {
+  const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  if (blockIdx.x == 0) {
+    uint32_t *p = reinterpret_cast<uint32_t *>(st);
+    for (uint32_t i = threadIdx.x; i < sizeof(DevState) / 4; i += blockDim.x) p[i] = 0;
+  }
+  for (size_t i = i0; i < n_rank; i += stride) rank[i] = 0;
+  for (size_t i = i0; i < n_hm; i += stride) hotmask[i] = 0;
 }
 
 // -------------------------------------------------------------- 1: hot scan
@@ -176,12 +185,10 @@ __global__ __launch_bounds__(256) void k_hot_scan(Geom G, const uint32_t *__rest
 
 // ---------------------------------------------------------- 2: HE compaction
 
-__global__ __launch_bounds__(1024) void k_he_compact(Geom G,
-                                                     const uint32_t *__restrict__ hotmask,
-                                                     uint32_t *__restrict__ he,
-                                                     DevState *__restrict__ st) {
-  __shared__ uint32_t sh[17];
-  const uint32_t row = blockIdx.x;
+__device__ __forceinline__ void compact_row(const Geom &G, uint32_t row,
+                                            const uint32_t *__restrict__ hotmask,
+                                            uint32_t *__restrict__ he,
+                                            DevState *__restrict__ st, uint32_t *sh) {
   const uint32_t nw = (1u << G.k) >> 5;
   const uint32_t *hm = hotmask + (size_t)row * nw;
   const uint32_t per = (nw + blockDim.x - 1) / blockDim.x;
@@ -242,27 +249,9 @@ __device__ __forceinline__ void bucket_rows(const Geom &G, uint32_t row, const u
   }
 }
 
-__global__ __launch_bounds__(1024) void k_buckets(Geom G, const uint32_t *__restrict__ he,
-                                                  uint32_t *__restrict__ bk_off,
-                                                  uint32_t *__restrict__ bk_cur,
-                                                  uint32_t *__restrict__ bk_val,
-                                                  const DevState *__restrict__ st) {
-  __shared__ uint32_t sh[17];
-  __shared__ uint32_t lcur[BK_LDS];
-  const uint32_t row = blockIdx.x + 2;
-  const uint32_t nb = 1u << (G.k - G.alpha);
-  uint32_t *off = bk_off + (size_t)row * (nb + 1);
-  const uint32_t *h = he + ((size_t)row << G.k);
-  uint32_t *val = bk_val + ((size_t)row << G.k);
-  const uint32_t n = st->he_count[row];
-  if (nb <= BK_LDS) bucket_rows(G, row, h, n, off, lds_ptr(lcur), val, sh);
-  else bucket_rows(G, row, h, n, off, bk_cur + (size_t)row * nb, val, sh);
-}
-
 // --------------------------------------------------------------- 4: scalars
 
-__global__ void k_scalars(Geom G, DevState *st, double e_theta) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ __forceinline__ void scalars(const Geom &G, DevState *st, double e_theta) {
   const double m = (double)G.g * (double)(1ull << G.k);
   double lsum = 0.0;
   for (uint32_t i = 0; i < G.r; i++) {
@@ -285,6 +274,31 @@ __global__ void k_scalars(Geom G, DevState *st, double e_theta) {
   st->d = d;
   st->trep = trep;
   st->szmax = (uint32_t)floor(trep);
+}
+
+// One block per row i: HE(i) from the hot bitmap (step 2), its bucket table
+// when i >= 2 (step 3), and in row 0's block the scalars (step 4), which
+// need only the ZR(i) of the hot scan.
+__global__ __launch_bounds__(1024) void k_rows(Geom G, const uint32_t *__restrict__ hotmask,
+                                               uint32_t *__restrict__ he,
+                                               uint32_t *__restrict__ bk_off,
+                                               uint32_t *__restrict__ bk_cur,
+                                               uint32_t *__restrict__ bk_val,
+                                               DevState *__restrict__ st, double e_theta) {
+  __shared__ uint32_t sh[17];
+  __shared__ uint32_t lcur[BK_LDS];
+  const uint32_t row = blockIdx.x;
+  compact_row(G, row, hotmask, he, st, sh);
+  if (row == 0 && threadIdx.x == 0) scalars(G, st, e_theta);
+  if (row < 2) return;                                 // uniform over the block
+  __syncthreads();                                     // this row's HE and count
+  const uint32_t nb = 1u << (G.k - G.alpha);
+  uint32_t *off = bk_off + (size_t)row * (nb + 1);
+  const uint32_t *h = he + ((size_t)row << G.k);
+  uint32_t *val = bk_val + ((size_t)row << G.k);
+  const uint32_t n = st->he_count[row];
+  if (nb <= BK_LDS) bucket_rows(G, row, h, n, off, lds_ptr(lcur), val, sh);
+  else bucket_rows(G, row, h, n, off, bk_cur + (size_t)row * nb, val, sh);
 }
 
 // ------------------------------------------------------------------ 5: join
@@ -670,27 +684,23 @@ __global__ __launch_bounds__(256) void k_rank_count(const T *__restrict__ in,
   if (c) atomicAdd(&rank[j], c);
 }
 
+// Lists of up to SMALL_SORT records: each record goes to its counted rank.
+// Longer lists: every record ranks itself against all keys, a tile of keys
+// at a time through LDS (grid-stride over the records).
 template <typename T>
 __global__ __launch_bounds__(256) void k_rank_place(const T *__restrict__ in,
                                                     const unsigned long long *__restrict__ count,
                                                     size_t cap, const uint32_t *__restrict__ rank,
                                                     T *__restrict__ out) {
-  const unsigned long long n_all = *count;
-  const uint32_t n = (uint32_t)(n_all < cap ? n_all : cap);
-  if (n > SMALL_SORT) return;
-  const uint32_t j = blockIdx.x * 256 + threadIdx.x;
-  if (j < n) out[rank[j]] = in[j];
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_rank_sort(const T *__restrict__ in,
-                                                   const unsigned long long *__restrict__ count,
-                                                   size_t cap, T *__restrict__ out) {
   constexpr int TILE = 2048;
   __shared__ uint32_t tile[TILE];
   const unsigned long long n_all = *count;
   const uint64_t n = n_all < cap ? n_all : cap;
-  if (n <= SMALL_SORT) return;
+  if (n <= SMALL_SORT) {
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j < n) out[rank[j]] = in[j];
+    return;
+  }
   for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n;
        base += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t j = base + threadIdx.x;
@@ -700,15 +710,15 @@ __global__ __launch_bounds__(256) void k_rank_sort(const T *__restrict__ in,
       mine = in[j];
       key = sort_key<T>(mine);
     }
-    uint32_t rank = 0;
+    uint32_t rk = 0;
     for (uint64_t t0 = 0; t0 < n; t0 += TILE) {
       const uint32_t len = (uint32_t)((n - t0) < TILE ? (n - t0) : TILE);
       __syncthreads();
       for (uint32_t t = threadIdx.x; t < len; t += blockDim.x) tile[t] = sort_key<T>(in[t0 + t]);
       __syncthreads();
-      for (uint32_t t = 0; t < len; t++) rank += tile[t] < key;
+      for (uint32_t t = 0; t < len; t++) rk += tile[t] < key;
     }
-    if (j < n) out[rank] = mine;
+    if (j < n) out[rk] = mine;
   }
 }
 
@@ -717,8 +727,8 @@ template <typename T>
 static void launch_sort(const T *in, const unsigned long long *count, size_t cap, T *out,
                         uint32_t *rank, int grid, hipStream_t st) {
   k_rank_count<T><<<dim3(SMALL_SORT / 256, RANK_SPLIT), 256, 0, st>>>(in, count, cap, rank);
-  k_rank_place<T><<<SMALL_SORT / 256, 256, 0, st>>>(in, count, cap, rank, out);
-  k_rank_sort<T><<<grid, 256, 0, st>>>(in, count, cap, out);
+  const int pg = grid > (int)(SMALL_SORT / 256) ? grid : (int)(SMALL_SORT / 256);
+  k_rank_place<T><<<pg, 256, 0, st>>>(in, count, cap, rank, out);
 }
 
 // ---------------------------------------------------------------- 8: publish
@@ -752,9 +762,8 @@ static hipError_t launch_wpl(const Geom &G, const uint32_t *sketch, const Restor
   const uint32_t r = G.r, k = G.k;
   const size_t n_le = (size_t)r << k;
   // 0: clear state and the hot bitmap
-  k_state_init<<<1, 1024, 0, st>>>(B.st, B.rank, SMALL_SORT);
-  hipError_t e = launch_fill_u32(B.hotmask, n_le / 32, 0u, grid, st);
-  if (e != hipSuccess) return e;
+  k_restore_init<<<(int)((n_le / 32 + 255) / 256 < 256 ? (n_le / 32 + 255) / 256 : 256), 256, 0,
+                   st>>>(B.st, B.rank, SMALL_SORT, B.hotmask, n_le / 32);
   // 1: hot scan
   {
     using S = LeShape<WPL>;
@@ -765,12 +774,8 @@ static hipError_t launch_wpl(const Geom &G, const uint32_t *sketch, const Restor
     const int gs = (int)((n_le + chunk - 1) / chunk);
     k_hot_scan<WPL><<<gs, 256, 0, st>>>(G, sketch, zhot, B.hotmask, B.st, chunk);
   }
-  // 2: HE(i)
-  k_he_compact<<<r, 1024, 0, st>>>(G, B.hotmask, B.he, B.st);
-  // 3: buckets for rows 2..r-1
-  k_buckets<<<r - 2, 1024, 0, st>>>(G, B.he, B.bk_off, B.bk_cur, B.bk_val, B.st);
-  // 4: scalars
-  k_scalars<<<1, 64, 0, st>>>(G, B.st, e_theta);
+  // 2-4: HE(i), bucket tables of rows 2..r-1, scalars
+  k_rows<<<r, 1024, 0, st>>>(G, B.hotmask, B.he, B.bk_off, B.bk_cur, B.bk_val, B.st, e_theta);
   // 5: join
   {
     const uint32_t jb = B.jblk;

@@ -90,3 +90,26 @@ def test_plan_rejects_bad_jobs():
             with pytest.raises(ddhf.SketchError) as e:
                 ddhf.sketch_plan_create(items, flags)
             assert e.value.code == ddhf.SKETCH_E_INVAL
+
+
+def test_plan_update_in_rounds_and_without_restore():
+    """A window cut into several binned rounds inside one graph, and a plan
+    that only resets and updates: the sketch equals the oracle's."""
+    p = oracle.Params(1024, 16, 5, 6)
+    data = windows(71, [(p, 3_000_000, 10)])
+    _, pairs = data[0]
+    ref = oracle.build_sketch(p, pairs)
+    with make_sketch(p) as sk:
+        sk.set_option(ddhf.SKETCH_OPT_UPDATE_PATH, 2)
+        sk.set_option(ddhf.SKETCH_OPT_BINNED_ROUND, 1 << 20)     # 3 rounds
+        buf = to_dev(pairs)
+        with ddhf.Plan([(sk, buf, 0.7 * p.g)], restore=False) as plan:
+            assert plan.launches >= 3
+            for rep in range(2):
+                say(f"update-only plan run {rep}")
+                plan.run()
+                torch.cuda.synchronize()
+                assert np.array_equal(sk.download(), ref)
+            with pytest.raises(ddhf.SketchError) as e:
+                plan.results()
+            assert e.value.code == ddhf.SKETCH_E_INVAL

@@ -102,6 +102,35 @@ def run_cpu_baseline(pairs_host, p, theta, n_sample):
     }
 
 
+def atomic_ceiling(ddhf, traffic, pairs, shape, stream, update_mpps):
+    """The atomic side of the update's roofline, measured on the same window:
+    the direct kernel with its bit test off issues exactly one global
+    atomicOr per (pair, row), so its rate is the random-atomic ceiling
+    (atomicOr rate / r) for this sketch in this cache state."""
+    import torch
+    g, k, r, alpha = shape
+    sk = ddhf.Sketch(g, k, r, alpha, traffic.HASH_SEED, device=0)
+    sk.set_option(ddhf.SKETCH_OPT_UPDATE_PATH, 1)
+    sk.set_option(ddhf.SKETCH_OPT_UPDATE_CHECK, 0)
+    ms = []
+    for i in range(4):
+        sk.reset()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        sk.update(pairs)
+        b.record(stream)
+        b.synchronize()
+        if i:
+            ms.append(a.elapsed_time(b))
+    sk.close()
+    n = pairs.shape[0]
+    ceiling = n / (sorted(ms)[len(ms) // 2] / 1e3) / 1e6
+    return {"kind": "one global atomicOr per (pair, row): direct kernel, bit test off",
+            "atomics_per_s": round(ceiling * 1e6 * r, 1), "ceiling_mpps": round(ceiling, 2),
+            "achieved_mpps": round(update_mpps, 2), "ratio": round(update_mpps / ceiling, 3)}
+
+
 def cpu_baseline_leg(pairs, shape, theta, n_sample):
     """The cpu_baseline object of the JSON line: the oracle on the host over
     the first n_sample pairs of the window (pairs: int32 [n, 2] tensor)."""
@@ -266,6 +295,8 @@ def main():
     }
     if hbm_traffic:
         out["roofline"]["traffic_gbs"] = round(hbm_traffic / (upd_mean / 1e3) / 1e9, 1)
+    out["atomic_roofline"] = atomic_ceiling(ddhf, traffic, pairs, (g, k, r, alpha), stream,
+                                            update_mpps)
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline_leg(pairs, (g, k, r, alpha), args.theta,

@@ -200,7 +200,7 @@ def test_restore_batch_equals_single_restores():
 def test_restore_batch_after_pools_grow_midway():
     """Batched restores against tiny shared buffers: an earlier job grows
     them, so a later job that overflowed the size it ran with must run again
-    (and match the oracle) rather than be judged by the grown size."""
+    (and match the oracle) rather than be checked against the grown size."""
     p = oracle.Params()
     rng = np.random.default_rng(53)
     sks, refs = [], []

@@ -331,10 +331,12 @@ def update_batch(items, stream=None) -> None:
                         _stream_handle(stream, dev))
 
 
-def restore_batch(items, stream=None):
+def restore_batch(items, stream=None, raise_errors: bool = True):
     """items: sequence of (Sketch, theta). One batched restore; returns
-    [(records, info)] in order. Raises SketchError for a failed job other
-    than CAPACITY; CAPACITY jobs are rerun in a second batch."""
+    [(records, info)] in order. CAPACITY jobs are rerun in a second batch.
+    Another failed job raises SketchError, or with raise_errors=False comes
+    back as (None, info) with info["status"] set (info of a SATURATED job
+    still holds its scalars)."""
     if not items:
         return []
     dev = items[0][0].device
@@ -343,15 +345,18 @@ def restore_batch(items, stream=None):
     out = [None] * len(items)
     retry = []
     for i, ((sk, th), (recs, info, st, need)) in enumerate(zip(items, res)):
+        info["status"] = st
         if st == SKETCH_OK:
             out[i] = (recs, info)
         elif st == SKETCH_E_CAPACITY:
             sk._cap = max(int(need) + 64, 2 * sk._cap)
             retry.append(i)
-        else:
+        elif raise_errors:
             raise SketchError(st, f"restore of batch item {i} failed: {last_error()}")
+        else:
+            out[i] = (None, info)
     if retry:
-        again = restore_batch([items[i] for i in retry], stream)
+        again = restore_batch([items[i] for i in retry], stream, raise_errors)
         for i, r in zip(retry, again):
             out[i] = r
     return out

@@ -72,6 +72,7 @@ class Response:
     done: float               # seconds after the start of serving
     batch: int                # requests served in the same batch
     n_pairs: int = 0
+    status: int = 0           # SKETCH_OK, or the library's error (records empty)
 
     @property
     def latency(self) -> float:
@@ -137,6 +138,15 @@ class _Links:
     def close(self):
         for kk in list(self.sk):
             self._drop(kk)
+
+
+def _response(q: Request, recs, info: dict, done: float, batch: int) -> Response:
+    """A request's response; a failed restore (a saturated sketch) gives an
+    empty list and its status instead of stopping the server."""
+    if recs is None:
+        recs = np.zeros(0, dtype=ddhf.SP_DTYPE)
+    return Response(q.rid, q.link, recs, info, q.arrival, done, batch, q.n_pairs,
+                    int(info.get("status", ddhf.SKETCH_OK)))
 
 
 class _Server:
@@ -205,11 +215,11 @@ class ContinuousServer(_Server):
             for sk in sks:
                 sk.reset()
             ddhf.update_batch([(sk, q.pairs) for sk, q in zip(sks, batch)])
-            res = ddhf.restore_batch([(sk, q.theta) for sk, q in zip(sks, batch)])
+            res = ddhf.restore_batch([(sk, q.theta) for sk, q in zip(sks, batch)],
+                                     raise_errors=False)
             done = time.perf_counter() - t0
             for q, (recs, info) in zip(batch, res):
-                out.append(Response(q.rid, q.link, recs, info, q.arrival, done, len(batch),
-                                    q.n_pairs))
+                out.append(_response(q, recs, info, done, len(batch)))
         return sorted(out, key=lambda r: r.rid)
 
 
@@ -225,9 +235,8 @@ class PlainServer(_Server):
             sk = self.links.get(q.link, q.n_pairs, {q.link})
             sk.reset()
             sk.update(q.pairs)
-            recs, info = sk.restore(q.theta)
-            out.append(Response(q.rid, q.link, recs, info, q.arrival,
-                                time.perf_counter() - t0, 1, q.n_pairs))
+            (recs, info), = ddhf.restore_batch([(sk, q.theta)], raise_errors=False)
+            out.append(_response(q, recs, info, time.perf_counter() - t0, 1))
         return sorted(out, key=lambda r: r.rid)
 
 

@@ -224,6 +224,27 @@ def test_restore_batch_after_pools_grow_midway():
             sk.close()
 
 
+def test_restore_batch_reports_a_saturated_job_and_serves_the_rest():
+    """A saturated sketch (every bit set) in a batch: its job reports
+    SATURATED, the other job still gets its list."""
+    p = oracle.Params()
+    rng = np.random.default_rng(59)
+    hosts = rng.choice(2**32, size=4, replace=False).astype(np.uint32)
+    pairs = np.concatenate([rand_pairs(rng, 200_000, 8000)] + planted(rng, hosts, 2500))
+    ref = oracle.restore(p, oracle.build_sketch(p, pairs), 0.7 * p.g)
+    with make_sketch(p) as full, make_sketch(p) as good:
+        full.upload(np.full(full.words, 0xFFFFFFFF, dtype=np.uint32))
+        good.update(to_dev(pairs))
+        res = ddhf.restore_batch([(full, 0.7 * p.g), (good, 0.7 * p.g)], raise_errors=False)
+        assert res[0][0] is None and res[0][1]["status"] == ddhf.SKETCH_E_SATURATED
+        recs, info = res[1]
+        assert info["status"] == ddhf.SKETCH_OK
+        assert_spl_equal(recs, *ref[:3])
+        with pytest.raises(ddhf.SketchError) as e:
+            ddhf.restore_batch([(full, 0.7 * p.g)])
+        assert e.value.code == ddhf.SKETCH_E_SATURATED
+
+
 def test_update_batch_rejects_duplicates():
     p = oracle.Params()
     with make_sketch(p) as sk:

@@ -80,6 +80,28 @@ struct RestoreBufs {
   size_t h_recs_cap;
 };
 
+// Inclusive prefix sum over the 64 lanes of a wave, in registers: four
+// row shifts inside each 16-lane row, then the row broadcasts of lanes 15
+// and 31 into the rows above (DPP, no LDS round trips). All lanes active.
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return v;
+}
+
+// Lane l's value broadcast to the wave (a scalar read, no LDS).
+__device__ __forceinline__ uint32_t wave_lane(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ unsigned long long wave_lane64(unsigned long long v, int l) {
+  const uint32_t lo = wave_lane((uint32_t)v, l), hi = wave_lane((uint32_t)(v >> 32), l);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 // Binned update (update.hip): the sketch is cut into 128 KiB tiles; a code
 // is the bit offset inside its tile.
 constexpr uint32_t BIN_TILE_LOG2 = 20;               // bits per tile = 2^20

@@ -34,25 +34,17 @@ namespace ddhf {
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-  const uint32_t lane = lane_id();
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t t = __shfl_up(v, d, 64);
-    if (lane >= (uint32_t)d) v += t;
-  }
-  return v;
-}
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) { return wave_scan_incl(v); }
 
 // Reserve `nout` consecutive slots of a global list for this lane, with one
 // atomic per wave. Must be called by all 64 lanes of the wave.
 __device__ __forceinline__ unsigned long long wave_reserve(
     unsigned long long *counter, uint32_t nout) {
   const uint32_t incl = wave_incl_scan(nout);
-  const uint32_t total = __shfl(incl, 63, 64);
+  const uint32_t total = wave_lane(incl, 63);
   unsigned long long base = 0;
   if (lane_id() == 63 && total) base = atomicAdd(counter, (unsigned long long)total);
-  base = __shfl(base, 63, 64);
+  base = wave_lane64(base, 63);
   return base + (incl - nout);
 }
 
@@ -468,7 +460,7 @@ __device__ __forceinline__ void join_items(
       cnt = T.start(key + 1) - b0;
     }
     const uint32_t incl = wave_incl_scan(cnt);
-    const uint32_t total = __shfl(incl, 63, 64);
+    const uint32_t total = wave_lane(incl, 63);
     if (total == 0) continue;
     // each item writes its own index into its output slots when they fit,
     // so a slot finds its item with one LDS read; otherwise by a binary
@@ -510,12 +502,12 @@ __device__ __forceinline__ void join_items(
       if (LAST) {
         unsigned long long gb = 0;
         if (lane == 0) gb = atomicAdd(&st->n_cand, (unsigned long long)n_ok);
-        gb = __shfl(gb, 0, 64);
+        gb = wave_lane64(gb, 0);
         if (ok && gb + rank < cand_cap) cand[gb + rank] = a;
       } else {
         uint32_t lb = 0;
         if (lane == 0) lb = atomicAdd((uint32_t *)&seg_fill, n_ok);   // an LDS atomic after inlining
-        lb = __shfl(lb, 0, 64);
+        lb = wave_lane(lb, 0);
         if (ok && (size_t)lb + rank < seg_cap) seg[lb + rank] = make_uint2(a, oc0);
       }
     }

@@ -196,21 +196,11 @@ __global__ __launch_bounds__(1024) void k_bin_count(const UpdJob *__restrict__ j
 // Exclusive prefix sum over a workgroup of 1024 threads.
 __device__ __forceinline__ uint32_t blk_scan_1024(uint32_t v, uint32_t *total, uint32_t *sh) {
   const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  uint32_t inc = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t t = __shfl_up(inc, d, 64);
-    if (lane >= (uint32_t)d) inc += t;
-  }
+  const uint32_t inc = wave_scan_incl(v);
   if (lane == 63) sh[wid] = inc;
   __syncthreads();
   if (wid == 0) {
-    uint32_t x = lane < 16 ? sh[lane] : 0;
-#pragma unroll
-    for (int d = 1; d < 16; d <<= 1) {
-      const uint32_t t = __shfl_up(x, d, 64);
-      if (lane >= (uint32_t)d) x += t;
-    }
+    const uint32_t x = wave_scan_incl(lane < 16 ? sh[lane] : 0);
     if (lane < 16) sh[lane] = x;
   }
   __syncthreads();

@@ -294,7 +294,7 @@ int ctx_acquire(int dev, int n_cu, DevCtx **out) {
     c = new DevCtx();
     c->dev = dev;
     c->n_cu = n_cu;
-    c->jblk = (uint32_t)(n_cu * 3);      // three join blocks per compute unit fit in LDS
+    c->jblk = (uint32_t)(n_cu * 4);      // four join blocks per compute unit fit in LDS
     int rc = SKETCH_OK;
     for (int i = 0; i < DevCtx::SLOTS && !rc; i++) {
       if (hipHostMalloc((void **)&c->h_jobs[i], sizeof(UpdJob) * MAX_JOBS) != hipSuccess) {

@@ -323,8 +323,8 @@ __device__ __forceinline__ void lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
 }
 constexpr uint32_t TAB_OFF_MAX = 8193;          // bucket offsets held in LDS
-constexpr uint32_t OWN_MAX = 512;               // output slots per wave pass set
-constexpr uint32_t TAB_VAL_BYTES = 16384;       // bucket entries held in LDS (3 blocks per CU)
+constexpr uint32_t OWN_MAX = 256;               // output slots per wave pass set
+constexpr uint32_t TAB_VAL_BYTES = 16384;       // bucket entries held in LDS (4 blocks per CU)
 
 // Bits of the address from block i >= 2: alpha new bits at k + (i-2)*alpha.
 // top = the new bits; false if any lands at or above bit 32.
@@ -370,15 +370,12 @@ __device__ __forceinline__ void join_items(
     const uint2 *__restrict__ in, const uint32_t *__restrict__ in_cnt,
     const JoinTable<TLDS> &T, DevState *__restrict__ st, uint2 *__restrict__ out,
     size_t seg_cap, uint32_t *__restrict__ cand, size_t cand_cap, uint32_t M,
-    LDSP uint32_t *w_incl, LDSP uint32_t *w_sub, LDSP uint32_t *w_c0, LDSP int32_t *w_base,
-    LDSP uint16_t *w_own, LDSP uint32_t *seg_fill_p) {
+    LDSP uint32_t *w_incl, LDSP uint16_t *w_own, LDSP uint32_t *seg_fill_p) {
   LDSP uint32_t &seg_fill = *seg_fill_p;
   const uint32_t lane = lane_id();
   const uint32_t wib = threadIdx.x >> 6;                    // wave in block
   const uint32_t wpb = blockDim.x >> 6;                     // waves per block
-  LDSP uint32_t *W_incl = w_incl + wib * 64, *W_sub = w_sub + wib * 64,
-                *W_c0 = w_c0 + wib * 64;
-  LDSP int32_t *W_base = w_base + wib * 64;
+  LDSP uint32_t *W_incl = w_incl + wib * 64;
   LDSP uint16_t *W_own = w_own + wib * OWN_MAX;
   const uint32_t sh = G.shift[row];
   uint2 *seg = LAST ? nullptr : out + (size_t)blockIdx.x * seg_cap;
@@ -471,28 +468,31 @@ __device__ __forceinline__ void join_items(
     } else {
       W_incl[lane] = incl;
     }
-    W_base[lane] = (int32_t)b0 - (int32_t)(incl - cnt);
-    W_sub[lane] = sub;
-    W_c0[lane] = c0;
+    const int32_t my_base = (int32_t)b0 - (int32_t)(incl - cnt);   // entry j = base + slot
     lds_fence();
     // ---- expand: one output slot per lane per pass
     for (uint32_t base = 0; base < total; base += 64) {
       const uint32_t slot = base + lane;
-      bool ok = false;
-      uint32_t a = 0, oc0 = 0;
-      if (slot < total) {
-        uint32_t o = 0;
-        if (own) {
-          o = W_own[slot];
-        } else {
+      const bool live = slot < total;
+      const uint32_t sl = live ? slot : total - 1;   // lanes past the end repeat the last slot
+      uint32_t o = 0;
+      if (own) {
+        o = W_own[sl];
+      } else {
 #pragma unroll
-          for (uint32_t s = 32; s; s >>= 1)
-            if (W_incl[o + s - 1] <= slot) o += s;
-        }
-        const uint32_t j = (uint32_t)(W_base[o] + (int32_t)slot);
-        oc0 = W_c0[o];
+        for (uint32_t s = 32; s; s >>= 1)
+          if (W_incl[o + s - 1] <= sl) o += s;
+      }
+      // the owning item's values straight from its lane (every lane takes part)
+      const int32_t ob = __builtin_amdgcn_ds_bpermute((int)(o << 2), my_base);
+      const uint32_t osub = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(o << 2), (int)sub);
+      const uint32_t oc0 = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(o << 2), (int)c0);
+      bool ok = false;
+      uint32_t a = 0;
+      if (live) {
+        const uint32_t j = (uint32_t)(ob + (int32_t)slot);
         const uint32_t top = (oc0 >> (G.k - G.alpha)) ^ T.top_bits(j);
-        ok = extend_top(G, row, W_sub[o], top, &a);
+        ok = extend_top(G, row, osub, top, &a);
         if (LAST) ok = ok && hash_dh0(G, a) == oc0;
       }
       const unsigned long long mask = __ballot(ok);
@@ -524,8 +524,7 @@ __global__ __launch_bounds__(JOIN_THREADS) void k_join(
     size_t seg_cap, uint32_t *__restrict__ cand, size_t cand_cap) {
   __shared__ uint16_t t_off[TAB_OFF_MAX];
   __shared__ __attribute__((aligned(16))) uint8_t t_val[TAB_VAL_BYTES];
-  __shared__ uint32_t w_incl[JOIN_THREADS], w_sub[JOIN_THREADS], w_c0[JOIN_THREADS];
-  __shared__ int32_t w_base[JOIN_THREADS];
+  __shared__ uint32_t w_incl[JOIN_THREADS];
   __shared__ uint16_t w_own[(JOIN_THREADS / 64) * OWN_MAX];
   __shared__ uint32_t seg_fill;
   if (st->saturated) return;
@@ -553,15 +552,14 @@ __global__ __launch_bounds__(JOIN_THREADS) void k_join(
                             lds_ptr(reinterpret_cast<uint16_t *>(t_val)), g_off, g_val,
                             G.k - G.alpha, wide_t};
     join_items<FIRST, LAST, true>(G, row, he, in, in_cnt, T, st, out, seg_cap, cand, cand_cap,
-                                  M, lds_ptr(w_incl), lds_ptr(w_sub), lds_ptr(w_c0),
-                                  lds_ptr(w_base), lds_ptr(w_own), lds_ptr(&seg_fill));
+                                  M, lds_ptr(w_incl), lds_ptr(w_own), lds_ptr(&seg_fill));
   } else {
     const JoinTable<false> T{lds_ptr(t_off), lds_ptr(t_val),
                              lds_ptr(reinterpret_cast<uint16_t *>(t_val)), g_off, g_val,
                              G.k - G.alpha, wide_t};
     join_items<FIRST, LAST, false>(G, row, he, in, in_cnt, T, st, out, seg_cap, cand,
-                                   cand_cap, M, lds_ptr(w_incl), lds_ptr(w_sub), lds_ptr(w_c0),
-                                   lds_ptr(w_base), lds_ptr(w_own), lds_ptr(&seg_fill));
+                                   cand_cap, M, lds_ptr(w_incl), lds_ptr(w_own),
+                                   lds_ptr(&seg_fill));
   }
   if (!LAST) {
     __syncthreads();

@@ -409,7 +409,7 @@ struct sketch {
   uint32_t scatter_ppt = 6;
   uint32_t apply_grid = 0;     // blocks of the apply pass (0: one per item)
   uint32_t *hist = nullptr, *totals = nullptr, *base = nullptr, *item_start = nullptr,
-           *xslot = nullptr, *n_items = nullptr, *item_tile = nullptr;
+           *xslot = nullptr, *n_items = nullptr, *item_tile = nullptr, *gcur = nullptr;
   // restore
   DevState *st = nullptr;
   DevState *h_state = nullptr, *d_h_state = nullptr;   // pinned copy of the device state
@@ -435,6 +435,7 @@ void free_sketch(sketch *s) {
   dev_free(s->xslot);
   dev_free(s->n_items);
   dev_free(s->item_tile);
+  dev_free(s->gcur);
   dev_free(s->st);
   dev_free(s->hotmask);
   dev_free(s->he);
@@ -625,6 +626,7 @@ UpdJob job_base(const sketch *s) {
   J.item_start = s->item_start;
   J.xslot = s->xslot;
   J.item_tile = s->item_tile;
+  J.gcur = s->gcur;
   J.n_items = s->n_items;
   J.check = (uint32_t)s->update_check;
   return J;
@@ -837,7 +839,7 @@ struct PlanJob {
   double theta = 0;
   Thresholds t{};
   uint32_t *hist = nullptr, *totals = nullptr, *base = nullptr, *item_start = nullptr,
-           *xslot = nullptr, *n_items = nullptr, *item_tile = nullptr;
+           *xslot = nullptr, *n_items = nullptr, *item_tile = nullptr, *gcur = nullptr;
   DevState *st = nullptr;
   DevState *h_state = nullptr, *d_h_state = nullptr;   // pinned
   uint4 *h_recs = nullptr, *d_h_recs = nullptr;         // pinned
@@ -894,6 +896,7 @@ void plan_free(sketch_plan *P) {
     dev_free(j.xslot);
     dev_free(j.n_items);
     dev_free(j.item_tile);
+    dev_free(j.gcur);
     dev_free(j.st);
     dev_free(j.sorted);
     pinned_free(j.h_state, j.d_h_state);
@@ -1052,6 +1055,7 @@ int sketch_create(const sketch_params_t *params, sketch_t **out) {
     if (!rc) rc = dev_alloc(&s->item_start, s->nbins + 1, "tile items");
     if (!rc) rc = dev_alloc(&s->xslot, s->nbins + 1, "tile scratch slots");
     if (!rc) rc = dev_alloc(&s->item_tile, ITEM_TILE_SLOTS(s->nbins), "item tiles");
+    if (!rc) rc = dev_alloc(&s->gcur, (size_t)BIN_GROUPS * s->nbins, "tile stream cursors");
     if (!rc) rc = dev_alloc(&s->n_items, 1, "tile item count");
   }
   if (!rc) rc = pinned_alloc(&s->h_state, &s->d_h_state, 1, "state");
@@ -1342,6 +1346,7 @@ int sketch_plan_create(const sketch_plan_job_t *jobs, size_t n_jobs, int flags,
       if (!rc) rc = dev_alloc(&pj.item_start, s->nbins + 1, "plan tile items");
       if (!rc) rc = dev_alloc(&pj.xslot, s->nbins + 1, "plan tile scratch slots");
       if (!rc) rc = dev_alloc(&pj.item_tile, ITEM_TILE_SLOTS(s->nbins), "plan item tiles");
+      if (!rc) rc = dev_alloc(&pj.gcur, (size_t)BIN_GROUPS * s->nbins, "plan tile stream cursors");
       if (!rc) rc = dev_alloc(&pj.n_items, 1, "plan tile item count");
     }
     if (!rc) rc = dev_alloc(&pj.st, 1, "plan state");
@@ -1369,6 +1374,7 @@ int sketch_plan_create(const sketch_plan_job_t *jobs, size_t n_jobs, int flags,
           J.xslot = pj.xslot;
           J.n_items = pj.n_items;
           J.item_tile = pj.item_tile;
+          J.gcur = pj.gcur;
           return J;
         },
         [&](Group &g) {

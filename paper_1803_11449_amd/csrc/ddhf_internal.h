@@ -113,6 +113,12 @@ constexpr uint32_t APPLY_ITEM = 1u << 19;            //   are cut into items of 
 
 constexpr uint32_t BIN_BLOCKS_MAX = 1024;
 
+// Scatter blocks are put in BIN_GROUPS groups by block index mod BIN_GROUPS:
+// gfx950 hands workgroups of a dispatch to its 8 XCDs in turn, so a group is
+// the blocks that share one XCD and its L2. The blocks of a group write
+// every tile's codes into one shared stream, not one stream each.
+constexpr uint32_t BIN_GROUPS = 8;
+
 // One sketch's share of an update launch. Kernels of a launch take a table
 // of these (device memory) and map each block, tile or work item to its
 // job by binary search over the prefix fields blk0 / tile0 / item0.
@@ -131,6 +137,7 @@ struct UpdJob {
   uint32_t pad0;
   uint32_t *hist, *totals, *base, *item_start, *xslot, *n_items;
   uint32_t *item_tile;   // tile of each apply item (ITEM_TILE_SLOTS(nbins) entries)
+  uint32_t *gcur;        // [BIN_GROUPS][nbins]: next slot of each group's stream per tile
   uint32_t *codes, *scratch;
   uint32_t item0;        // first global apply item (written on the device)
   uint32_t check;        // direct kernel: test the bit before the atomicOr

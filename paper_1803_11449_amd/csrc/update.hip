@@ -22,17 +22,25 @@
 //          one bit string; tile = B >> 20 names the 128 KiB slice it falls
 //          in and code = B mod 2^20 the bit inside it.
 //            count    each block counts its chunk's codes per tile (LDS)
-//            scan     per tile, the blocks' counts become write offsets;
-//                     over tiles, the totals become run starts; a tile with
-//                     many codes is cut into several apply items
+//            scan     per tile, the blocks' counts become the starts of
+//                     the block groups' parts of the tile's run; over tiles,
+//                     the totals become run starts; a tile with many codes
+//                     is cut into several apply items
 //            scatter  each block sorts a batch of pairs' codes by tile in
-//                     LDS and writes them into its part of each tile's run
+//                     LDS, claims room in its group's part of each tile's
+//                     run with one atomicAdd per tile and writes the codes
+//                     there. A group is the blocks of one XCD: they fill
+//                     each tile's stream together, so the L2 holds one
+//                     partly written line per tile and stream rather than
+//                     one per tile and block, and lines leave it whole
 //            apply    one workgroup per item: the tile in LDS (up to 160 KiB
 //                     per workgroup on gfx950), ds_or per code. The first
 //                     item of a tile reads and writes the tile itself; the
 //                     other items of a cut tile write scratch tiles instead
 //            merge    each cut tile ORs its scratch tiles into the sketch
 //          Only the pairs, the code runs and whole tiles move through HBM.
+#include <type_traits>
+
 #include "ddhf_internal.h"
 
 namespace ddhf {
@@ -194,8 +202,9 @@ __global__ __launch_bounds__(1024) void k_bin_count(const UpdJob *__restrict__ j
 }
 
 // Exclusive prefix sum over a workgroup of 1024 threads.
-__device__ __forceinline__ uint32_t blk_scan_1024(uint32_t v, uint32_t *total, uint32_t *sh) {
-  const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+__device__ __forceinline__ uint32_t blk_scan_1024(uint32_t v, uint32_t *total, uint32_t *sh,
+                                                  uint32_t tid = threadIdx.x) {
+  const uint32_t lane = tid & 63, wid = tid >> 6;
   const uint32_t inc = wave_scan_incl(v);
   if (lane == 63) sh[wid] = inc;
   __syncthreads();
@@ -210,18 +219,29 @@ __device__ __forceinline__ uint32_t blk_scan_1024(uint32_t v, uint32_t *total, u
   return off + inc - v;
 }
 
-// Per tile: the blocks' counts -> exclusive offsets (in place); the total.
+// Per tile: the blocks' counts -> the start of each block group's part of
+// the tile's run, relative to the run (gcur), and the tile's total.
 __global__ __launch_bounds__(1024) void k_bin_scan_cols(const UpdJob *__restrict__ jobs,
                                                         uint32_t nj) {
-  __shared__ uint32_t sh[16];
+  __shared__ uint32_t sg[BIN_GROUPS];
   const UpdJob &J = jobs[job_of_tile(jobs, nj, blockIdx.x)];
   const uint32_t t = blockIdx.x - J.tile0;
-  GMEM uint32_t *col = gmem(J.hist) + (size_t)t * J.hstride;
+  const GMEM uint32_t *col = gmem(J.hist) + (size_t)t * J.hstride;
+  if (threadIdx.x < BIN_GROUPS) sg[threadIdx.x] = 0;
+  __syncthreads();
   const uint32_t v = threadIdx.x < J.nblk ? col[threadIdx.x] : 0;
-  uint32_t total;
-  const uint32_t ex = blk_scan_1024(v, &total, sh);
-  if (threadIdx.x < J.nblk) col[threadIdx.x] = ex;
-  if (threadIdx.x == 0) gmem(J.totals)[t] = total;
+  if (v) atomicAdd(&sg[(J.blk0 + threadIdx.x) % BIN_GROUPS], v);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    GMEM uint32_t *gc = gmem(J.gcur);
+    uint32_t ex = 0;
+#pragma unroll
+    for (uint32_t g = 0; g < BIN_GROUPS; g++) {
+      gc[(size_t)g * J.nbins + t] = ex;
+      ex += sg[g];
+    }
+    gmem(J.totals)[t] = ex;
+  }
 }
 
 // Apply items of a tile with v codes: one if v <= SPLIT_MIN, else one per
@@ -230,7 +250,8 @@ __device__ __forceinline__ uint32_t tile_items(uint32_t v) {
   return v == 0 ? 0u : (v <= SPLIT_MIN ? 1u : (v + APPLY_ITEM - 1) / APPLY_ITEM);
 }
 
-// Over one job's tiles (block = job): run starts, apply-item starts,
+// Over one job's tiles (block = job): run starts (which also turn the
+// groups' relative starts in gcur into slots), apply-item starts,
 // scratch-slot starts (a tile cut into j items owns j-1 scratch tiles) and
 // the item count.
 __global__ __launch_bounds__(1024) void k_bin_scan_tiles(const UpdJob *__restrict__ jobs) {
@@ -239,7 +260,7 @@ __global__ __launch_bounds__(1024) void k_bin_scan_tiles(const UpdJob *__restric
   const uint32_t nbins = J.nbins;
   const GMEM uint32_t *totals = gmem(J.totals);
   GMEM uint32_t *base = gmem(J.base), *item_start = gmem(J.item_start), *xslot = gmem(J.xslot);
-  GMEM uint32_t *item_tile = gmem(J.item_tile);
+  GMEM uint32_t *item_tile = gmem(J.item_tile), *gcur = gmem(J.gcur);
   constexpr uint32_t PER = (BIN_MAX + 1) / 1024;
   const uint32_t t0 = threadIdx.x * PER;
   uint32_t c = 0, it = 0, xs = 0;
@@ -263,6 +284,8 @@ __global__ __launch_bounds__(1024) void k_bin_scan_tiles(const UpdJob *__restric
       const uint32_t v = totals[t];
       const uint32_t ni = tile_items(v);
       base[t] = ec;
+#pragma unroll
+      for (uint32_t g = 0; g < BIN_GROUPS; g++) gcur[(size_t)g * nbins + t] += ec;
       item_start[t] = ei;
       xslot[t] = ex;
       for (uint32_t q = 0; q < ni; q++) item_tile[ei + q] = t;
@@ -311,18 +334,15 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
   __shared__ uint32_t cnt[TMAX];       // codes per tile in this batch
   __shared__ uint32_t lofs[TMAX];      // batch-local run starts
   __shared__ uint32_t dst[TMAX];       // global slot of batch entry e is dst[t] + e
-  __shared__ uint32_t gcur[TMAX];      // next global slot of this block per tile
   __shared__ uint32_t sh[16];
   const UpdJob &J = jobs[job_of_block(jobs, nj, blockIdx.x)];
   const Geom G = J.G;
-  const uint32_t nbins = J.nbins, lb = blockIdx.x - J.blk0;
+  const uint32_t lb = blockIdx.x - J.blk0;
   const GMEM uint2 *__restrict__ pairs = gmem(J.pairs);
   GMEM uint32_t *__restrict__ codes = gmem(J.codes);
-  const GMEM uint32_t *base = gmem(J.base), *hist = gmem(J.hist);
-  for (uint32_t t = threadIdx.x; t < TMAX; t += blockDim.x) {
-    cnt[t] = 0;
-    gcur[t] = t < nbins ? base[t] + hist[(size_t)t * J.hstride + lb] : 0;
-  }
+  // this block's group's stream cursors, one per tile
+  GMEM uint32_t *gcur = gmem(J.gcur) + (size_t)(blockIdx.x % BIN_GROUPS) * J.nbins;
+  for (uint32_t t = threadIdx.x; t < TMAX; t += blockDim.x) cnt[t] = 0;
   __syncthreads();
   const size_t p0 = (size_t)lb * J.chunk;
   const size_t p1 = p0 + J.chunk < J.n ? p0 + J.chunk : J.n;
@@ -332,30 +352,34 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
   // written. Loads past the chunk re-read its last pair (their lanes are
   // masked later): with no branch around them the compiler can wait for
   // the older batch alone instead of for every load in flight.
-  uint2 nxt[PPT];
-#pragma unroll
-  for (int k = 0; k < PPT; k++) {
-    const size_t i = p0 + (size_t)k * blockDim.x + threadIdx.x;
-    nxt[k] = ld2(pairs + (i < p1 ? i : p1 - 1));
-  }
-  const uint32_t t0 = threadIdx.x * TPT;              // tiles this thread keeps
-  for (size_t i0 = p0; i0 < p1; i0 += step) {
-    // ranks are < BATCH <= 2^15: two per register
-    uint32_t v[PPT * R], rk2[(PPT * R + 1) / 2];
-    uint2 cur[PPT];
+  uint2 cur[PPT], nxt[PPT];
+  auto advance = [&](size_t i_next) {
 #pragma unroll
     for (int k = 0; k < PPT; k++) {
       cur[k] = nxt[k];
-      const size_t i = i0 + step + (size_t)k * blockDim.x + threadIdx.x;
+      const size_t i = i_next + (size_t)k * blockDim.x + threadIdx.x;
       nxt[k] = ld2(pairs + (i < p1 ? i : p1 - 1));
     }
-    // 1: codes and their rank inside their tile's run of this batch (a full
-    // batch takes no per-pair bounds test; only a chunk's last batch can be
-    // partial, and its missing pairs get the code ~0)
-    const bool full = i0 + step <= p1;
-    if (full) {
+  };
+  // One batch: the pairs [i0, i0 + step) of the chunk, held in cur. A full
+  // batch (FULL) has all its pairs, so no per-pair bounds test and exactly
+  // PPT * R stores per thread; only a chunk's last batch can be partial,
+  // and its missing pairs get the code ~0.
+  auto batch = [&](auto full_c, size_t i0) {
+    constexpr bool FULL = decltype(full_c)::value;
+    // The thread index is taken afresh per batch, so that addresses derived
+    // from it are recomputed here rather than held in registers (or spilled)
+    // across the batch loop.
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const uint32_t t0 = tid * TPT;                      // tiles this thread keeps
+    // ranks are < BATCH <= 2^15: two per register
+    uint32_t v[PPT * R], rk2[(PPT * R + 1) / 2];
+    // 1: codes and their rank inside their tile's run of this batch
 #pragma unroll
-      for (int k = 0; k < PPT; k++) {
+    for (int k = 0; k < PPT; k++) {
+      const size_t i = i0 + (size_t)k * blockDim.x + tid;
+      if (FULL || i < p1) {
         uint32_t B[R];
         pair_codes<R>(G, cur[k], B);
 #pragma unroll
@@ -363,73 +387,89 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
           v[k * R + row] = B[row];
           put_rank(rk2, k * R + row, atomicAdd(&cnt[B[row] >> BIN_TILE_LOG2], 1u));
         }
-      }
-    } else {
+      } else {
 #pragma unroll
-      for (int k = 0; k < PPT; k++) {
-        const size_t i = i0 + (size_t)k * blockDim.x + threadIdx.x;
-        if (i < p1) {
-          uint32_t B[R];
-          pair_codes<R>(G, cur[k], B);
-#pragma unroll
-          for (int row = 0; row < R; row++) {
-            v[k * R + row] = B[row];
-            put_rank(rk2, k * R + row, atomicAdd(&cnt[B[row] >> BIN_TILE_LOG2], 1u));
-          }
-        } else {
-#pragma unroll
-          for (int row = 0; row < R; row++) v[k * R + row] = ~0u;
-        }
+        for (int row = 0; row < R; row++) v[k * R + row] = ~0u;
       }
     }
     __syncthreads();
-    // 2: run starts; dst maps a sorted position to its global slot
-    uint32_t c[TPT], sum = 0;
+    // 2: claim each tile's run in the group's stream (the claims' latency
+    // is hidden behind the scan and step 3); batch-local run starts
+    uint32_t c[TPT], run[TPT], lo[TPT], sum = 0;
 #pragma unroll
     for (uint32_t u = 0; u < TPT; u++) {
-      c[u] = cnt[t0 + u];
+      c[u] = cnt[t0 + u];                   // 0 for the LDS slots past the tiles
       sum += c[u];
+      run[u] = c[u] ? atomicAdd((uint32_t *)&gcur[t0 + u], c[u]) : 0;
     }
     uint32_t total;
-    uint32_t ex = blk_scan_1024(sum, &total, sh);
+    uint32_t ex = blk_scan_1024(sum, &total, sh, tid);
 #pragma unroll
     for (uint32_t u = 0; u < TPT; u++) {
       const uint32_t t = t0 + u;
+      lo[u] = ex;
       lofs[t] = ex;
-      dst[t] = gcur[t] - ex;
-      gcur[t] += c[u];
       cnt[t] = 0;
       ex += c[u];
     }
     __syncthreads();
-    // 3: group by tile in LDS
-    if (full) {
+    // 3: group by tile in LDS; dst maps a sorted position to its slot
 #pragma unroll
-      for (int q = 0; q < PPT * R; q++)
-        sorted[lofs[v[q] >> BIN_TILE_LOG2] + get_rank(rk2, q)] = v[q];
+    for (int q = 0; q < PPT * R; q++)
+      if (FULL || v[q] != ~0u) sorted[lofs[v[q] >> BIN_TILE_LOG2] + get_rank(rk2, q)] = v[q];
+#pragma unroll
+    for (uint32_t u = 0; u < TPT; u++) dst[t0 + u] = run[u] - lo[u];
+    __syncthreads();
+    // 4: write the runs
+    if constexpr (FULL) {
+      // total == BATCH: a fixed count of stores, all unrolled
+#pragma unroll
+      for (uint32_t u = 0; u < PPT * R; u++) {
+        const uint32_t e = tid + u * 1024;
+        const uint32_t x = sorted[e];
+        codes[dst[x >> BIN_TILE_LOG2] + e] = x & CODE_MASK;
+      }
     } else {
+      uint32_t e = tid;
+      for (; e + (SCATTER_UNROLL - 1) * 1024 < total; e += SCATTER_UNROLL * 1024) {
+        uint32_t x[SCATTER_UNROLL], d[SCATTER_UNROLL];
 #pragma unroll
-      for (int q = 0; q < PPT * R; q++)
-        if (v[q] != ~0u) sorted[lofs[v[q] >> BIN_TILE_LOG2] + get_rank(rk2, q)] = v[q];
+        for (int u = 0; u < SCATTER_UNROLL; u++) x[u] = sorted[e + u * 1024];
+#pragma unroll
+        for (int u = 0; u < SCATTER_UNROLL; u++) d[u] = dst[x[u] >> BIN_TILE_LOG2];
+#pragma unroll
+        for (int u = 0; u < SCATTER_UNROLL; u++) codes[d[u] + e + u * 1024] = x[u] & CODE_MASK;
+      }
+      for (; e < total; e += 1024) {
+        const uint32_t x = sorted[e];
+        codes[dst[x >> BIN_TILE_LOG2] + e] = x & CODE_MASK;
+      }
     }
     __syncthreads();
-    // 4: write the runs, SCATTER_UNROLL entries per thread at a time so
-    // their LDS reads overlap
-    uint32_t e = threadIdx.x;
-    for (; e + (SCATTER_UNROLL - 1) * 1024 < total; e += SCATTER_UNROLL * 1024) {
-      uint32_t x[SCATTER_UNROLL], d[SCATTER_UNROLL];
+  };
 #pragma unroll
-      for (int u = 0; u < SCATTER_UNROLL; u++) x[u] = sorted[e + u * 1024];
-#pragma unroll
-      for (int u = 0; u < SCATTER_UNROLL; u++) d[u] = dst[x[u] >> BIN_TILE_LOG2];
-#pragma unroll
-      for (int u = 0; u < SCATTER_UNROLL; u++) codes[d[u] + e + u * 1024] = x[u] & CODE_MASK;
+  for (int k = 0; k < PPT; k++) {
+    const size_t i = p0 + (size_t)k * blockDim.x + threadIdx.x;
+    nxt[k] = ld2(pairs + (i < p1 ? i : p1 - 1));
+  }
+  // Loads and stores share one in-order completion counter, so a wait for
+  // the next batch's pairs also waits for every store issued before them.
+  // The full batches therefore run as one peeled batch and a loop: on both
+  // edges into the loop the prefetch is followed by exactly one batch's
+  // stores, and the wait for it leaves that batch's stores in flight.
+  size_t i0 = p0;
+  if (i0 + step <= p1) {
+    advance(i0 + step);
+    batch(std::true_type{}, i0);
+    for (i0 += step; i0 + step <= p1; i0 += step) {
+      advance(i0 + step);
+      batch(std::true_type{}, i0);
     }
-    for (; e < total; e += 1024) {
-      const uint32_t x = sorted[e];
-      codes[dst[x >> BIN_TILE_LOG2] + e] = x & CODE_MASK;
-    }
-    __syncthreads();
+  }
+  if (i0 < p1) {
+#pragma unroll
+    for (int k = 0; k < PPT; k++) cur[k] = nxt[k];
+    batch(std::false_type{}, i0);
   }
 }
 

@@ -661,8 +661,8 @@ void layout_launch(UpdJob *J, uint32_t n, bool binned, uint32_t r, size_t *words
     blk += J[j].nblk;
     tile += J[j].nbins;
     if (binned) {
-      const size_t w = (size_t)r * J[j].n;
-      *words += (w + 3) & ~(size_t)3;        // keep every job's codes 16-byte aligned
+      const size_t w = code_words_bound(J[j].n, r, J[j].nbins, J[j].nblk, J[j].chunk);
+      *words += (2 * w + 3) & ~(size_t)3;    // 32-bit words; every job's codes 16-byte aligned
       *tiles += w / APPLY_ITEM + 1;
     }
   }
@@ -672,10 +672,10 @@ void layout_launch(UpdJob *J, uint32_t n, bool binned, uint32_t r, size_t *words
 void place_arena(UpdJob *J, uint32_t n, uint32_t r, uint32_t *codes, uint32_t *scratch) {
   size_t wo = 0, to = 0;
   for (uint32_t j = 0; j < n; j++) {
-    const size_t w = (size_t)r * J[j].n;
+    const size_t w = code_words_bound(J[j].n, r, J[j].nbins, J[j].nblk, J[j].chunk);
     J[j].codes = codes + wo;
     J[j].scratch = scratch + to * (size_t)BIN_TILE_WORDS;
-    wo += (w + 3) & ~(size_t)3;
+    wo += (2 * w + 3) & ~(size_t)3;
     to += w / APPLY_ITEM + 1;
   }
 }

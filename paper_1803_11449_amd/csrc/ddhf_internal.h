@@ -108,8 +108,8 @@ constexpr uint32_t BIN_TILE_LOG2 = 20;               // bits per tile = 2^20
 constexpr uint32_t BIN_TILE_WORDS = 1u << 15;        // 128 KiB
 constexpr uint32_t BIN_MAX = 4095;                   // tiles (sketch < 512 MiB); the
                                                      // bit index of a code stays < 2^32 - 1
-constexpr uint32_t SPLIT_MIN = 1u << 20;             // tiles above this many codes
-constexpr uint32_t APPLY_ITEM = 1u << 19;            //   are cut into items of this many
+constexpr uint32_t SPLIT_MIN = 1u << 18;             // tiles above this many code words
+constexpr uint32_t APPLY_ITEM = 1u << 17;            //   are cut into items of this many
 
 constexpr uint32_t BIN_BLOCKS_MAX = 1024;
 
@@ -146,11 +146,23 @@ struct UpdJob {
 constexpr uint32_t MAX_JOBS = 256;     // jobs per launch group
 
 // Pairs of one job in one binned round, at most; it bounds the apply items
-// of a job: a tile with v codes makes at most 1 + v / APPLY_ITEM of them,
-// and a round has at most 8 * MAX_ROUND_PAIRS codes.
+// of a job: a tile with v code words makes at most 1 + v / APPLY_ITEM of
+// them, and a round has at most 8 * MAX_ROUND_PAIRS codes (and no more
+// words than codes).
 constexpr uint64_t MAX_ROUND_PAIRS = (uint64_t)1 << 27;
 constexpr uint64_t ITEM_TILE_SLOTS(uint32_t nbins) {
   return (uint64_t)nbins + 8 * MAX_ROUND_PAIRS / APPLY_ITEM + 1;
+}
+
+// Upper bound of the 64-bit code words (three codes each) a binned job
+// writes: a block's batch with c codes in a tile writes ceil(c / 3) words
+// there, and every batch but a block's last holds at least 2048 pairs.
+inline uint64_t code_words_bound(uint64_t n, uint32_t r, uint32_t nbins, uint32_t nblk,
+                                 uint64_t chunk) {
+  const uint64_t codes = (uint64_t)r * n;
+  const uint64_t runs = (uint64_t)nbins * nblk * ((chunk + 2047) / 2048);
+  const uint64_t b = (codes + 2 * runs) / 3 + 1;
+  return b < codes ? b : codes;
 }
 
 // Launches one update round for n_jobs jobs that share r: `h_jobs` is the

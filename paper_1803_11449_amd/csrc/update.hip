@@ -144,11 +144,6 @@ __device__ __forceinline__ void pair_codes(const Geom &G, uint2 p, uint32_t *B) 
   }
 }
 
-// Pairs are read as uint4 (two pairs per lane per load), COUNT_V4 loads in
-// flight per lane; a job's pairs start 16-byte aligned and its chunks are
-// even, so every block's loads are aligned.
-constexpr int COUNT_V4 = 8;
-
 template <int R>
 __device__ __forceinline__ void count_pair(const Geom &G, uint2 p, uint32_t *h) {
   uint32_t B[R];
@@ -157,48 +152,81 @@ __device__ __forceinline__ void count_pair(const Geom &G, uint2 p, uint32_t *h) 
   for (int row = 0; row < R; row++) atomicAdd(&h[B[row] >> BIN_TILE_LOG2], 1u);
 }
 
-template <int R>
+// Codes are stored three to a 64-bit word (bits 0-19, 20-39, 40-59), and
+// every run the scatter writes (one tile, one batch of a block) is padded
+// to whole words. Per block and tile, the count therefore is the words its
+// batches will write there: it walks the same batches as the scatter (PPT
+// pairs per thread of 1024, from the start of the block's chunk) and adds
+// ceil(c / 3) for a batch with c codes in the tile.
+//
+// A full batch's pairs are read as uint4 (two pairs per lane per load); a
+// job's pairs start 16-byte aligned and its chunks and batches are even,
+// so these loads are aligned. The next batch's loads are issued before
+// this batch is counted; past the chunk's last whole uint4 they re-read it.
+template <int R, int PPT>
 __global__ __launch_bounds__(1024) void k_bin_count(const UpdJob *__restrict__ jobs, uint32_t nj) {
+  constexpr uint32_t TPT = (BIN_MAX + 1) / 1024;       // tiles per thread
+  constexpr int V4 = PPT / 2;
   __shared__ uint32_t h[BIN_MAX + 1];
   const UpdJob &J = jobs[job_of_block(jobs, nj, blockIdx.x)];
   const Geom G = J.G;
   const uint32_t nbins = J.nbins, lb = blockIdx.x - J.blk0;
-  for (uint32_t t = threadIdx.x; t < nbins; t += blockDim.x) h[t] = 0;
+  const uint32_t t0 = threadIdx.x * TPT;
+  for (uint32_t t = threadIdx.x; t < BIN_MAX + 1; t += blockDim.x) h[t] = 0;
   __syncthreads();
+  uint32_t acc[TPT] = {};
+  // a batch's run of c codes in a tile takes ceil(c / 3) words
+  auto close_batch = [&]() {
+    __syncthreads();
+#pragma unroll
+    for (uint32_t u = 0; u < TPT; u++) {
+      acc[u] += (h[t0 + u] + 2) / 3;
+      h[t0 + u] = 0;
+    }
+    __syncthreads();
+  };
   const size_t p0 = (size_t)lb * J.chunk;
   const size_t p1 = p0 + J.chunk < J.n ? p0 + J.chunk : J.n;
-  if (p0 < p1) {
-    const GMEM uint4 *q = gmem(reinterpret_cast<const uint4 *>(J.pairs + p0));
-    const size_t nq = (p1 - p0) / 2;
-    for (size_t i0 = 0; i0 < nq; i0 += (size_t)blockDim.x * COUNT_V4) {
-      // loads past the end re-read the last uint4 (no branch around them)
-      uint4 v[COUNT_V4];
+  const size_t step = (size_t)blockDim.x * PPT;
+  const GMEM uint4 *q = gmem(reinterpret_cast<const uint4 *>(J.pairs + p0));
+  const size_t nq = (p1 - p0) / 2;                      // whole uint4 of the chunk
+  size_t i0 = p0;
+  if (i0 + step <= p1) {                                 // uniform over the block
+    uint4 nxt[V4];
+    auto load = [&](size_t b0) {                         // b0: the batch's first pair
 #pragma unroll
-      for (int u = 0; u < COUNT_V4; u++) {
-        const size_t i = i0 + (size_t)u * blockDim.x + threadIdx.x;
-        v[u] = ld4(q + (i < nq ? i : nq - 1));
+      for (int k = 0; k < V4; k++) {
+        const size_t i = (b0 - p0) / 2 + (size_t)k * blockDim.x + threadIdx.x;
+        nxt[k] = ld4(q + (i < nq ? i : nq - 1));
       }
-      if (i0 + (size_t)blockDim.x * COUNT_V4 <= nq) {
+    };
+    load(i0);
+    for (; i0 + step <= p1; i0 += step) {
+      uint4 cur[V4];
 #pragma unroll
-        for (int u = 0; u < COUNT_V4; u++) {
-          count_pair<R>(G, make_uint2(v[u].x, v[u].y), h);
-          count_pair<R>(G, make_uint2(v[u].z, v[u].w), h);
-        }
-      } else {
+      for (int k = 0; k < V4; k++) cur[k] = nxt[k];
+      load(i0 + step);
 #pragma unroll
-        for (int u = 0; u < COUNT_V4; u++) {
-          const size_t i = i0 + (size_t)u * blockDim.x + threadIdx.x;
-          if (i >= nq) continue;
-          count_pair<R>(G, make_uint2(v[u].x, v[u].y), h);
-          count_pair<R>(G, make_uint2(v[u].z, v[u].w), h);
-        }
+      for (int k = 0; k < V4; k++) {
+        count_pair<R>(G, make_uint2(cur[k].x, cur[k].y), h);
+        count_pair<R>(G, make_uint2(cur[k].z, cur[k].w), h);
       }
+      close_batch();
     }
-    if (((p1 - p0) & 1) && threadIdx.x == 0) count_pair<R>(G, ld2(gmem(J.pairs) + (p1 - 1)), h);
   }
-  __syncthreads();
+  if (i0 < p1) {                                         // the chunk's partial batch
+    const GMEM uint2 *pairs = gmem(J.pairs);
+#pragma unroll
+    for (int k = 0; k < PPT; k++) {
+      const size_t i = i0 + (size_t)k * blockDim.x + threadIdx.x;
+      if (i < p1) count_pair<R>(G, ld2(pairs + i), h);
+    }
+    close_batch();
+  }
   GMEM uint32_t *hist = gmem(J.hist);
-  for (uint32_t t = threadIdx.x; t < nbins; t += blockDim.x) hist[(size_t)t * J.hstride + lb] = h[t];
+#pragma unroll
+  for (uint32_t u = 0; u < TPT; u++)
+    if (t0 + u < nbins) hist[(size_t)(t0 + u) * J.hstride + lb] = acc[u];
 }
 
 // Exclusive prefix sum over a workgroup of 1024 threads.
@@ -330,17 +358,22 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
                                                       uint32_t nj) {
   constexpr uint32_t BATCH = 1024 * PPT * R;
   constexpr uint32_t TPT = TMAX / 1024;                // tiles per thread
-  __shared__ uint32_t sorted[BATCH];   // sketch bit index, grouped by tile
+  // a batch's codes grouped by tile, each run padded to whole words (at
+  // most 2 pad slots per tile); with the three tile arrays this is at most
+  // 160 KiB for every (R, PPT, TMAX) the launcher picks
+  __shared__ uint32_t sorted[BATCH + 2 * TMAX];
   __shared__ uint32_t cnt[TMAX];       // codes per tile in this batch
-  __shared__ uint32_t lofs[TMAX];      // batch-local run starts
-  __shared__ uint32_t dst[TMAX];       // global slot of batch entry e is dst[t] + e
-  __shared__ uint32_t sh[16];
+  __shared__ uint32_t lofs[TMAX];      // batch-local run starts (multiples of 3)
+  __shared__ uint32_t dst[TMAX];       // word slot of batch word j is dst[t] + j
+  // the block scan's 16 words: dst is not in use from the end of a batch
+  // until step 3 of the next
+  uint32_t *const sh = dst;
   const UpdJob &J = jobs[job_of_block(jobs, nj, blockIdx.x)];
   const Geom G = J.G;
   const uint32_t lb = blockIdx.x - J.blk0;
   const GMEM uint2 *__restrict__ pairs = gmem(J.pairs);
-  GMEM uint32_t *__restrict__ codes = gmem(J.codes);
-  // this block's group's stream cursors, one per tile
+  GMEM uint64_t *__restrict__ words = gmem(reinterpret_cast<uint64_t *>(J.codes));
+  // this block's group's stream cursors (in words), one per tile
   GMEM uint32_t *gcur = gmem(J.gcur) + (size_t)(blockIdx.x % BIN_GROUPS) * J.nbins;
   for (uint32_t t = threadIdx.x; t < TMAX; t += blockDim.x) cnt[t] = 0;
   __syncthreads();
@@ -362,9 +395,9 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
     }
   };
   // One batch: the pairs [i0, i0 + step) of the chunk, held in cur. A full
-  // batch (FULL) has all its pairs, so no per-pair bounds test and exactly
-  // PPT * R stores per thread; only a chunk's last batch can be partial,
-  // and its missing pairs get the code ~0.
+  // batch (FULL) has all its pairs and takes no per-pair bounds test; only
+  // a chunk's last batch can be partial, and its missing pairs get the
+  // code ~0.
   auto batch = [&](auto full_c, size_t i0) {
     constexpr bool FULL = decltype(full_c)::value;
     // The thread index is taken afresh per batch, so that addresses derived
@@ -393,58 +426,53 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
       }
     }
     __syncthreads();
-    // 2: claim each tile's run in the group's stream (the claims' latency
-    // is hidden behind the scan and step 3); batch-local run starts
-    uint32_t c[TPT], run[TPT], lo[TPT], sum = 0;
+    // 2: claim each tile's run, ceil(c / 3) words, in the group's stream
+    // (the claims' latency is hidden behind the scan and step 3); run
+    // starts; the pad slots of each run get the marker ~0
+    uint32_t c[TPT], run[TPT], sum = 0;
 #pragma unroll
     for (uint32_t u = 0; u < TPT; u++) {
       c[u] = cnt[t0 + u];                   // 0 for the LDS slots past the tiles
-      sum += c[u];
-      run[u] = c[u] ? atomicAdd((uint32_t *)&gcur[t0 + u], c[u]) : 0;
+      const uint32_t w = (c[u] + 2) / 3;
+      sum += 3 * w;
+      run[u] = w ? atomicAdd((uint32_t *)&gcur[t0 + u], w) : 0;
     }
     uint32_t total;
     uint32_t ex = blk_scan_1024(sum, &total, sh, tid);
 #pragma unroll
     for (uint32_t u = 0; u < TPT; u++) {
-      const uint32_t t = t0 + u;
-      lo[u] = ex;
+      const uint32_t t = t0 + u, padded = 3 * ((c[u] + 2) / 3);
       lofs[t] = ex;
       cnt[t] = 0;
-      ex += c[u];
+      if (padded > c[u]) sorted[ex + c[u]] = ~0u;         // at most two pad slots
+      if (padded > c[u] + 1) sorted[ex + c[u] + 1] = ~0u;
+      ex += padded;
     }
     __syncthreads();
-    // 3: group by tile in LDS; dst maps a sorted position to its slot
+    // 3: group by tile in LDS; dst maps a batch word to its word slot
 #pragma unroll
     for (int q = 0; q < PPT * R; q++)
       if (FULL || v[q] != ~0u) sorted[lofs[v[q] >> BIN_TILE_LOG2] + get_rank(rk2, q)] = v[q];
 #pragma unroll
-    for (uint32_t u = 0; u < TPT; u++) dst[t0 + u] = run[u] - lo[u];
+    for (uint32_t u = 0; u < TPT; u++) dst[t0 + u] = run[u] - lofs[t0 + u] / 3;
     __syncthreads();
-    // 4: write the runs
-    if constexpr (FULL) {
-      // total == BATCH: a fixed count of stores, all unrolled
+    // 4: write the words; batch word j holds sorted slots 3j..3j+2, whose
+    // first is always a code of the run and stands in for a pad (a code
+    // set twice sets the same bit)
+    const uint32_t nw = total / 3;
+    auto put = [&](uint32_t j) {
+      const uint32_t x = sorted[3 * j], y0 = sorted[3 * j + 1], z0 = sorted[3 * j + 2];
+      const uint32_t y = y0 == ~0u ? x : y0, z = z0 == ~0u ? x : z0;
+      const uint64_t wv = (uint64_t)(x & CODE_MASK) | ((uint64_t)(y & CODE_MASK) << 20) |
+                          ((uint64_t)(z & CODE_MASK) << 40);
+      words[dst[x >> BIN_TILE_LOG2] + j] = wv;
+    };
+    uint32_t j = tid;
+    for (; j + (SCATTER_UNROLL - 1) * 1024 < nw; j += SCATTER_UNROLL * 1024) {
 #pragma unroll
-      for (uint32_t u = 0; u < PPT * R; u++) {
-        const uint32_t e = tid + u * 1024;
-        const uint32_t x = sorted[e];
-        codes[dst[x >> BIN_TILE_LOG2] + e] = x & CODE_MASK;
-      }
-    } else {
-      uint32_t e = tid;
-      for (; e + (SCATTER_UNROLL - 1) * 1024 < total; e += SCATTER_UNROLL * 1024) {
-        uint32_t x[SCATTER_UNROLL], d[SCATTER_UNROLL];
-#pragma unroll
-        for (int u = 0; u < SCATTER_UNROLL; u++) x[u] = sorted[e + u * 1024];
-#pragma unroll
-        for (int u = 0; u < SCATTER_UNROLL; u++) d[u] = dst[x[u] >> BIN_TILE_LOG2];
-#pragma unroll
-        for (int u = 0; u < SCATTER_UNROLL; u++) codes[d[u] + e + u * 1024] = x[u] & CODE_MASK;
-      }
-      for (; e < total; e += 1024) {
-        const uint32_t x = sorted[e];
-        codes[dst[x >> BIN_TILE_LOG2] + e] = x & CODE_MASK;
-      }
+      for (int u = 0; u < SCATTER_UNROLL; u++) put(j + u * 1024);
     }
+    for (; j < nw; j += 1024) put(j);
     __syncthreads();
   };
 #pragma unroll
@@ -452,19 +480,10 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
     const size_t i = p0 + (size_t)k * blockDim.x + threadIdx.x;
     nxt[k] = ld2(pairs + (i < p1 ? i : p1 - 1));
   }
-  // Loads and stores share one in-order completion counter, so a wait for
-  // the next batch's pairs also waits for every store issued before them.
-  // The full batches therefore run as one peeled batch and a loop: on both
-  // edges into the loop the prefetch is followed by exactly one batch's
-  // stores, and the wait for it leaves that batch's stores in flight.
   size_t i0 = p0;
-  if (i0 + step <= p1) {
+  for (; i0 + step <= p1; i0 += step) {
     advance(i0 + step);
     batch(std::true_type{}, i0);
-    for (i0 += step; i0 + step <= p1; i0 += step) {
-      advance(i0 + step);
-      batch(std::true_type{}, i0);
-    }
   }
   if (i0 < p1) {
 #pragma unroll
@@ -474,6 +493,16 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
 }
 
 constexpr int APPLY_UNROLL = 4;
+
+// The three codes of a word (low half lo, high half hi) into the LDS tile.
+__device__ __forceinline__ void or_word(uint32_t *tile, uint2 w) {
+  const uint32_t a = w.x & CODE_MASK;
+  const uint32_t b = __builtin_amdgcn_alignbit(w.y, w.x, 20) & CODE_MASK;
+  const uint32_t c = (w.y >> 8) & CODE_MASK;
+  atomicOr(&tile[a >> 5], 1u << (a & 31));
+  atomicOr(&tile[b >> 5], 1u << (b & 31));
+  atomicOr(&tile[c >> 5], 1u << (c & 31));
+}
 
 __global__ __launch_bounds__(1024) void k_bin_apply(const UpdJob *__restrict__ jobs, uint32_t nj,
                                                     const uint32_t *__restrict__ n_items_p) {
@@ -493,7 +522,7 @@ __global__ __launch_bounds__(1024) void k_bin_apply(const UpdJob *__restrict__ j
     const uint32_t c1 = whole ? c_end : (c_end - c0 > APPLY_ITEM ? c0 + APPLY_ITEM : c_end);
     const size_t w0 = (size_t)t * BIN_TILE_WORDS;
     const uint32_t tw = (uint32_t)(J.words - w0 < BIN_TILE_WORDS ? J.words - w0 : BIN_TILE_WORDS);
-    const GMEM uint32_t *__restrict__ codes = gmem(J.codes);
+    const GMEM uint2 *__restrict__ codes = gmem(reinterpret_cast<const uint2 *>(J.codes));
     // the first item of a tile owns the tile; item s >= 1 of a cut tile
     // writes scratch tile xslot[t] + s - 1
     GMEM uint32_t *dstp =
@@ -514,17 +543,14 @@ __global__ __launch_bounds__(1024) void k_bin_apply(const UpdJob *__restrict__ j
       for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) tile[w] = dstp[w];
     }
     __syncthreads();
-    // codes [c0,c1): a scalar head up to a 4-aligned index, uint4 body,
-    // scalar tail
-    const uint32_t up4 = (c0 + 3u) & ~3u;
-    const uint32_t a0 = up4 < c1 ? up4 : c1;
-    const uint32_t a1 = a0 + ((c1 - a0) & ~3u);
-    for (uint32_t c = c0 + threadIdx.x; c < a0; c += blockDim.x) {
-      const uint32_t x = codes[c];
-      atomicOr(&tile[x >> 5], 1u << (x & 31));
-    }
+    // words [c0,c1): a single word up to an even index, uint4 body (two
+    // words), a single word at the end
+    const uint32_t a0 = (c0 & 1) && c0 < c1 ? c0 + 1 : c0;
+    const uint32_t a1 = a0 + ((c1 - a0) & ~1u);
+    if (threadIdx.x == 0 && a0 != c0) or_word(tile, ld2(codes + c0));
+    if (threadIdx.x == 0 && a1 != c1) or_word(tile, ld2(codes + a1));
     const GMEM uint4 *q = reinterpret_cast<const GMEM uint4 *>(codes + a0);
-    const uint32_t nq = (a1 - a0) / 4;
+    const uint32_t nq = (a1 - a0) / 2;
     // whole rounds of APPLY_UNROLL uint4 per thread with no bounds test,
     // then the rest one uint4 at a time
     uint32_t i = threadIdx.x;
@@ -534,22 +560,14 @@ __global__ __launch_bounds__(1024) void k_bin_apply(const UpdJob *__restrict__ j
       for (int u = 0; u < APPLY_UNROLL; u++) x[u] = ld4(q + i + u * blockDim.x);
 #pragma unroll
       for (int u = 0; u < APPLY_UNROLL; u++) {
-        atomicOr(&tile[x[u].x >> 5], 1u << (x[u].x & 31));
-        atomicOr(&tile[x[u].y >> 5], 1u << (x[u].y & 31));
-        atomicOr(&tile[x[u].z >> 5], 1u << (x[u].z & 31));
-        atomicOr(&tile[x[u].w >> 5], 1u << (x[u].w & 31));
+        or_word(tile, make_uint2(x[u].x, x[u].y));
+        or_word(tile, make_uint2(x[u].z, x[u].w));
       }
     }
     for (; i < nq; i += blockDim.x) {
       const uint4 x = ld4(q + i);
-      atomicOr(&tile[x.x >> 5], 1u << (x.x & 31));
-      atomicOr(&tile[x.y >> 5], 1u << (x.y & 31));
-      atomicOr(&tile[x.z >> 5], 1u << (x.z & 31));
-      atomicOr(&tile[x.w >> 5], 1u << (x.w & 31));
-    }
-    for (uint32_t c = a1 + threadIdx.x; c < c1; c += blockDim.x) {
-      const uint32_t x = codes[c];
-      atomicOr(&tile[x >> 5], 1u << (x & 31));
+      or_word(tile, make_uint2(x.x, x.y));
+      or_word(tile, make_uint2(x.z, x.w));
     }
     __syncthreads();
     if (tw == BIN_TILE_WORDS) {
@@ -603,6 +621,16 @@ __global__ __launch_bounds__(256) void k_bin_merge(const UpdJob *__restrict__ jo
 
 // ---------------------------------------------------------------- launch
 
+// count, the two scans and the scatter of a binned round
+template <int R, int PPT, int TMAX>
+static void launch_front(UpdJob *d, uint32_t nj, uint32_t blocks, uint32_t tiles,
+                         hipStream_t st) {
+  k_bin_count<R, PPT><<<blocks, 1024, 0, st>>>(d, nj);
+  k_bin_scan_cols<<<tiles, 1024, 0, st>>>(d, nj);
+  k_bin_scan_tiles<<<nj, 1024, 0, st>>>(d);
+  k_bin_scatter<R, PPT, TMAX><<<blocks, 1024, 0, st>>>(d, nj);
+}
+
 template <int R>
 static hipError_t launch_r(const UpdJob *h, UpdJob *d, uint32_t nj, uint32_t *d_total,
                            bool binned, uint32_t ppt, uint32_t apply_grid, hipStream_t st) {
@@ -617,32 +645,33 @@ static hipError_t launch_r(const UpdJob *h, UpdJob *d, uint32_t nj, uint32_t *d_
     else k_update<R, false><<<blocks, 256, 0, st>>>(d, nj);
     return hipGetLastError();
   }
-  k_bin_count<R><<<blocks, 1024, 0, st>>>(d, nj);
-  k_bin_scan_cols<<<tiles, 1024, 0, st>>>(d, nj);
-  k_bin_scan_tiles<<<nj, 1024, 0, st>>>(d);
-  // LDS: 4*1024*PPT*r bytes of sorted codes + 16*TMAX bytes of tile arrays
-  // <= 160 KiB. Up to 2048 tiles: 6 pairs per thread for r <= 5, 4 for
-  // r <= 7, else 2. Up to 4095 tiles: 4 for r <= 5, else 2.
+  // LDS of the scatter: 4*(1024*PPT*r + 2*TMAX) bytes of sorted codes +
+  // 12*TMAX bytes of tile arrays <= 160 KiB. Up to 2048 tiles: 6 pairs per
+  // thread for r <= 5, 4 for r <= 7, else 2. Up to 4095 tiles: 4 for
+  // r <= 5, else 2. The count pass walks the scatter's batches, so both take
+  // the same PPT.
   uint32_t max_tiles = 0;
   for (uint32_t j = 0; j < nj; j++) max_tiles = max_tiles > h[j].nbins ? max_tiles : h[j].nbins;
   if (max_tiles <= 2048) {
     constexpr int P4 = R <= 7 ? 4 : 2;
     constexpr int P6 = R <= 5 ? 6 : P4;
-    if (ppt == 2) k_bin_scatter<R, 2, 2048><<<blocks, 1024, 0, st>>>(d, nj);
-    else if (ppt == 6) k_bin_scatter<R, P6, 2048><<<blocks, 1024, 0, st>>>(d, nj);
-    else k_bin_scatter<R, P4, 2048><<<blocks, 1024, 0, st>>>(d, nj);
+    if (ppt == 2) launch_front<R, 2, 2048>(d, nj, blocks, tiles, st);
+    else if (ppt == 6) launch_front<R, P6, 2048>(d, nj, blocks, tiles, st);
+    else launch_front<R, P4, 2048>(d, nj, blocks, tiles, st);
   } else {
     constexpr int P4 = R <= 5 ? 4 : 2;
-    if (ppt == 2) k_bin_scatter<R, 2, 4096><<<blocks, 1024, 0, st>>>(d, nj);
-    else k_bin_scatter<R, P4, 4096><<<blocks, 1024, 0, st>>>(d, nj);
+    if (ppt == 2) launch_front<R, 2, 4096>(d, nj, blocks, tiles, st);
+    else launch_front<R, P4, 4096>(d, nj, blocks, tiles, st);
   }
   k_item_offsets<<<1, 1024, 0, st>>>(d, nj, d_total);
   // apply_grid 0: one workgroup per apply item (an upper bound of the
-  // items: a tile with v codes makes at most 1 + v / APPLY_ITEM of them), so
-  // the dispatcher hands items to compute units as they free up
+  // items: a tile with v code words makes at most 1 + v / APPLY_ITEM of
+  // them), so the dispatcher hands items to compute units as they free up
   uint64_t grid = apply_grid;
   if (grid == 0)
-    for (uint32_t j = 0; j < nj; j++) grid += h[j].nbins + (uint64_t)R * h[j].n / APPLY_ITEM + 1;
+    for (uint32_t j = 0; j < nj; j++)
+      grid += h[j].nbins +
+              code_words_bound(h[j].n, R, h[j].nbins, h[j].nblk, h[j].chunk) / APPLY_ITEM + 1;
   if (grid > 0x7FFFFFFFull) grid = 0x7FFFFFFFull;
   k_bin_apply<<<(uint32_t)grid, 1024, 0, st>>>(d, nj, d_total);
   k_bin_merge<<<dim3(tiles, BIN_TILE_WORDS / MERGE_SLICE), 256, 0, st>>>(d, nj);

@@ -381,20 +381,21 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
   const size_t p1 = p0 + J.chunk < J.n ? p0 + J.chunk : J.n;
   if (p0 >= p1) return;                                // uniform over the block
   const size_t step = (size_t)blockDim.x * PPT;
-  // The next batch's pairs are loaded while this batch is sorted and
-  // written. Loads past the chunk re-read its last pair (their lanes are
-  // masked later): with no branch around them the compiler can wait for
-  // the older batch alone instead of for every load in flight.
-  uint2 cur[PPT], nxt[PPT];
-  auto advance = [&](size_t i_next) {
+  // A batch's pairs are held in pr. The next batch's pairs are loaded into
+  // pr as soon as this batch's codes are made (step 1), so they arrive
+  // while the batch is sorted and written, and no second set of registers
+  // is live. Loads past the chunk re-read its last pair (their lanes are
+  // masked later): with no branch around them the compiler need not wait
+  // for every load in flight.
+  uint2 pr[PPT];
+  auto load = [&](size_t b0, uint32_t tid) {
 #pragma unroll
     for (int k = 0; k < PPT; k++) {
-      cur[k] = nxt[k];
-      const size_t i = i_next + (size_t)k * blockDim.x + threadIdx.x;
-      nxt[k] = ld2(pairs + (i < p1 ? i : p1 - 1));
+      const size_t i = b0 + (size_t)k * blockDim.x + tid;
+      pr[k] = ld2(pairs + (i < p1 ? i : p1 - 1));
     }
   };
-  // One batch: the pairs [i0, i0 + step) of the chunk, held in cur. A full
+  // One batch: the pairs [i0, i0 + step) of the chunk, held in pr. A full
   // batch (FULL) has all its pairs and takes no per-pair bounds test; only
   // a chunk's last batch can be partial, and its missing pairs get the
   // code ~0.
@@ -414,7 +415,7 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
       const size_t i = i0 + (size_t)k * blockDim.x + tid;
       if (FULL || i < p1) {
         uint32_t B[R];
-        pair_codes<R>(G, cur[k], B);
+        pair_codes<R>(G, pr[k], B);
 #pragma unroll
         for (int row = 0; row < R; row++) {
           v[k * R + row] = B[row];
@@ -425,6 +426,7 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
         for (int row = 0; row < R; row++) v[k * R + row] = ~0u;
       }
     }
+    load(i0 + step, tid);
     __syncthreads();
     // 2: claim each tile's run, ceil(c / 3) words, in the group's stream
     // (the claims' latency is hidden behind the scan and step 3); run
@@ -475,21 +477,10 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
     for (; j < nw; j += 1024) put(j);
     __syncthreads();
   };
-#pragma unroll
-  for (int k = 0; k < PPT; k++) {
-    const size_t i = p0 + (size_t)k * blockDim.x + threadIdx.x;
-    nxt[k] = ld2(pairs + (i < p1 ? i : p1 - 1));
-  }
+  load(p0, threadIdx.x);
   size_t i0 = p0;
-  for (; i0 + step <= p1; i0 += step) {
-    advance(i0 + step);
-    batch(std::true_type{}, i0);
-  }
-  if (i0 < p1) {
-#pragma unroll
-    for (int k = 0; k < PPT; k++) cur[k] = nxt[k];
-    batch(std::false_type{}, i0);
-  }
+  for (; i0 + step <= p1; i0 += step) batch(std::true_type{}, i0);
+  if (i0 < p1) batch(std::false_type{}, i0);
 }
 
 constexpr int APPLY_UNROLL = 4;

@@ -252,8 +252,8 @@ int sketch_merge(sketch_t *dst, const sketch_t *src, void *hip_stream);
 /* Options of sketch_set_option. The update has two kernels computing the
  * same sketch: "direct" (each pair sets its r bits with a check-then-
  * atomicOr in the sketch, Alg. 1 as written) and "binned" (the bit sets are
- * grouped by 64 KiB slice of the sketch and applied in LDS, one workgroup
- * per slice). */
+ * grouped by 128 KiB tile of the sketch and applied in LDS, one workgroup
+ * per tile or part of a tile). */
 enum {
   SKETCH_OPT_UPDATE_PATH = 1,       /* 0 = choose by size (default),
                                        1 = direct, 2 = binned */
@@ -263,8 +263,9 @@ enum {
   SKETCH_OPT_UPDATE_CHECK = 4,      /* direct kernel: 1 = test the bit before
                                        the atomicOr (default), 0 = always OR */
   SKETCH_OPT_BINNED_ROUND = 5,      /* binned: pairs per round; the round's
-                                       codes take 4*r bytes per pair of device
-                                       memory, allocated on first use */
+                                       codes (three per 8 bytes) take about
+                                       2.7*r bytes per pair of device memory,
+                                       allocated on first use */
   SKETCH_OPT_SCATTER_PPT = 6,       /* binned: pairs per thread in one LDS
                                        sorting batch: 2, 4 or 6 (default);
                                        capped by LDS at 4 for r in 6..7 and

@@ -235,7 +235,12 @@ size_t sketch_plan_launches(const sketch_plan_t *plan);
 void sketch_plan_destroy(sketch_plan_t *plan);
 
 /* Start a new window: every bit of the sketch back to 0 (Sec. 4).
- * Asynchronous on hip_stream. */
+ * Enqueues nothing: the sketch is marked all zero, and the zeros are written
+ * by the next call that needs them, on that call's stream. A binned update
+ * from the window's first pair writes every tile from zeros instead of
+ * reading it; a direct update, restore, merge into the sketch or plan run
+ * without SKETCH_PLAN_RESET writes the zeros first; a download returns
+ * zeros. hip_stream is unused. Errors: INVAL. */
 int sketch_reset(sketch_t *s, void *hip_stream);
 
 /* Merge the window of another monitor into this one: dst |= src, bit by bit

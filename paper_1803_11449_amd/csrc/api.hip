@@ -398,6 +398,11 @@ struct sketch {
   int grid = 0;                 // blocks of grid-stride kernels
   uint32_t *d_sketch = nullptr;
   size_t words = 0;
+  // All zero but not yet written: a reset only sets this. The first binned
+  // update then writes every tile from zeros instead of reading it; other
+  // work that reads the sketch or sets bits in place writes the zeros first
+  // (materialize).
+  bool fresh = false;
   // update
   int update_grid = 0;          // blocks of the direct kernel
   int update_check = 1;
@@ -542,11 +547,21 @@ Thresholds thresholds(const sketch *s, double theta) {
   return t;
 }
 
+// Write the zeros of a fresh sketch (on st).
+int materialize(sketch *s, hipStream_t st) {
+  if (!s->fresh) return SKETCH_OK;
+  HIP_OK(launch_fill_u32(s->d_sketch, s->words, 0u, s->grid * 4, st));
+  s->fresh = false;
+  return SKETCH_OK;
+}
+
 // Enqueue the restore kernels and the copy of the device state (no wait).
 // Caller holds ctx->mu.
 int restore_launch(sketch *s, const Thresholds &t, int estimate, hipStream_t st) {
   DevCtx *c = s->ctx;
-  int rc = pool_enter(c, st);
+  int rc = materialize(s, st);
+  if (rc) return rc;
+  rc = pool_enter(c, st);
   if (rc) return rc;
   const RestoreBufs B = restore_bufs(s);
   s->ran_seg_cap = B.seg_cap;
@@ -739,8 +754,17 @@ int check_update_jobs(const sketch_update_job_t *jobs, size_t n_jobs, const char
 // hands them, in order, to flush(Group&). Binned work runs in rounds of at
 // most ARENA_MAX_PAIRS pairs in total (and a job's binned_round each); job
 // j's per-sketch arrays come from base(j).
+// Whether an update of n pairs at p takes binned rounds from its first pair
+// on (no pair goes through the direct kernel first).
+bool binned_from_start(const sketch *s, const uint32_t *p, size_t n) {
+  return n && wants_binned(s, n) && !(((uintptr_t)p) & 15u);
+}
+
+// fresh (may be null): per job, 1 if the job's first binned round starts
+// from a fresh sketch (binned_from_start must hold); consumed by that round.
 template <class Base, class Flush>
-int schedule_update(const sketch_update_job_t *jobs, size_t n_jobs, Base base, Flush flush) {
+int schedule_update(const sketch_update_job_t *jobs, size_t n_jobs, Base base, Flush flush,
+                    char *fresh = nullptr) {
   std::vector<const uint32_t *> ptr(n_jobs);
   std::vector<size_t> left(n_jobs);
   std::vector<char> binned(n_jobs);
@@ -782,6 +806,10 @@ int schedule_update(const sketch_update_job_t *jobs, size_t n_jobs, Base base, F
         chunk += chunk & 1;
         J.chunk = chunk;
         J.nblk = (uint32_t)((m + chunk - 1) / chunk);
+        if (fresh) {
+          J.fresh = (uint32_t)fresh[j];
+          fresh[j] = 0;
+        }
         add_job(groups, s, J, true);
         ptr[j] += 2 * m;
         left[j] -= m;
@@ -814,9 +842,23 @@ int update_jobs(const sketch_update_job_t *jobs, size_t n_jobs, hipStream_t st) 
   DEVICE_GUARD(jobs[0].sketch->p.device);
   DevCtx *c = jobs[0].sketch->ctx;
   std::lock_guard<std::mutex> lk(c->mu);
+  // a fresh sketch whose update is binned from its first pair skips its
+  // zero fill; any other fresh sketch with pairs gets its zeros first
+  std::vector<char> fresh(n_jobs, 0);
+  for (size_t j = 0; j < n_jobs; j++) {
+    sketch *s = jobs[j].sketch;
+    if (!s->fresh || jobs[j].n_pairs == 0) continue;
+    if (binned_from_start(s, jobs[j].d_pairs, jobs[j].n_pairs)) {
+      fresh[j] = 1;
+      s->fresh = false;
+    } else {
+      rc = materialize(s, st);
+      if (rc) return rc;
+    }
+  }
   return schedule_update(
       jobs, n_jobs, [&](size_t j) { return job_base(jobs[j].sketch); },
-      [&](Group &g) { return flush_group(c, g, st); });
+      [&](Group &g) { return flush_group(c, g, st); }, fresh.data());
 }
 
 
@@ -848,6 +890,8 @@ struct PlanJob {
   size_t sorted_cap = 0;
   size_t ran_spl_cap = 0;       // record capacity the captured restore has
   bool eager = false;           // this result comes from an eager rerun
+  bool fresh = false;           // RESET plan: the first binned round writes every
+                                // tile from zeros, so no zero fill
 };
 
 struct PlanLaunch {
@@ -934,7 +978,7 @@ RestoreBufs plan_restore_bufs(const sketch_plan *P, const PlanJob &j) {
 int plan_enqueue(sketch_plan *P, hipStream_t st) {
   if (P->flags & SKETCH_PLAN_RESET)
     for (PlanJob &j : P->jobs)
-      HIP_OK(launch_fill_u32(j.s->d_sketch, j.s->words, 0u, j.s->grid * 4, st));
+      if (!j.fresh) HIP_OK(launch_fill_u32(j.s->d_sketch, j.s->words, 0u, j.s->grid * 4, st));
   for (PlanLaunch &L : P->launches)
     HIP_OK(launch_update_jobs(L.h.data(), L.d, (uint32_t)L.h.size(), L.d_total, L.binned, L.r,
                               L.ppt, L.apply_grid, st));
@@ -1097,8 +1141,8 @@ int sketch_update_batch(const sketch_update_job_t *jobs, size_t n_jobs, void *hi
 
 int sketch_reset(sketch_t *s, void *hip_stream) {
   if (!s) return fail(SKETCH_E_INVAL, "sketch_reset: NULL handle");
-  DEVICE_GUARD(s->p.device);
-  HIP_OK(launch_fill_u32(s->d_sketch, s->words, 0u, s->grid * 4, (hipStream_t)hip_stream));
+  (void)hip_stream;
+  s->fresh = true;                  // the zeros are written when needed
   return SKETCH_OK;
 }
 
@@ -1110,7 +1154,10 @@ int sketch_merge(sketch_t *dst, const sketch_t *src, void *hip_stream) {
     return fail(SKETCH_E_INVAL, "sketch_merge: sketches differ in parameters or seed");
   if (a.device != b.device)
     return fail(SKETCH_E_INVAL, "sketch_merge: sketches on different devices");
+  if (src->fresh) return SKETCH_OK;   // OR with zeros
   DEVICE_GUARD(a.device);
+  int rc = materialize(dst, (hipStream_t)hip_stream);
+  if (rc) return rc;
   HIP_OK(launch_or_u32(dst->d_sketch, src->d_sketch, dst->words, dst->grid * 4,
                        (hipStream_t)hip_stream));
   return SKETCH_OK;
@@ -1282,6 +1329,10 @@ int sketch_download(const sketch_t *s, uint32_t *host_words, size_t n_words, voi
   if (!s || !host_words) return fail(SKETCH_E_INVAL, "sketch_download: NULL argument");
   if (n_words != s->words)
     return fail(SKETCH_E_INVAL, "sketch_download: n_words %zu, sketch has %zu", n_words, s->words);
+  if (s->fresh) {                   // all zero, not yet written
+    memset(host_words, 0, n_words * 4);
+    return SKETCH_OK;
+  }
   DEVICE_GUARD(s->p.device);
   hipStream_t st = (hipStream_t)hip_stream;
   HIP_OK(hipMemcpyAsync(host_words, s->d_sketch, n_words * 4, hipMemcpyDeviceToHost, st));
@@ -1297,6 +1348,7 @@ int sketch_upload(sketch_t *s, const uint32_t *host_words, size_t n_words, void 
   hipStream_t st = (hipStream_t)hip_stream;
   HIP_OK(hipMemcpyAsync(s->d_sketch, host_words, n_words * 4, hipMemcpyHostToDevice, st));
   HIP_OK(hipStreamSynchronize(st));
+  s->fresh = false;
   return SKETCH_OK;
 }
 
@@ -1359,6 +1411,12 @@ int sketch_plan_create(const sketch_plan_job_t *jobs, size_t n_jobs, int flags,
     P->cap = nullptr;
     rc = fail(SKETCH_E_HIP, "plan: hipStreamCreate failed");
   }
+  std::vector<char> fresh(n_jobs, 0);
+  if (flags & SKETCH_PLAN_RESET)
+    for (size_t j = 0; j < n_jobs; j++) {
+      P->jobs[j].fresh = binned_from_start(uj[j].sketch, uj[j].d_pairs, uj[j].n_pairs);
+      fresh[j] = P->jobs[j].fresh;
+    }
   if (!rc) {
     std::lock_guard<std::mutex> lk(c->mu);
     // the update launches, with this plan's per-job arrays
@@ -1393,7 +1451,8 @@ int sketch_plan_create(const sketch_plan_job_t *jobs, size_t n_jobs, int flags,
             P->launches.push_back(std::move(L));
           }
           return SKETCH_OK;
-        });
+        },
+        fresh.data());
     for (size_t i = 0; i < P->launches.size() && !rc; i++) {
       PlanLaunch &L = P->launches[i];
       rc = dev_alloc(&L.d, L.h.size(), "plan job table");
@@ -1429,6 +1488,16 @@ int sketch_plan_run(sketch_plan_t *P, void *hip_stream) {
     int rc = pool_idle(c);
     if (!rc) rc = plan_build_graph(P);
     if (rc) return rc;
+  }
+  // a plan that does not reset works on the sketches as they are: write the
+  // zeros of fresh ones first; a resetting plan leaves none fresh
+  for (PlanJob &j : P->jobs) {
+    if (P->flags & SKETCH_PLAN_RESET) {
+      j.s->fresh = false;
+    } else {
+      int rc = materialize(j.s, st);
+      if (rc) return rc;
+    }
   }
   int rc = pool_enter(c, st);
   if (rc) return rc;

@@ -134,7 +134,9 @@ struct UpdJob {
   uint32_t blk0;         // first global block of this job
   uint32_t tile0;        // first global tile of this job
   uint32_t hstride;      // row stride of hist (>= nblk)
-  uint32_t pad0;
+  uint32_t fresh;        // binned: the sketch is all zero and not yet written
+                         // (the first round after a reset): tiles are not
+                         // read, and every tile is written
   uint32_t *hist, *totals, *base, *item_start, *xslot, *n_items;
   uint32_t *item_tile;   // tile of each apply item (ITEM_TILE_SLOTS(nbins) entries)
   uint32_t *gcur;        // [BIN_GROUPS][nbins]: next slot of each group's stream per tile

@@ -272,10 +272,11 @@ __global__ __launch_bounds__(1024) void k_bin_scan_cols(const UpdJob *__restrict
   }
 }
 
-// Apply items of a tile with v codes: one if v <= SPLIT_MIN, else one per
-// APPLY_ITEM codes.
-__device__ __forceinline__ uint32_t tile_items(uint32_t v) {
-  return v == 0 ? 0u : (v <= SPLIT_MIN ? 1u : (v + APPLY_ITEM - 1) / APPLY_ITEM);
+// Apply items of a tile with v code words: one if v <= SPLIT_MIN, else one
+// per APPLY_ITEM words; none for an empty tile, unless the sketch is fresh
+// (all zero and not yet written), when the tile's one item writes its zeros.
+__device__ __forceinline__ uint32_t tile_items(uint32_t v, uint32_t fresh) {
+  return v == 0 ? (fresh ? 1u : 0u) : (v <= SPLIT_MIN ? 1u : (v + APPLY_ITEM - 1) / APPLY_ITEM);
 }
 
 // Over one job's tiles (block = job): run starts (which also turn the
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(1024) void k_bin_scan_tiles(const UpdJob *__restric
   for (uint32_t k = 0; k < PER; k++) {
     const uint32_t t = t0 + k;
     const uint32_t v = t < nbins ? totals[t] : 0;
-    const uint32_t ni = tile_items(v);
+    const uint32_t ni = t < nbins ? tile_items(v, J.fresh) : 0;
     c += v;
     it += ni;
     xs += ni > 1 ? ni - 1 : 0;
@@ -310,7 +311,7 @@ __global__ __launch_bounds__(1024) void k_bin_scan_tiles(const UpdJob *__restric
     const uint32_t t = t0 + k;
     if (t < nbins) {
       const uint32_t v = totals[t];
-      const uint32_t ni = tile_items(v);
+      const uint32_t ni = tile_items(v, J.fresh);
       base[t] = ec;
 #pragma unroll
       for (uint32_t g = 0; g < BIN_GROUPS; g++) gcur[(size_t)g * nbins + t] += ec;
@@ -519,9 +520,10 @@ __global__ __launch_bounds__(1024) void k_bin_apply(const UpdJob *__restrict__ j
     GMEM uint32_t *dstp =
         sub == 0 ? gmem(J.sk) + w0
                  : gmem(J.scratch) + (size_t)(gmem(J.xslot)[t] + sub - 1) * BIN_TILE_WORDS;
-    // the tile in: a whole tile as 16-byte loads, all in flight before the
-    // LDS writes (tiles and scratch tiles are 128 KiB aligned)
-    if (sub != 0) {
+    // the tile in: zeros for a scratch tile or a fresh sketch, else a whole
+    // tile as 16-byte loads, all in flight before the LDS writes (tiles and
+    // scratch tiles are 128 KiB aligned)
+    if (sub != 0 || J.fresh) {
       for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) tile[w] = 0;
     } else if (tw == BIN_TILE_WORDS) {
       const GMEM uint4 *src = reinterpret_cast<const GMEM uint4 *>(dstp);

@@ -1,0 +1,138 @@
+"""A reset marks the sketch all zero without writing it (the zeros are
+written by the next work that needs them, or not at all by a binned update
+that starts at the window's first pair). Every kind of work that can follow
+a reset must see an all-zero sketch: each case here fills the sketch with
+an earlier window first, resets, and compares with the oracle, bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1803_11449_amd import ddhf
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+P = oracle.Params(1024, 18, 5, 5)
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def to_dev(pairs_np):
+    return torch.from_numpy(np.ascontiguousarray(pairs_np).view(np.int32)).to(DEV)
+
+
+def rand_pairs(rng, n, n_src):
+    src = rng.integers(0, 2**32, size=n_src, dtype=np.uint64)[rng.integers(0, n_src, size=n)]
+    dst = rng.integers(0, 2**32, size=n, dtype=np.uint64)
+    return np.stack([src, dst], 1).astype(np.uint32)
+
+
+def dirty_sketch(rng, path=0):
+    """A sketch holding an earlier window, then reset."""
+    sk = ddhf.Sketch(P.g, P.k, P.r, P.alpha, P.seed, device=0)
+    if path:
+        sk.set_option(ddhf.SKETCH_OPT_UPDATE_PATH, path)
+    sk.update(to_dev(rand_pairs(rng, 600_000, 30_000)))
+    sk.reset()
+    return sk
+
+
+def test_reset_then_updates_of_every_kind():
+    rng = np.random.default_rng(71)
+    pairs = rand_pairs(rng, 900_000, 40_000)
+    ref = oracle.build_sketch(P, pairs)
+    # a tile with more code words than one apply item: the fresh tile's
+    # first item writes it from zeros, the others go through scratch tiles
+    heavy = np.stack([np.full(1_200_000, 0x0A0B0C0D, dtype=np.uint32),
+                      rng.integers(0, 2**32, size=1_200_000, dtype=np.uint64).astype(np.uint32)],
+                     1)
+    split = np.concatenate([pairs, heavy])[rng.permutation(len(pairs) + len(heavy))]
+    ref_split = oracle.build_sketch(P, split)
+    cases = [
+        ("binned from the first pair", 2, {}, pairs, ref),
+        ("direct", 1, {}, pairs, ref),
+        ("binned, odd offset (first pair direct)", 2, {"offset": 1}, pairs, ref),
+        ("binned in rounds of 2^18 pairs", 2, {ddhf.SKETCH_OPT_BINNED_ROUND: 1 << 18}, pairs, ref),
+        ("binned, split tiles", 2, {}, split, ref_split),
+    ]
+    for name, path, opts, data, want in cases:
+        say(f"reset then update: {name}")
+        with dirty_sketch(rng, path) as sk:
+            for o, v in opts.items():
+                if o != "offset":
+                    sk.set_option(o, v)
+            if opts.get("offset"):
+                t = to_dev(np.concatenate([data[-1:], data]))
+                sk.update(t[1:])        # 8 bytes past a 16-byte boundary
+            else:
+                sk.update(to_dev(data))
+            torch.cuda.synchronize()
+            assert np.array_equal(sk.download(), want), name
+
+
+def test_reset_then_two_updates_in_one_window():
+    """The first update writes the tiles from zeros; the second reads them."""
+    rng = np.random.default_rng(72)
+    a, b = rand_pairs(rng, 500_000, 20_000), rand_pairs(rng, 400_000, 20_000)
+    ref = oracle.build_sketch(P, np.concatenate([a, b]))
+    with dirty_sketch(rng, 2) as sk:
+        sk.update(to_dev(a))
+        sk.update(to_dev(b))
+        torch.cuda.synchronize()
+        assert np.array_equal(sk.download(), ref)
+
+
+def test_reset_then_restore_merge_download_upload():
+    rng = np.random.default_rng(73)
+    pairs = rand_pairs(rng, 300_000, 10_000)
+    ref = oracle.build_sketch(P, pairs)
+    zeros = np.zeros_like(ref)
+    theta = 0.7 * P.g
+    say("reset then restore of an empty window")
+    with dirty_sketch(rng) as sk:
+        recs, info = sk.restore(theta)
+        ip, sz, c, _ = oracle.restore(P, zeros, theta)
+        assert len(recs) == len(ip) == 0
+        assert not sk.download().any()
+    say("reset then download")
+    with dirty_sketch(rng) as sk:
+        assert not sk.download().any()
+    say("merge into a reset sketch, and merge of a reset sketch")
+    with dirty_sketch(rng) as dst, ddhf.Sketch(P.g, P.k, P.r, P.alpha, P.seed, device=0) as src:
+        src.update(to_dev(pairs))
+        dst.merge(src)
+        torch.cuda.synchronize()
+        assert np.array_equal(dst.download(), ref)
+        with dirty_sketch(rng) as empty:
+            src.merge(empty)
+            torch.cuda.synchronize()
+            assert np.array_equal(src.download(), ref)
+    say("upload over a reset sketch")
+    with dirty_sketch(rng) as sk:
+        sk.upload(ref)
+        assert np.array_equal(sk.download(), ref)
+        sk.update(to_dev(pairs[:1000]))       # same pairs: no change
+        torch.cuda.synchronize()
+        assert np.array_equal(sk.download(), ref)
+
+
+def test_plan_without_reset_after_a_reset():
+    """A plan that does not reset works on the sketch as it is: after
+    sketch_reset that is all zero."""
+    rng = np.random.default_rng(74)
+    pairs = rand_pairs(rng, 700_000, 30_000)
+    ref = oracle.build_sketch(P, pairs)
+    with dirty_sketch(rng, 2) as sk:
+        t = to_dev(pairs)
+        with ddhf.Plan([(sk, t, 0.7 * P.g)], reset=False, restore=False) as plan:
+            plan.run()
+            torch.cuda.synchronize()
+            assert np.array_equal(sk.download(), ref)
+            sk.reset()
+            plan.run()
+            torch.cuda.synchronize()
+            assert np.array_equal(sk.download(), ref)

@@ -403,6 +403,13 @@ struct sketch {
   // work that reads the sketch or sets bits in place writes the zeros first
   // (materialize).
   bool fresh = false;
+  // Zeros per LE as the binned update leaves them (when lez_kept(g)). Valid
+  // after a binned update of a fresh window from its first pair (which
+  // writes every tile) and through later binned updates (which rewrite the
+  // counts of every tile they write); anything else that sets bits makes it
+  // stale, and the restore then counts zeros in the sketch.
+  uint32_t *lez = nullptr;
+  bool lez_valid = false;
   // update
   int update_grid = 0;          // blocks of the direct kernel
   int update_check = 1;
@@ -441,6 +448,7 @@ void free_sketch(sketch *s) {
   dev_free(s->n_items);
   dev_free(s->item_tile);
   dev_free(s->gcur);
+  dev_free(s->lez);
   dev_free(s->st);
   dev_free(s->hotmask);
   dev_free(s->he);
@@ -467,6 +475,7 @@ int grow_sorted(sketch *s, size_t need) {
 RestoreBufs restore_bufs(const sketch *s) {
   const DevCtx *c = s->ctx;
   RestoreBufs B{};
+  B.lez = s->lez_valid ? s->lez : nullptr;
   B.st = s->st;
   B.hotmask = s->hotmask;
   B.he = s->he;
@@ -552,6 +561,7 @@ int materialize(sketch *s, hipStream_t st) {
   if (!s->fresh) return SKETCH_OK;
   HIP_OK(launch_fill_u32(s->d_sketch, s->words, 0u, s->grid * 4, st));
   s->fresh = false;
+  s->lez_valid = false;
   return SKETCH_OK;
 }
 
@@ -642,6 +652,7 @@ UpdJob job_base(const sketch *s) {
   J.xslot = s->xslot;
   J.item_tile = s->item_tile;
   J.gcur = s->gcur;
+  J.lez = s->lez;
   J.n_items = s->n_items;
   J.check = (uint32_t)s->update_check;
   return J;
@@ -847,13 +858,16 @@ int update_jobs(const sketch_update_job_t *jobs, size_t n_jobs, hipStream_t st) 
   std::vector<char> fresh(n_jobs, 0);
   for (size_t j = 0; j < n_jobs; j++) {
     sketch *s = jobs[j].sketch;
-    if (!s->fresh || jobs[j].n_pairs == 0) continue;
-    if (binned_from_start(s, jobs[j].d_pairs, jobs[j].n_pairs)) {
+    if (jobs[j].n_pairs == 0) continue;
+    const bool binned = binned_from_start(s, jobs[j].d_pairs, jobs[j].n_pairs);
+    if (s->fresh && binned) {
       fresh[j] = 1;
       s->fresh = false;
+      s->lez_valid = s->lez != nullptr;     // every tile is written
     } else {
       rc = materialize(s, st);
       if (rc) return rc;
+      if (!binned) s->lez_valid = false;    // the direct kernel sets bits
     }
   }
   return schedule_update(
@@ -964,6 +978,9 @@ int plan_alloc_sorted(PlanJob &j, size_t cap) {
 
 RestoreBufs plan_restore_bufs(const sketch_plan *P, const PlanJob &j) {
   RestoreBufs B = restore_bufs(j.s);      // the sketch's rows, the shared pool
+  // the zero counts are known valid at capture only when each run starts
+  // the window and its update writes every tile
+  B.lez = (P->flags & SKETCH_PLAN_RESET) && j.fresh ? j.s->lez : nullptr;
   B.st = j.st;
   B.spl_sorted = j.sorted;
   B.spl_cap = std::min(P->ctx->spl_cap, j.sorted_cap);
@@ -1100,6 +1117,7 @@ int sketch_create(const sketch_params_t *params, sketch_t **out) {
     if (!rc) rc = dev_alloc(&s->xslot, s->nbins + 1, "tile scratch slots");
     if (!rc) rc = dev_alloc(&s->item_tile, ITEM_TILE_SLOTS(s->nbins), "item tiles");
     if (!rc) rc = dev_alloc(&s->gcur, (size_t)BIN_GROUPS * s->nbins, "tile stream cursors");
+    if (!rc && lez_kept(params->g)) rc = dev_alloc(&s->lez, n_le, "LE zero counts");
     if (!rc) rc = dev_alloc(&s->n_items, 1, "tile item count");
   }
   if (!rc) rc = pinned_alloc(&s->h_state, &s->d_h_state, 1, "state");
@@ -1143,6 +1161,7 @@ int sketch_reset(sketch_t *s, void *hip_stream) {
   if (!s) return fail(SKETCH_E_INVAL, "sketch_reset: NULL handle");
   (void)hip_stream;
   s->fresh = true;                  // the zeros are written when needed
+  s->lez_valid = false;
   return SKETCH_OK;
 }
 
@@ -1160,6 +1179,7 @@ int sketch_merge(sketch_t *dst, const sketch_t *src, void *hip_stream) {
   if (rc) return rc;
   HIP_OK(launch_or_u32(dst->d_sketch, src->d_sketch, dst->words, dst->grid * 4,
                        (hipStream_t)hip_stream));
+  dst->lez_valid = false;
   return SKETCH_OK;
 }
 
@@ -1349,6 +1369,7 @@ int sketch_upload(sketch_t *s, const uint32_t *host_words, size_t n_words, void 
   HIP_OK(hipMemcpyAsync(s->d_sketch, host_words, n_words * 4, hipMemcpyHostToDevice, st));
   HIP_OK(hipStreamSynchronize(st));
   s->fresh = false;
+  s->lez_valid = false;
   return SKETCH_OK;
 }
 
@@ -1494,9 +1515,11 @@ int sketch_plan_run(sketch_plan_t *P, void *hip_stream) {
   for (PlanJob &j : P->jobs) {
     if (P->flags & SKETCH_PLAN_RESET) {
       j.s->fresh = false;
+      j.s->lez_valid = j.fresh && j.s->lez;
     } else {
       int rc = materialize(j.s, st);
       if (rc) return rc;
+      j.s->lez_valid = false;
     }
   }
   int rc = pool_enter(c, st);

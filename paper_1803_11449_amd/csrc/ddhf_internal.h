@@ -55,6 +55,8 @@ struct DevState {
 
 // Restore work buffers (device pointers) and capacities.
 struct RestoreBufs {
+  const uint32_t *lez;    // zeros per LE as the update left them, or null
+                          // (the hot scan counts them in the sketch)
   DevState *st;
   uint32_t *hotmask;      // r * 2^k bits
   uint32_t *he;           // r * 2^k entries, row i at i*2^k, ascending
@@ -113,6 +115,11 @@ constexpr uint32_t APPLY_ITEM = 1u << 17;            //   are cut into items of 
 
 constexpr uint32_t BIN_BLOCKS_MAX = 1024;
 
+// The binned update keeps each LE's zero count (for the restore's hot scan)
+// when an LE spans 4 to 256 words: a whole number of 16-byte vectors held by
+// at most one wave's lanes.
+constexpr bool lez_kept(uint32_t g) { return g >= 128 && g <= 8192; }
+
 // Scatter blocks are put in BIN_GROUPS groups by block index mod BIN_GROUPS:
 // gfx950 hands workgroups of a dispatch to its 8 XCDs in turn, so a group is
 // the blocks that share one XCD and its L2. The blocks of a group write
@@ -140,6 +147,8 @@ struct UpdJob {
   uint32_t *hist, *totals, *base, *item_start, *xslot, *n_items;
   uint32_t *item_tile;   // tile of each apply item (ITEM_TILE_SLOTS(nbins) entries)
   uint32_t *gcur;        // [BIN_GROUPS][nbins]: next slot of each group's stream per tile
+  uint32_t *lez;         // zeros of every LE of each tile the update writes
+                         // (one word per LE), or null
   uint32_t *codes, *scratch;
   uint32_t item0;        // first global apply item (written on the device)
   uint32_t check;        // direct kernel: test the bit before the atomicOr

@@ -175,6 +175,45 @@ __global__ __launch_bounds__(256) void k_hot_scan(Geom G, const uint32_t *__rest
     atomicAdd(&st->zr[threadIdx.x], zr_sh[threadIdx.x]);
 }
 
+// The same from the zero counts the binned update kept (one word per LE, 4
+// bytes instead of g/8 per LE read). A wave takes 64 consecutive LEs at a
+// time, so one ballot is two whole words of the hot bitmap.
+__global__ __launch_bounds__(256) void k_hot_scan_lez(Geom G, const uint32_t *__restrict__ lez,
+                                                      uint32_t zhot,
+                                                      uint32_t *__restrict__ hotmask,
+                                                      DevState *__restrict__ st) {
+  __shared__ unsigned long long zr_sh[8];
+  if (threadIdx.x < 8) zr_sh[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t n_le = (uint64_t)G.r << G.k;           // a multiple of 32
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint32_t cur_row = 0;
+  unsigned long long acc = 0;
+  for (uint64_t e0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane); e0 < n_le;
+       e0 += stride) {                                   // uniform over the wave
+    const uint64_t e = e0 + lane;
+    const bool in = e < n_le;
+    const uint32_t z0 = in ? lez[e] : 0;
+    const unsigned long long hot = __ballot(in && z0 <= zhot);
+    if (lane == 0) hotmask[e0 >> 5] = (uint32_t)hot;
+    if (lane == 32 && in) hotmask[e >> 5] = (uint32_t)(hot >> 32);
+    if (in) {
+      const uint32_t row = (uint32_t)(e >> G.k);
+      if (row != cur_row) {
+        if (acc) atomicAdd(&zr_sh[cur_row], acc);
+        acc = 0;
+        cur_row = row;
+      }
+      acc += z0;
+    }
+  }
+  if (acc) atomicAdd(&zr_sh[cur_row], acc);
+  __syncthreads();
+  if (threadIdx.x < G.r && zr_sh[threadIdx.x])
+    atomicAdd(&st->zr[threadIdx.x], zr_sh[threadIdx.x]);
+}
+
 // ---------------------------------------------------------- 2: HE compaction
 
 __device__ __forceinline__ void compact_row(const Geom &G, uint32_t row,
@@ -755,7 +794,11 @@ static hipError_t launch_wpl(const Geom &G, const uint32_t *sketch, const Restor
   k_restore_init<<<(int)((n_le / 32 + 255) / 256 < 256 ? (n_le / 32 + 255) / 256 : 256), 256, 0,
                    st>>>(B.st, B.rank, SMALL_SORT, B.hotmask, n_le / 32);
   // 1: hot scan
-  {
+  if (B.lez) {
+    const uint64_t blocks = (n_le + 255) / 256;
+    k_hot_scan_lez<<<(int)(blocks < (uint64_t)grid ? blocks : (uint64_t)grid), 256, 0, st>>>(
+        G, B.lez, zhot, B.hotmask, B.st);
+  } else {
     using S = LeShape<WPL>;
     const uint64_t pass = (uint64_t)(256 / S::LPL) * HS_UNROLL;
     const uint64_t passes = (n_le + pass - 1) / pass;

@@ -486,6 +486,17 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
 
 constexpr int APPLY_UNROLL = 4;
 
+// Zero count of the LE that holds sketch words [w, w+4) (v), when the LE's
+// W = wpl words are spread over W/4 consecutive lanes, each with one 16-byte
+// vector (4 <= W <= 256): the lanes' one-counts are summed across the group
+// and its first lane writes g - ones. Every lane of a group must call it.
+__device__ __forceinline__ void le_zeros(const Geom &G, GMEM uint32_t *lez, size_t w, uint4 v) {
+  const uint32_t L = G.wpl / 4;                         // lanes per LE, 1..64
+  uint32_t ones = __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w);
+  for (uint32_t m = L >> 1; m >= 1; m >>= 1) ones += __shfl_xor(ones, (int)m, 64);
+  if ((w / 4) % L == 0) lez[w / G.wpl] = G.g - ones;
+}
+
 // The three codes of a word (low half lo, high half hi) into the LDS tile.
 __device__ __forceinline__ void or_word(uint32_t *tile, uint2 w) {
   const uint32_t a = w.x & CODE_MASK;
@@ -563,6 +574,9 @@ __global__ __launch_bounds__(1024) void k_bin_apply(const UpdJob *__restrict__ j
       or_word(tile, make_uint2(x.z, x.w));
     }
     __syncthreads();
+    // a tile with one item is final here: its LEs' zero counts go out too
+    // (a cut tile's are counted by the merge)
+    GMEM uint32_t *lez = whole && J.lez ? gmem(J.lez) : nullptr;
     if (tw == BIN_TILE_WORDS) {
       GMEM uint4 *d4 = reinterpret_cast<GMEM uint4 *>(dstp);
       uint4 v[TV4];
@@ -570,8 +584,21 @@ __global__ __launch_bounds__(1024) void k_bin_apply(const UpdJob *__restrict__ j
       for (uint32_t u = 0; u < TV4; u++) v[u] = tile4[threadIdx.x + u * 1024];
 #pragma unroll
       for (uint32_t u = 0; u < TV4; u++) st4(d4 + threadIdx.x + u * 1024, v[u]);
+      if (lez) {
+#pragma unroll
+        for (uint32_t u = 0; u < TV4; u++)
+          le_zeros(J.G, lez, w0 + 4 * (size_t)(threadIdx.x + u * 1024), v[u]);
+      }
     } else {
       for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) dstp[w] = tile[w];
+      if (lez) {                                         // the sketch's last, partial tile
+        const uint32_t W = J.G.wpl;
+        for (uint32_t e = threadIdx.x; e < tw / W; e += blockDim.x) {
+          uint32_t ones = 0;
+          for (uint32_t w = 0; w < W; w++) ones += __popc(tile[e * W + w]);
+          lez[(w0 + (size_t)e * W) / W] = J.G.g - ones;
+        }
+      }
     }
     __syncthreads();
   }
@@ -593,6 +620,9 @@ __global__ __launch_bounds__(256) void k_bin_merge(const UpdJob *__restrict__ jo
   const uint32_t s_hi = s_lo + MERGE_SLICE < tw ? s_lo + MERGE_SLICE : tw;
   const GMEM uint32_t *s0 = gmem(J.scratch) + (size_t)gmem(J.xslot)[t] * BIN_TILE_WORDS;
   GMEM uint32_t *sk = gmem(J.sk) + w0;
+  // a slice is a whole number of LEs when the zero counts are kept (an LE
+  // of at most 256 words), so a lane group never straddles its end
+  GMEM uint32_t *lez = J.lez ? gmem(J.lez) : nullptr;
   for (uint32_t w = s_lo + threadIdx.x * 4; w < s_hi; w += blockDim.x * 4) {
     if (w + 4 <= s_hi) {
       uint4 v = ld4(reinterpret_cast<const GMEM uint4 *>(sk + w));
@@ -602,6 +632,7 @@ __global__ __launch_bounds__(256) void k_bin_merge(const UpdJob *__restrict__ jo
         v.x |= x.x; v.y |= x.y; v.z |= x.z; v.w |= x.w;
       }
       st4(reinterpret_cast<GMEM uint4 *>(sk + w), v);
+      if (lez) le_zeros(J.G, lez, w0 + w, v);
     } else {
       for (uint32_t ww = w; ww < s_hi; ww++) {
         uint32_t v = sk[ww];

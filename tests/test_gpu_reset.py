@@ -136,3 +136,101 @@ def test_plan_without_reset_after_a_reset():
             plan.run()
             torch.cuda.synchronize()
             assert np.array_equal(sk.download(), ref)
+
+
+# ---------------------------------------------------------------- restore
+
+def assert_restore_equal(sk, p, pairs, theta):
+    """The restore of sk equals the oracle's restore of the window's sketch:
+    records (addresses, SZ bit for bit, estimates to 1e-6), psi, D and the
+    hot-LE counts."""
+    recs, info = sk.restore(theta)
+    ip, sz, c, sc = oracle.restore(p, oracle.build_sketch(p, pairs), theta)
+    for v in (info["trep"], info["zmin"]):
+        assert abs(v - round(v)) > 1e-9, f"threshold {v} too close to an integer"
+    assert np.array_equal(recs["ip"], ip), (len(recs), len(ip))
+    assert np.array_equal(recs["sz"], sz)
+    fin = ~np.isinf(c)
+    assert np.array_equal(np.isinf(recs["est"]), ~fin)
+    np.testing.assert_allclose(recs["est"][fin], c[fin], rtol=1e-6, atol=0)
+    assert info["psi"] == pytest.approx(sc["psi"], rel=1e-12)
+    assert info["d"] == pytest.approx(sc["D"], rel=1e-12)
+    return recs, info
+
+
+def window(rng, n, n_src, hosts, card):
+    planted = [np.stack([np.full(card, h, dtype=np.uint32),
+                         rng.choice(2**32, size=card, replace=False).astype(np.uint32)], 1)
+               for h in hosts]
+    w = np.concatenate([rand_pairs(rng, n, n_src)] + planted)
+    return w[rng.permutation(len(w))]
+
+
+# g = 128 and 8192 are the ends of the range whose zero counts the update
+# keeps (an LE over 1 and over 64 lanes); g = 128 at k = 12, r = 5 also
+# ends in a partial tile. g = 64 and 16384 restore from the sketch.
+RESTORE_PARAMS = [oracle.Params(1024, 18, 5, 5), oracle.Params(128, 12, 5, 7),
+                  oracle.Params(8192, 12, 4, 10), oracle.Params(256, 14, 5, 6),
+                  oracle.Params(64, 14, 5, 6), oracle.Params(16384, 12, 5, 7)]
+
+
+@pytest.mark.parametrize("p", RESTORE_PARAMS, ids=lambda p: f"g{p.g}k{p.k}r{p.r}a{p.alpha}")
+def test_restore_after_reset_and_binned_updates(p):
+    rng = np.random.default_rng(p.g + 7 * p.k)
+    theta = 0.7 * p.g
+    card = int(2.5 * p.g)
+    hosts = rng.choice(2**32, size=4, replace=False).astype(np.uint32)
+    # about 2^k * g / 8 pairs at most, so that the sketch stays far from
+    # saturation and the oracle's join stays small
+    n = min(300_000, (p.g << p.k) // 8)
+    a = window(rng, n, max(1000, n // 15), hosts[:2], card)
+    b = window(rng, 2 * n // 3, max(1000, n // 15), hosts[2:], card)
+    say(f"g={p.g}: reset, binned update, restore")
+    with ddhf.Sketch(p.g, p.k, p.r, p.alpha, p.seed, device=0) as sk:
+        sk.set_option(ddhf.SKETCH_OPT_UPDATE_PATH, 2)
+        sk.update(to_dev(window(rng, 100_000, 5000, [], 0)))
+        sk.reset()
+        sk.update(to_dev(a))
+        recs, _ = assert_restore_equal(sk, p, a, theta)
+        assert len(recs) >= 2
+        say(f"g={p.g}: a second binned update in the window, restore")
+        sk.update(to_dev(b))
+        ab = np.concatenate([a, b])
+        assert_restore_equal(sk, p, ab, theta)
+        say(f"g={p.g}: a direct update in the window, restore")
+        sk.set_option(ddhf.SKETCH_OPT_UPDATE_PATH, 1)
+        c = rand_pairs(rng, 5000, 500)
+        sk.update(to_dev(c))
+        assert_restore_equal(sk, p, np.concatenate([ab, c]), theta)
+
+
+def test_restore_after_reset_with_split_tiles():
+    """A tile with more words than one apply item is finished by the merge,
+    which also counts its LEs' zeros."""
+    rng = np.random.default_rng(75)
+    hosts = rng.choice(2**32, size=3, replace=False).astype(np.uint32)
+    heavy = np.stack([np.full(1_200_000, hosts[0], dtype=np.uint32),
+                      rng.integers(0, 2**32, size=1_200_000, dtype=np.uint64).astype(np.uint32)],
+                     1)
+    w = np.concatenate([window(rng, 400_000, 30_000, hosts[1:], 3000), heavy])
+    w = w[rng.permutation(len(w))]
+    with dirty_sketch(rng, 2) as sk:
+        sk.update(to_dev(w))
+        recs, _ = assert_restore_equal(sk, P, w, 0.7 * P.g)
+        assert hosts[0] in set(recs["ip"].tolist())
+
+
+def test_plan_reset_restore_uses_the_update_counts():
+    """A RESET + RESTORE plan of a binned window (restore from the counts the
+    update kept), run twice, equals the oracle each time."""
+    rng = np.random.default_rng(76)
+    hosts = rng.choice(2**32, size=3, replace=False).astype(np.uint32)
+    w = window(rng, 500_000, 30_000, hosts, 3000)
+    ip, sz, c, _ = oracle.restore(P, oracle.build_sketch(P, w), 0.7 * P.g)
+    with dirty_sketch(rng, 2) as sk:
+        t = to_dev(w)
+        with ddhf.Plan([(sk, t, 0.7 * P.g)]) as plan:
+            for _ in range(2):
+                plan.run()
+                (recs, info), = plan.results()
+                assert np.array_equal(recs["ip"], ip) and np.array_equal(recs["sz"], sz)

@@ -176,39 +176,64 @@ __global__ __launch_bounds__(256) void k_hot_scan(Geom G, const uint32_t *__rest
 }
 
 // The same from the zero counts the binned update kept (one word per LE, 4
-// bytes instead of g/8 per LE read). A wave takes 64 consecutive LEs at a
-// time, so one ballot is two whole words of the hot bitmap.
-__global__ __launch_bounds__(256) void k_hot_scan_lez(Geom G, const uint32_t *__restrict__ lez,
+// bytes instead of g/8 per LE read). A lane takes 4 consecutive LEs with
+// one 16-byte load; 8 lanes make one word of the hot bitmap (their nibbles
+// ORed across the group), so every word is written once, with no atomics.
+// Rows start at multiples of 2^k >= 32 LEs, so a lane's 4 LEs share a row.
+constexpr int HS_LEZ_UNROLL = 4;
+
+__global__ __launch_bounds__(256) void k_hot_scan_lez(Geom G, const uint4 *__restrict__ lez4,
                                                       uint32_t zhot,
                                                       uint32_t *__restrict__ hotmask,
                                                       DevState *__restrict__ st) {
   __shared__ unsigned long long zr_sh[8];
   if (threadIdx.x < 8) zr_sh[threadIdx.x] = 0;
   __syncthreads();
-  const uint64_t n_le = (uint64_t)G.r << G.k;           // a multiple of 32
+  const uint64_t n_q = ((uint64_t)G.r << G.k) / 4;      // n_le is a multiple of 32
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   uint32_t cur_row = 0;
   unsigned long long acc = 0;
-  for (uint64_t e0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane); e0 < n_le;
-       e0 += stride) {                                   // uniform over the wave
-    const uint64_t e = e0 + lane;
-    const bool in = e < n_le;
-    const uint32_t z0 = in ? lez[e] : 0;
-    const unsigned long long hot = __ballot(in && z0 <= zhot);
-    if (lane == 0) hotmask[e0 >> 5] = (uint32_t)hot;
-    if (lane == 32 && in) hotmask[e >> 5] = (uint32_t)(hot >> 32);
-    if (in) {
-      const uint32_t row = (uint32_t)(e >> G.k);
+  // HS_LEZ_UNROLL loads per lane are issued before any is used; n_q is a
+  // multiple of 8, so a group of 8 lanes is whole or absent
+  for (uint64_t q0 = (uint64_t)blockIdx.x * blockDim.x * HS_LEZ_UNROLL + threadIdx.x; q0 < n_q;
+       q0 += stride * HS_LEZ_UNROLL) {
+    uint4 z[HS_LEZ_UNROLL];
+#pragma unroll
+    for (int u = 0; u < HS_LEZ_UNROLL; u++) {
+      const uint64_t q = q0 + (uint64_t)u * blockDim.x;
+      z[u] = q < n_q ? lez4[q] : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < HS_LEZ_UNROLL; u++) {
+      const uint64_t q = q0 + (uint64_t)u * blockDim.x;
+      if (q >= n_q) break;
+      uint32_t nib = (z[u].x <= zhot ? 1u : 0u) | (z[u].y <= zhot ? 2u : 0u) |
+                     (z[u].z <= zhot ? 4u : 0u) | (z[u].w <= zhot ? 8u : 0u);
+      nib <<= 4 * (lane & 7);
+      nib |= __shfl_xor(nib, 1, 64);
+      nib |= __shfl_xor(nib, 2, 64);
+      nib |= __shfl_xor(nib, 4, 64);
+      if ((lane & 7) == 0) hotmask[q >> 3] = nib;
+      const uint32_t row = (uint32_t)((q * 4) >> G.k);
       if (row != cur_row) {
         if (acc) atomicAdd(&zr_sh[cur_row], acc);
         acc = 0;
         cur_row = row;
       }
-      acc += z0;
+      acc += (unsigned long long)z[u].x + z[u].y + z[u].z + z[u].w;
     }
   }
-  if (acc) atomicAdd(&zr_sh[cur_row], acc);
+  // a lane's sum is below 2^22 (at most 2 passes of HS_LEZ_UNROLL x 4 LEs of
+  // <= 2^16 zeros), a wave's below 2^28: a wave whose lanes share a row
+  // folds its sum in registers and adds it once
+  const uint32_t row0 = __builtin_amdgcn_readfirstlane(cur_row);
+  if (__all(cur_row == row0)) {
+    const uint32_t tot = wave_scan_incl((uint32_t)acc);
+    if (lane == 63 && tot) atomicAdd(&zr_sh[row0], (unsigned long long)tot);
+  } else if (acc) {
+    atomicAdd(&zr_sh[cur_row], acc);
+  }
   __syncthreads();
   if (threadIdx.x < G.r && zr_sh[threadIdx.x])
     atomicAdd(&st->zr[threadIdx.x], zr_sh[threadIdx.x]);
@@ -795,9 +820,11 @@ static hipError_t launch_wpl(const Geom &G, const uint32_t *sketch, const Restor
                    st>>>(B.st, B.rank, SMALL_SORT, B.hotmask, n_le / 32);
   // 1: hot scan
   if (B.lez) {
-    const uint64_t blocks = (n_le + 255) / 256;
-    k_hot_scan_lez<<<(int)(blocks < (uint64_t)grid ? blocks : (uint64_t)grid), 256, 0, st>>>(
-        G, B.lez, zhot, B.hotmask, B.st);
+    // HS_LEZ_UNROLL 16-byte loads per lane, the whole array in one pass
+    // (few blocks: each adds its row sums to ZR with global atomics)
+    const uint64_t blocks = (n_le / 4 + 256 * HS_LEZ_UNROLL - 1) / (256 * HS_LEZ_UNROLL);
+    k_hot_scan_lez<<<(int)(blocks < 65535 ? blocks : 65535), 256, 0, st>>>(
+        G, reinterpret_cast<const uint4 *>(B.lez), zhot, B.hotmask, B.st);
   } else {
     using S = LeShape<WPL>;
     const uint64_t pass = (uint64_t)(256 / S::LPL) * HS_UNROLL;

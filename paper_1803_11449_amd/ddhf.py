@@ -193,7 +193,7 @@ def sketch_reset(h: int, stream: int = 0) -> None:
 def sketch_restore(h: int, theta: float, cap: int, stream: int = 0):
     """Returns (records[:n], info). Raises SketchError (with n_needed on
     CAPACITY)."""
-    out = np.zeros(max(cap, 1), dtype=SP_DTYPE)
+    out = np.empty(max(cap, 1), dtype=SP_DTYPE)       # the first n are written
     n = c_sz(0)
     info = sketch_info_t()
     rc = lib().sketch_restore(h, float(theta), out.ctypes.data, cap,
@@ -212,7 +212,7 @@ def sketch_restore_batch(items, stream: int = 0):
     arr = (sketch_restore_job_t * max(1, n))()
     outs, infos = [], []
     for i, (h, theta, cap) in enumerate(items):
-        out = np.zeros(max(cap, 1), dtype=SP_DTYPE)
+        out = np.empty(max(cap, 1), dtype=SP_DTYPE)       # the first n are written
         info = sketch_info_t()
         outs.append(out)
         infos.append(info)
@@ -251,7 +251,7 @@ def sketch_plan_results(plan: int, items, stream: int = 0):
     arr = (sketch_restore_job_t * max(1, n))()
     outs, infos = [], []
     for i, (h, cap) in enumerate(items):
-        out = np.zeros(max(cap, 1), dtype=SP_DTYPE)
+        out = np.empty(max(cap, 1), dtype=SP_DTYPE)       # the first n are written
         info = sketch_info_t()
         outs.append(out)
         infos.append(info)

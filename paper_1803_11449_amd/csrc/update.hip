@@ -606,7 +606,8 @@ __global__ __launch_bounds__(1024) void k_bin_apply(const UpdJob *__restrict__ j
 
 // OR the scratch tiles of every cut tile into the sketch: block (t, y)
 // takes the y-th MERGE_SLICE-word slice of global tile t.
-constexpr uint32_t MERGE_SLICE = 4096;
+constexpr uint32_t MERGE_SLICE = 2048;
+constexpr uint32_t MERGE_BATCH = 8;
 
 __global__ __launch_bounds__(256) void k_bin_merge(const UpdJob *__restrict__ jobs, uint32_t nj) {
   const UpdJob &J = jobs[job_of_tile(jobs, nj, blockIdx.x)];
@@ -626,10 +627,19 @@ __global__ __launch_bounds__(256) void k_bin_merge(const UpdJob *__restrict__ jo
   for (uint32_t w = s_lo + threadIdx.x * 4; w < s_hi; w += blockDim.x * 4) {
     if (w + 4 <= s_hi) {
       uint4 v = ld4(reinterpret_cast<const GMEM uint4 *>(sk + w));
-      for (uint32_t k = 1; k < n; k++) {
-        const uint4 x =
-            ld4(reinterpret_cast<const GMEM uint4 *>(s0 + (size_t)(k - 1) * BIN_TILE_WORDS + w));
-        v.x |= x.x; v.y |= x.y; v.z |= x.z; v.w |= x.w;
+      // MERGE_BATCH scratch tiles' loads in flight at once; past the last
+      // one they re-read it, which ORs in bits already there
+      for (uint32_t k0 = 1; k0 < n; k0 += MERGE_BATCH) {
+        uint4 x[MERGE_BATCH];
+#pragma unroll
+        for (uint32_t u = 0; u < MERGE_BATCH; u++) {
+          const uint32_t k = k0 + u < n ? k0 + u : n - 1;
+          x[u] = ld4(reinterpret_cast<const GMEM uint4 *>(s0 + (size_t)(k - 1) * BIN_TILE_WORDS + w));
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < MERGE_BATCH; u++) {
+          v.x |= x[u].x; v.y |= x[u].y; v.z |= x[u].z; v.w |= x[u].w;
+        }
       }
       st4(reinterpret_cast<GMEM uint4 *>(sk + w), v);
       if (lez) le_zeros(J.G, lez, w0 + w, v);

@@ -20,11 +20,15 @@
 // binned   The bit sets are moved into LDS. Every (pair, row) gives the bit
 //          index B = ((row * 2^k + cell) * g) + bit of the sketch seen as
 //          one bit string; tile = B >> 20 names the 128 KiB slice it falls
-//          in and code = B mod 2^20 the bit inside it.
-//            count    each block counts its chunk's codes per tile (LDS)
+//          in and code = B mod 2^20 the bit inside it. Codes are stored
+//          three to a 64-bit word; every run a block writes for one tile in
+//          one batch is padded to whole words with copies of a code of the
+//          run (setting a bit twice sets it once).
+//            count    each block walks its chunk in the scatter's batches
+//                     and adds, per tile, the words each batch will write
 //            scan     per tile, the blocks' counts become the starts of
 //                     the block groups' parts of the tile's run; over tiles,
-//                     the totals become run starts; a tile with many codes
+//                     the totals become run starts; a tile with many words
 //                     is cut into several apply items
 //            scatter  each block sorts a batch of pairs' codes by tile in
 //                     LDS, claims room in its group's part of each tile's
@@ -35,8 +39,10 @@
 //                     one per tile and block, and lines leave it whole
 //            apply    one workgroup per item: the tile in LDS (up to 160 KiB
 //                     per workgroup on gfx950), ds_or per code. The first
-//                     item of a tile reads and writes the tile itself; the
-//                     other items of a cut tile write scratch tiles instead
+//                     item of a tile reads and writes the tile itself (or,
+//                     after a reset, builds it from zeros); the other items
+//                     of a cut tile write scratch tiles instead. A finished
+//                     tile's LE zero counts are written with it
 //            merge    each cut tile ORs its scratch tiles into the sketch
 //          Only the pairs, the code runs and whole tiles move through HBM.
 #include <type_traits>

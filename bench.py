@@ -10,9 +10,11 @@ generated on the device and are resident in HBM before timing starts.
 
 Prints one JSON line. value = pairs per second over the whole step (reset +
 update + restore, wall clock, inputs in HBM), in Mpps. Also reported: the
-update kernel's own rate, the restore latency (window close to super point
-list on the host) p50/p99 over the timed steps, the roofline of the
-dominant kernel and the CPU oracle's rate on the same window.
+update's own rate (HIP events around it in the timed steps), the restore
+latency (window close to super point list on the host) p50/p99 over
+separate runs after the timed steps, each started on an idle device, the
+roofline of the dominant kernel and the CPU oracle's rate on the same
+window.
 """
 from __future__ import annotations
 

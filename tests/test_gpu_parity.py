@@ -149,6 +149,35 @@ def test_binned_rounds_and_split_tiles():
             assert np.array_equal(sk.download(), ref), rnd
 
 
+@pytest.mark.parametrize("p", [oracle.Params(1024, 19, 5, 5), oracle.Params(2048, 18, 7, 3)],
+                         ids=lambda p: f"g{p.g}k{p.k}r{p.r}a{p.alpha}")
+def test_binned_sketch_over_2048_tiles(p):
+    """Sketches of 2049..4095 tiles (320 and 448 MiB) take the scatter's
+    4096-tile variant: every pairs-per-thread setting it has, a heavy source
+    whose tiles are cut into several apply items, and (r = 5) the restore."""
+    say(f"binned over 2048 tiles: g={p.g} k={p.k} r={p.r} alpha={p.alpha}")
+    rng = np.random.default_rng(p.k * 11 + p.r)
+    hosts = rng.choice(2**32, size=6, replace=False).astype(np.uint32)
+    heavy = np.stack([np.full(900_000, hosts[0], dtype=np.uint32),
+                      rng.integers(0, 2**32, size=900_000, dtype=np.uint64).astype(np.uint32)], 1)
+    pairs = np.concatenate([rand_pairs(rng, 700_000, 40_000), heavy] + planted(rng, hosts[1:], 4000))
+    pairs = pairs[rng.permutation(len(pairs))]
+    ref = oracle.build_sketch(p, pairs)
+    for ppt in (4, 2):
+        with make_sketch(p, 2) as sk:
+            sk.set_option(ddhf.SKETCH_OPT_SCATTER_PPT, ppt)
+            sk.update(to_dev(pairs))
+            torch.cuda.synchronize()
+            assert np.array_equal(sk.download(), ref), ppt
+            if p.r == 5 and ppt == 4:
+                theta = 0.7 * p.g
+                ip, sz, c, _ = oracle.restore(p, ref, theta)
+                recs, info = sk.restore(theta)
+                assert_not_boundary(info)
+                assert_spl_equal(recs, ip, sz, c)
+                assert set(hosts.tolist()) <= set(recs["ip"].tolist())
+
+
 def test_update_batch_mixed_sketches():
     """One batched update over sketches of different parameters and sizes
     (direct and binned jobs, several r) equals the oracle for each."""

@@ -274,7 +274,11 @@ enum {
   SKETCH_OPT_SCATTER_PPT = 6,       /* binned: pairs per thread in one LDS
                                        sorting batch: 2, 4 or 6 (default);
                                        capped by LDS at 4 for r in 6..7 and
-                                       at 2 for r = 8 */
+                                       at 2 for r = 8. Sketches of more than
+                                       2048 tiles (of 128 KiB) take 5 for
+                                       r <= 5 up to 3072 tiles and 4 above
+                                       (4 and 6 both ask for that), and 2
+                                       for r >= 6 */
   SKETCH_OPT_BINNED_BLOCKS = 7,     /* binned: blocks of the count and
                                        scatter passes, 1..1024 (default: one
                                        per compute unit) */

@@ -165,9 +165,9 @@ __device__ __forceinline__ void count_pair(const Geom &G, uint2 p, uint32_t *h) 
 // pairs per thread of 1024, from the start of the block's chunk) and adds
 // ceil(c / 3) for a batch with c codes in the tile.
 //
-// A full batch's pairs are read as uint4 (two pairs per lane per load); a
-// job's pairs start 16-byte aligned and its chunks and batches are even,
-// so these loads are aligned. The next batch's loads are issued before
+// A full batch's pairs are read as uint4 (two pairs per lane per load)
+// when PPT is even; a job's pairs start 16-byte aligned and its chunks and
+// batches are even, so these loads are aligned. The next batch's loads are issued before
 // this batch is counted; past the chunk's last whole uint4 they re-read it.
 template <int R, int PPT>
 __global__ __launch_bounds__(1024) void k_bin_count(const UpdJob *__restrict__ jobs, uint32_t nj) {
@@ -197,27 +197,52 @@ __global__ __launch_bounds__(1024) void k_bin_count(const UpdJob *__restrict__ j
   const GMEM uint4 *q = gmem(reinterpret_cast<const uint4 *>(J.pairs + p0));
   const size_t nq = (p1 - p0) / 2;                      // whole uint4 of the chunk
   size_t i0 = p0;
-  if (i0 + step <= p1) {                                 // uniform over the block
-    uint4 nxt[V4];
-    auto load = [&](size_t b0) {                         // b0: the batch's first pair
+  if constexpr (PPT % 2 == 0) {
+    if (i0 + step <= p1) {                               // uniform over the block
+      uint4 nxt[V4];
+      auto load = [&](size_t b0) {                       // b0: the batch's first pair
 #pragma unroll
-      for (int k = 0; k < V4; k++) {
-        const size_t i = (b0 - p0) / 2 + (size_t)k * blockDim.x + threadIdx.x;
-        nxt[k] = ld4(q + (i < nq ? i : nq - 1));
+        for (int k = 0; k < V4; k++) {
+          const size_t i = (b0 - p0) / 2 + (size_t)k * blockDim.x + threadIdx.x;
+          nxt[k] = ld4(q + (i < nq ? i : nq - 1));
+        }
+      };
+      load(i0);
+      for (; i0 + step <= p1; i0 += step) {
+        uint4 cur[V4];
+#pragma unroll
+        for (int k = 0; k < V4; k++) cur[k] = nxt[k];
+        load(i0 + step);
+#pragma unroll
+        for (int k = 0; k < V4; k++) {
+          count_pair<R>(G, make_uint2(cur[k].x, cur[k].y), h);
+          count_pair<R>(G, make_uint2(cur[k].z, cur[k].w), h);
+        }
+        close_batch();
       }
-    };
-    load(i0);
-    for (; i0 + step <= p1; i0 += step) {
-      uint4 cur[V4];
+    }
+  } else {
+    // an odd PPT: 8-byte loads, in the scatter's order
+    const GMEM uint2 *pairs = gmem(J.pairs);
+    if (i0 + step <= p1) {
+      uint2 nxt[PPT];
+      auto load = [&](size_t b0) {
 #pragma unroll
-      for (int k = 0; k < V4; k++) cur[k] = nxt[k];
-      load(i0 + step);
+        for (int k = 0; k < PPT; k++) {
+          const size_t i = b0 + (size_t)k * blockDim.x + threadIdx.x;
+          nxt[k] = ld2(pairs + (i < p1 ? i : p1 - 1));
+        }
+      };
+      load(i0);
+      for (; i0 + step <= p1; i0 += step) {
+        uint2 cur[PPT];
 #pragma unroll
-      for (int k = 0; k < V4; k++) {
-        count_pair<R>(G, make_uint2(cur[k].x, cur[k].y), h);
-        count_pair<R>(G, make_uint2(cur[k].z, cur[k].w), h);
+        for (int k = 0; k < PPT; k++) cur[k] = nxt[k];
+        load(i0 + step);
+#pragma unroll
+        for (int k = 0; k < PPT; k++) count_pair<R>(G, cur[k], h);
+        close_batch();
       }
-      close_batch();
     }
   }
   if (i0 < p1) {                                         // the chunk's partial batch
@@ -359,7 +384,8 @@ __device__ __forceinline__ uint32_t get_rank(const uint32_t *rk2, int q) {
   return (q & 1) ? rk2[q >> 1] >> 16 : rk2[q >> 1] & 0xFFFFu;
 }
 
-// TMAX: tiles the LDS arrays hold (2048 or 4096), at least the jobs' tiles.
+// TMAX: tiles the LDS arrays hold (2048, 3072 or 4096), at least the jobs'
+// tiles.
 template <int R, int PPT, int TMAX>
 __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__ jobs,
                                                       uint32_t nj) {
@@ -687,9 +713,9 @@ static hipError_t launch_r(const UpdJob *h, UpdJob *d, uint32_t nj, uint32_t *d_
   }
   // LDS of the scatter: 4*(1024*PPT*r + 2*TMAX) bytes of sorted codes +
   // 12*TMAX bytes of tile arrays <= 160 KiB. Up to 2048 tiles: 6 pairs per
-  // thread for r <= 5, 4 for r <= 7, else 2. Up to 4095 tiles: 4 for
-  // r <= 5, else 2. The count pass walks the scatter's batches, so both take
-  // the same PPT.
+  // thread for r <= 5, 4 for r <= 7, else 2. Up to 3072 tiles and r <= 5: 5.
+  // Up to 4095 tiles: 4 for r <= 5, else 2. The count pass walks the
+  // scatter's batches, so both take the same PPT.
   uint32_t max_tiles = 0;
   for (uint32_t j = 0; j < nj; j++) max_tiles = max_tiles > h[j].nbins ? max_tiles : h[j].nbins;
   if (max_tiles <= 2048) {
@@ -698,6 +724,8 @@ static hipError_t launch_r(const UpdJob *h, UpdJob *d, uint32_t nj, uint32_t *d_
     if (ppt == 2) launch_front<R, 2, 2048>(d, nj, blocks, tiles, st);
     else if (ppt == 6) launch_front<R, P6, 2048>(d, nj, blocks, tiles, st);
     else launch_front<R, P4, 2048>(d, nj, blocks, tiles, st);
+  } else if (R <= 5 && max_tiles <= 3072 && ppt != 2) {
+    if constexpr (R <= 5) launch_front<R, 5, 3072>(d, nj, blocks, tiles, st);
   } else {
     constexpr int P4 = R <= 5 ? 4 : 2;
     if (ppt == 2) launch_front<R, 2, 4096>(d, nj, blocks, tiles, st);

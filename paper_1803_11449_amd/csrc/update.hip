@@ -169,8 +169,19 @@ __device__ __forceinline__ void count_pair(const Geom &G, uint2 p, uint32_t *h) 
 // when PPT is even; a job's pairs start 16-byte aligned and its chunks and
 // batches are even, so these loads are aligned. The next batch's loads are issued before
 // this batch is counted; past the chunk's last whole uint4 they re-read it.
+//
+// Register budget: left free, the compiler gives some instantiations 65-90
+// VGPRs. Capped at 64 (8 waves per SIMD), the 5-row, 6-pair count of a
+// 100M-pair window ran 205 us instead of 224 us. The cap is set only where
+// the compiler then still needs no spills (several instantiations spill
+// under it, and a spill stalls every batch on the scratch access).
+template <int R, int PPT> constexpr int count_waves_per_eu() {
+  return (R == 4 && PPT >= 5) || (R == 5 && PPT >= 5) || (R == 7 && PPT == 4) ? 8 : 1;
+}
+
 template <int R, int PPT>
-__global__ __launch_bounds__(1024) void k_bin_count(const UpdJob *__restrict__ jobs, uint32_t nj) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(count_waves_per_eu<R, PPT>())))
+void k_bin_count(const UpdJob *__restrict__ jobs, uint32_t nj) {
   constexpr uint32_t TPT = (BIN_MAX + 1) / 1024;       // tiles per thread
   constexpr int V4 = PPT / 2;
   __shared__ uint32_t h[BIN_MAX + 1];

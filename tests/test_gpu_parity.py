@@ -103,7 +103,9 @@ PARAMS = [oracle.Params(), oracle.Params(1024, 18, 5, 5), oracle.Params(1024, 16
           oracle.Params(256, 12, 6, 5), oracle.Params(512, 10, 8, 4),
           oracle.Params(32, 14, 5, 6), oracle.Params(64, 14, 5, 6),
           oracle.Params(4096, 14, 5, 6), oracle.Params(16384, 12, 5, 7),
-          oracle.Params(32, 5, 8, 5), oracle.Params(64, 8, 6, 7)]
+          oracle.Params(32, 5, 8, 5), oracle.Params(64, 8, 6, 7),
+          # r = 4 and r = 7 under 2048 tiles: 6 and 4 pairs per thread
+          oracle.Params(1024, 16, 4, 8), oracle.Params(512, 14, 7, 4)]
 
 
 @PATHS

@@ -4,7 +4,7 @@ A request is the close of one window of one link: its (src,dst) pairs are
 already in device memory; the response is the window's super point list
 (Alg. 2 restore after Alg. 1 update). Each link keeps a sketch resident on
 the device, sized for its windows by the sizing rule (smallest k >= 14 with
-n / (g 2^k) <= 0.45, alpha = ceil((32 - k) / (r - 2))).
+n / (g 2^k) <= 0.45 and alpha = ceil((32 - k) / (r - 2)) <= k).
 
 ContinuousServer batches continuously: every loop iteration admits all
 requests that have arrived, one per link and as long as the resident
@@ -32,11 +32,15 @@ from . import ddhf, traffic
 
 def sized_params(n_pairs: int, g: int = 1024, r: int = 5, k_min: int = 14,
                  k_max: int = 20, load: float = 0.45):
-    """(k, alpha) of the sizing rule for a window of n_pairs pairs."""
+    """(k, alpha) of the sizing rule for a window of n_pairs pairs. alpha is
+    the least that meets (r - 2) alpha + k >= 32; k also grows until
+    alpha <= k (for r = 3 that is k >= 16)."""
+    def alpha_of(k):
+        return max(1, math.ceil((32 - k) / (r - 2)))
     k = k_min
-    while k < k_max and n_pairs / (g * 2 ** k) > load:
+    while k < k_max and (n_pairs / (g * 2 ** k) > load or alpha_of(k) > k):
         k += 1
-    return k, math.ceil((32 - k) / (r - 2))
+    return k, alpha_of(k)
 
 
 def resident_bytes(g: int, k: int, r: int, alpha: int) -> int:

@@ -241,6 +241,12 @@ __global__ __launch_bounds__(256) void k_hot_scan_lez(Geom G, const uint4 *__res
 
 // ---------------------------------------------------------- 2: HE compaction
 
+// Per-thread values k_rows keeps in registers: hot-mask words (all of a
+// row's when 2^k / 32 <= 8 * 1024, i.e. k <= 18) and HE entries (all when
+// |HE(i)| <= 8192). Loaded together, they cost one memory latency instead
+// of one per loop trip; larger rows take the loops.
+constexpr uint32_t ROW_REG = 8;
+
 __device__ __forceinline__ void compact_row(const Geom &G, uint32_t row,
                                             const uint32_t *__restrict__ hotmask,
                                             uint32_t *__restrict__ he,
@@ -249,17 +255,37 @@ __device__ __forceinline__ void compact_row(const Geom &G, uint32_t row,
   const uint32_t *hm = hotmask + (size_t)row * nw;
   const uint32_t per = (nw + blockDim.x - 1) / blockDim.x;
   const uint32_t w0 = min(threadIdx.x * per, nw), w1 = min(w0 + per, nw);
-  uint32_t cnt = 0;
-  for (uint32_t w = w0; w < w1; w++) cnt += __popc(hm[w]);
   uint32_t total;
-  const uint32_t excl = block_excl_scan<1024>(cnt, &total, sh);
-  uint32_t *out = he + ((size_t)row << G.k) + excl;
-  for (uint32_t w = w0; w < w1; w++) {
-    uint32_t m = hm[w];
-    while (m) {
-      const uint32_t b = __ffs(m) - 1;
-      *out++ = (w << 5) | b;
-      m &= m - 1;
+  if (per <= ROW_REG) {                                // uniform: k <= 18
+    // the thread's words, loaded together and kept for the write pass
+    uint32_t m[ROW_REG], cnt = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < ROW_REG; u++) {
+      m[u] = w0 + u < w1 ? hm[w0 + u] : 0u;
+      cnt += __popc(m[u]);
+    }
+    const uint32_t excl = block_excl_scan<1024>(cnt, &total, sh);
+    uint32_t *out = he + ((size_t)row << G.k) + excl;
+#pragma unroll
+    for (uint32_t u = 0; u < ROW_REG; u++) {
+      while (m[u]) {
+        const uint32_t b = __ffs(m[u]) - 1;
+        *out++ = ((w0 + u) << 5) | b;
+        m[u] &= m[u] - 1;
+      }
+    }
+  } else {
+    uint32_t cnt = 0;
+    for (uint32_t w = w0; w < w1; w++) cnt += __popc(hm[w]);
+    const uint32_t excl = block_excl_scan<1024>(cnt, &total, sh);
+    uint32_t *out = he + ((size_t)row << G.k) + excl;
+    for (uint32_t w = w0; w < w1; w++) {
+      uint32_t m = hm[w];
+      while (m) {
+        const uint32_t b = __ffs(m) - 1;
+        *out++ = (w << 5) | b;
+        m &= m - 1;
+      }
     }
   }
   if (threadIdx.x == 0) st->he_count[row] = total;
@@ -280,9 +306,23 @@ __device__ __forceinline__ void bucket_rows(const Geom &G, uint32_t row, const u
                                             uint32_t *val, uint32_t *sh) {
   const uint32_t nb = 1u << (G.k - G.alpha), M = nb - 1;
   const uint32_t tid = threadIdx.x, bs = blockDim.x;
+  // up to ROW_REG entries per thread are loaded together, before the
+  // counters are cleared, and kept for the placing pass
+  const bool in_regs = n <= ROW_REG * bs;              // uniform
+  uint32_t hv[ROW_REG];
+  if (in_regs) {
+#pragma unroll
+    for (uint32_t u = 0; u < ROW_REG; u++) hv[u] = tid + u * bs < n ? h[tid + u * bs] : 0u;
+  }
   for (uint32_t b = tid; b < nb; b += bs) cur[b] = 0;
   __syncthreads();
-  for (uint32_t x = tid; x < n; x += bs) atomicAdd((uint32_t *)&cur[h[x] & M], 1u);
+  if (in_regs) {
+#pragma unroll
+    for (uint32_t u = 0; u < ROW_REG; u++)
+      if (tid + u * bs < n) atomicAdd((uint32_t *)&cur[hv[u] & M], 1u);
+  } else {
+    for (uint32_t x = tid; x < n; x += bs) atomicAdd((uint32_t *)&cur[h[x] & M], 1u);
+  }
   __syncthreads();
   const uint32_t per = (nb + bs - 1) / bs;
   const uint32_t b0 = min(tid * per, nb), b1 = min(b0 + per, nb);
@@ -298,10 +338,20 @@ __device__ __forceinline__ void bucket_rows(const Geom &G, uint32_t row, const u
   }
   if (tid == 0) off[nb] = total;
   __syncthreads();
-  for (uint32_t x = tid; x < n; x += bs) {
-    const uint32_t c = h[x];
-    const uint32_t pos = atomicAdd((uint32_t *)&cur[c & M], 1u);
-    val[pos] = c;
+  if (in_regs) {
+#pragma unroll
+    for (uint32_t u = 0; u < ROW_REG; u++) {
+      if (tid + u * bs < n) {
+        const uint32_t pos = atomicAdd((uint32_t *)&cur[hv[u] & M], 1u);
+        val[pos] = hv[u];
+      }
+    }
+  } else {
+    for (uint32_t x = tid; x < n; x += bs) {
+      const uint32_t c = h[x];
+      const uint32_t pos = atomicAdd((uint32_t *)&cur[c & M], 1u);
+      val[pos] = c;
+    }
   }
 }
 

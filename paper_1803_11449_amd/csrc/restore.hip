@@ -69,6 +69,9 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total,
   return off + inc - v;
 }
 
+// The most rows a sketch has.
+constexpr uint32_t R_MAX = 8;
+
 // How lanes share one LE of WPL words: LPL lanes, each reading VPL uint4.
 template <int WPL>
 struct LeShape {
@@ -707,27 +710,40 @@ __global__ __launch_bounds__(256) void k_estimate(Geom G, const uint32_t *__rest
     const uint32_t a = valid ? cand[e] : 0u;
     uint32_t ones = 0;
     if (valid) {
+      // the candidate's LE in each row; all rows' loads of a slice are
+      // issued before any is used (rows past r read as all ones)
       const uint32_t c0 = hash_dh0(G, a);
-      if constexpr (WPL >= 4) {
+      size_t le[R_MAX];
 #pragma unroll
+      for (uint32_t i = 0; i < R_MAX; i++)
+        le[i] = (size_t)((i << G.k) | (i == 0 ? c0 : (bit_block(G, i, a) ^ c0))) * WPL;
+      if constexpr (WPL >= 4) {
+#pragma unroll 1
         for (int v = 0; v < S::VPL; v++) {
-          uint4 acc = make_uint4(~0u, ~0u, ~0u, ~0u);
-          for (uint32_t i = 0; i < G.r; i++) {
-            const uint32_t cell = i == 0 ? c0 : (bit_block(G, i, a) ^ c0);
-            const uint4 *le =
-                reinterpret_cast<const uint4 *>(sk + ((size_t)((i << G.k) | cell)) * WPL);
-            const uint4 q = le[v * S::LPL + sub];
-            acc.x &= q.x; acc.y &= q.y; acc.z &= q.z; acc.w &= q.w;
+          uint4 q[R_MAX];
+#pragma unroll
+          for (uint32_t i = 0; i < R_MAX; i++) {
+            q[i] = make_uint4(~0u, ~0u, ~0u, ~0u);
+            if (i < G.r) q[i] = reinterpret_cast<const uint4 *>(sk + le[i])[v * S::LPL + sub];
+          }
+          uint4 acc = q[0];
+#pragma unroll
+          for (uint32_t i = 1; i < R_MAX; i++) {
+            acc.x &= q[i].x; acc.y &= q[i].y; acc.z &= q[i].z; acc.w &= q[i].w;
           }
           ones += __popc(acc.x) + __popc(acc.y) + __popc(acc.z) + __popc(acc.w);
         }
       } else {
         for (int w = 0; w < WPL; w++) {
-          uint32_t acc = ~0u;
-          for (uint32_t i = 0; i < G.r; i++) {
-            const uint32_t cell = i == 0 ? c0 : (bit_block(G, i, a) ^ c0);
-            acc &= sk[((size_t)((i << G.k) | cell)) * WPL + w];
+          uint32_t q[R_MAX];
+#pragma unroll
+          for (uint32_t i = 0; i < R_MAX; i++) {
+            q[i] = ~0u;
+            if (i < G.r) q[i] = sk[le[i] + w];
           }
+          uint32_t acc = q[0];
+#pragma unroll
+          for (uint32_t i = 1; i < R_MAX; i++) acc &= q[i];
           ones += __popc(acc);
         }
       }

@@ -334,13 +334,21 @@ __global__ __launch_bounds__(1024) void k_bin_scan_tiles(const UpdJob *__restric
   GMEM uint32_t *item_tile = gmem(J.item_tile), *gcur = gmem(J.gcur);
   constexpr uint32_t PER = (BIN_MAX + 1) / 1024;
   const uint32_t t0 = threadIdx.x * PER;
-  uint32_t c = 0, it = 0, xs = 0;
+  // the thread's tile totals and group cursors are all loaded before any
+  // store (the stores below could alias them, so a later load would wait)
+  uint32_t v[PER], gc[PER][BIN_GROUPS];
 #pragma unroll
   for (uint32_t k = 0; k < PER; k++) {
     const uint32_t t = t0 + k;
-    const uint32_t v = t < nbins ? totals[t] : 0;
-    const uint32_t ni = t < nbins ? tile_items(v, J.fresh) : 0;
-    c += v;
+    v[k] = t < nbins ? totals[t] : 0;
+#pragma unroll
+    for (uint32_t g = 0; g < BIN_GROUPS; g++) gc[k][g] = t < nbins ? gcur[(size_t)g * nbins + t] : 0;
+  }
+  uint32_t c = 0, it = 0, xs = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < PER; k++) {
+    const uint32_t ni = t0 + k < nbins ? tile_items(v[k], J.fresh) : 0;
+    c += v[k];
     it += ni;
     xs += ni > 1 ? ni - 1 : 0;
   }
@@ -352,15 +360,14 @@ __global__ __launch_bounds__(1024) void k_bin_scan_tiles(const UpdJob *__restric
   for (uint32_t k = 0; k < PER; k++) {
     const uint32_t t = t0 + k;
     if (t < nbins) {
-      const uint32_t v = totals[t];
-      const uint32_t ni = tile_items(v, J.fresh);
+      const uint32_t ni = tile_items(v[k], J.fresh);
       base[t] = ec;
 #pragma unroll
-      for (uint32_t g = 0; g < BIN_GROUPS; g++) gcur[(size_t)g * nbins + t] += ec;
+      for (uint32_t g = 0; g < BIN_GROUPS; g++) gcur[(size_t)g * nbins + t] = gc[k][g] + ec;
       item_start[t] = ei;
       xslot[t] = ex;
       for (uint32_t q = 0; q < ni; q++) item_tile[ei + q] = t;
-      ec += v;
+      ec += v[k];
       ei += ni;
       ex += ni > 1 ? ni - 1 : 0;
     }

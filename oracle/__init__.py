@@ -12,8 +12,8 @@ Every function follows the paper directly:
                  Alg. 2, the denominator of eq. (4)
   hot_lists      HE(i), first loop of Alg. 2
   candidates     Algs. 3-4 join (mode "join"), all 2^32 addresses ("brute"),
-                 Alg. 2 read literally ("alg2"), join without the re-hash
-                 test ("join_norehash")
+                 every tuple of hot LEs judged by the address it names
+                 ("tuples"), join without the re-hash test ("join_norehash")
   estimate       ULE, SZ (Def. 1) and C by eq. (4)
   restore        Alg. 2 end to end
   exact_cardinality  |CO(a)| per measured host (Sec. 3.1), by sort/unique
@@ -32,7 +32,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 OK, E_INVAL, E_NOMEM, E_SATURATED = 0, -1, -2, -5
 
-MODES = {"join": 0, "brute": 1, "alg2": 2, "join_norehash": 3}
+MODES = {"join": 0, "brute": 1, "tuples": 2, "join_norehash": 3}
 
 
 def build() -> str:

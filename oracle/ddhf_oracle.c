@@ -17,7 +17,7 @@
  *
  * Readings where the paper is silent or garbled (each listed in the design
  * notes of the repository):
- *   - H1 and DH0 are "random hash" functions the paper does not specify.
+ *   - H1 and DH0 are random hash functions the paper does not specify.
  *     Here both are multiply-add-shift hashes (Dietzfelbinger 1996) on the
  *     32-bit key with a 64-bit odd multiplier:
  *        DH0(x) = ((A0*x + B0) mod 2^64) >> (64 - k)
@@ -387,38 +387,36 @@ done:
   return rc;
 }
 
-/* Alg. 2 read literally: every tuple of HE(0) x ... x HE(r-1); the top
- * k-alpha bits of BL(i) must match the low k-alpha bits of BL(i+1) for
- * i = 1..r-2, where BL(i) = CL0 ^ CL_i; the address is the OR of every
- * BL(i) shifted to bit (i-1)*alpha. Exponential in r: tiny inputs only. */
-static int64_t join_alg2(const orc_t *o, const uint32_t *he,
-                         const uint32_t *he_n, uint32_t *cand, size_t cap) {
+/* Every tuple of hot LEs, one per row (the search space of Alg. 2), judged
+ * by what a tuple stands for: the 32-bit address a with DH_i(a) = CL_i in
+ * every row. By eq. (3) such an a has BL(i)(a) = CL_0 ^ CL_i for i >= 1, and
+ * since the blocks together cover bits 0..31 ((r-2)*alpha + k >= 32 and
+ * alpha <= k, Sec. 3.3), that a, if it exists, is the OR of those blocks
+ * placed at their offsets. The tuple names an address iff that OR satisfies
+ * all r equations; no overlap rule is applied separately. Exponential in r:
+ * tiny inputs only. */
+static int64_t join_tuples(const orc_t *o, const uint32_t *he,
+                           const uint32_t *he_n, uint32_t *cand, size_t cap) {
   const uint32_t k = o->k, al = o->alpha, r = o->r;
-  const uint64_t M = (1ull << (k - al)) - 1;
   uint64_t total = 1;
   for (uint32_t i = 0; i < r; i++) total *= he_n[i];
   ulist_t out = {0};
-  uint32_t idx[8] = {0};
   for (uint64_t t = 0; t < total; t++) {
-    uint64_t rem = t;
-    for (uint32_t i = 0; i < r; i++) { idx[i] = (uint32_t)(rem % he_n[i]); rem /= he_n[i]; }
     uint32_t cl[8];
-    for (uint32_t i = 0; i < r; i++) cl[i] = he[((size_t)i << k) + idx[i]];
-    int contains_ip = 1;
-    for (uint32_t i = 1; i + 1 < r; i++) {
-      uint64_t bli = cl[0] ^ cl[i], blj = cl[0] ^ cl[i + 1];
-      if ((bli >> al) != (blj & M)) { contains_ip = 0; break; }
+    uint64_t rem = t;
+    for (uint32_t i = 0; i < r; i++) {
+      cl[i] = he[((size_t)i << k) + (uint32_t)(rem % he_n[i])];
+      rem /= he_n[i];
     }
-    if (!contains_ip) continue;
     uint64_t a = 0;
-    int high = 0;
     for (uint32_t i = 1; i < r; i++) {
-      uint64_t bl = cl[0] ^ cl[i];
       uint32_t s = (i - 1) * al;
-      if (s >= 32) { if (bl) high = 1; continue; }
-      a |= bl << s;
+      if (s < 32) a |= (uint64_t)(cl[0] ^ cl[i]) << s;
     }
-    if (high || !accept_rebuilt(o, a, cl[0])) continue;
+    a &= 0xFFFFFFFFull;
+    int names = 1;
+    for (uint32_t i = 0; i < r && names; i++) names = dh(o, i, (uint32_t)a) == cl[i];
+    if (!names) continue;
     if (ulist_push(&out, (uint32_t)a)) { free(out.v); return ORC_E_NOMEM; }
   }
   if (out.n) qsort(out.v, out.n, sizeof(uint32_t), cmp_u32);
@@ -479,7 +477,7 @@ static int64_t join_bruteforce(const orc_t *o, const uint32_t *he,
 /* Candidate set CAND for threshold theta.
  * mode 0: Algs. 3-4 (incremental join) with the re-hash test
  * mode 1: brute force over all 2^32 addresses
- * mode 2: Alg. 2 read literally (product of all hot lists; tiny only)
+ * mode 2: every tuple of hot LEs judged by the address it names (tiny only)
  * mode 3: Algs. 3-4 without the re-hash test (distinct 32-bit results)
  * Returns the count (may exceed cap) or a negative error. */
 int64_t orc_candidates(uint32_t g, uint32_t k, uint32_t r, uint32_t alpha,
@@ -495,7 +493,7 @@ int64_t orc_candidates(uint32_t g, uint32_t k, uint32_t r, uint32_t alpha,
   switch (mode) {
     case 0: n = join_incremental(&o, he, he_n, 1, cand, cap); break;
     case 1: n = join_bruteforce(&o, he, he_n, nthreads, cand, cap); break;
-    case 2: n = join_alg2(&o, he, he_n, cand, cap); break;
+    case 2: n = join_tuples(&o, he, he_n, cand, cap); break;
     case 3: n = join_incremental(&o, he, he_n, 0, cand, cap); break;
     default: n = ORC_E_INVAL;
   }

@@ -279,13 +279,13 @@ def test_single_isolated_host_is_recovered():
     assert abs(c[0] / n - 1) < 0.2
 
 
-def test_join_equals_alg2_and_bruteforce_tiny():
+def test_join_equals_tuples_and_bruteforce_tiny():
     hosts, pairs = planted_small()
     sk = oracle.build_sketch(DEF, pairs)
     he = oracle.hot_lists(DEF, sk, 1024.0)
     assert 0 < np.prod([len(h) for h in he]) <= 200_000
     j = oracle.candidates(DEF, sk, 1024.0, "join")
-    a2 = oracle.candidates(DEF, sk, 1024.0, "alg2")
+    a2 = oracle.candidates(DEF, sk, 1024.0, "tuples")
     bf = oracle.candidates(DEF, sk, 1024.0, "brute")
     assert np.array_equal(j, a2) and np.array_equal(j, bf)
     assert set(hosts) <= set(j)

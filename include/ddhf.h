@@ -16,8 +16,14 @@
  *    sketch_last_error() gives a message (per calling thread).
  *  - hip_stream is a hipStream_t passed as void* (NULL = the null stream).
  *    Device work is issued on it in order.
- *  - A handle is not thread-safe: use one handle from one thread/stream at a
- *    time. Several handles may share a device and a stream.
+ *  - A handle is not thread-safe: use one handle from one thread at a time.
+ *    Several handles may share a device and a stream. Work a call enqueues
+ *    on a sketch is ordered after the last work any earlier call enqueued
+ *    on it, also from another stream (each handle keeps an event of its
+ *    last work), and the device's shared scratch buffers are ordered the
+ *    same way: the update's scratch and the restore's separately, so an
+ *    update on one stream may run while a restore of another sketch runs
+ *    on another.
  *  - The device is params->device; every call makes it current for its
  *    duration and restores the caller's current device before returning.
  *
@@ -177,6 +183,25 @@ typedef struct {
  * before any work (NULL list or handle, bad theta or out, a sketch twice,
  * several devices): INVAL, with no job run. */
 int sketch_restore_batch(sketch_restore_job_t *jobs, size_t n_jobs, void *hip_stream);
+
+/* sketch_restore_batch in two halves, so that a caller can enqueue more
+ * work (the next batch's update, on another stream) while these restores
+ * run: the per-period cycle of Sec. 4 with one period's restore (Alg. 2,
+ * Sec. 4.2) overlapping the next period's update (Alg. 1).
+ * _begin checks the jobs and enqueues every restore on hip_stream, then
+ * returns without waiting; it reads only the sketch and theta of each job.
+ * _end waits for each job's restore (not for other work on the stream),
+ * runs a job again on hip_stream if its output outgrew the shared buffers,
+ * and fills out, info, n_out and status as sketch_restore_batch does.
+ * Between the two calls the jobs' sketches may be used by no other call
+ * except sketch_update / sketch_update_batch / sketch_reset, whose device
+ * work the library orders after the pending restore (each sketch keeps an
+ * event of its last work). _end must get the same sketches as _begin (in
+ * any order, any subset at a time). Errors: as sketch_restore_batch; INVAL
+ * also for a sketch with a restore begun and not ended (_begin) or none
+ * begun (_end). */
+int sketch_restore_batch_begin(sketch_restore_job_t *jobs, size_t n_jobs, void *hip_stream);
+int sketch_restore_batch_end(sketch_restore_job_t *jobs, size_t n_jobs, void *hip_stream);
 
 /* ---- plans: one window cycle of a fixed batch, replayed as a HIP graph ----
  *

@@ -112,6 +112,50 @@ void pinned_free(T *&h, T *&d) {
   d = nullptr;
 }
 
+// ---------------------------------------------------------- ordering
+
+// Orders device work on one resource (a shared buffer, a sketch) across
+// streams: work about to be enqueued on a stream waits for the last work
+// that used the resource when that work was enqueued on another stream.
+struct Lane {
+  hipEvent_t ev = nullptr;
+  bool armed = false;
+  hipStream_t stream = nullptr;   // stream of the last work
+};
+
+int lane_init(Lane &l) {
+  if (hipEventCreateWithFlags(&l.ev, hipEventDisableTiming) != hipSuccess) {
+    l.ev = nullptr;
+    return fail(SKETCH_E_HIP, "hipEventCreate failed");
+  }
+  return SKETCH_OK;
+}
+
+void lane_free(Lane &l) {
+  if (l.armed) (void)hipEventSynchronize(l.ev);
+  if (l.ev) (void)hipEventDestroy(l.ev);
+  l.ev = nullptr;
+  l.armed = false;
+}
+
+int lane_enter(Lane &l, hipStream_t st) {
+  if (l.armed && st != l.stream) HIP_OK(hipStreamWaitEvent(st, l.ev, 0));
+  return SKETCH_OK;
+}
+
+int lane_leave(Lane &l, hipStream_t st) {
+  HIP_OK(hipEventRecord(l.ev, st));
+  l.armed = true;
+  l.stream = st;
+  return SKETCH_OK;
+}
+
+// Wait on the host until the last work that used the resource is done.
+int lane_idle(Lane &l) {
+  if (l.armed) HIP_OK(hipEventSynchronize(l.ev));
+  return SKETCH_OK;
+}
+
 // ---------------------------------------------------------- device context
 
 constexpr size_t ARENA_MAX_PAIRS = MAX_ROUND_PAIRS;   // pairs per binned launch group
@@ -144,37 +188,20 @@ struct DevCtx {
   uint4 *spl = nullptr;
   size_t spl_cap = 0;
   uint32_t *rank = nullptr;
-  // last work that used the arena or the pool
-  hipEvent_t pool_ev = nullptr;
-  bool pool_armed = false;
-  hipStream_t pool_stream = nullptr;   // stream of that work
+  // last work that used the update arena, and the restore pool: separate,
+  // so that one batch's update can run while another batch's restore does
+  Lane arena_lane, pool_lane;
   uint64_t gen = 0;              // bumped whenever the arena or the pool moves
 };
 
 std::mutex g_ctx_mu;
 DevCtx *g_ctx[256] = {};
 
-// Order work about to be enqueued on st after the last use of the pools.
-int pool_enter(DevCtx *c, hipStream_t st) {
-  // work on the stream that used the pools last is ordered after it anyway
-  if (c->pool_armed && st != c->pool_stream) HIP_OK(hipStreamWaitEvent(st, c->pool_ev, 0));
-  return SKETCH_OK;
-}
+// Wait on the host until the restore pool is idle (before reallocating it).
+int pool_idle(DevCtx *c) { return lane_idle(c->pool_lane); }
+int arena_idle(DevCtx *c) { return lane_idle(c->arena_lane); }
 
-int pool_leave(DevCtx *c, hipStream_t st) {
-  HIP_OK(hipEventRecord(c->pool_ev, st));
-  c->pool_armed = true;
-  c->pool_stream = st;
-  return SKETCH_OK;
-}
-
-// Wait on the host until the pools are idle (before reallocating them).
-int pool_idle(DevCtx *c) {
-  if (c->pool_armed) HIP_OK(hipEventSynchronize(c->pool_ev));
-  return SKETCH_OK;
-}
-
-// Restore pool buffers at exactly `cap` entries (after the pools are idle).
+// Restore pool buffers at exactly `cap` entries (after the pool is idle).
 int alloc_partials(DevCtx *c, size_t cap) {
   int rc = pool_idle(c);
   if (rc) return rc;
@@ -225,7 +252,7 @@ constexpr size_t POOL_SEG0 = (size_t)1 << 12, POOL_CAND0 = (size_t)1 << 16,
 // Update arena for `words` code words and `tiles` scratch tiles.
 int ensure_arena(DevCtx *c, size_t words, size_t tiles) {
   if (c->codes_cap >= words && c->scratch_tiles >= tiles) return SKETCH_OK;
-  int rc = pool_idle(c);
+  int rc = arena_idle(c);
   if (rc) return rc;
   c->gen++;
   if (c->codes_cap < words) {
@@ -250,6 +277,7 @@ int ensure_arena(DevCtx *c, size_t words, size_t tiles) {
 // buffer (0: the initial sizes). Caller holds c->mu.
 int trim_pools(DevCtx *c, size_t entries) {
   int rc = pool_idle(c);
+  if (!rc) rc = arena_idle(c);
   if (rc) return rc;
   c->gen++;
   dev_free(c->codes);
@@ -269,8 +297,8 @@ void ctx_free(DevCtx *c) {
     if (c->h_jobs[i]) (void)hipHostFree(c->h_jobs[i]);
     dev_free(c->d_jobs[i]);
   }
-  (void)pool_idle(c);
-  if (c->pool_ev) (void)hipEventDestroy(c->pool_ev);
+  lane_free(c->pool_lane);
+  lane_free(c->arena_lane);
   dev_free(c->d_total);
   dev_free(c->codes);
   dev_free(c->scratch);
@@ -306,8 +334,8 @@ int ctx_acquire(int dev, int n_cu, DevCtx **out) {
       if (!rc && hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming) != hipSuccess)
         rc = fail(SKETCH_E_HIP, "device context: hipEventCreate failed");
     }
-    if (!rc && hipEventCreateWithFlags(&c->pool_ev, hipEventDisableTiming) != hipSuccess)
-      rc = fail(SKETCH_E_HIP, "device context: hipEventCreate failed");
+    if (!rc) rc = lane_init(c->pool_lane);
+    if (!rc) rc = lane_init(c->arena_lane);
     if (!rc) rc = dev_alloc(&c->d_total, DevCtx::SLOTS, "item totals");
     if (!rc) rc = dev_alloc(&c->rank, 16384, "sort ranks");
     if (!rc) rc = dev_alloc(&c->segc[0], c->jblk, "segment counts");
@@ -386,6 +414,12 @@ Geom make_geom(const sketch_params_t &p) {
   return G;
 }
 
+// Thresholds that depend on theta only (host, float64).
+struct Thresholds {
+  double e_theta, zmin;
+  uint32_t zhot;
+};
+
 }  // namespace
 
 // ------------------------------------------------------------------ handle
@@ -394,6 +428,12 @@ struct sketch {
   sketch_params_t p;
   Geom G;
   DevCtx *ctx = nullptr;
+  mutable Lane lane;            // last work on this sketch (any stream)
+  // a restore begun by sketch_restore_batch_begin and not yet ended: its
+  // thresholds, and the event that marks the end of its device work
+  bool pending = false;
+  Thresholds pend_t{};
+  hipEvent_t restore_ev = nullptr;
   int n_cu = 0;
   int grid = 0;                 // blocks of grid-stride kernels
   uint32_t *d_sketch = nullptr;
@@ -439,6 +479,9 @@ struct sketch {
 namespace {
 
 void free_sketch(sketch *s) {
+  lane_free(s->lane);
+  if (s->restore_ev) (void)hipEventDestroy(s->restore_ev);
+  s->restore_ev = nullptr;
   dev_free(s->d_sketch);
   dev_free(s->hist);
   dev_free(s->totals);
@@ -540,12 +583,6 @@ void fill_info(const sketch *s, const DevState &st, double zmin, uint32_t zhot,
   info->szmax = st.szmax;
 }
 
-// Thresholds that depend on theta only (host, float64).
-struct Thresholds {
-  double e_theta, zmin;
-  uint32_t zhot;
-};
-
 Thresholds thresholds(const sketch *s, double theta) {
   Thresholds t;
   t.e_theta = exp(-theta / (double)s->p.g);
@@ -569,9 +606,9 @@ int materialize(sketch *s, hipStream_t st) {
 // Caller holds ctx->mu.
 int restore_launch(sketch *s, const Thresholds &t, int estimate, hipStream_t st) {
   DevCtx *c = s->ctx;
-  int rc = materialize(s, st);
-  if (rc) return rc;
-  rc = pool_enter(c, st);
+  int rc = lane_enter(s->lane, st);
+  if (!rc) rc = materialize(s, st);
+  if (!rc) rc = lane_enter(c->pool_lane, st);
   if (rc) return rc;
   const RestoreBufs B = restore_bufs(s);
   s->ran_seg_cap = B.seg_cap;
@@ -579,7 +616,9 @@ int restore_launch(sketch *s, const Thresholds &t, int estimate, hipStream_t st)
   s->ran_spl_cap = B.spl_cap;
   s->ran_h_recs_cap = B.h_recs_cap;
   HIP_OK(launch_restore(s->G, s->d_sketch, B, t.zhot, t.e_theta, estimate, s->grid, st));
-  return pool_leave(c, st);
+  rc = lane_leave(c->pool_lane, st);
+  if (!rc) rc = lane_leave(s->lane, st);
+  return rc;
 }
 
 // After the state copy has landed: grow any buffer that overflowed.
@@ -719,11 +758,12 @@ int flush_group(DevCtx *c, Group &g, hipStream_t st) {
       if (rc) return rc;
       place_arena(J, n, g.r, c->codes, c->scratch);
     }
-    int rc = pool_enter(c, st);
+    // only binned launches use the shared arena
+    int rc = g.binned ? lane_enter(c->arena_lane, st) : SKETCH_OK;
     if (rc) return rc;
     rc = launch_jobs(c, J, n, g.binned, g.r, g.ppt, g.apply_grid, st);
     if (rc) return rc;
-    rc = pool_leave(c, st);
+    rc = g.binned ? lane_leave(c->arena_lane, st) : SKETCH_OK;
     if (rc) return rc;
   }
   g.jobs.clear();
@@ -740,6 +780,25 @@ void add_job(std::vector<Group> &groups, const sketch *s, const UpdJob &J, bool 
       return;
     }
   groups.push_back(Group{s->p.r, binned, J.check, s->scatter_ppt, s->apply_grid, {J}});
+}
+
+// Pairs, blocks and pairs per block of a binned round of m pairs: about
+// 32k pairs or more per block, at most the sketch's configured count.
+void bin_shape(const sketch *s, size_t m, UpdJob &J) {
+  J.n = m;
+  const size_t want = (m + 32767) / 32768;
+  J.nblk = (uint32_t)std::max<size_t>(1, std::min<size_t>(s->bin_nblk, want));
+  size_t chunk = (m + J.nblk - 1) / J.nblk;
+  chunk += chunk & 1;
+  J.chunk = chunk;
+  J.nblk = (uint32_t)((m + chunk - 1) / chunk);
+}
+
+// Bytes of scratch a binned round of one job takes: its code words (at the
+// bound code_words_bound gives, 16-byte aligned) and its scratch tiles.
+size_t round_scratch_bytes(const UpdJob &J, uint32_t r) {
+  const size_t w = code_words_bound(J.n, r, J.nbins, J.nblk, J.chunk);
+  return ((2 * w + 3) & ~(size_t)3) * 4 + (w / APPLY_ITEM + 1) * (size_t)BIN_TILE_WORDS * 4;
 }
 
 // Checks the jobs of an update of several sketches on one device.
@@ -809,14 +868,7 @@ int schedule_update(const sketch_update_job_t *jobs, size_t n_jobs, Base base, F
         const size_t m = std::min({left[j], s->binned_round, room});
         if (m == 0) continue;
         room -= m;
-        J.n = m;
-        // about 32k pairs or more per block, at most the configured count
-        const size_t want = (m + 32767) / 32768;
-        J.nblk = (uint32_t)std::max<size_t>(1, std::min<size_t>(s->bin_nblk, want));
-        size_t chunk = (m + J.nblk - 1) / J.nblk;
-        chunk += chunk & 1;
-        J.chunk = chunk;
-        J.nblk = (uint32_t)((m + chunk - 1) / chunk);
+        bin_shape(s, m, J);
         if (fresh) {
           J.fresh = (uint32_t)fresh[j];
           fresh[j] = 0;
@@ -844,6 +896,26 @@ int schedule_update(const sketch_update_job_t *jobs, size_t n_jobs, Base base, F
   return SKETCH_OK;
 }
 
+// Checks the jobs of a batched restore: distinct sketches on one device,
+// valid thresholds and outputs.
+int check_restore_jobs(const sketch_restore_job_t *jobs, size_t n_jobs, const char *who) {
+  if (!jobs) return fail(SKETCH_E_INVAL, "%s: NULL jobs", who);
+  const int dev = jobs[0].sketch ? jobs[0].sketch->p.device : -1;
+  for (size_t j = 0; j < n_jobs; j++) {
+    const sketch_restore_job_t &J = jobs[j];
+    if (!J.sketch) return fail(SKETCH_E_INVAL, "%s: NULL handle (job %zu)", who, j);
+    if (J.sketch->p.device != dev)
+      return fail(SKETCH_E_INVAL, "%s: sketches on different devices", who);
+    if (!(J.theta > 0.0) || !isfinite(J.theta))
+      return fail(SKETCH_E_INVAL, "%s: theta must be finite and > 0 (job %zu)", who, j);
+    if (J.cap && !J.out) return fail(SKETCH_E_INVAL, "%s: NULL out with cap > 0 (job %zu)", who, j);
+    for (size_t i = 0; i < j; i++)
+      if (jobs[i].sketch == J.sketch)
+        return fail(SKETCH_E_INVAL, "%s: a sketch appears twice (jobs %zu, %zu)", who, i, j);
+  }
+  return SKETCH_OK;
+}
+
 // The update of several distinct sketches on one device: every pair of every
 // job is applied.
 int update_jobs(const sketch_update_job_t *jobs, size_t n_jobs, hipStream_t st) {
@@ -859,6 +931,8 @@ int update_jobs(const sketch_update_job_t *jobs, size_t n_jobs, hipStream_t st) 
   for (size_t j = 0; j < n_jobs; j++) {
     sketch *s = jobs[j].sketch;
     if (jobs[j].n_pairs == 0) continue;
+    rc = lane_enter(s->lane, st);
+    if (rc) return rc;
     const bool binned = binned_from_start(s, jobs[j].d_pairs, jobs[j].n_pairs);
     if (s->fresh && binned) {
       fresh[j] = 1;
@@ -870,9 +944,12 @@ int update_jobs(const sketch_update_job_t *jobs, size_t n_jobs, hipStream_t st) 
       if (!binned) s->lez_valid = false;    // the direct kernel sets bits
     }
   }
-  return schedule_update(
+  rc = schedule_update(
       jobs, n_jobs, [&](size_t j) { return job_base(jobs[j].sketch); },
       [&](Group &g) { return flush_group(c, g, st); }, fresh.data());
+  for (size_t j = 0; j < n_jobs && !rc; j++)
+    if (jobs[j].n_pairs) rc = lane_leave(jobs[j].sketch->lane, st);
+  return rc;
 }
 
 
@@ -1101,6 +1178,11 @@ int sketch_create(const sketch_params_t *params, sketch_t **out) {
   const size_t n_le = (size_t)params->r << params->k;
   const size_t nb = (size_t)1 << (params->k - params->alpha);
   int rc = ctx_acquire(params->device, s->n_cu, &s->ctx);
+  if (!rc) rc = lane_init(s->lane);
+  if (!rc && hipEventCreateWithFlags(&s->restore_ev, hipEventDisableTiming) != hipSuccess) {
+    s->restore_ev = nullptr;
+    rc = fail(SKETCH_E_HIP, "sketch_create: hipEventCreate failed");
+  }
   if (!rc) rc = dev_alloc(&s->d_sketch, s->words, "sketch");
   if (!rc) rc = dev_alloc(&s->st, 1, "state");
   if (!rc) rc = dev_alloc(&s->hotmask, n_le / 32, "hot bitmap");
@@ -1175,12 +1257,16 @@ int sketch_merge(sketch_t *dst, const sketch_t *src, void *hip_stream) {
     return fail(SKETCH_E_INVAL, "sketch_merge: sketches on different devices");
   if (src->fresh) return SKETCH_OK;   // OR with zeros
   DEVICE_GUARD(a.device);
-  int rc = materialize(dst, (hipStream_t)hip_stream);
+  hipStream_t st = (hipStream_t)hip_stream;
+  int rc = lane_enter(dst->lane, st);
+  if (!rc) rc = lane_enter(src->lane, st);
+  if (!rc) rc = materialize(dst, st);
   if (rc) return rc;
-  HIP_OK(launch_or_u32(dst->d_sketch, src->d_sketch, dst->words, dst->grid * 4,
-                       (hipStream_t)hip_stream));
+  HIP_OK(launch_or_u32(dst->d_sketch, src->d_sketch, dst->words, dst->grid * 4, st));
   dst->lez_valid = false;
-  return SKETCH_OK;
+  rc = lane_leave(dst->lane, st);
+  if (!rc) rc = lane_leave(src->lane, st);
+  return rc;
 }
 
 int sketch_restore(sketch_t *s, double theta, sketch_sp_t *out, size_t cap, size_t *n_out,
@@ -1207,47 +1293,57 @@ int sketch_restore(sketch_t *s, double theta, sketch_sp_t *out, size_t cap, size
   return copy_records(s, out, (size_t)h.n_spl, s->ran_h_recs_cap, st);
 }
 
-int sketch_restore_batch(sketch_restore_job_t *jobs, size_t n_jobs, void *hip_stream) {
+int sketch_restore_batch_begin(sketch_restore_job_t *jobs, size_t n_jobs, void *hip_stream) {
   if (n_jobs == 0) return SKETCH_OK;
-  if (!jobs) return fail(SKETCH_E_INVAL, "sketch_restore_batch: NULL jobs");
-  const int dev = jobs[0].sketch ? jobs[0].sketch->p.device : -1;
-  for (size_t j = 0; j < n_jobs; j++) {
-    const sketch_restore_job_t &J = jobs[j];
-    if (!J.sketch) return fail(SKETCH_E_INVAL, "sketch_restore_batch: NULL handle (job %zu)", j);
-    if (J.sketch->p.device != dev)
-      return fail(SKETCH_E_INVAL, "sketch_restore_batch: sketches on different devices");
-    if (!(J.theta > 0.0) || !isfinite(J.theta))
-      return fail(SKETCH_E_INVAL, "sketch_restore_batch: theta must be finite and > 0 (job %zu)",
-                  j);
-    if (J.cap && !J.out)
-      return fail(SKETCH_E_INVAL, "sketch_restore_batch: NULL out with cap > 0 (job %zu)", j);
-    for (size_t i = 0; i < j; i++)
-      if (jobs[i].sketch == J.sketch)
-        return fail(SKETCH_E_INVAL, "sketch_restore_batch: a sketch appears twice (jobs %zu, %zu)",
-                    i, j);
-  }
-  DEVICE_GUARD(dev);
+  int rc = check_restore_jobs(jobs, n_jobs, "sketch_restore_batch_begin");
+  if (rc) return rc;
+  for (size_t j = 0; j < n_jobs; j++)
+    if (jobs[j].sketch->pending)
+      return fail(SKETCH_E_INVAL, "sketch_restore_batch_begin: job %zu's sketch has a restore "
+                  "that was begun and not ended", j);
+  DEVICE_GUARD(jobs[0].sketch->p.device);
   hipStream_t st = (hipStream_t)hip_stream;
   DevCtx *c = jobs[0].sketch->ctx;
   std::lock_guard<std::mutex> lk(c->mu);
-  std::vector<Thresholds> th(n_jobs);
-  // every restore enqueued, one wait
+  // every restore enqueued; each one's end is marked by its sketch's event
   for (size_t j = 0; j < n_jobs; j++) {
-    th[j] = thresholds(jobs[j].sketch, jobs[j].theta);
-    int rc = restore_launch(jobs[j].sketch, th[j], 1, st);
+    sketch *s = jobs[j].sketch;
+    s->pend_t = thresholds(s, jobs[j].theta);
+    rc = restore_launch(s, s->pend_t, 1, st);
+    if (!rc && hipEventRecord(s->restore_ev, st) != hipSuccess)
+      rc = fail(SKETCH_E_HIP, "sketch_restore_batch_begin: hipEventRecord failed");
     if (rc) return rc;
+    s->pending = true;
   }
-  HIP_OK(hipStreamSynchronize(st));
+  return SKETCH_OK;
+}
+
+int sketch_restore_batch_end(sketch_restore_job_t *jobs, size_t n_jobs, void *hip_stream) {
+  if (n_jobs == 0) return SKETCH_OK;
+  int rc = check_restore_jobs(jobs, n_jobs, "sketch_restore_batch_end");
+  if (rc) return rc;
+  for (size_t j = 0; j < n_jobs; j++)
+    if (!jobs[j].sketch->pending)
+      return fail(SKETCH_E_INVAL, "sketch_restore_batch_end: job %zu's sketch has no begun "
+                  "restore", j);
+  DEVICE_GUARD(jobs[0].sketch->p.device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  DevCtx *c = jobs[0].sketch->ctx;
   int first_err = SKETCH_OK;
   for (size_t j = 0; j < n_jobs; j++) {
     sketch_restore_job_t &J = jobs[j];
     sketch *s = J.sketch;
-    bool again;
-    int rc = restore_check(s, 1, &again);
-    if (rc == SKETCH_OK && again) rc = run_restore(s, th[j], 1, st);  // this job alone
+    // wait for this restore only (outside the lock: other work may be queued)
+    rc = hipEventSynchronize(s->restore_ev) == hipSuccess
+             ? SKETCH_OK : fail(SKETCH_E_HIP, "sketch_restore_batch_end: hipEventSynchronize");
+    std::lock_guard<std::mutex> lk(c->mu);
+    s->pending = false;
+    bool again = false;
+    if (rc == SKETCH_OK) rc = restore_check(s, 1, &again);
+    if (rc == SKETCH_OK && again) rc = run_restore(s, s->pend_t, 1, st);   // this job alone
     const DevState h = *s->h_state;
     if (rc == SKETCH_OK || rc == SKETCH_E_SATURATED)
-      fill_info(s, h, th[j].zmin, th[j].zhot, J.info);
+      fill_info(s, h, s->pend_t.zmin, s->pend_t.zhot, J.info);
     J.n_out = rc == SKETCH_OK ? (size_t)h.n_spl : 0;
     if (rc == SKETCH_OK && h.n_spl > J.cap) rc = SKETCH_E_CAPACITY;
     if (rc == SKETCH_OK)
@@ -1258,6 +1354,12 @@ int sketch_restore_batch(sketch_restore_job_t *jobs, size_t n_jobs, void *hip_st
   if (first_err)
     return fail(first_err, "sketch_restore_batch: a job failed (see each job's status)");
   return SKETCH_OK;
+}
+
+int sketch_restore_batch(sketch_restore_job_t *jobs, size_t n_jobs, void *hip_stream) {
+  int rc = sketch_restore_batch_begin(jobs, n_jobs, hip_stream);
+  if (rc) return rc;
+  return sketch_restore_batch_end(jobs, n_jobs, hip_stream);
 }
 
 int sketch_candidates(sketch_t *s, double theta, uint32_t *out, size_t cap, size_t *n_out,
@@ -1355,6 +1457,8 @@ int sketch_download(const sketch_t *s, uint32_t *host_words, size_t n_words, voi
   }
   DEVICE_GUARD(s->p.device);
   hipStream_t st = (hipStream_t)hip_stream;
+  int rc = lane_enter(s->lane, st);
+  if (rc) return rc;
   HIP_OK(hipMemcpyAsync(host_words, s->d_sketch, n_words * 4, hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
   return SKETCH_OK;
@@ -1366,6 +1470,8 @@ int sketch_upload(sketch_t *s, const uint32_t *host_words, size_t n_words, void 
     return fail(SKETCH_E_INVAL, "sketch_upload: n_words %zu, sketch has %zu", n_words, s->words);
   DEVICE_GUARD(s->p.device);
   hipStream_t st = (hipStream_t)hip_stream;
+  int rc = lane_enter(s->lane, st);
+  if (rc) return rc;
   HIP_OK(hipMemcpyAsync(s->d_sketch, host_words, n_words * 4, hipMemcpyHostToDevice, st));
   HIP_OK(hipStreamSynchronize(st));
   s->fresh = false;
@@ -1486,6 +1592,7 @@ int sketch_plan_create(const sketch_plan_job_t *jobs, size_t n_jobs, int flags,
       }
     }
     if (!rc) rc = pool_idle(c);           // nothing else uses the shared buffers now
+    if (!rc) rc = arena_idle(c);
     if (!rc) rc = plan_build_graph(P);
   }
   if (rc) {
@@ -1507,12 +1614,15 @@ int sketch_plan_run(sketch_plan_t *P, void *hip_stream) {
       c->codes_cap < P->arena_words || c->scratch_tiles < P->arena_tiles) {
     if (P->ran) HIP_OK(hipStreamSynchronize(P->run_stream));   // the old graph is done
     int rc = pool_idle(c);
+    if (!rc) rc = arena_idle(c);
     if (!rc) rc = plan_build_graph(P);
     if (rc) return rc;
   }
   // a plan that does not reset works on the sketches as they are: write the
   // zeros of fresh ones first; a resetting plan leaves none fresh
   for (PlanJob &j : P->jobs) {
+    int rc = lane_enter(j.s->lane, st);
+    if (rc) return rc;
     if (P->flags & SKETCH_PLAN_RESET) {
       j.s->fresh = false;
       j.s->lez_valid = j.fresh && j.s->lez;
@@ -1522,10 +1632,14 @@ int sketch_plan_run(sketch_plan_t *P, void *hip_stream) {
       j.s->lez_valid = false;
     }
   }
-  int rc = pool_enter(c, st);
+  int rc = lane_enter(c->pool_lane, st);
+  if (!rc) rc = lane_enter(c->arena_lane, st);
   if (rc) return rc;
   HIP_OK(hipGraphLaunch(P->exec, st));
-  rc = pool_leave(c, st);
+  rc = lane_leave(c->pool_lane, st);
+  if (!rc) rc = lane_leave(c->arena_lane, st);
+  for (PlanJob &j : P->jobs)
+    if (!rc) rc = lane_leave(j.s->lane, st);
   if (rc) return rc;
   P->ran = true;
   P->run_stream = st;

@@ -25,10 +25,12 @@ SKETCH_E_SATURATED = -5
 DEFAULT_SEED = 0x1803114490000001
 
 EXPORTS = ("sketch_params_default", "sketch_params_check", "sketch_bytes",
-           "sketch_create", "sketch_destroy", "sketch_update", "sketch_restore",
+           "sketch_create", "sketch_destroy", "sketch_update",
+           "sketch_restore",
            "sketch_reset", "sketch_download", "sketch_upload",
            "sketch_candidates", "sketch_last_error", "sketch_set_option",
-           "sketch_update_batch", "sketch_restore_batch", "sketch_merge",
+           "sketch_update_batch", "sketch_restore_batch", "sketch_restore_batch_begin",
+           "sketch_restore_batch_end", "sketch_merge",
            "sketch_plan_create", "sketch_plan_run", "sketch_plan_results",
            "sketch_plan_launches", "sketch_plan_destroy")
 
@@ -120,6 +122,8 @@ def lib() -> ctypes.CDLL:
             "sketch_set_option": (c_i32, [c_vp, c_i32, ctypes.c_int64]),
             "sketch_update_batch": (c_i32, [c_vp, c_sz, c_vp]),
             "sketch_restore_batch": (c_i32, [c_vp, c_sz, c_vp]),
+            "sketch_restore_batch_begin": (c_i32, [c_vp, c_sz, c_vp]),
+            "sketch_restore_batch_end": (c_i32, [c_vp, c_sz, c_vp]),
             "sketch_merge": (c_i32, [c_vp, c_vp, c_vp]),
             "sketch_plan_create": (c_i32, [c_vp, c_sz, c_i32, P(c_vp)]),
             "sketch_plan_run": (c_i32, [c_vp, c_vp]),
@@ -205,28 +209,57 @@ def sketch_restore(h: int, theta: float, cap: int, stream: int = 0):
     return out[: n.value].copy(), info_dict(info)
 
 
+class _RestoreJobs:
+    """A job array for the batched restore calls and the host buffers its
+    entries point at (kept alive together)."""
+
+    def __init__(self, items):
+        self.n = len(items)
+        self.arr = (sketch_restore_job_t * max(1, self.n))()
+        self.outs, self.infos = [], []
+        for i, (h, theta, cap) in enumerate(items):
+            out = np.empty(max(cap, 1), dtype=SP_DTYPE)   # the first n are written
+            info = sketch_info_t()
+            self.outs.append(out)
+            self.infos.append(info)
+            self.arr[i] = sketch_restore_job_t(h, float(theta), out.ctypes.data, cap,
+                                               ctypes.addressof(info), 0, 0)
+
+    def call(self, fn, stream: int) -> None:
+        rc = fn(ctypes.cast(self.arr, c_vp), self.n, stream)
+        if rc == SKETCH_E_INVAL and all(self.arr[i].status == 0 for i in range(self.n)):
+            raise SketchError(rc, last_error())
+
+    def results(self):
+        res = []
+        for i in range(self.n):
+            st = self.arr[i].status
+            recs = self.outs[i][: self.arr[i].n_out].copy() if st == SKETCH_OK \
+                else self.outs[i][:0].copy()
+            res.append((recs, info_dict(self.infos[i]), st, self.arr[i].n_out))
+        return res
+
+
 def sketch_restore_batch(items, stream: int = 0):
     """items: sequence of (handle, theta, cap). Returns a list of
     (records, info, status, n_needed) per item, in order."""
-    n = len(items)
-    arr = (sketch_restore_job_t * max(1, n))()
-    outs, infos = [], []
-    for i, (h, theta, cap) in enumerate(items):
-        out = np.empty(max(cap, 1), dtype=SP_DTYPE)       # the first n are written
-        info = sketch_info_t()
-        outs.append(out)
-        infos.append(info)
-        arr[i] = sketch_restore_job_t(h, float(theta), out.ctypes.data, cap,
-                                      ctypes.addressof(info), 0, 0)
-    rc = lib().sketch_restore_batch(ctypes.cast(arr, c_vp), n, stream)
-    if rc == SKETCH_E_INVAL and all(arr[i].status == 0 for i in range(n)):
-        raise SketchError(rc, last_error())
-    res = []
-    for i in range(n):
-        st = arr[i].status
-        recs = outs[i][: arr[i].n_out].copy() if st == SKETCH_OK else outs[i][:0].copy()
-        res.append((recs, info_dict(infos[i]), st, arr[i].n_out))
-    return res
+    jobs = _RestoreJobs(items)
+    jobs.call(lib().sketch_restore_batch, stream)
+    return jobs.results()
+
+
+def sketch_restore_batch_begin(items, stream: int = 0) -> _RestoreJobs:
+    """items: sequence of (handle, theta, cap). Enqueues the restores and
+    returns the pending jobs for sketch_restore_batch_end."""
+    jobs = _RestoreJobs(items)
+    jobs.call(lib().sketch_restore_batch_begin, stream)
+    return jobs
+
+
+def sketch_restore_batch_end(jobs: _RestoreJobs, stream: int = 0):
+    """Waits for the pending restores; results as sketch_restore_batch."""
+    jobs.call(lib().sketch_restore_batch_end, stream)
+    return jobs.results()
 
 
 def sketch_plan_create(jobs, flags: int) -> int:
@@ -342,6 +375,12 @@ def restore_batch(items, stream=None, raise_errors: bool = True):
     dev = items[0][0].device
     s = _stream_handle(stream, dev)
     res = sketch_restore_batch([(sk.handle, th, sk._cap) for sk, th in items], s)
+    return _collect(items, res, stream, raise_errors)
+
+
+def _collect(items, res, stream, raise_errors):
+    """Per-item results of a batched restore; CAPACITY jobs run again in a
+    second (synchronous) batch with room for their lists."""
     out = [None] * len(items)
     retry = []
     for i, ((sk, th), (recs, info, st, need)) in enumerate(zip(items, res)):
@@ -360,6 +399,33 @@ def restore_batch(items, stream=None, raise_errors: bool = True):
         for i, r in zip(retry, again):
             out[i] = r
     return out
+
+
+class PendingRestore:
+    """Restores enqueued by restore_batch_begin; end() collects them."""
+
+    def __init__(self, items, stream=None):
+        self.items = list(items)
+        self.dev = self.items[0][0].device if self.items else None
+        self.stream = stream
+        self.jobs = None
+        if self.items:
+            self.jobs = sketch_restore_batch_begin(
+                [(sk.handle, th, sk._cap) for sk, th in self.items],
+                _stream_handle(stream, self.dev))
+
+    def end(self, raise_errors: bool = True):
+        """[(records, info)] in item order, as restore_batch returns them."""
+        if not self.items:
+            return []
+        res = sketch_restore_batch_end(self.jobs, _stream_handle(self.stream, self.dev))
+        return _collect(self.items, res, self.stream, raise_errors)
+
+
+def restore_batch_begin(items, stream=None) -> PendingRestore:
+    """items: sequence of (Sketch, theta). Enqueues one batched restore on
+    the stream and returns without waiting (sketch_restore_batch_begin)."""
+    return PendingRestore(items, stream)
 
 
 class Plan:

@@ -6,13 +6,16 @@ already in device memory; the response is the window's super point list
 the device, sized for its windows by the sizing rule (smallest k >= 14 with
 n / (g 2^k) <= 0.45 and alpha = ceil((32 - k) / (r - 2)) <= k).
 
-ContinuousServer batches continuously: every loop iteration admits all
-requests that have arrived, one per link and as long as the resident
-sketches fit the HBM budget, and runs their updates as one batched update
-and their restores as one batched restore. Requests that arrive while a
-batch is on the GPU wait for the next iteration, so the batch size follows
-the load. PlainServer handles one request at a time in arrival order (the
-per-window launch). Both report every request's close-to-report latency.
+ContinuousServer batches continuously and keeps two batches on the GPU:
+each loop iteration admits the requests that have arrived (one per link,
+links with a batch still on the GPU wait, and only while the resident
+sketches fit the HBM budget), enqueues their updates as one batched update
+and their restores as one batched restore on one of two streams of equal
+priority, and only then waits for the older batch's restores. So a batch's
+update runs on the device while the batch before it restores, and requests
+that arrive meanwhile are admitted as soon as a slot frees. PlainServer
+handles one request at a time in arrival order (the per-window launch).
+Both report every request's close-to-report latency.
 
 The scheduling is host code over the batched C ABI; every step of the
 update and the restore runs in the HIP library.
@@ -179,52 +182,109 @@ class _Server:
 
 
 class ContinuousServer(_Server):
-    """Continuous batching: see the module docstring."""
+    """Continuous batching with two batches in flight: see the module
+    docstring. With trace=True every batch records timing events on its
+    stream (update start and end, restore end) in self.trace."""
 
     def __init__(self, budget_bytes: int = 64 << 30, g: int = 1024, r: int = 5,
-                 device: int = 0, max_batch: int = 64):
+                 device: int = 0, max_batch: int = 64, depth: int = 2, trace: bool = False):
         super().__init__(budget_bytes, g, r, device)
         self.max_batch = max_batch
+        self.depth = max(1, depth)
+        # streams of the default priority, one per batch in flight
+        self.streams = [torch.cuda.Stream(self.dev) for _ in range(self.depth)]
+        self.trace_on = trace
+        self.trace = []
+
+    def _event(self, stream):
+        if not self.trace_on:
+            return None
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
+
+    def _admit(self, waiting, busy: set):
+        """Requests of the next batch, in arrival order: one per link, none
+        for a link with a batch in flight, within the budget (bytes of new
+        sketches promised to the batch count, and the sketches of batches in
+        flight are never evicted)."""
+        batch, links, pending = [], set(), 0
+        for q in waiting:
+            if len(batch) == self.max_batch:
+                break
+            if q.link in links or q.link in busy:
+                continue
+            need = self.links.need(q.link, q.n_pairs)
+            if not self.links.fits(need, links | busy | {q.link}, pending):
+                continue
+            batch.append(q)
+            links.add(q.link)
+            pending += need
+        if not batch and not busy:     # the oldest request alone may evict anything
+            batch = [waiting[0]]
+        return batch
 
     def serve(self, requests) -> list:
         reqs = sorted(requests, key=lambda q: q.arrival)
         out, waiting, nxt = [], [], 0
+        inflight = []         # (batch, PendingRestore, done event, trace events), oldest first
+        k = 0
         t0 = time.perf_counter()
-        while nxt < len(reqs) or waiting:
+        base = self._event(self.streams[0])
+        while nxt < len(reqs) or waiting or inflight:
             now = time.perf_counter() - t0
             while nxt < len(reqs) and reqs[nxt].arrival <= now:
                 waiting.append(reqs[nxt])
                 nxt += 1
-            if not waiting:
-                self._wait_until(t0, reqs[nxt].arrival)
+            busy = {q.link for b, _, _, _ in inflight for q in b}
+            batch = self._admit(waiting, busy) if waiting and len(inflight) < self.depth else []
+            if batch:
+                taken = {id(q) for q in batch}
+                waiting = [q for q in waiting if id(q) not in taken]
+                busy |= {q.link for q in batch}
+                sks = [self.links.get(q.link, q.n_pairs, busy) for q in batch]
+                st = self.streams[k % self.depth]
+                k += 1
+                e0 = self._event(st)
+                for sk in sks:
+                    sk.reset(st)
+                ddhf.update_batch([(sk, q.pairs) for sk, q in zip(sks, batch)], st)
+                e1 = self._event(st)
+                pend = ddhf.restore_batch_begin([(sk, q.theta) for sk, q in zip(sks, batch)], st)
+                done_ev = torch.cuda.Event()
+                done_ev.record(st)
+                inflight.append((batch, pend, done_ev, (e0, e1, self._event(st))))
+                continue               # admit more while this batch is on the GPU
+            if inflight:
+                # collect the oldest batch once it is done, or at once when no
+                # other batch can start before it is (every slot taken, or no
+                # request left to come); else look again shortly for arrivals
+                if (len(inflight) == self.depth or nxt == len(reqs)
+                        or inflight[0][2].query()):
+                    b, pend, _, ev = inflight.pop(0)
+                    res = pend.end(raise_errors=False)
+                    done = time.perf_counter() - t0
+                    for q, (recs, info) in zip(b, res):
+                        out.append(_response(q, recs, info, done, len(b)))
+                    if self.trace_on:
+                        self.trace.append((base, ev, len(b)))
+                else:
+                    time.sleep(2e-5)
                 continue
-            # admit in arrival order: one request per link, within the budget
-            batch, links, pending = [], set(), 0
-            for q in waiting:
-                if len(batch) == self.max_batch:
-                    break
-                if q.link in links:
-                    continue
-                need = self.links.need(q.link, q.n_pairs)
-                if not self.links.fits(need, links | {q.link}, pending):
-                    continue
-                batch.append(q)
-                links.add(q.link)
-                pending += need
-            if not batch:          # the oldest request alone may evict anything
-                batch, links = [waiting[0]], {waiting[0].link}
-            taken = {id(q) for q in batch}
-            waiting = [q for q in waiting if id(q) not in taken]
-            sks = [self.links.get(q.link, q.n_pairs, links) for q in batch]
-            for sk in sks:
-                sk.reset()
-            ddhf.update_batch([(sk, q.pairs) for sk, q in zip(sks, batch)])
-            res = ddhf.restore_batch([(sk, q.theta) for sk, q in zip(sks, batch)],
-                                     raise_errors=False)
-            done = time.perf_counter() - t0
-            for q, (recs, info) in zip(batch, res):
-                out.append(_response(q, recs, info, done, len(batch)))
+            if nxt < len(reqs):
+                self._wait_until(t0, reqs[nxt].arrival)
         return sorted(out, key=lambda r: r.rid)
+
+    def overlaps(self) -> int:
+        """Batches whose update had finished on the device before the
+        previous batch's restore had (from the trace's timing events): the
+        update of one batch ran while an earlier batch restored."""
+        torch.cuda.synchronize(self.dev)
+        n = 0
+        for (base, ev, _), (_, prev, _) in zip(self.trace[1:], self.trace[:-1]):
+            if base.elapsed_time(ev[1]) < base.elapsed_time(prev[2]):
+                n += 1
+        return n
 
 
 class PlainServer(_Server):

@@ -502,7 +502,7 @@ def test_config2_large_window_full_size():
         f"he={info['he_count'][:5]}, partials={info['n_partials'][:5]}")
 
 
-@pytest.mark.parametrize("window", [0, 59])
+@pytest.mark.parametrize("window", [0, 29, 59])
 def test_config3_stream_window_full_size(window):
     """Windows of the sustained 117M-pair stream, with a reset between."""
     spec = T.spec_stream_window(window)

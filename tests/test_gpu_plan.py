@@ -113,3 +113,62 @@ def test_plan_update_in_rounds_and_without_restore():
             with pytest.raises(ddhf.SketchError) as e:
                 plan.results()
             assert e.value.code == ddhf.SKETCH_E_INVAL
+
+
+# The 64-link batch's shape at reduced sizes: link windows from the same
+# generator (Zipf sources over n/25 hosts, planted log-uniform in
+# [1024, 50000]), exponents across [0.8, 1.3], theta 512 and 1024, one
+# k = 19 sketch (2560 tiles: the scatter's 3072-tile variant for the whole
+# launch group) next to k = 14..15 ones, autotuned update options.
+LINKS = [  # (n_pairs, zipf_s, planted, theta, forced (k, alpha) or None)
+    (2_000_000, 0.80, 10, 512.0, None),
+    (9_000_000, 0.85, 200, 512.0, None),
+    (4_000_000, 1.30, 500, 1024.0, None),
+    (12_000_000, 1.00, 50, 1024.0, (19, 5)),
+    (1_000_000, 1.10, 30, 1024.0, None),
+    (6_000_000, 0.90, 100, 512.0, (18, 5)),
+]
+
+
+def test_link_batch_shape_plan_equals_oracle_per_link():
+    from paper_1803_11449_amd import serving, traffic, tune
+    links, refs = [], []
+    for i, (n, s, m, theta, forced) in enumerate(LINKS):
+        key = traffic.config_seed(4, 1000 + i)
+        spec = traffic.spec_link_window(n, s, m, key)
+        w = traffic.generate(spec, key, device=DEV)
+        k, alpha = forced or serving.sized_params(n, k_max=19)
+        p = oracle.Params(1024, k, 5, alpha, traffic.HASH_SEED)
+        say(f"link {i}: n={n} s={s} planted={len(spec.planted_card)} theta={theta:g} k={k}")
+        hp = w.pairs.cpu().numpy().view(np.uint32)
+        refs.append(oracle.restore(p, oracle.build_sketch(p, hp), theta, mode="brute"))
+        links.append((p, w.pairs, theta))
+    sks = []
+    tuned = {}
+    try:
+        for p, pairs, theta in links:
+            sk = make_sketch(p)
+            tk = (p.k, tune.size_class(pairs.shape[0]))
+            if tk not in tuned:
+                tuned[tk] = tune.tune(p.g, p.k, p.r, p.alpha, pairs, p.seed, trials=1,
+                                      use_cache=False)
+            tune.apply(sk, tuned[tk])
+            sks.append(sk)
+        items = [(sk, pairs, theta) for sk, (_, pairs, theta) in zip(sks, links)]
+        with ddhf.Plan(items) as plan:
+            for rep in range(2):
+                say(f"link plan run {rep}")
+                plan.run()
+                for i, ((recs, info), (ip, sz, c, _)) in enumerate(zip(plan.results(), refs)):
+                    assert len(ip) > 0, i
+                    assert_spl_equal(recs, ip, sz, c)
+        say("link batch, eager")
+        for sk in sks:
+            sk.reset()
+        ddhf.update_batch([(sk, pairs) for sk, pairs, _ in items])
+        for (recs, _), (ip, sz, c, _) in zip(
+                ddhf.restore_batch([(sk, th) for sk, _, th in items]), refs):
+            assert_spl_equal(recs, ip, sz, c)
+    finally:
+        for sk in sks:
+            sk.close()

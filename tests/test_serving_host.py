@@ -45,7 +45,7 @@ class FakeSketch:
         self.k, self.closed = k, False
         FakeSketch.live.add(id(self))
 
-    def reset(self):
+    def reset(self, stream=None):
         assert not self.closed
 
     def close(self):
@@ -54,25 +54,65 @@ class FakeSketch:
         FakeSketch.live.discard(id(self))
 
 
+class Batches(list):
+    """The batches the server formed, in order (and the peak number of
+    sketches with a restore in flight, as .peak[0])."""
+
+
+class FakeEvent:
+    """Stands in for torch.cuda.Event: the work before it is always done."""
+
+    def __init__(self, enable_timing=False):
+        pass
+
+    def record(self, stream=None):
+        pass
+
+    def query(self):
+        return True
+
+
 @pytest.fixture
 def fake_lib(monkeypatch):
     FakeSketch.live = set()
-    batches = []
+    batches = Batches()
+    inflight = set()          # ids of sketches with a restore begun, not ended
+    peak = [0]
 
-    def update_batch(items):
+    def update_batch(items, stream=None):
         assert all(not sk.closed for sk, _ in items)
+        # a sketch is never updated while its last restore is in flight
+        assert not inflight & {id(sk) for sk, _ in items}
         batches.append([sk for sk, _ in items])
 
-    def restore_batch(items, raise_errors=True):
+    def restore_batch(items, stream=None, raise_errors=True):
         assert not raise_errors
         assert [sk for sk, _ in items] == batches[-1]
         return [(np.zeros(0, dtype=ddhf.SP_DTYPE), {"status": ddhf.SKETCH_OK})] * len(items)
+
+    class Pending:
+        def __init__(self, items, stream=None):
+            assert [sk for sk, _ in items] == batches[-1]
+            self.items = items
+            inflight.update(id(sk) for sk, _ in items)
+            peak[0] = max(peak[0], len(inflight))
+
+        def end(self, raise_errors=True):
+            assert not raise_errors
+            for sk, _ in self.items:
+                inflight.discard(id(sk))
+            return [(np.zeros(0, dtype=ddhf.SP_DTYPE), {"status": ddhf.SKETCH_OK})] * \
+                len(self.items)
 
     monkeypatch.setattr(ddhf, "Sketch", FakeSketch)
     monkeypatch.setattr(FakeSketch, "update", lambda sk, pairs: update_batch([(sk, pairs)]),
                         raising=False)
     monkeypatch.setattr(ddhf, "update_batch", update_batch)
     monkeypatch.setattr(ddhf, "restore_batch", restore_batch)
+    monkeypatch.setattr(ddhf, "restore_batch_begin", Pending)
+    monkeypatch.setattr(serving.torch.cuda, "Stream", lambda device=None: object())
+    monkeypatch.setattr(serving.torch.cuda, "Event", FakeEvent)
+    batches.peak = peak
     return batches
 
 
@@ -162,6 +202,22 @@ def test_a_window_larger_than_the_budget_is_refused(fake_lib):
     with serving.ContinuousServer(one_link_bytes() // 2) as srv:
         with pytest.raises(MemoryError):
             srv.serve(reqs)
+
+
+def test_two_batches_in_flight_never_share_a_link(fake_lib, monkeypatch):
+    """With two batches in flight, the second is formed from links the
+    first does not use, and a link waits until its batch is collected."""
+    # completion events say "not done" until the batch was collected, so the
+    # server must keep the first batch in flight while it forms the second
+    monkeypatch.setattr(FakeEvent, "query", lambda self: False)
+    reqs = requests(30, 6)
+    with serving.ContinuousServer(100 * one_link_bytes(), max_batch=2) as srv:
+        out = srv.serve(reqs)
+    assert [r.rid for r in out] == list(range(30))
+    # two batches of two sketches were in flight at once; the stand-in
+    # update asserts that no batch touched a sketch whose restore was
+    # still in flight
+    assert fake_lib.peak[0] == 4
 
 
 def test_plain_server_serves_one_at_a_time(fake_lib):

@@ -78,37 +78,54 @@ def cpu_threads() -> int:
     return max(1, min(n, 16))
 
 
-def run_cpu_baseline(pairs_host, p, theta, n_sample):
-    """The oracle as it is: Alg. 1 single-threaded over a sample of the
-    window, then its restore (the candidate set by scanning all 2^32
-    addresses on `threads` threads, eq. (4) estimates) on the sample's
-    sketch. Rate = sample pairs / (update + restore) time."""
+def cpu_baseline_leg(pairs, shape, theta, n_sample, threads):
+    """The oracle as it stands on the host, over the first n_sample pairs
+    of the window (pairs: int32 [n, 2] tensor on the device):
+      update      Alg. 1, sequential loop, 1 thread
+      update_omp  the same on `threads` threads (atomic OR after the test)
+      restore     candidates by scanning all 2^32 addresses on `threads`
+                  threads, eq. (4) estimates
+    value = sample pairs / (update_omp + restore) seconds, the whole job on
+    `threads` host threads (cores)."""
+    import numpy as np
     import oracle
-    threads = cpu_threads()
-    sample = pairs_host[: 2 * n_sample]
+    from paper_1803_11449_amd import traffic
+    host = pairs[:n_sample].cpu().numpy().view(np.uint32).reshape(-1)
+    g, k, r, alpha = shape
+    p = oracle.Params(g, k, r, alpha, traffic.HASH_SEED)
     t0 = time.perf_counter()
-    sk = oracle.build_sketch(p, sample)
+    sk1 = oracle.build_sketch(p, host)
     t1 = time.perf_counter()
+    skn = oracle.update_omp(p, oracle.new_sketch(p), host, nthreads=threads)
+    t2 = time.perf_counter()
+    same = bool(np.array_equal(sk1, skn))
+    del sk1
     try:
-        oracle.restore(p, sk, theta, mode="brute", nthreads=threads)
+        oracle.restore(p, skn, theta, mode="brute", nthreads=threads)
     except oracle.OracleError:
         pass
-    t2 = time.perf_counter()
+    t3 = time.perf_counter()
     return {
-        "value": n_sample / (t2 - t0) / 1e6, "unit": "Mpps", "cores": threads,
-        "kind": "oracle",
-        "sample": (f"first {n_sample} pairs of the same window; update "
-                   f"{t1 - t0:.2f} s on 1 thread ({n_sample / (t1 - t0) / 1e6:.1f} Mpps), "
-                   f"restore by 2^32 scan {t2 - t1:.2f} s on {threads} threads"),
-        "update_s": t1 - t0, "restore_s": t2 - t1,
+        "value": round(n_sample / ((t2 - t1) + (t3 - t2)) / 1e6, 3), "unit": "Mpps",
+        "cores": threads, "kind": "oracle",
+        "sample": (f"first {n_sample} pairs of the same window: Alg. 1 on {threads} threads "
+                   f"{t2 - t1:.2f} s, restore by 2^32 scan on {threads} threads {t3 - t2:.2f} s; "
+                   f"Alg. 1 on 1 thread {t1 - t0:.2f} s"),
+        "legs": {"update_1thread": {"threads": 1, "s": round(t1 - t0, 3),
+                                    "mpps": round(n_sample / (t1 - t0) / 1e6, 2)},
+                 "update_omp": {"threads": threads, "s": round(t2 - t1, 3),
+                                "mpps": round(n_sample / (t2 - t1) / 1e6, 2),
+                                "same_sketch_as_1thread": same},
+                 "restore_2to32_scan": {"threads": threads, "s": round(t3 - t2, 3)}},
     }
 
 
-def atomic_ceiling(ddhf, traffic, pairs, shape, stream, update_mpps):
-    """The atomic side of the update's roofline, measured on the same window:
-    the direct kernel with its bit test off issues exactly one global
-    atomicOr per (pair, row), so its rate is the random-atomic ceiling
-    (atomicOr rate / r) for this sketch in this cache state."""
+def direct_kernel_rate(ddhf, traffic, pairs, shape, stream):
+    """The direct update kernel with its bit test off issues exactly one
+    global atomicOr per (pair, row): its rate on this window is the random
+    global-atomic throughput of the chip for this sketch size. It is a
+    measured reference, not a ceiling of the binned update, which moves
+    every bit set into LDS."""
     import torch
     g, k, r, alpha = shape
     sk = ddhf.Sketch(g, k, r, alpha, traffic.HASH_SEED, device=0)
@@ -127,69 +144,59 @@ def atomic_ceiling(ddhf, traffic, pairs, shape, stream, update_mpps):
             ms.append(a.elapsed_time(b))
     sk.close()
     n = pairs.shape[0]
-    ceiling = n / (sorted(ms)[len(ms) // 2] / 1e3) / 1e6
-    return {"kind": "one global atomicOr per (pair, row): direct kernel, bit test off",
-            "atomics_per_s": round(ceiling * 1e6 * r, 1), "ceiling_mpps": round(ceiling, 2),
-            "achieved_mpps": round(update_mpps, 2), "ratio": round(update_mpps / ceiling, 3)}
+    rate = n / (sorted(ms)[len(ms) // 2] / 1e3) / 1e6
+    return {"kind": "direct kernel, one global atomicOr per (pair, row), bit test off",
+            "atomics_per_s": round(rate * 1e6 * r, 1), "mpps": round(rate, 2)}
 
 
-def cpu_baseline_leg(pairs, shape, theta, n_sample):
-    """The cpu_baseline object of the JSON line: the oracle on the host over
-    the first n_sample pairs of the window (pairs: int32 [n, 2] tensor)."""
-    import numpy as np
-    import oracle
-    from paper_1803_11449_amd import traffic
-    host = pairs.cpu().numpy().view(np.uint32).reshape(-1)
-    g, k, r, alpha = shape
-    cb = run_cpu_baseline(host, oracle.Params(g, k, r, alpha, traffic.HASH_SEED), theta,
-                          n_sample)
-    return {kk: (round(v, 3) if isinstance(v, float) else v) for kk, v in cb.items()}
+# LDS of one compute unit: 32 banks of 4 bytes, one access per bank per
+# clock (a wave's 64 lanes in two halves), at the 2.4 GHz peak clock
+LDS_LANE_OPS_PEAK = 256 * 32 * 2.4e9
+# LDS lane operations per join output and per probe, counted in k_join:
+# per probe the two bucket-offset reads; per output slot the owner write and
+# read, three ds_bpermute, the entry's top-bits read and the append counter
+JOIN_LDS_OPS_PER_OUTPUT = 6
+JOIN_LDS_OPS_PER_PROBE = 2
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--pairs", type=int, default=100_000_000)
-    ap.add_argument("--theta", type=float, default=1024.0)
-    ap.add_argument("--cpu-sample", type=int, default=100_000_000,
-                    help="pairs of the window the oracle baseline processes")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--update-path", type=int, default=0, choices=(0, 1, 2),
-                    help="0 = library's choice by size, 1 = direct, 2 = binned")
-    ap.add_argument("--workload", default="large_window_100m",
-                    choices=("large_window_100m", "batched_64_links", "serving_256_links"),
-                    help="large_window_100m (default, the headline); batched_64_links: 64 "
-                         "links of uneven windows in one batched launch vs one launch per "
-                         "window; serving_256_links: Poisson window closes from 256 links, "
-                         "continuous batching vs one window at a time")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="also run one plain device copy of this many MiB "
-                         "(for scaling HBM counters)")
-    args = ap.parse_args()
+def restore_roofline(timings: list) -> dict:
+    """Restore-side rooflines from the phase timings of the latency runs
+    (median of each phase): the hot scan against HBM bandwidth, the join's
+    LDS lane operations against the LDS peak, the estimate's LE gathers
+    against HBM bandwidth."""
+    med = {k: percentile([t[k] for t in timings], 50) for k in timings[0]}
+    hs = med["hot_scan_bytes"] / (med["hot_scan_ms"] / 1e3) / 1e9
+    lds_ops = (JOIN_LDS_OPS_PER_OUTPUT * med["join_outputs"] +
+               JOIN_LDS_OPS_PER_PROBE * med["join_probes"])
+    jr = lds_ops / (med["join_ms"] / 1e3)
+    eg = med["estimate_bytes"] / (med["estimate_ms"] / 1e3) / 1e9
+    return {
+        "phase_ms": {k: round(med[k], 4) for k in ("hot_scan_ms", "rows_ms", "join_ms",
+                                                     "estimate_ms", "sort_publish_ms")},
+        "hot_scan": {"bound": "hbm", "bytes": int(med["hot_scan_bytes"]),
+                     "achieved": round(hs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(hs / HBM_PEAK_GBS, 5)},
+        "join": {"bound": "lds", "probes": int(med["join_probes"]),
+                 "outputs": int(med["join_outputs"]),
+                 "probes_per_s": round(med["join_probes"] / (med["join_ms"] / 1e3), 1),
+                 "achieved": round(jr / 1e12, 4), "peak": round(LDS_LANE_OPS_PEAK / 1e12, 2),
+                 "unit": "T LDS lane-ops/s", "frac": round(jr / LDS_LANE_OPS_PEAK, 5)},
+        "estimate": {"bound": "hbm", "bytes": int(med["estimate_bytes"]),
+                     "achieved": round(eg, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(eg / HBM_PEAK_GBS, 5)},
+    }
 
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sketch would shard by an OR all-reduce, not built here).",
-              file=sys.stderr)
-        sys.exit(2)
 
-    import numpy as np
+def headline(args, dev) -> dict:
+    """The 100M-pair window: timed steps, update events, restore latency
+    with phase timings, rooflines, the direct kernel's atomic rate and the
+    CPU baseline. Returns the JSON line's fields."""
     import torch
-
     from paper_1803_11449_amd import ddhf, traffic
-
-    if args.workload == "batched_64_links":
-        return run_batched(args)
-    if args.workload == "serving_256_links":
-        return run_serving(args)
-
-    dev = torch.device("cuda:0")
     spec = traffic.spec_large_window_100m(args.pairs)
     k, alpha = sized_k(spec.n_pairs)
     g, r = 1024, 5
-    print(f"bench: generating {spec.n_pairs} pairs on {dev}", file=sys.stderr, flush=True)
+    log(f"generating {spec.n_pairs} pairs on {dev}")
     w = traffic.generate(spec, traffic.config_seed(2), device=dev)
     pairs = w.pairs
     torch.cuda.synchronize()
@@ -227,38 +234,40 @@ def main():
 
     def latency_step(record):
         """Window close to report: the restore alone, timed from the moment
-        every pair of the window is in the sketch."""
+        every pair of the window is in the sketch (its phases timed by the
+        library's events)."""
         sk.reset()
         sk.update(pairs)
         torch.cuda.synchronize()
         t_close = time.perf_counter()
         sk.restore(args.theta)
         record["restore_ms"].append((time.perf_counter() - t_close) * 1e3)
+        record["phases"].append(ddhf.sketch_timings(sk.handle))
 
-    print("bench: warmup", file=sys.stderr, flush=True)
+    log("warmup")
     for _ in range(args.warmup):
         step()
-    rec = {"events": [], "restore_ms": []}
+    rec = {"events": [], "restore_ms": [], "phases": []}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step(rec)
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
-    print(f"bench: {args.steps} steps in {total:.3f} s", file=sys.stderr, flush=True)
+    log(f"{args.steps} steps in {total:.3f} s")
     rec["update_ms"] = [a.elapsed_time(b) for a, b in rec["events"]]
-    for _ in range(max(5, min(args.steps, 20))):
+    sk.set_option(ddhf.SKETCH_OPT_TIMING, 1)
+    for _ in range(max(20, min(args.steps, 50))):
         latency_step(rec)
+    sk.set_option(ddhf.SKETCH_OPT_TIMING, 0)
 
     ms_per_step = total / args.steps * 1e3
     upd_ms = percentile(rec["update_ms"], 50)
     upd_mean = sum(rec["update_ms"]) / len(rec["update_ms"])
     update_mpps = n / (upd_mean / 1e3) / 1e6
-    alg_bytes = n * PAIR_BYTES
-    achieved = alg_bytes / (upd_mean / 1e3) / 1e9
+    achieved = n * PAIR_BYTES / (upd_mean / 1e3) / 1e9
     info = rec["info"]
     hbm_traffic = measured_update_traffic() if n == 100_000_000 else None
-
     out = {
         "metric": METRIC,
         "value": round(n * args.steps / total / 1e6, 3),
@@ -283,6 +292,7 @@ def main():
         "restore_ms_p99": round(percentile(rec["restore_ms"], 99), 4),
         "latency_ms_p50": round(percentile(rec["restore_ms"], 50), 4),
         "latency_ms_p99": round(percentile(rec["restore_ms"], 99), 4),
+        "latency_samples": len(rec["restore_ms"]),
         "super_points": rec["n_sp"],
         "candidates": info["n_candidates"],
         "he_count": info["he_count"][:r],
@@ -294,26 +304,169 @@ def main():
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": hbm_traffic},
+        "restore_roofline": restore_roofline(rec["phases"]),
     }
     if hbm_traffic:
         out["roofline"]["traffic_gbs"] = round(hbm_traffic / (upd_mean / 1e3) / 1e9, 1)
-    out["atomic_roofline"] = atomic_ceiling(ddhf, traffic, pairs, (g, k, r, alpha), stream,
-                                            update_mpps)
-    if not args.no_cpu_baseline:
-        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline_leg(pairs, (g, k, r, alpha), args.theta,
-                                               min(args.cpu_sample, n))
+    out["direct_kernel_atomics"] = direct_kernel_rate(ddhf, traffic, pairs, (g, k, r, alpha),
+                                                      stream)
     sk.close()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline_leg(pairs, (g, k, r, alpha), args.theta,
+                                               min(args.cpu_sample, n), cpu_threads())
+    del pairs, w
+    torch.cuda.empty_cache()
+    return out
+
+
+def config1_run(args, dev) -> dict:
+    """The 1M-pair single window on the default sketch: update rate (HIP
+    events, median of 30), restore latency (window close to list on the
+    host) and whole steps."""
+    import torch
+    from paper_1803_11449_amd import ddhf, traffic
+    w = traffic.generate(traffic.spec_single_window_1m(), traffic.config_seed(1), device=dev)
+    stream = torch.cuda.current_stream(dev)
+    n = w.pairs.shape[0]
+    upd, lat = [], []
+    with ddhf.Sketch(1024, 14, 5, 6, traffic.HASH_SEED, device=0) as sk:
+        for i in range(33):
+            sk.reset()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            sk.update(w.pairs)
+            b.record(stream)
+            b.synchronize()
+            t = time.perf_counter()
+            recs, _ = sk.restore(1024.0)
+            if i >= 3:
+                upd.append(a.elapsed_time(b))
+                lat.append((time.perf_counter() - t) * 1e3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(30):
+            sk.reset()
+            sk.update(w.pairs)
+            sk.restore(1024.0)
+        step = (time.perf_counter() - t0) / 30
+    return {"workload": "single_window_1m", "n_pairs": n, "g": 1024, "k": 14, "r": 5,
+            "alpha": 6, "theta": 1024.0,
+            "update_ms_p50": round(percentile(upd, 50), 4),
+            "update_mpps": round(n / (percentile(upd, 50) / 1e3) / 1e6, 1),
+            "restore_ms_p50": round(percentile(lat, 50), 4),
+            "restore_ms_p99": round(percentile(lat, 99), 4),
+            "step_ms": round(step * 1e3, 4), "step_mpps": round(n / step / 1e6, 1),
+            "super_points": len(recs)}
+
+
+def stream_run(args, dev) -> dict:
+    """The sustained stream: consecutive windows of 117M pairs (Zipf(1.0)
+    over 8M sources, 1000 planted with 20% replaced each window), each
+    generated on the device from its own seed before timing, then processed
+    back to back on one k = 18 sketch: reset, update, restore with the list
+    on the host. Sustained rate against the 117 Mpps line rate (750 Gb/s at
+    800-byte packets)."""
+    import torch
+    from paper_1803_11449_amd import ddhf, traffic
+    nw = args.stream_windows
+    wins = []
+    t0 = time.perf_counter()
+    for i in range(nw):
+        wins.append(traffic.generate(traffic.spec_stream_window(i), traffic.config_seed(3, i),
+                                     device=dev).pairs)
+        if i % 10 == 9 or i == nw - 1:
+            torch.cuda.synchronize()
+            log(f"stream: {i + 1} of {nw} windows generated ({time.perf_counter() - t0:.1f} s)")
+    n = wins[0].shape[0]
+    k, alpha = sized_k(n)
+    sps = []
+    with ddhf.Sketch(1024, k, 5, alpha, traffic.HASH_SEED, device=0) as sk:
+        for p in wins[:2]:                                  # warm up
+            sk.reset()
+            sk.update(p)
+            sk.restore(1024.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for p in wins:
+            sk.reset()
+            sk.update(p)
+            recs, _ = sk.restore(1024.0)
+            sps.append(len(recs))
+        dt = time.perf_counter() - t0
+    del wins
+    torch.cuda.empty_cache()
+    total = n * nw
+    return {"workload": "stream_117m_windows", "windows": nw, "pairs_per_window": n,
+            "k": k, "alpha": alpha, "theta": 1024.0,
+            "sustained_mpps": round(total / dt / 1e6, 1),
+            "line_rate_mpps": 117.0,
+            "x_line_rate": round(total / dt / 1e6 / 117.0, 1),
+            "ms_per_window": round(dt / nw * 1e3, 4),
+            "super_points_mean": round(sum(sps) / len(sps), 1)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--pairs", type=int, default=100_000_000)
+    ap.add_argument("--theta", type=float, default=1024.0)
+    ap.add_argument("--cpu-sample", type=int, default=100_000_000,
+                    help="pairs of the window the oracle baseline processes")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--update-path", type=int, default=0, choices=(0, 1, 2),
+                    help="0 = library's choice by size, 1 = direct, 2 = binned")
+    ap.add_argument("--workload", default="large_window_100m",
+                    choices=("large_window_100m", "batched_64_links", "serving_256_links"),
+                    help="large_window_100m (default, the headline); batched_64_links: 64 "
+                         "links of uneven windows in one batched launch vs one launch per "
+                         "window; serving_256_links: Poisson window closes from 256 links, "
+                         "continuous batching vs one window at a time")
+    ap.add_argument("--extras", default="config1,stream,batched,serving",
+                    help="sub-objects of the default line (comma list; empty for none)")
+    ap.add_argument("--stream-windows", type=int, default=60)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run one plain device copy of this many MiB "
+                         "(for scaling HBM counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sketch would shard by an OR all-reduce, not built here).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    dev = torch.device("cuda:0")
+    if args.workload == "batched_64_links":
+        b = batched_run(args, dev)
+        return _line(b.pop("plan_mpps"), b.pop("steps"), args.warmup, b.pop("plan_ms_per_step"),
+                     b.pop("config"), b)
+    if args.workload == "serving_256_links":
+        s = serving_run(args, dev)
+        ov = s["runs"]["overload_20gpps_continuous"]
+        return _line(ov["served_mpps"], 1, 0, ov["span_s"] * 1e3, s.pop("config"),
+                     {"latency_ms_p50": ov["latency_ms_p50"],
+                      "latency_ms_p99": ov["latency_ms_p99"], "runs": s["runs"]})
+
+    out = headline(args, dev)
+    extras = [x for x in args.extras.split(",") if x]
+    for name, fn in (("config1", config1_run), ("stream", stream_run),
+                     ("batched", batched_run), ("serving", serving_run)):
+        if name in extras:
+            log(f"{name}")
+            t = time.perf_counter()
+            out[name] = fn(args, dev)
+            log(f"{name} done in {time.perf_counter() - t:.1f} s")
     print(json.dumps(out), flush=True)
 
 
-def _line(metric_value, steps, warmup, ms_per_step, config, extra):
-    out = {"metric": METRIC, "value": round(metric_value, 3), "unit": "Mpps", "n_gpus": 1,
-           "steps": steps, "warmup": warmup, "ms_per_step": round(ms_per_step, 4),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
-           "data": "synthetic", "config": config}
-    out.update(extra)
-    print(json.dumps(out), flush=True)
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def batched_links(dev, n_links=64, seed=0x640):
@@ -335,20 +488,19 @@ def batched_links(dev, n_links=64, seed=0x640):
     return out
 
 
-def run_batched(args):
+def batched_run(args, dev) -> dict:
     """64 links, each with its own sketch and one window (sizes log-uniform
     in [1M, 200M] pairs, Zipf exponent uniform in [0.8, 1.3], 10..500
     planted super points, theta 512 or 1024, sizing rule with k <= 19).
     Update options per (sketch shape, size class) come from the autotuner.
     A step is one window cycle of every link: reset, update, restore. The
-    value is the plan's rate (the whole cycle as one HIP graph); the same
-    cycle as eager batched calls and as one reset/update/restore per window
-    in turn are timed beside it, and all three must agree."""
+    plan runs the whole cycle as one HIP graph; the same cycle as eager
+    batched calls and as one reset/update/restore per window in turn are
+    timed beside it, and all three must agree."""
     import numpy as np
     import torch
     from paper_1803_11449_amd import ddhf, serving, traffic, tune
-    dev = torch.device("cuda:0")
-    print("bench: generating 64 link windows", file=sys.stderr, flush=True)
+    log("generating 64 link windows")
     links = batched_links(dev)
     total = sum(x[0] for x in links)
     sks, tuned = [], {}
@@ -356,7 +508,7 @@ def run_batched(args):
         k, alpha = serving.sized_params(n, k_max=19)
         key = (k, tune.size_class(n))
         if key not in tuned:
-            print(f"bench: tuning k={k} n~2^{key[1]}", file=sys.stderr, flush=True)
+            log(f"tuning k={k} n~2^{key[1]}")
             tuned[key] = tune.tune(1024, k, 5, alpha, pairs, traffic.HASH_SEED, use_cache=False)
         sk = ddhf.Sketch(1024, k, 5, alpha, traffic.HASH_SEED, device=0)
         tune.apply(sk, tuned[key])
@@ -385,20 +537,16 @@ def run_batched(args):
 
     # the eager calls grow the shared buffers to this batch's needs; the plan
     # runs last so that its graph is captured against the grown buffers once
-    print("bench: warmup", file=sys.stderr, flush=True)
+    log("batched warmup")
     for _ in range(max(1, args.warmup)):
         rb = batched()
         rp = plain()
         rg = planned()
     rg = planned()
     for (n, s, planted, theta, _), sk, (recs, info) in zip(links, sks, rg):
-        print(f"bench: link n={n} s={s:.2f} planted={planted} theta={theta:g} "
-              f"k={sk.params.k} he={info['he_count'][:5]} partials={info['n_partials'][2:4]} "
-              f"cand={info['n_candidates']} spl={len(recs)} psi={info['psi']:.3f}",
-              file=sys.stderr, flush=True)
-    free, tot = torch.cuda.mem_get_info()
-    print(f"bench: device memory free {free / 2**30:.1f} of {tot / 2**30:.1f} GiB, torch "
-          f"reserved {torch.cuda.memory_reserved() / 2**30:.1f} GiB", file=sys.stderr, flush=True)
+        log(f"link n={n} s={s:.2f} planted={planted} theta={theta:g} k={sk.params.k} "
+            f"he={info['he_count'][:5]} partials={info['n_partials'][2:4]} "
+            f"cand={info['n_candidates']} spl={len(recs)} psi={info['psi']:.3f}")
     differ = sum(not (np.array_equal(a[0], b[0]) and np.array_equal(a[0], c[0]))
                  for a, b, c in zip(rg, rb, rp))
     steps = max(1, min(args.steps, 5))
@@ -412,51 +560,59 @@ def run_batched(args):
         return (time.perf_counter() - t0) / steps
 
     tg, tb, tp = timed(planned), timed(batched), timed(plain)
-    _line(total / tg / 1e6, steps, args.warmup, tg * 1e3,
-          {"workload": "batched_64_links", "links": 64, "pairs": total,
-           "window_pairs": "log-uniform [1e6, 2e8]", "zipf_s": "U[0.8, 1.3]",
-           "planted": "U{10..500}", "theta": "512 or 1024", "k_max": 19},
-          {"plan_update_launches": plan.launches,
+    out = {"config": {"workload": "batched_64_links", "links": 64, "pairs": total,
+                      "window_pairs": "log-uniform [1e6, 2e8]", "zipf_s": "U[0.8, 1.3]",
+                      "planted": "U{10..500}", "theta": "512 or 1024", "k_max": 19},
+           "steps": steps,
+           "plan_mpps": round(total / tg / 1e6, 2), "plan_ms_per_step": round(tg * 1e3, 3),
+           "plan_update_launches": plan.launches,
            "eager_batched_mpps": round(total / tb / 1e6, 2),
            "eager_batched_ms_per_step": round(tb * 1e3, 3),
            "plain_mpps": round(total / tp / 1e6, 2), "plain_ms_per_step": round(tp * 1e3, 3),
            "speedup_vs_plain": round(tp / tg, 3),
            "windows_differing": differ,
            "super_points": int(sum(len(r[0]) for r in rg)),
-           "tuned": {f"k{k}_n2^{c}": v for (k, c), v in sorted(tuned.items())}})
+           "tuned": {f"k{k}_n2^{c}": v for (k, c), v in sorted(tuned.items())}}
     plan.close()
     for sk in sks:
         sk.close()
+    del links, items
+    torch.cuda.empty_cache()
+    return out
 
 
-def run_serving(args):
+def serving_run(args, dev) -> dict:
     """256 links whose windows close at Poisson times: sizes log-uniform in
     [1e5, 5e7] pairs, Zipf(1.0) sources with 0.05% planted, theta 1024, 64 GB
     HBM budget for resident sketches. Runs at the nominal aggregate rate of
     150 Mpps and at an overload of 20 G pairs/s; for each, continuous
-    batching and one window at a time, with close-to-report latency."""
-    import numpy as np
+    batching (two batches in flight) and one window at a time, with
+    close-to-report latency."""
     import torch
     from paper_1803_11449_amd import serving, traffic
-    dev = torch.device("cuda:0")
-    print("bench: generating 2 pools of 2^27 pairs", file=sys.stderr, flush=True)
+    log("generating 2 pools of 2^27 pairs")
     pools = [serving.pair_pool(1 << 27, 1.0, traffic.config_seed(5, i), dev) for i in range(2)]
     res = {}
     for name, rate, dur in (("nominal_150mpps", 1.5e8, 3.0), ("overload_20gpps", 2e10, 0.25)):
         reqs = serving.poisson_windows(pools, 256, rate, dur, 100_000, 50_000_000,
                                        seed=0x256, theta=(1024.0,))
         for mode, cls in (("continuous", serving.ContinuousServer), ("plain", serving.PlainServer)):
-            print(f"bench: {name} {mode}: {len(reqs)} windows", file=sys.stderr, flush=True)
-            with cls(budget_bytes=64 << 30) as srv:
+            log(f"{name} {mode}: {len(reqs)} windows")
+            kw = {"trace": True} if cls is serving.ContinuousServer else {}
+            with cls(budget_bytes=64 << 30, **kw) as srv:
                 srv.links.prewarm(reqs)
                 out = srv.serve(reqs)
-            res[f"{name}_{mode}"] = serving.latency_summary(out)
-    ov = res["overload_20gpps_continuous"]
-    _line(ov["served_mpps"], 1, 0, ov["span_s"] * 1e3,
-          {"workload": "serving_256_links", "links": 256,
-           "window_pairs": "log-uniform [1e5, 5e7]", "hbm_budget_gb": 64, "theta": 1024},
-          {"latency_ms_p50": ov["latency_ms_p50"], "latency_ms_p99": ov["latency_ms_p99"],
-           "runs": res})
+                summ = serving.latency_summary(out)
+                if kw:
+                    summ["batches"] = len(srv.trace)
+                    summ["batches_overlapping_previous"] = srv.overlaps()
+            res[f"{name}_{mode}"] = summ
+    del pools
+    torch.cuda.empty_cache()
+    return {"config": {"workload": "serving_256_links", "links": 256,
+                       "window_pairs": "log-uniform [1e5, 5e7]", "hbm_budget_gb": 64,
+                       "theta": 1024},
+            "runs": res}
 
 
 if __name__ == "__main__":

@@ -314,12 +314,46 @@ enum {
                                        buffer, 0..2^24 (0 = the initial sizes);
                                        both grow again on demand. Frees device
                                        memory for callers under a budget */
-  SKETCH_OPT_APPLY_BLOCKS = 9       /* binned: blocks of the apply pass;
+  SKETCH_OPT_APPLY_BLOCKS = 9,      /* binned: blocks of the apply pass;
                                        0 = one per apply item (default: the
                                        dispatcher balances uneven tiles), else
                                        that many blocks striding over the
                                        items */
+  SKETCH_OPT_TIMING = 10,           /* 1 = every restore records timing
+                                       events between its phases (read them
+                                       with sketch_timings), 0 = off (default) */
+  SKETCH_OPT_CANDIDATES = 11        /* how the restore finds the addresses
+                                       whose r LEs are all hot (the same set
+                                       either way): 0 = the cheaper by the
+                                       hot-list sizes (default), 1 = the join
+                                       of Algs. 3-4, 2 = the lattice search
+                                       (every address of each hot row-0 LE,
+                                       enumerated from the structure of DH0,
+                                       tested in rows 1..r-1; needs k <= 20) */
 };
+
+/* Phases of the last restore that ran with SKETCH_OPT_TIMING on (device
+ * time between events recorded on its stream), with the work each phase
+ * did, for rooflines of the restore kernels (Alg. 2 and Algs. 3-4 as
+ * computed in Sec. 4.2, eq. (4)). */
+typedef struct {
+  float hot_scan_ms;        /* state reset and hot scan: z0, ZR(i), hot bitmap */
+  float rows_ms;            /* HE(i) compaction, bucket tables, scalars */
+  float join_ms;            /* every join stage */
+  float estimate_ms;        /* ULE gathers, SZ, C, report test */
+  float sort_publish_ms;    /* sort by address, state and records to the host */
+  uint64_t hot_scan_bytes;  /* bytes the hot scan read: the zero counts the
+                               binned update kept (4 per LE) or the sketch */
+  uint64_t join_probes;     /* bucket probes: |HE(0)|*|HE(1)| for stage 1,
+                               then one per partial address of each stage */
+  uint64_t join_outputs;    /* tuples the probes accepted, every stage */
+  uint64_t estimate_bytes;  /* candidates * r * g / 8 (the LEs gathered) */
+} sketch_timings_t;
+
+/* The timings of the last timed restore of s (waits for its events).
+ * Errors: INVAL (NULL argument, or no restore ran with timing on since
+ * SKETCH_OPT_TIMING was set), HIP. */
+int sketch_timings(sketch_t *s, sketch_timings_t *out);
 
 /* Set a tuning option; results never depend on it. Errors: INVAL (NULL
  * handle, unknown option, value out of range, binned path on a sketch of

@@ -6,7 +6,7 @@ never does. It wraps ``ddhf_oracle.c`` (plain C, built with gcc) and shares no
 code with the GPU library.
 
 Every function follows the paper directly:
-  update         Alg. 1 (Sec. 3.2)
+  update         Alg. 1 (Sec. 3.2); update_omp, the same on several threads
   zero_counts    z0 per LE (Alg. 2) and ZR(i) (Sec. 3.3)
   scalars        Lemma 1 with the flow-count estimate of Sec. 3.3, Zmin of
                  Alg. 2, the denominator of eq. (4)
@@ -66,6 +66,7 @@ def lib() -> ctypes.CDLL:
             "orc_h1": (i32, [u32, u32, u32, u32, u64, vp, vp, sz]),
             "orc_sketch_words": (sz, [u32, u32, u32]),
             "orc_update": (i32, [u32, u32, u32, u32, u64, vp, vp, sz]),
+            "orc_update_omp": (i32, [u32, u32, u32, u32, u64, vp, vp, sz, i32]),
             "orc_zero_counts": (i32, [u32, u32, u32, u32, vp, vp, vp]),
             "orc_scalars": (i32, [u32, u32, u32, vp, dbl, vp]),
             "orc_hot_lists": (i32, [u32, u32, u32, u32, vp, dbl, vp, vp]),
@@ -174,6 +175,15 @@ def update(p: Params, sketch: np.ndarray, pairs) -> np.ndarray:
     assert sketch.dtype == np.uint32 and sketch.size == p.words()
     _check(lib().orc_update(*p.t(), p.seed, _ptr(sketch), _ptr(flat),
                             flat.size // 2), "update")
+    return sketch
+
+
+def update_omp(p: Params, sketch: np.ndarray, pairs, nthreads: int | None = None) -> np.ndarray:
+    """Alg. 1 on several threads (same sketch as update)."""
+    flat = as_pairs(pairs)
+    assert sketch.dtype == np.uint32 and sketch.size == p.words()
+    _check(lib().orc_update_omp(*p.t(), p.seed, _ptr(sketch), _ptr(flat), flat.size // 2,
+                                nthreads or default_threads()), "update_omp")
     return sketch
 
 

@@ -207,6 +207,29 @@ int orc_update(uint32_t g, uint32_t k, uint32_t r, uint32_t alpha,
   return ORC_OK;
 }
 
+/* Alg. 1 with the pairs shared out among nthreads threads (OpenMP), for the
+ * CPU baseline's timing. Each bit is set with an atomic OR after Alg. 1's
+ * test, so the sketch equals the sequential loop's (OR is order-free). */
+int orc_update_omp(uint32_t g, uint32_t k, uint32_t r, uint32_t alpha,
+                   uint64_t seed, uint32_t *sketch, const uint32_t *pairs,
+                   size_t n, int nthreads) {
+  orc_t o;
+  if (orc_init(&o, g, k, r, alpha, seed)) return ORC_E_INVAL;
+  int nt = nthreads > 0 ? nthreads : 1;
+#pragma omp parallel for num_threads(nt) schedule(static)
+  for (int64_t j = 0; j < (int64_t)n; j++) {
+    uint32_t a = pairs[2 * j], b = pairs[2 * j + 1];
+    uint32_t bit = h1(&o, b);
+    for (uint32_t i = 0; i < o.r; i++) {
+      size_t w = le_index(&o, i, dh(&o, i, a)) * o.words_per_le + (bit >> 5);
+      uint32_t mask = 1u << (bit & 31);
+      if (__atomic_load_n(&sketch[w], __ATOMIC_RELAXED) & mask) continue;
+      __atomic_fetch_or(&sketch[w], mask, __ATOMIC_RELAXED);
+    }
+  }
+  return ORC_OK;
+}
+
 /* z0 of every LE (g minus its weight |LA(i,j)|, Alg. 2) and ZR(i), the zero
  * count of row i (Sec. 3.3). z0 has r*2^k entries, zr has r. */
 int orc_zero_counts(uint32_t g, uint32_t k, uint32_t r, uint32_t alpha,

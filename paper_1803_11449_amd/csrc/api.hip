@@ -399,6 +399,60 @@ bool params_ok(const sketch_params_t *p) {
   return true;
 }
 
+// A reduced basis of the lattice {(a, y) : y = A a (mod 2^64)} in the
+// metric where the box of one row-0 cell, 2^32 wide in a and 2^(64-k) in y,
+// is a square (a scaled by 2^(32-k)): Lagrange's reduction, with exact
+// 128-bit components and long double only to pick each step's multiple.
+// ok only if the kernel's arithmetic holds for it: k <= 20 (row 1's hot
+// bitmap in LDS), the determinant is +-2^64, and the components and the
+// lines per cell stay small.
+Lattice make_lattice(uint64_t A, uint32_t k) {
+  Lattice L{};
+  if (k > 20) return L;
+  typedef __int128 i128;
+  const i128 sig = (i128)1 << (32 - k);
+  i128 x1 = sig, y1 = (i128)A, x2 = 0, y2 = (i128)1 << 64;
+  auto ld = [](i128 v) { return (long double)v; };
+  for (int it = 0; it < 256; it++) {
+    long double n1 = ld(x1) * ld(x1) + ld(y1) * ld(y1);
+    const long double n2 = ld(x2) * ld(x2) + ld(y2) * ld(y2);
+    if (n2 < n1) {
+      std::swap(x1, x2);
+      std::swap(y1, y2);
+      n1 = n2;
+    }
+    const long double mu = roundl((ld(x1) * ld(x2) + ld(y1) * ld(y2)) / n1);
+    if (mu == 0) break;
+    x2 -= (i128)mu * x1;
+    y2 -= (i128)mu * y1;
+  }
+  if (x1 % sig || x2 % sig) return L;
+  const i128 ua = x1 / sig, va = x2 / sig;
+  const i128 lim_a = (i128)1 << 40, lim_y = (i128)1 << 58;
+  if (ua >= lim_a || ua <= -lim_a || va >= lim_a || va <= -lim_a || y1 >= lim_y ||
+      y1 <= -lim_y || y2 >= lim_y || y2 <= -lim_y)
+    return L;
+  const i128 det = ua * y2 - va * y1;
+  const i128 d64 = (i128)1 << 64;
+  if (det != d64 && det != -d64) return L;
+  L.ua = (int64_t)ua;
+  L.uy = (int64_t)y1;
+  L.va = (int64_t)va;
+  L.vy = (int64_t)y2;
+  L.dneg = det < 0;
+  // j spans (|u_y| 2^32 + |u_a| 2^(64-k)) / 2^64 over a cell's box; the
+  // kernel widens each side by 1 and rounds outwards
+  const long double width =
+      (fabsl(ld(y1)) * 4294967296.0L + fabsl(ld(ua)) * ldexpl(1.0L, 64 - (int)k)) /
+      ldexpl(1.0L, 64);
+  if (width > 1e6L) return L;
+  L.lines = (uint32_t)floorl(width) + 6;
+  // the kernel indexes (cell, line) in 32 bits
+  if ((((uint64_t)1 << k) * (uint64_t)L.lines) >> 32) return L;
+  L.ok = 1;
+  return L;
+}
+
 Geom make_geom(const sketch_params_t &p) {
   Geom G{};
   G.g = p.g; G.k = p.k; G.r = p.r; G.alpha = p.alpha;
@@ -427,6 +481,8 @@ struct Thresholds {
 struct sketch {
   sketch_params_t p;
   Geom G;
+  Lattice lat{};                // row 0's cells as lattice boxes (restore)
+  uint32_t cand_path = 0;       // SKETCH_OPT_CANDIDATES: 0 auto, 1 join, 2 lattice
   DevCtx *ctx = nullptr;
   mutable Lane lane;            // last work on this sketch (any stream)
   // a restore begun by sketch_restore_batch_begin and not yet ended: its
@@ -434,6 +490,12 @@ struct sketch {
   bool pending = false;
   Thresholds pend_t{};
   hipEvent_t restore_ev = nullptr;
+  // SKETCH_OPT_TIMING: events between the restore's phases, and what the
+  // last timed restore read
+  bool timing = false;
+  hipEvent_t tev[6] = {};
+  bool timed = false;           // a restore has recorded tev
+  bool timed_lez = false;       // ... from the update's zero counts
   int n_cu = 0;
   int grid = 0;                 // blocks of grid-stride kernels
   uint32_t *d_sketch = nullptr;
@@ -480,6 +542,10 @@ namespace {
 
 void free_sketch(sketch *s) {
   lane_free(s->lane);
+  for (hipEvent_t &e : s->tev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
   if (s->restore_ev) (void)hipEventDestroy(s->restore_ev);
   s->restore_ev = nullptr;
   dev_free(s->d_sketch);
@@ -541,6 +607,8 @@ RestoreBufs restore_bufs(const sketch *s) {
   B.h_state = s->d_h_state;
   B.h_recs = s->d_h_recs;
   B.h_recs_cap = s->h_recs_cap;
+  B.lat = s->lat;
+  B.cand_path = s->cand_path;
   return B;
 }
 
@@ -615,7 +683,12 @@ int restore_launch(sketch *s, const Thresholds &t, int estimate, hipStream_t st)
   s->ran_cand_cap = B.cand_cap;
   s->ran_spl_cap = B.spl_cap;
   s->ran_h_recs_cap = B.h_recs_cap;
-  HIP_OK(launch_restore(s->G, s->d_sketch, B, t.zhot, t.e_theta, estimate, s->grid, st));
+  HIP_OK(launch_restore(s->G, s->d_sketch, B, t.zhot, t.e_theta, estimate, s->grid, st,
+                        s->timing ? s->tev : nullptr));
+  if (s->timing) {
+    s->timed = true;
+    s->timed_lez = B.lez != nullptr;
+  }
   rc = lane_leave(c->pool_lane, st);
   if (!rc) rc = lane_leave(s->lane, st);
   return rc;
@@ -1162,6 +1235,7 @@ int sketch_create(const sketch_params_t *params, sketch_t **out) {
   sketch *s = new sketch();
   s->p = *params;
   s->G = make_geom(*params);
+  s->lat = make_lattice(s->G.a0, params->k);
   s->words = sketch_bytes(params) / 4;
   s->n_cu = prop.multiProcessorCount;
   s->grid = s->n_cu * 8;
@@ -1434,6 +1508,25 @@ int sketch_set_option(sketch_t *s, int option, int64_t value) {
       if (value < 1024 || (uint64_t)value > ARENA_MAX_PAIRS) break;
       s->binned_round = (size_t)value;
       return SKETCH_OK;
+    case SKETCH_OPT_CANDIDATES:
+      if (value < 0 || value > 2) break;
+      if (value == 2 && !s->lat.ok)
+        return fail(SKETCH_E_INVAL, "sketch_set_option: the lattice search needs k <= 20");
+      s->cand_path = (uint32_t)value;
+      return SKETCH_OK;
+    case SKETCH_OPT_TIMING:
+      if (value < 0 || value > 1) break;
+      if (value && !s->tev[0]) {
+        DEVICE_GUARD(s->p.device);
+        for (hipEvent_t &e : s->tev)
+          if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            return fail(SKETCH_E_HIP, "sketch_set_option: hipEventCreate failed");
+          }
+      }
+      s->timing = value != 0;
+      s->timed = false;
+      return SKETCH_OK;
     case SKETCH_OPT_TRIM_POOLS: {
       if (value < 0 || value > (1 << 24)) break;
       DEVICE_GUARD(s->p.device);
@@ -1445,6 +1538,36 @@ int sketch_set_option(sketch_t *s, int option, int64_t value) {
   }
   return fail(SKETCH_E_INVAL, "sketch_set_option: bad value %lld for option %d",
               (long long)value, option);
+}
+
+int sketch_timings(sketch_t *s, sketch_timings_t *out) {
+  if (!s || !out) return fail(SKETCH_E_INVAL, "sketch_timings: NULL argument");
+  if (!s->timed) return fail(SKETCH_E_INVAL, "sketch_timings: no timed restore has run");
+  DEVICE_GUARD(s->p.device);
+  HIP_OK(hipEventSynchronize(s->tev[5]));
+  float ms[5];
+  for (int i = 0; i < 5; i++) HIP_OK(hipEventElapsedTime(&ms[i], s->tev[i], s->tev[i + 1]));
+  const DevState &h = *s->h_state;
+  memset(out, 0, sizeof *out);
+  out->hot_scan_ms = ms[0];
+  out->rows_ms = ms[1];
+  out->join_ms = ms[2];
+  out->estimate_ms = ms[3];
+  out->sort_publish_ms = ms[4];
+  const uint64_t n_le = (uint64_t)s->p.r << s->p.k;
+  out->hot_scan_bytes = s->timed_lez ? n_le * 4 : n_le * (s->p.g / 8);
+  if (!h.saturated) {
+    // stage 1 probes every (CL_0, CL_1); stage i probes stage i-1's outputs
+    uint64_t probes = (uint64_t)h.he_count[0] * h.he_count[1], outputs = 0;
+    for (uint32_t i = 2; i + 1 < s->p.r; i++) {
+      outputs += h.n_out[i];
+      probes += h.n_out[i];
+    }
+    out->join_probes = probes;
+    out->join_outputs = outputs + h.n_cand;
+    out->estimate_bytes = h.n_cand * (uint64_t)s->p.r * (s->p.g / 8);
+  }
+  return SKETCH_OK;
 }
 
 int sketch_download(const sketch_t *s, uint32_t *host_words, size_t n_words, void *hip_stream) {

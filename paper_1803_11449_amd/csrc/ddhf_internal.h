@@ -53,6 +53,22 @@ struct DevState {
   uint32_t pad[2];
 };
 
+// Row 0's hash DH0(a) = ((A0 a + B0) mod 2^64) >> (64 - k) puts a in cell c
+// iff the point (a, y), y = A0 a mod 2^64 + t 2^64, of the lattice
+// {(a, y) : y = A0 a (mod 2^64)} lies in the box 0 <= a < 2^32,
+// c 2^(64-k) - B0 <= y < (c + 1) 2^(64-k) - B0. A reduced basis (u, v) of
+// that lattice (in the metric that makes the box square) lets the restore
+// enumerate each hot cell's 2^(32-k) addresses line by line (k_lattice)
+// instead of joining the hot lists. Computed on the host per sketch.
+struct Lattice {
+  int64_t ua, uy;          // u = (u_a, u_y)
+  int64_t va, vy;          // v = (v_a, v_y); u_a v_y - v_a u_y = +-2^64
+  uint32_t dneg;           // 1 if that determinant is -2^64
+  uint32_t lines;          // lines j = const of a cell's box, at most
+  uint32_t ok;             // the basis fits the kernel's 64-bit arithmetic
+  uint32_t pad;
+};
+
 // Restore work buffers (device pointers) and capacities.
 struct RestoreBufs {
   const uint32_t *lez;    // zeros per LE as the update left them, or null
@@ -80,6 +96,10 @@ struct RestoreBufs {
   DevState *h_state;
   uint4 *h_recs;          // may be null (no records published)
   size_t h_recs_cap;
+  // candidate search: the lattice of row 0's cells, and the choice
+  // (0 = by estimated work, 1 = the join of Algs. 3-4, 2 = the lattice)
+  Lattice lat;
+  uint32_t cand_path;
 };
 
 // Inclusive prefix sum over the 64 lanes of a wave, in registers: four
@@ -193,8 +213,12 @@ hipError_t launch_or_u32(uint32_t *dst, const uint32_t *src, size_t n_words, int
 // Runs every restore step up to and including the candidate list (and, when
 // estimate != 0, the estimate, report filter and sort). All counts stay on
 // the device; the caller reads DevState afterwards.
+// marks: null, or 6 events recorded on st at the phase boundaries (before
+// the hot scan, after it, after the per-row kernel, after the join, after
+// the estimate, after the publish).
 hipError_t launch_restore(const Geom &G, const uint32_t *sketch,
                           const RestoreBufs &B, uint32_t zhot, double e_theta,
-                          int estimate, int grid, hipStream_t st);
+                          int estimate, int grid, hipStream_t st,
+                          const hipEvent_t *marks = nullptr);
 
 }  // namespace ddhf

@@ -13,13 +13,21 @@
 //  4 scalars       psi (Lemma 1 with the flow-count estimate of Sec. 3.3),
 //                  D = g(1 - psi^r) (eq. (4)), T_rep = D*exp(-theta/g) and
 //                  the integer report bound floor(T_rep), in float64.
-//  5 join          stage 1 (Alg. 3) over HE(0) x HE(1) probing row 2;
-//                  stages 3..r-1 (Alg. 4) over the partial addresses probing
-//                  row i. Each stage appends its outputs with one atomic per
-//                  wave; counts are exact even past a buffer's capacity so
-//                  the host can grow it and run again. The last stage keeps
-//                  a rebuilt address only if it fits 32 bits and DH0 of it
-//                  is the CL_0 it was built from.
+//  5 candidates   the addresses whose r LEs are all hot, by one of two
+//                  searches, chosen on the device from the hot-list sizes
+//                  by their estimated work:
+//                  join     stage 1 (Alg. 3) over HE(0) x HE(1) probing row
+//                           2; stages 3..r-1 (Alg. 4) over the partial
+//                           addresses probing row i. Each stage appends its
+//                           outputs with one atomic per wave; counts are
+//                           exact even past a buffer's capacity so the host
+//                           can grow it and run again. The last stage keeps
+//                           a rebuilt address only if it fits 32 bits and
+//                           DH0 of it is the CL_0 it was built from.
+//                  lattice  every address of every hot row-0 cell, found as
+//                           the points of a lattice in a box (see Lattice),
+//                           tested against the hot bitmaps of rows 1..r-1:
+//                           eq. (2) read forwards, no partial addresses.
 //  6 estimate      per candidate, AND of its r LEs (ULE), SZ = g - popcount,
 //                  report iff SZ <= floor(T_rep) (<=> C >= theta),
 //                  C = -g*ln(SZ/D) (eq. (4)), +inf when SZ = 0.
@@ -410,6 +418,129 @@ __global__ __launch_bounds__(1024) void k_rows(Geom G, const uint32_t *__restric
   else bucket_rows(G, row, h, n, off, bk_cur + (size_t)row * nb, val, sh);
 }
 
+// ------------------------------------------------------ 5: search choice
+
+// The join's work is about its probes and partial addresses, |HE(0)||HE(1)|
+// then times |HE(i)| / 2^(k-alpha) per further row; the lattice search's is
+// 2^(32-k) addresses per hot row-0 cell, each a few integer operations and
+// one LDS read (about a quarter of a join item). Every kernel of both
+// searches evaluates this on the same counts, so exactly one of them runs.
+constexpr double LATTICE_COST = 0.25;
+
+__device__ __forceinline__ bool lattice_chosen(const Geom &G, const DevState *st,
+                                               const Lattice &L, uint32_t path) {
+  if (!L.ok || path == 1) return false;
+  if (path == 2) return true;
+  const double nb = (double)(1u << (G.k - G.alpha));
+  double p = (double)st->he_count[0] * (double)st->he_count[1], join = p;
+  for (uint32_t i = 2; i < G.r; i++) {
+    p *= (double)st->he_count[i] / nb;
+    join += p;
+  }
+  const double lat = (double)st->he_count[0] * (double)(1ull << (32 - G.k)) * LATTICE_COST;
+  return lat < join;
+}
+
+// --------------------------------------------------------- 5b: lattice search
+//
+// Cell c of row 0 holds exactly the addresses a whose lattice point
+// (a, y) lies in the box 0 <= a < 2^32, Y <= y < Y + S, where S = 2^(64-k)
+// and Y = c S - B0 (mod 2^64). Every lattice point is p0 + i u + j v for a
+// point p0 near (0, Y) and integers (i, j); the box is a parallelogram in
+// (i, j). One work item is one line j of one cell: its lane solves the
+// line's range of i (in double, widened by one on each side; every point is
+// then tested exactly in 64-bit integers) and walks it. A point whose LE in
+// row 1 is hot (row 1's hot bitmap is in LDS) is tested in rows 2..r-1 and,
+// if hot everywhere, checked once more by hashing (DH0(a) == c) and
+// appended. Each address lies in exactly one cell, so there are no
+// duplicates.
+
+constexpr int LAT_THREADS = 256;
+constexpr uint32_t LATTICE_LDS_MAX = 131072;           // row 1's bitmap for k <= 20
+
+__device__ __forceinline__ int64_t mul_hi_s(int64_t m, uint64_t y) {
+  return (int64_t)(((__int128)m * (__int128)(unsigned __int128)y) >> 64);
+}
+
+__global__ __launch_bounds__(LAT_THREADS) void k_lattice(
+    Geom G, Lattice L, uint32_t path, const uint32_t *__restrict__ he,
+    const uint32_t *__restrict__ hotmask, DevState *__restrict__ st,
+    uint32_t *__restrict__ cand, size_t cand_cap) {
+  extern __shared__ uint32_t row1[];                   // 2^k bits
+  if (st->saturated || !lattice_chosen(G, st, L, path)) return;
+  const uint32_t k = G.k, kw = 1u << (k - 5);
+  for (uint32_t w = threadIdx.x; w < kw; w += blockDim.x) row1[w] = hotmask[kw + w];
+  __syncthreads();
+  const uint32_t s = 64 - k;
+  const uint64_t S = 1ull << s;
+  const uint32_t kmask = (1u << k) - 1;
+  const double D = L.dneg ? -0x1p64 : 0x1p64;
+  const uint32_t lines = L.lines;
+  const uint32_t items = st->he_count[0] * lines;      // < 2^32 for k <= 24
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < items;
+       t += gridDim.x * blockDim.x) {
+    const uint32_t x = t / lines, line = t - x * lines;
+    const uint32_t c = he[x];
+    const uint64_t Y = ((uint64_t)c << s) - G.b0;
+    // p0 = i0 u + j0 v with (i0, j0) ~ M^-1 (0, Y), M = [u v]; its offsets
+    // from (0, Y) are small, so wrapping 64-bit arithmetic gives them exactly
+    int64_t i0 = mul_hi_s(-L.va, Y), j0 = mul_hi_s(L.ua, Y);
+    if (L.dneg) {
+      i0 = -i0;
+      j0 = -j0;
+    }
+    const int64_t a0 = (int64_t)((uint64_t)i0 * (uint64_t)L.ua + (uint64_t)j0 * (uint64_t)L.va);
+    const int64_t dy0 =
+        (int64_t)((uint64_t)i0 * (uint64_t)L.uy + (uint64_t)j0 * (uint64_t)L.vy - Y);
+    // the cell's lines: j over the box corners
+    double jmin = 0, jmax = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const double da = ((q & 1) ? 4294967296.0 : 0.0) - (double)a0;
+      const double dy = ((q & 2) ? (double)S : 0.0) - (double)dy0;
+      const double j = (-(double)L.uy * da + (double)L.ua * dy) / D;
+      jmin = q ? fmin(jmin, j) : j;
+      jmax = q ? fmax(jmax, j) : j;
+    }
+    const int64_t jlo = (int64_t)floor(jmin) - 1, jhi = (int64_t)ceil(jmax) + 1;
+    const int64_t j = jlo + line;
+    if (j > jhi) continue;
+    // this line's i: 0 <= a0 + i ua + j va < 2^32, 0 <= dy0 + i uy + j vy < S
+    const double al = -(double)a0 - (double)j * (double)L.va, ah = al + 4294967296.0;
+    const double yl = -(double)dy0 - (double)j * (double)L.vy, yh = yl + (double)S;
+    double lo = -1e300, hi = 1e300;
+    if (L.ua) {
+      const double p = al / (double)L.ua, q = ah / (double)L.ua;
+      lo = fmax(lo, fmin(p, q));
+      hi = fmin(hi, fmax(p, q));
+    }
+    if (L.uy) {
+      const double p = yl / (double)L.uy, q = yh / (double)L.uy;
+      lo = fmax(lo, fmin(p, q));
+      hi = fmin(hi, fmax(p, q));
+    }
+    if (!(lo <= hi + 2.0)) continue;
+    const int64_t ilo = (int64_t)floor(lo) - 1, ihi = (int64_t)ceil(hi) + 1;
+    int64_t a = a0 + ilo * L.ua + j * L.va;
+    int64_t dy = dy0 + ilo * L.uy + j * L.vy;
+    for (int64_t i = ilo; i <= ihi; i++, a += L.ua, dy += L.uy) {
+      if ((uint64_t)a >= 4294967296ull || (uint64_t)dy >= S) continue;
+      const uint32_t ad = (uint32_t)a;
+      const uint32_t c1 = c ^ (ad & kmask);            // row 1: BL(1) xor DH0
+      if (!((row1[c1 >> 5] >> (c1 & 31)) & 1u)) continue;
+      bool all = true;
+      for (uint32_t row = 2; row < G.r && all; row++) {
+        const uint32_t ci = c ^ bit_block(G, row, ad);
+        const uint32_t bit = (row << k) | ci;
+        all = (hotmask[bit >> 5] >> (bit & 31)) & 1u;
+      }
+      if (!all || hash_dh0(G, ad) != c) continue;
+      const unsigned long long slot = atomicAdd(&st->n_cand, 1ull);
+      if (slot < cand_cap) cand[slot] = ad;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ 5: join
 //
 // Stage 1 (Alg. 3) takes every (CL_0, CL_1) of HE(0) x HE(1); stage i >= 3
@@ -634,7 +765,7 @@ __device__ __forceinline__ void join_items(
 
 template <bool FIRST, bool LAST>
 __global__ __launch_bounds__(JOIN_THREADS) void k_join(
-    Geom G, uint32_t row, const uint32_t *__restrict__ he,
+    Geom G, Lattice Lt, uint32_t path, uint32_t row, const uint32_t *__restrict__ he,
     const uint2 *__restrict__ in, const uint32_t *__restrict__ in_cnt,
     const uint32_t *__restrict__ bk_off, const uint32_t *__restrict__ bk_val,
     DevState *__restrict__ st, uint2 *__restrict__ out, uint32_t *__restrict__ out_cnt,
@@ -644,7 +775,7 @@ __global__ __launch_bounds__(JOIN_THREADS) void k_join(
   __shared__ uint32_t w_incl[JOIN_THREADS];
   __shared__ uint16_t w_own[(JOIN_THREADS / 64) * OWN_MAX];
   __shared__ uint32_t seg_fill;
-  if (st->saturated) return;
+  if (st->saturated || lattice_chosen(G, st, Lt, path)) return;
 
   const uint32_t nb = 1u << (G.k - G.alpha), M = nb - 1;
   const uint32_t h = st->he_count[row];
@@ -881,9 +1012,13 @@ __global__ __launch_bounds__(256) void k_publish(const DevState *__restrict__ st
 template <int WPL>
 static hipError_t launch_wpl(const Geom &G, const uint32_t *sketch, const RestoreBufs &B,
                              uint32_t zhot, double e_theta, int estimate, int grid,
-                             hipStream_t st) {
+                             hipStream_t st, const hipEvent_t *marks) {
   const uint32_t r = G.r, k = G.k;
   const size_t n_le = (size_t)r << k;
+  auto mark = [&](int i) {
+    if (marks) (void)hipEventRecord(marks[i], st);
+  };
+  mark(0);
   // 0: clear state and the hot bitmap
   k_restore_init<<<(int)((n_le / 32 + 255) / 256 < 256 ? (n_le / 32 + 255) / 256 : 256), 256, 0,
                    st>>>(B.st, B.rank, SMALL_SORT, B.hotmask, n_le / 32);
@@ -903,17 +1038,36 @@ static hipError_t launch_wpl(const Geom &G, const uint32_t *sketch, const Restor
     const int gs = (int)((n_le + chunk - 1) / chunk);
     k_hot_scan<WPL><<<gs, 256, 0, st>>>(G, sketch, zhot, B.hotmask, B.st, chunk);
   }
+  mark(1);
   // 2-4: HE(i), bucket tables of rows 2..r-1, scalars
   k_rows<<<r, 1024, 0, st>>>(G, B.hotmask, B.he, B.bk_off, B.bk_cur, B.bk_val, B.st, e_theta);
-  // 5: join
+  mark(2);
+  // 5: candidates, by the lattice search or the join (each kernel returns
+  // at once unless its search is the chosen one)
+  if (B.lat.ok) {
+    const size_t lds = (size_t)4 << (k - 5);          // row 1's hot bitmap
+    static bool lds_raised = false;                   // above 64 KiB needs the attribute
+    if (lds > 65536 && !lds_raised) {
+      if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_lattice),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)LATTICE_LDS_MAX) != hipSuccess)
+        return hipErrorInvalidValue;
+      lds_raised = true;
+    }
+    // half the usual grid: each block first copies row 1's bitmap
+    k_lattice<<<grid > 1 ? grid / 2 : 1, LAT_THREADS, lds, st>>>(
+        G, B.lat, B.cand_path, B.he, B.hotmask, B.st, B.cand, B.cand_cap);
+  }
   {
     const uint32_t jb = B.jblk;
+    const Lattice &Lt = B.lat;
+    const uint32_t pth = B.cand_path;
     if (r == 3) {
-      k_join<true, true><<<jb, JOIN_THREADS, 0, st>>>(G, 2, B.he, nullptr, nullptr, B.bk_off,
+      k_join<true, true><<<jb, JOIN_THREADS, 0, st>>>(G, Lt, pth, 2, B.he, nullptr, nullptr, B.bk_off,
                                                       B.bk_val, B.st, nullptr, nullptr, 0,
                                                       B.cand, B.cand_cap);
     } else {
-      k_join<true, false><<<jb, JOIN_THREADS, 0, st>>>(G, 2, B.he, nullptr, nullptr, B.bk_off,
+      k_join<true, false><<<jb, JOIN_THREADS, 0, st>>>(G, Lt, pth, 2, B.he, nullptr, nullptr, B.bk_off,
                                                        B.bk_val, B.st, B.part[0], B.segc[0],
                                                        B.seg_cap, B.cand, B.cand_cap);
       for (uint32_t row = 3; row < r; row++) {
@@ -921,47 +1075,52 @@ static hipError_t launch_wpl(const Geom &G, const uint32_t *sketch, const Restor
         const int ib = (row - 3) & 1, ob = ib ^ 1;
         if (row + 1 == r)
           k_join<false, true><<<jb, JOIN_THREADS, 0, st>>>(
-              G, row, B.he, B.part[ib], B.segc[ib], B.bk_off, B.bk_val, B.st, nullptr, nullptr,
+              G, Lt, pth, row, B.he, B.part[ib], B.segc[ib], B.bk_off, B.bk_val, B.st, nullptr, nullptr,
               B.seg_cap, B.cand, B.cand_cap);
         else
           k_join<false, false><<<jb, JOIN_THREADS, 0, st>>>(
-              G, row, B.he, B.part[ib], B.segc[ib], B.bk_off, B.bk_val, B.st, B.part[ob],
+              G, Lt, pth, row, B.he, B.part[ib], B.segc[ib], B.bk_off, B.bk_val, B.st, B.part[ob],
               B.segc[ob], B.seg_cap, B.cand, B.cand_cap);
       }
     }
   }
+  mark(3);
   if (!estimate) {
+    mark(4);
     launch_sort<uint32_t>(B.cand, &B.st->n_cand, B.cand_cap, B.cand_sorted, B.rank, grid, st);
     k_publish<<<1, 256, 0, st>>>(B.st, nullptr, 0, B.h_state, nullptr, 0);
+    mark(5);
     return hipGetLastError();
   }
   // 6: estimate and report
   k_estimate<WPL><<<grid, 256, 0, st>>>(G, sketch, B.cand, B.cand_cap, B.st, B.spl,
                                         B.spl_cap);
+  mark(4);
   // 7: sort
   launch_sort<uint4>(B.spl, &B.st->n_spl, B.spl_cap, B.spl_sorted, B.rank, grid, st);
   // 8: state and records to the host
   k_publish<<<16, 256, 0, st>>>(B.st, B.spl_sorted, B.spl_cap, B.h_state, B.h_recs,
                                 B.h_recs_cap);
+  mark(5);
   return hipGetLastError();
 }
 
 hipError_t launch_restore(const Geom &G, const uint32_t *sketch, const RestoreBufs &B,
                           uint32_t zhot, double e_theta, int estimate, int grid,
-                          hipStream_t st) {
+                          hipStream_t st, const hipEvent_t *marks) {
   switch (G.wpl) {
-    case 1: return launch_wpl<1>(G, sketch, B, zhot, e_theta, estimate, grid, st);
-    case 2: return launch_wpl<2>(G, sketch, B, zhot, e_theta, estimate, grid, st);
-    case 4: return launch_wpl<4>(G, sketch, B, zhot, e_theta, estimate, grid, st);
-    case 8: return launch_wpl<8>(G, sketch, B, zhot, e_theta, estimate, grid, st);
-    case 16: return launch_wpl<16>(G, sketch, B, zhot, e_theta, estimate, grid, st);
-    case 32: return launch_wpl<32>(G, sketch, B, zhot, e_theta, estimate, grid, st);
-    case 64: return launch_wpl<64>(G, sketch, B, zhot, e_theta, estimate, grid, st);
-    case 128: return launch_wpl<128>(G, sketch, B, zhot, e_theta, estimate, grid, st);
-    case 256: return launch_wpl<256>(G, sketch, B, zhot, e_theta, estimate, grid, st);
-    case 512: return launch_wpl<512>(G, sketch, B, zhot, e_theta, estimate, grid, st);
-    case 1024: return launch_wpl<1024>(G, sketch, B, zhot, e_theta, estimate, grid, st);
-    case 2048: return launch_wpl<2048>(G, sketch, B, zhot, e_theta, estimate, grid, st);
+    case 1: return launch_wpl<1>(G, sketch, B, zhot, e_theta, estimate, grid, st, marks);
+    case 2: return launch_wpl<2>(G, sketch, B, zhot, e_theta, estimate, grid, st, marks);
+    case 4: return launch_wpl<4>(G, sketch, B, zhot, e_theta, estimate, grid, st, marks);
+    case 8: return launch_wpl<8>(G, sketch, B, zhot, e_theta, estimate, grid, st, marks);
+    case 16: return launch_wpl<16>(G, sketch, B, zhot, e_theta, estimate, grid, st, marks);
+    case 32: return launch_wpl<32>(G, sketch, B, zhot, e_theta, estimate, grid, st, marks);
+    case 64: return launch_wpl<64>(G, sketch, B, zhot, e_theta, estimate, grid, st, marks);
+    case 128: return launch_wpl<128>(G, sketch, B, zhot, e_theta, estimate, grid, st, marks);
+    case 256: return launch_wpl<256>(G, sketch, B, zhot, e_theta, estimate, grid, st, marks);
+    case 512: return launch_wpl<512>(G, sketch, B, zhot, e_theta, estimate, grid, st, marks);
+    case 1024: return launch_wpl<1024>(G, sketch, B, zhot, e_theta, estimate, grid, st, marks);
+    case 2048: return launch_wpl<2048>(G, sketch, B, zhot, e_theta, estimate, grid, st, marks);
     default: return hipErrorInvalidValue;
   }
 }

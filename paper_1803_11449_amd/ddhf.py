@@ -32,7 +32,7 @@ EXPORTS = ("sketch_params_default", "sketch_params_check", "sketch_bytes",
            "sketch_update_batch", "sketch_restore_batch", "sketch_restore_batch_begin",
            "sketch_restore_batch_end", "sketch_merge",
            "sketch_plan_create", "sketch_plan_run", "sketch_plan_results",
-           "sketch_plan_launches", "sketch_plan_destroy")
+           "sketch_plan_launches", "sketch_plan_destroy", "sketch_timings")
 
 SKETCH_PLAN_RESET = 1
 SKETCH_PLAN_RESTORE = 2
@@ -46,6 +46,8 @@ SKETCH_OPT_SCATTER_PPT = 6
 SKETCH_OPT_BINNED_BLOCKS = 7
 SKETCH_OPT_TRIM_POOLS = 8
 SKETCH_OPT_APPLY_BLOCKS = 9
+SKETCH_OPT_TIMING = 10
+SKETCH_OPT_CANDIDATES = 11
 
 c_u32, c_u64, c_i32, c_sz, c_dbl, c_vp = (ctypes.c_uint32, ctypes.c_uint64,
                                           ctypes.c_int32, ctypes.c_size_t,
@@ -67,6 +69,13 @@ class sketch_info_t(ctypes.Structure):
                 ("n_reported", c_u64), ("psi", c_dbl), ("d", c_dbl),
                 ("zmin", c_dbl), ("trep", c_dbl), ("zhot", c_u32),
                 ("szmax", c_u32)]
+
+
+class sketch_timings_t(ctypes.Structure):
+    _fields_ = [("hot_scan_ms", ctypes.c_float), ("rows_ms", ctypes.c_float),
+                ("join_ms", ctypes.c_float), ("estimate_ms", ctypes.c_float),
+                ("sort_publish_ms", ctypes.c_float), ("hot_scan_bytes", c_u64),
+                ("join_probes", c_u64), ("join_outputs", c_u64), ("estimate_bytes", c_u64)]
 
 
 class sketch_update_job_t(ctypes.Structure):
@@ -130,6 +139,7 @@ def lib() -> ctypes.CDLL:
             "sketch_plan_results": (c_i32, [c_vp, c_vp, c_sz, c_vp]),
             "sketch_plan_launches": (c_sz, [c_vp]),
             "sketch_plan_destroy": (None, [c_vp]),
+            "sketch_timings": (c_i32, [c_vp, P(sketch_timings_t)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -307,6 +317,13 @@ def sketch_candidates(h: int, theta: float, cap: int, stream: int = 0) -> np.nda
                                  ctypes.byref(n), stream)
     _check(rc, n.value)
     return out[: n.value].copy()
+
+
+def sketch_timings(h: int) -> dict:
+    """Phase times and work of the last restore run with SKETCH_OPT_TIMING."""
+    t = sketch_timings_t()
+    _check(lib().sketch_timings(h, ctypes.byref(t)))
+    return {name: getattr(t, name) for name, _ in sketch_timings_t._fields_}
 
 
 def sketch_merge(dst: int, src: int, stream: int = 0) -> None:

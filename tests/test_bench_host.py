@@ -14,10 +14,25 @@ from paper_1803_11449_amd import traffic  # noqa: E402
 
 def test_cpu_baseline_leg_reports_the_oracle():
     w = traffic.generate(traffic.spec_single_window_1m(), traffic.config_seed(1), device="cpu")
-    cb = bench.cpu_baseline_leg(w.pairs, (1024, 14, 5, 6), 1024.0, 20_000)
+    cb = bench.cpu_baseline_leg(w.pairs, (1024, 14, 5, 6), 1024.0, 20_000, 2)
     assert cb["kind"] == "oracle" and cb["unit"] == "Mpps"
-    assert cb["value"] > 0 and cb["cores"] >= 1
+    assert cb["value"] > 0 and cb["cores"] == 2
     assert "20000 pairs" in cb["sample"]
+    legs = cb["legs"]
+    assert legs["update_1thread"]["threads"] == 1
+    assert legs["update_omp"]["threads"] == 2 and legs["update_omp"]["same_sketch_as_1thread"]
+    assert legs["restore_2to32_scan"]["threads"] == 2
+
+
+def test_restore_roofline_arithmetic():
+    t = {"hot_scan_ms": 0.01, "rows_ms": 0.02, "join_ms": 0.1, "estimate_ms": 0.01,
+         "sort_publish_ms": 0.01, "hot_scan_bytes": 8e7, "join_probes": 1e6,
+         "join_outputs": 2e6, "estimate_bytes": 6.4e6}
+    rr = bench.restore_roofline([t, t, t])
+    assert rr["hot_scan"]["achieved"] == 8000.0 and rr["hot_scan"]["frac"] == 1.0
+    ops = bench.JOIN_LDS_OPS_PER_OUTPUT * 2e6 + bench.JOIN_LDS_OPS_PER_PROBE * 1e6
+    assert abs(rr["join"]["achieved"] - ops / 1e-4 / 1e12) < 1e-3
+    assert rr["estimate"]["achieved"] == 640.0
 
 
 def test_more_than_one_gpu_is_refused():

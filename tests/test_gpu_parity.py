@@ -399,6 +399,48 @@ def test_restore_other_params_vs_bruteforce(p):
     assert_spl_equal(recs, ip, sz, c)
 
 
+@pytest.mark.parametrize("path", [1, 2], ids=["join", "lattice"])
+@pytest.mark.parametrize("p", [oracle.Params(), oracle.Params(1024, 18, 5, 5),
+                               oracle.Params(1024, 16, 3, 16), oracle.Params(256, 12, 6, 5),
+                               oracle.Params(512, 18, 5, 5), oracle.Params(1024, 19, 5, 5),
+                               oracle.Params(1024, 20, 5, 4), oracle.Params(64, 14, 5, 6),
+                               oracle.Params(2048, 15, 7, 4)],
+                         ids=lambda p: f"g{p.g}k{p.k}r{p.r}a{p.alpha}")
+def test_candidate_search_join_and_lattice_vs_bruteforce(p, path):
+    """Both candidate searches (the join of Algs. 3-4 and the lattice search
+    over each hot row-0 LE) give the brute-force set and the oracle's list."""
+    say(f"candidate search path={path} g={p.g} k={p.k} r={p.r} alpha={p.alpha}")
+    rng = np.random.default_rng(p.k * 13 + p.r + p.g)
+    hosts = rng.choice(2**32, size=12, replace=False).astype(np.uint32)
+    pairs = np.concatenate([rand_pairs(rng, 300_000, 30_000)] + planted(rng, hosts, 3000))
+    # g = 64: a threshold at which the join's partial addresses stay in the
+    # tens of millions (at theta = 20 they would be about 10^12)
+    theta = 0.7 * p.g if p.g >= 256 else 48.0
+    ref = oracle.build_sketch(p, pairs)
+    with make_sketch(p) as sk:
+        sk.set_option(ddhf.SKETCH_OPT_CANDIDATES, path)
+        sk.upload(ref)
+        cand = sk.candidates(theta)
+        recs, info = sk.restore(theta)
+    assert np.array_equal(cand, oracle.candidates(p, ref, theta, "brute"))
+    ip, sz, c, _ = oracle.restore(p, ref, theta, mode="brute")
+    assert_not_boundary(info)
+    assert_spl_equal(recs, ip, sz, c)
+    he = info["he_count"]
+    if path == 2:
+        assert not any(info["n_partials"])        # no partial addresses
+    elif p.r > 3 and he[0] * he[1] > 0:
+        assert info["n_partials"][2] > 0
+
+
+def test_lattice_option_needs_k_at_most_20():
+    with make_sketch(oracle.Params(1024, 21, 5, 4)) as sk:
+        with pytest.raises(ddhf.SketchError) as e:
+            sk.set_option(ddhf.SKETCH_OPT_CANDIDATES, 2)
+        assert e.value.code == ddhf.SKETCH_E_INVAL
+        sk.set_option(ddhf.SKETCH_OPT_CANDIDATES, 1)
+
+
 def test_more_super_points_than_the_small_sort():
     """More than 16384 reported addresses: the large-list sort path."""
     p = oracle.Params(1024, 18, 5, 5)
@@ -500,6 +542,8 @@ def test_config2_large_window_full_size():
     assert_spl_equal(recs, ip, sz, c)
     say(f"  {len(recs)} super points, {len(cand)} candidates, psi={info['psi']:.4f}, "
         f"he={info['he_count'][:5]}, partials={info['n_partials'][:5]}")
+    # thousands of hot LEs per row: the automatic choice is the lattice search
+    assert min(info["he_count"][:5]) > 3000 and not any(info["n_partials"])
 
 
 @pytest.mark.parametrize("window", [0, 29, 59])

@@ -93,6 +93,15 @@ def test_eq3_block_inversion(p):
         assert np.array_equal(ci ^ c0, block)
 
 
+def test_threaded_update_equals_sequential_alg1():
+    rng = np.random.default_rng(12)
+    pairs = rand_pairs(rng, 300_000, 2000)
+    for p in (DEF, oracle.Params(1024, 18, 5, 5), oracle.Params(256, 12, 6, 5)):
+        ref = oracle.build_sketch(p, pairs)
+        got = oracle.update_omp(p, oracle.new_sketch(p), pairs, nthreads=4)
+        assert np.array_equal(got, ref)
+
+
 # --------------------------------------------------------------- parameters
 
 def test_paper_parameters_and_constraints():

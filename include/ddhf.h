@@ -161,6 +161,27 @@ int sketch_update_batch(const sketch_update_job_t *jobs, size_t n_jobs, void *hi
 int sketch_restore(sketch_t *s, double theta, sketch_sp_t *out, size_t cap,
                    size_t *n_out, sketch_info_t *info, void *hip_stream);
 
+/* sketch_restore for callers that cannot allocate memory: code under HIP
+ * graph capture, tight serving loops, hosts that forbid allocation while
+ * running. It makes no device or host allocation and calls no allocating
+ * library routine. Its work buffers (partial addresses, candidates, records
+ * and their sorted copies, sort ranks) live in one fixed 64 MiB array per
+ * GPU, set up when the first sketch on that GPU is created and held until
+ * the process ends; the sketch's own restore arrays and pinned buffers
+ * were allocated by sketch_create. Limits: at most 2^20 candidates and
+ * 2^18 reported records; a join whose partial addresses outgrow the array
+ * is redone by the lattice search (the same candidate set), or fails when
+ * that search was ruled out (SKETCH_OPT_CANDIDATES = 1, or k > 20).
+ * Beyond a limit it returns CAPACITY with a message naming it (*n_out is
+ * then not set unless only cap was too small). Arguments, results and the
+ * other errors are those of sketch_restore, and so is the output (the same
+ * records, in the same order). Every call on a GPU shares that GPU's
+ * array: the library orders calls through it like its other shared
+ * buffers, but two threads calling it at once for handles on one GPU race
+ * for the array (use one thread per GPU). */
+int sketch_restore_noalloc(sketch_t *s, double theta, sketch_sp_t *out, size_t cap,
+                           size_t *n_out, sketch_info_t *info, void *hip_stream);
+
 /* One sketch's share of a batched restore. Inputs: sketch, theta, out
  * (HOST memory for cap records), cap, info (nullable). Outputs: n_out (the
  * number of records, also on CAPACITY) and status (the sketch_restore code

@@ -160,6 +160,16 @@ int lane_idle(Lane &l) {
 
 constexpr size_t ARENA_MAX_PAIRS = MAX_ROUND_PAIRS;   // pairs per binned launch group
 
+// Work memory of sketch_restore_noalloc, for callers that cannot allocate:
+// one fixed array per GPU, held until the process ends. Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in
+// for the symbol): it uses the per-device address that ctx_acquire looks up
+// with hipGetSymbolAddress.
+constexpr size_t NOALLOC_BYTES = (size_t)64 << 20;
+constexpr size_t NOALLOC_CAND = (size_t)1 << 20;      // candidates (and sorted copy)
+constexpr size_t NOALLOC_SPL = (size_t)1 << 18;       // records (and sorted copy)
+static __device__ __align__(256) uint8_t scratch[NOALLOC_BYTES];
+
 struct DevCtx {
   static constexpr int SLOTS = 16;
   int dev = -1;
@@ -192,6 +202,10 @@ struct DevCtx {
   // so that one batch's update can run while another batch's restore does
   Lane arena_lane, pool_lane;
   uint64_t gen = 0;              // bumped whenever the arena or the pool moves
+  // this device's copy of the no-alloc restore's work array (its address
+  // from hipGetSymbolAddress at set-up) and the last work that used it
+  uint8_t *noalloc = nullptr;
+  Lane noalloc_lane;
 };
 
 std::mutex g_ctx_mu;
@@ -299,6 +313,7 @@ void ctx_free(DevCtx *c) {
   }
   lane_free(c->pool_lane);
   lane_free(c->arena_lane);
+  lane_free(c->noalloc_lane);
   dev_free(c->d_total);
   dev_free(c->codes);
   dev_free(c->scratch);
@@ -336,6 +351,12 @@ int ctx_acquire(int dev, int n_cu, DevCtx **out) {
     }
     if (!rc) rc = lane_init(c->pool_lane);
     if (!rc) rc = lane_init(c->arena_lane);
+    if (!rc) rc = lane_init(c->noalloc_lane);
+    // the caller made dev current: this is dev's copy of the array
+    if (!rc && hipGetSymbolAddress((void **)&c->noalloc, HIP_SYMBOL(scratch)) != hipSuccess) {
+      c->noalloc = nullptr;
+      rc = fail(SKETCH_E_HIP, "device context: hipGetSymbolAddress(scratch) failed");
+    }
     if (!rc) rc = dev_alloc(&c->d_total, DevCtx::SLOTS, "item totals");
     if (!rc) rc = dev_alloc(&c->rank, 16384, "sort ranks");
     if (!rc) rc = dev_alloc(&c->segc[0], c->jblk, "segment counts");
@@ -670,28 +691,60 @@ int materialize(sketch *s, hipStream_t st) {
   return SKETCH_OK;
 }
 
-// Enqueue the restore kernels and the copy of the device state (no wait).
-// Caller holds ctx->mu.
-int restore_launch(sketch *s, const Thresholds &t, int estimate, hipStream_t st) {
-  DevCtx *c = s->ctx;
+// Enqueue the restore kernels on buffers B, whose shared part is ordered by
+// `pool`, and the copy of the device state (no wait). Caller holds ctx->mu.
+int restore_launch_on(sketch *s, const RestoreBufs &B, Lane &pool, const Thresholds &t,
+                      int estimate, hipStream_t st) {
   int rc = lane_enter(s->lane, st);
   if (!rc) rc = materialize(s, st);
-  if (!rc) rc = lane_enter(c->pool_lane, st);
+  if (!rc) rc = lane_enter(pool, st);
   if (rc) return rc;
-  const RestoreBufs B = restore_bufs(s);
-  s->ran_seg_cap = B.seg_cap;
-  s->ran_cand_cap = B.cand_cap;
-  s->ran_spl_cap = B.spl_cap;
-  s->ran_h_recs_cap = B.h_recs_cap;
   HIP_OK(launch_restore(s->G, s->d_sketch, B, t.zhot, t.e_theta, estimate, s->grid, st,
                         s->timing ? s->tev : nullptr));
   if (s->timing) {
     s->timed = true;
     s->timed_lez = B.lez != nullptr;
   }
-  rc = lane_leave(c->pool_lane, st);
+  rc = lane_leave(pool, st);
   if (!rc) rc = lane_leave(s->lane, st);
   return rc;
+}
+
+// The restore on the device's restore pool.
+int restore_launch(sketch *s, const Thresholds &t, int estimate, hipStream_t st) {
+  const RestoreBufs B = restore_bufs(s);
+  s->ran_seg_cap = B.seg_cap;
+  s->ran_cand_cap = B.cand_cap;
+  s->ran_spl_cap = B.spl_cap;
+  s->ran_h_recs_cap = B.h_recs_cap;
+  return restore_launch_on(s, B, s->ctx->pool_lane, t, estimate, st);
+}
+
+// The restore's shared buffers carved from the no-alloc array at `base`:
+// sort ranks, segment counts, candidates and records (each with its sorted
+// copy) at fixed sizes, the rest split into the join's partial segments.
+RestoreBufs noalloc_bufs(const sketch *s, uint8_t *base) {
+  RestoreBufs B = restore_bufs(s);
+  const uint32_t jb = s->ctx->jblk;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    uint8_t *p = base + off;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  B.rank = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * 16384));
+  B.segc[0] = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * jb));
+  B.segc[1] = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * jb));
+  B.cand = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * NOALLOC_CAND));
+  B.cand_sorted = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * NOALLOC_CAND));
+  B.cand_cap = NOALLOC_CAND;
+  B.spl = reinterpret_cast<uint4 *>(take(sizeof(uint4) * NOALLOC_SPL));
+  B.spl_sorted = reinterpret_cast<uint4 *>(take(sizeof(uint4) * NOALLOC_SPL));
+  B.spl_cap = NOALLOC_SPL;
+  B.seg_cap = (NOALLOC_BYTES - off) / (2 * sizeof(uint2) * jb);
+  B.part[0] = reinterpret_cast<uint2 *>(base + off);
+  B.part[1] = B.part[0] + B.seg_cap * jb;
+  return B;
 }
 
 // After the state copy has landed: grow any buffer that overflowed.
@@ -1365,6 +1418,71 @@ int sketch_restore(sketch_t *s, double theta, sketch_sp_t *out, size_t cap, size
   if (h.n_spl > cap)
     return fail(SKETCH_E_CAPACITY, "sketch_restore: %llu records, cap %zu", h.n_spl, cap);
   return copy_records(s, out, (size_t)h.n_spl, s->ran_h_recs_cap, st);
+}
+
+int sketch_restore_noalloc(sketch_t *s, double theta, sketch_sp_t *out, size_t cap,
+                           size_t *n_out, sketch_info_t *info, void *hip_stream) {
+  if (!s || !n_out) return fail(SKETCH_E_INVAL, "sketch_restore_noalloc: NULL handle or n_out");
+  if (!(theta > 0.0) || !isfinite(theta))
+    return fail(SKETCH_E_INVAL, "sketch_restore_noalloc: theta must be finite and > 0");
+  if (cap && !out) return fail(SKETCH_E_INVAL, "sketch_restore_noalloc: NULL out with cap > 0");
+  if (s->pending)
+    return fail(SKETCH_E_INVAL, "sketch_restore_noalloc: a batched restore of this sketch "
+                "was begun and not ended");
+  DEVICE_GUARD(s->p.device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  DevCtx *c = s->ctx;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (!c->noalloc) return fail(SKETCH_E_HIP, "sketch_restore_noalloc: no work array on device");
+  const Thresholds t = thresholds(s, theta);
+  RestoreBufs B = noalloc_bufs(s, c->noalloc);
+  // a join whose partial addresses outgrow the array gives way to the
+  // lattice search, which makes none (both give the same candidates)
+  for (int attempt = 0; attempt < 2; attempt++) {
+    int rc = restore_launch_on(s, B, c->noalloc_lane, t, 1, st);
+    if (rc) return rc;
+    HIP_OK(hipStreamSynchronize(st));
+    const DevState &h = *s->h_state;
+    if (h.saturated) break;
+    uint32_t seg = 0;
+    for (uint32_t i = 2; i + 1 < s->p.r; i++) seg = std::max(seg, h.seg_max[i]);
+    if (seg <= B.seg_cap) break;
+    if (attempt == 0 && s->lat.ok && B.cand_path != 1) {
+      B.cand_path = 2;
+      continue;
+    }
+    return fail(SKETCH_E_CAPACITY, "sketch_restore_noalloc: a join block's %u partial "
+                "addresses exceed the work array's %zu", seg, B.seg_cap);
+  }
+  const DevState h = *s->h_state;
+  fill_info(s, h, t.zmin, t.zhot, info);
+  if (h.saturated) {
+    *n_out = 0;
+    return fail(SKETCH_E_SATURATED, "sketch_restore_noalloc: a row has no zero bit (psi = 1)");
+  }
+  if (h.n_cand > B.cand_cap)
+    return fail(SKETCH_E_CAPACITY, "sketch_restore_noalloc: %llu candidates exceed the work "
+                "array's %zu", h.n_cand, B.cand_cap);
+  if (h.n_spl > B.spl_cap)
+    return fail(SKETCH_E_CAPACITY, "sketch_restore_noalloc: %llu records exceed the work "
+                "array's %zu", h.n_spl, B.spl_cap);
+  *n_out = (size_t)h.n_spl;
+  if (h.n_spl > cap)
+    return fail(SKETCH_E_CAPACITY, "sketch_restore_noalloc: %llu records, cap %zu", h.n_spl, cap);
+  const size_t n = (size_t)h.n_spl;
+  if (n <= B.h_recs_cap) {          // k_publish wrote them to the pinned buffer
+    if (n) memcpy(out, s->h_recs, n * sizeof(uint4));
+    return SKETCH_OK;
+  }
+  // more than the pinned buffer holds: through it, a buffer's worth at a time
+  for (size_t i = 0; i < n; i += B.h_recs_cap) {
+    const size_t m = std::min(B.h_recs_cap, n - i);
+    HIP_OK(hipMemcpyAsync(s->h_recs, B.spl_sorted + i, m * sizeof(uint4),
+                          hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    memcpy(out + i, s->h_recs, m * sizeof(uint4));
+  }
+  return SKETCH_OK;
 }
 
 int sketch_restore_batch_begin(sketch_restore_job_t *jobs, size_t n_jobs, void *hip_stream) {

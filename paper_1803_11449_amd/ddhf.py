@@ -26,7 +26,7 @@ DEFAULT_SEED = 0x1803114490000001
 
 EXPORTS = ("sketch_params_default", "sketch_params_check", "sketch_bytes",
            "sketch_create", "sketch_destroy", "sketch_update",
-           "sketch_restore",
+           "sketch_restore", "sketch_restore_noalloc",
            "sketch_reset", "sketch_download", "sketch_upload",
            "sketch_candidates", "sketch_last_error", "sketch_set_option",
            "sketch_update_batch", "sketch_restore_batch", "sketch_restore_batch_begin",
@@ -123,6 +123,8 @@ def lib() -> ctypes.CDLL:
             "sketch_update": (c_i32, [c_vp, c_vp, c_sz, c_vp]),
             "sketch_restore": (c_i32, [c_vp, c_dbl, c_vp, c_sz, P(c_sz),
                                        P(sketch_info_t), c_vp]),
+            "sketch_restore_noalloc": (c_i32, [c_vp, c_dbl, c_vp, c_sz, P(c_sz),
+                                               P(sketch_info_t), c_vp]),
             "sketch_reset": (c_i32, [c_vp, c_vp]),
             "sketch_download": (c_i32, [c_vp, c_vp, c_sz, c_vp]),
             "sketch_upload": (c_i32, [c_vp, c_vp, c_sz, c_vp]),
@@ -204,19 +206,25 @@ def sketch_reset(h: int, stream: int = 0) -> None:
     _check(lib().sketch_reset(h, stream))
 
 
-def sketch_restore(h: int, theta: float, cap: int, stream: int = 0):
+def sketch_restore(h: int, theta: float, cap: int, stream: int = 0, _fn="sketch_restore"):
     """Returns (records[:n], info). Raises SketchError (with n_needed on
     CAPACITY)."""
     out = np.empty(max(cap, 1), dtype=SP_DTYPE)       # the first n are written
     n = c_sz(0)
     info = sketch_info_t()
-    rc = lib().sketch_restore(h, float(theta), out.ctypes.data, cap,
-                              ctypes.byref(n), ctypes.byref(info), stream)
+    rc = getattr(lib(), _fn)(h, float(theta), out.ctypes.data, cap,
+                             ctypes.byref(n), ctypes.byref(info), stream)
     if rc != SKETCH_OK:
         err = SketchError(rc, last_error(), n.value)
         err.info = info_dict(info)
         raise err
     return out[: n.value].copy(), info_dict(info)
+
+
+def sketch_restore_noalloc(h: int, theta: float, cap: int, stream: int = 0):
+    """sketch_restore_noalloc: as sketch_restore, on the library's fixed
+    per-GPU work array (no allocation inside the call)."""
+    return sketch_restore(h, theta, cap, stream, _fn="sketch_restore_noalloc")
 
 
 class _RestoreJobs:
@@ -542,6 +550,17 @@ class Sketch:
                 return recs, info
             except SketchError as e:
                 if e.code != SKETCH_E_CAPACITY:
+                    raise
+                self._cap = max(int(e.n_needed) + 64, 2 * self._cap)
+
+    def restore_noalloc(self, theta: float, stream=None):
+        """restore() through sketch_restore_noalloc (records, info)."""
+        s = _stream_handle(stream, self.device)
+        while True:
+            try:
+                return sketch_restore_noalloc(self.handle, theta, self._cap, s)
+            except SketchError as e:
+                if e.code != SKETCH_E_CAPACITY or not e.n_needed or e.n_needed <= self._cap:
                     raise
                 self._cap = max(int(e.n_needed) + 64, 2 * self._cap)
 

@@ -157,30 +157,49 @@ LDS_LANE_OPS_PEAK = 256 * 32 * 2.4e9
 # read, three ds_bpermute, the entry's top-bits read and the append counter
 JOIN_LDS_OPS_PER_OUTPUT = 6
 JOIN_LDS_OPS_PER_PROBE = 2
+# Integer vector ALU of the chip: 256 compute units, 4 SIMDs of 16 lanes
+# each, one 32-bit operation per lane per clock, at 2.4 GHz
+VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
+# The lattice search's integer operations per address walked: the step to
+# the next address, its row-1 LE (xor, and), the LE's bitmap word (shift),
+# the bit's test (shift, and)
+LATTICE_OPS_PER_POINT = 6
 
 
 def restore_roofline(timings: list) -> dict:
     """Restore-side rooflines from the phase timings of the latency runs
-    (median of each phase): the hot scan against HBM bandwidth, the join's
-    LDS lane operations against the LDS peak, the estimate's LE gathers
-    against HBM bandwidth."""
+    (median of each phase): the hot scan against HBM bandwidth; the
+    candidate search, the lattice walk's integer operations against the
+    vector ALU peak or the join's LDS lane operations against the LDS peak;
+    the estimate's LE gathers against HBM bandwidth."""
     med = {k: percentile([t[k] for t in timings], 50) for k in timings[0]}
     hs = med["hot_scan_bytes"] / (med["hot_scan_ms"] / 1e3) / 1e9
-    lds_ops = (JOIN_LDS_OPS_PER_OUTPUT * med["join_outputs"] +
-               JOIN_LDS_OPS_PER_PROBE * med["join_probes"])
-    jr = lds_ops / (med["join_ms"] / 1e3)
     eg = med["estimate_bytes"] / (med["estimate_ms"] / 1e3) / 1e9
+    search_s = med["join_ms"] / 1e3
+    if int(med["search"]) == 2:
+        ops = LATTICE_OPS_PER_POINT * med["lattice_points"] / search_s
+        search = {"kind": "lattice", "bound": "alu", "points": int(med["lattice_points"]),
+                  "outputs": int(med["join_outputs"]),
+                  "points_per_s": round(med["lattice_points"] / search_s, 1),
+                  "achieved": round(ops / 1e12, 4),
+                  "peak": round(VALU_LANE_OPS_PEAK / 1e12, 2),
+                  "unit": "T int32 lane-ops/s", "frac": round(ops / VALU_LANE_OPS_PEAK, 5)}
+    else:
+        lds_ops = (JOIN_LDS_OPS_PER_OUTPUT * med["join_outputs"] +
+                   JOIN_LDS_OPS_PER_PROBE * med["join_probes"])
+        jr = lds_ops / search_s
+        search = {"kind": "join", "bound": "lds", "probes": int(med["join_probes"]),
+                  "outputs": int(med["join_outputs"]),
+                  "probes_per_s": round(med["join_probes"] / search_s, 1),
+                  "achieved": round(jr / 1e12, 4), "peak": round(LDS_LANE_OPS_PEAK / 1e12, 2),
+                  "unit": "T LDS lane-ops/s", "frac": round(jr / LDS_LANE_OPS_PEAK, 5)}
     return {
         "phase_ms": {k: round(med[k], 4) for k in ("hot_scan_ms", "rows_ms", "join_ms",
                                                      "estimate_ms", "sort_publish_ms")},
         "hot_scan": {"bound": "hbm", "bytes": int(med["hot_scan_bytes"]),
                      "achieved": round(hs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(hs / HBM_PEAK_GBS, 5)},
-        "join": {"bound": "lds", "probes": int(med["join_probes"]),
-                 "outputs": int(med["join_outputs"]),
-                 "probes_per_s": round(med["join_probes"] / (med["join_ms"] / 1e3), 1),
-                 "achieved": round(jr / 1e12, 4), "peak": round(LDS_LANE_OPS_PEAK / 1e12, 2),
-                 "unit": "T LDS lane-ops/s", "frac": round(jr / LDS_LANE_OPS_PEAK, 5)},
+        "candidate_search": search,
         "estimate": {"bound": "hbm", "bytes": int(med["estimate_bytes"]),
                      "achieved": round(eg, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(eg / HBM_PEAK_GBS, 5)},
@@ -298,8 +317,8 @@ def headline(args, dev) -> dict:
         "he_count": info["he_count"][:r],
         "psi": round(info["psi"], 6),
         "roofline": {"kernel": "sketch_update (k_bin_count, k_bin_scan_cols, "
-                               "k_bin_scan_tiles, k_bin_scatter, k_item_offsets, "
-                               "k_bin_apply, k_bin_merge)",
+                               "k_bin_layout, k_bin_scatter, k_bin_items, "
+                               "k_item_offsets, k_bin_apply, k_bin_merge)",
                      "bound": "hbm",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),

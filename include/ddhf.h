@@ -8,7 +8,8 @@
  * estimators ("LE") of g bits each (the DHLA of Sec. 3.2), in device memory.
  * sketch_update streams (src,dst) IPv4 pairs into it (Alg. 1);
  * sketch_restore recovers the super points of the window from it (Alg. 2,
- * computed as in Sec. 4.2: hot-LE scan, incremental join of Algs. 3-4,
+ * computed as in Sec. 4.2: hot-LE scan, candidate search by the incremental
+ * join of Algs. 3-4 or by walking the addresses of each hot row-0 LE,
  * estimate by eq. (4)); sketch_reset starts a new window.
  *
  * Conventions for every entry point
@@ -148,8 +149,10 @@ typedef struct {
 int sketch_update_batch(const sketch_update_job_t *jobs, size_t n_jobs, void *hip_stream);
 
 /* Alg. 2 (Sec. 3.3) computed as in Sec. 4.2: LEs with z0 < g*exp(-theta/g)
- * are hot; the join of Algs. 3-4 rebuilds every address whose r LEs are
- * all hot and which re-hashes to its own LE in row 0; each is reported iff
+ * are hot; the candidates are every address whose r LEs are all hot (and
+ * which re-hashes to its own LE in row 0), found by the join of Algs. 3-4
+ * or by the lattice search, whichever the hot-list sizes make cheaper (the
+ * same set either way; SKETCH_OPT_CANDIDATES forces one); each is reported iff
  * its eq. (4) estimate C >= theta (decided exactly as SZ <= floor(trep)).
  * out is HOST memory for cap records, filled ascending by address.
  * Synchronous: returns after the records are on the host. Does not change
@@ -314,9 +317,10 @@ enum {
   SKETCH_OPT_UPDATE_CHECK = 4,      /* direct kernel: 1 = test the bit before
                                        the atomicOr (default), 0 = always OR */
   SKETCH_OPT_BINNED_ROUND = 5,      /* binned: pairs per round; the round's
-                                       codes (three per 8 bytes) take about
-                                       2.7*r bytes per pair of device memory,
-                                       allocated on first use */
+                                       codes (three per 8 bytes, in regions
+                                       and a spill area of that size each)
+                                       take about 5.4*r bytes per pair of
+                                       device memory, allocated on first use */
   SKETCH_OPT_SCATTER_PPT = 6,       /* binned: pairs per thread in one LDS
                                        sorting batch: 2, 4 or 6 (default);
                                        capped by LDS at 4 for r in 6..7 and
@@ -343,7 +347,7 @@ enum {
   SKETCH_OPT_TIMING = 10,           /* 1 = every restore records timing
                                        events between its phases (read them
                                        with sketch_timings), 0 = off (default) */
-  SKETCH_OPT_CANDIDATES = 11        /* how the restore finds the addresses
+  SKETCH_OPT_CANDIDATES = 11,       /* how the restore finds the addresses
                                        whose r LEs are all hot (the same set
                                        either way): 0 = the cheaper by the
                                        hot-list sizes (default), 1 = the join
@@ -351,6 +355,19 @@ enum {
                                        (every address of each hot row-0 LE,
                                        enumerated from the structure of DH0,
                                        tested in rows 1..r-1; needs k <= 20) */
+  SKETCH_OPT_BINNED_SAMPLE = 12,    /* binned: the count pass, which sizes
+                                       each tile's code regions, reads every
+                                       n-th batch of pairs, 1..1024 (1: all,
+                                       regions sized exactly); 0 = 16 for
+                                       blocks of 64 batches or more, fewer
+                                       below (default) */
+  SKETCH_OPT_BINNED_REGIONS = 13    /* binned: a region holds value/64 of its
+                                       estimate plus 64 code words, 0..1024;
+                                       0 = 9/8 of a sampled estimate, the
+                                       exact count when every batch is read
+                                       (default). Runs that do not fit go to
+                                       a spill area (small values force that,
+                                       for tests) */
 };
 
 /* Phases of the last restore that ran with SKETCH_OPT_TIMING on (device
@@ -360,15 +377,22 @@ enum {
 typedef struct {
   float hot_scan_ms;        /* state reset and hot scan: z0, ZR(i), hot bitmap */
   float rows_ms;            /* HE(i) compaction, bucket tables, scalars */
-  float join_ms;            /* every join stage */
+  float join_ms;            /* the candidate search: every join stage, or
+                               the lattice search */
   float estimate_ms;        /* ULE gathers, SZ, C, report test */
   float sort_publish_ms;    /* sort by address, state and records to the host */
   uint64_t hot_scan_bytes;  /* bytes the hot scan read: the zero counts the
                                binned update kept (4 per LE) or the sketch */
   uint64_t join_probes;     /* bucket probes: |HE(0)|*|HE(1)| for stage 1,
                                then one per partial address of each stage */
-  uint64_t join_outputs;    /* tuples the probes accepted, every stage */
+  uint64_t join_outputs;    /* tuples the probes accepted, every stage (the
+                               lattice search: the candidates) */
   uint64_t estimate_bytes;  /* candidates * r * g / 8 (the LEs gathered) */
+  uint32_t search;          /* the search that ran: 1 join, 2 lattice (0: none,
+                               the sketch was saturated) */
+  uint32_t pad;
+  uint64_t lattice_points;  /* lattice search: addresses of the hot row-0 LEs,
+                               |HE(0)| * 2^(32-k); 0 for the join */
 } sketch_timings_t;
 
 /* The timings of the last timed restore of s (waits for its events).

@@ -197,7 +197,8 @@ struct DevCtx {
   size_t cand_cap = 0;
   uint4 *spl = nullptr;
   size_t spl_cap = 0;
-  uint32_t *rank = nullptr;
+  uint32_t *rank = nullptr, *skeys = nullptr;
+  size_t rank_cap = 0;           // entries of rank and skeys
   // last work that used the update arena, and the restore pool: separate,
   // so that one batch's update can run while another batch's restore does
   Lane arena_lane, pool_lane;
@@ -214,6 +215,21 @@ DevCtx *g_ctx[256] = {};
 // Wait on the host until the restore pool is idle (before reallocating it).
 int pool_idle(DevCtx *c) { return lane_idle(c->pool_lane); }
 int arena_idle(DevCtx *c) { return lane_idle(c->arena_lane); }
+
+// Sort ranks and tile-sorted keys for the longer of the candidate and
+// record buffers (after the pool is idle).
+int ensure_rank(DevCtx *c) {
+  const size_t need = (std::max<size_t>({c->cand_cap, c->spl_cap, 16384}) + 4095) & ~(size_t)4095;
+  if (c->rank_cap >= need) return SKETCH_OK;
+  c->gen++;
+  dev_free(c->rank);
+  dev_free(c->skeys);
+  c->rank_cap = 0;
+  int rc = dev_alloc(&c->rank, need, "sort ranks");
+  if (!rc) rc = dev_alloc(&c->skeys, need, "sort keys");
+  if (!rc) c->rank_cap = need;
+  return rc;
+}
 
 // Restore pool buffers at exactly `cap` entries (after the pool is idle).
 int alloc_partials(DevCtx *c, size_t cap) {
@@ -239,6 +255,7 @@ int alloc_cand(DevCtx *c, size_t cap) {
   rc = dev_alloc(&c->cand, cap, "candidates");
   if (!rc) rc = dev_alloc(&c->cand_sorted, cap, "candidates");
   if (!rc) c->cand_cap = cap;
+  if (!rc) rc = ensure_rank(c);
   return rc;
 }
 
@@ -250,6 +267,7 @@ int alloc_pool_spl(DevCtx *c, size_t cap) {
   c->spl_cap = 0;
   rc = dev_alloc(&c->spl, cap, "records");
   if (!rc) c->spl_cap = cap;
+  if (!rc) rc = ensure_rank(c);
   return rc;
 }
 
@@ -298,6 +316,9 @@ int trim_pools(DevCtx *c, size_t entries) {
   c->codes_cap = 0;
   dev_free(c->scratch);
   c->scratch_tiles = 0;
+  dev_free(c->rank);
+  dev_free(c->skeys);
+  c->rank_cap = 0;
   rc = alloc_partials(c, entries ? entries : POOL_SEG0);
   if (!rc) rc = alloc_cand(c, entries ? entries : POOL_CAND0);
   if (!rc) rc = alloc_pool_spl(c, entries ? entries : POOL_SPL0);
@@ -325,6 +346,7 @@ void ctx_free(DevCtx *c) {
   dev_free(c->cand_sorted);
   dev_free(c->spl);
   dev_free(c->rank);
+  dev_free(c->skeys);
   delete c;
 }
 
@@ -358,7 +380,6 @@ int ctx_acquire(int dev, int n_cu, DevCtx **out) {
       rc = fail(SKETCH_E_HIP, "device context: hipGetSymbolAddress(scratch) failed");
     }
     if (!rc) rc = dev_alloc(&c->d_total, DevCtx::SLOTS, "item totals");
-    if (!rc) rc = dev_alloc(&c->rank, 16384, "sort ranks");
     if (!rc) rc = dev_alloc(&c->segc[0], c->jblk, "segment counts");
     if (!rc) rc = dev_alloc(&c->segc[1], c->jblk, "segment counts");
     if (!rc) rc = alloc_partials(c, POOL_SEG0);
@@ -542,9 +563,12 @@ struct sketch {
   uint32_t nbins = 0;
   uint32_t bin_nblk = 0;        // count/scatter blocks per job (hist width)
   uint32_t scatter_ppt = 6;
+  uint32_t bin_sample = 0;      // count every n-th batch (0: by the block's batches)
+  uint32_t bin_rscale = 0;      // region = estimate * rscale / 64 + pad (0: default)
   uint32_t apply_grid = 0;     // blocks of the apply pass (0: one per item)
   uint32_t *hist = nullptr, *totals = nullptr, *base = nullptr, *item_start = nullptr,
-           *xslot = nullptr, *n_items = nullptr, *item_tile = nullptr, *gcur = nullptr;
+           *xslot = nullptr, *n_items = nullptr, *item_tile = nullptr, *gcur = nullptr,
+           *tst = nullptr;
   // restore
   DevState *st = nullptr;
   DevState *h_state = nullptr, *d_h_state = nullptr;   // pinned copy of the device state
@@ -578,6 +602,7 @@ void free_sketch(sketch *s) {
   dev_free(s->n_items);
   dev_free(s->item_tile);
   dev_free(s->gcur);
+  dev_free(s->tst);
   dev_free(s->lez);
   dev_free(s->st);
   dev_free(s->hotmask);
@@ -625,6 +650,7 @@ RestoreBufs restore_bufs(const sketch *s) {
   B.spl_sorted = s->spl_sorted;
   B.spl_cap = std::min(c->spl_cap, s->spl_sorted_cap);
   B.rank = c->rank;
+  B.skeys = c->skeys;
   B.h_state = s->d_h_state;
   B.h_recs = s->d_h_recs;
   B.h_recs_cap = s->h_recs_cap;
@@ -732,7 +758,8 @@ RestoreBufs noalloc_bufs(const sketch *s, uint8_t *base) {
     off += (bytes + 255) & ~(size_t)255;
     return p;
   };
-  B.rank = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * 16384));
+  B.rank = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * NOALLOC_CAND));
+  B.skeys = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * NOALLOC_CAND));
   B.segc[0] = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * jb));
   B.segc[1] = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * jb));
   B.cand = reinterpret_cast<uint32_t *>(take(sizeof(uint32_t) * NOALLOC_CAND));
@@ -817,6 +844,7 @@ UpdJob job_base(const sketch *s) {
   J.xslot = s->xslot;
   J.item_tile = s->item_tile;
   J.gcur = s->gcur;
+  J.tst = s->tst;
   J.lez = s->lez;
   J.n_items = s->n_items;
   J.check = (uint32_t)s->update_check;
@@ -839,13 +867,31 @@ struct Group {
   std::vector<UpdJob> jobs;
 };
 
+// The scatter batch (pairs per thread) of a binned launch of n jobs with
+// the requested setting ppt.
+uint32_t launch_ppt(const UpdJob *J, uint32_t n, uint32_t r, uint32_t ppt) {
+  uint32_t max_tiles = 0;
+  for (uint32_t j = 0; j < n; j++) max_tiles = std::max(max_tiles, J[j].nbins);
+  return scatter_ppt(r, max_tiles, ppt);
+}
+
+// 32-bit words a binned job takes from the arena's code buffer: its code
+// regions and spill area (job_code_words 64-bit words) and its tiles'
+// spill-run lists (nbins * dmax uint2), 16-byte aligned.
+size_t job_arena_words(const UpdJob &J, uint32_t r, uint32_t ppt) {
+  const uint64_t w = code_words_bound(J.n, r, J.nbins, J.nblk, J.chunk);
+  const uint64_t dmax = job_batches(J.nblk, J.chunk, ppt);
+  return (size_t)(2 * job_code_words(w, J.nbins) + ((2 * J.nbins * dmax + 3) & ~3ull));
+}
+
 // Block and tile prefixes of one launch's jobs; for a binned launch, the
 // code words and scratch tiles its jobs take from an arena.
-void layout_launch(UpdJob *J, uint32_t n, bool binned, uint32_t r, size_t *words,
+void layout_launch(UpdJob *J, uint32_t n, bool binned, uint32_t r, uint32_t ppt, size_t *words,
                    size_t *tiles) {
   uint32_t blk = 0, tile = 0;
   *words = 0;
   *tiles = 0;
+  const uint32_t pe = binned ? launch_ppt(J, n, r, ppt) : 0;
   for (uint32_t j = 0; j < n; j++) {
     J[j].blk0 = blk;
     J[j].tile0 = tile;
@@ -853,20 +899,26 @@ void layout_launch(UpdJob *J, uint32_t n, bool binned, uint32_t r, size_t *words
     tile += J[j].nbins;
     if (binned) {
       const size_t w = code_words_bound(J[j].n, r, J[j].nbins, J[j].nblk, J[j].chunk);
-      *words += (2 * w + 3) & ~(size_t)3;    // 32-bit words; every job's codes 16-byte aligned
+      *words += job_arena_words(J[j], r, pe);
       *tiles += w / APPLY_ITEM + 1;
     }
   }
 }
 
-// Binned jobs' codes and scratch tiles, packed one after another.
-void place_arena(UpdJob *J, uint32_t n, uint32_t r, uint32_t *codes, uint32_t *scratch) {
+// Binned jobs' code buffers (regions, spill area, spill-run lists) and
+// scratch tiles, packed one after another.
+void place_arena(UpdJob *J, uint32_t n, uint32_t r, uint32_t ppt, uint32_t *codes,
+                 uint32_t *scratch) {
+  const uint32_t pe = launch_ppt(J, n, r, ppt);
   size_t wo = 0, to = 0;
   for (uint32_t j = 0; j < n; j++) {
-    const size_t w = code_words_bound(J[j].n, r, J[j].nbins, J[j].nblk, J[j].chunk);
+    const uint64_t w = code_words_bound(J[j].n, r, J[j].nbins, J[j].nblk, J[j].chunk);
     J[j].codes = codes + wo;
+    J[j].rcap = job_region_words(w, J[j].nbins);
+    J[j].dmax = job_batches(J[j].nblk, J[j].chunk, pe);
+    J[j].desc = reinterpret_cast<uint2 *>(codes + wo + 2 * job_code_words(w, J[j].nbins));
     J[j].scratch = scratch + to * (size_t)BIN_TILE_WORDS;
-    wo += (2 * w + 3) & ~(size_t)3;
+    wo += job_arena_words(J[j], r, pe);
     to += w / APPLY_ITEM + 1;
   }
 }
@@ -878,11 +930,11 @@ int flush_group(DevCtx *c, Group &g, hipStream_t st) {
     const uint32_t n = (uint32_t)std::min<size_t>(MAX_JOBS, g.jobs.size() - at);
     UpdJob *J = g.jobs.data() + at;
     size_t words, tiles;
-    layout_launch(J, n, g.binned, g.r, &words, &tiles);
+    layout_launch(J, n, g.binned, g.r, g.ppt, &words, &tiles);
     if (g.binned) {
       int rc = ensure_arena(c, words, tiles);
       if (rc) return rc;
-      place_arena(J, n, g.r, c->codes, c->scratch);
+      place_arena(J, n, g.r, g.ppt, c->codes, c->scratch);
     }
     // only binned launches use the shared arena
     int rc = g.binned ? lane_enter(c->arena_lane, st) : SKETCH_OK;
@@ -909,7 +961,9 @@ void add_job(std::vector<Group> &groups, const sketch *s, const UpdJob &J, bool 
 }
 
 // Pairs, blocks and pairs per block of a binned round of m pairs: about
-// 32k pairs or more per block, at most the sketch's configured count.
+// 32k pairs or more per block, at most the sketch's configured count. The
+// count samples every BIN_SAMPLE-th batch of a block once the block has
+// four samples' worth of batches (fewer: a smaller stride; one: all).
 void bin_shape(const sketch *s, size_t m, UpdJob &J) {
   J.n = m;
   const size_t want = (m + 32767) / 32768;
@@ -918,13 +972,10 @@ void bin_shape(const sketch *s, size_t m, UpdJob &J) {
   chunk += chunk & 1;
   J.chunk = chunk;
   J.nblk = (uint32_t)((m + chunk - 1) / chunk);
-}
-
-// Bytes of scratch a binned round of one job takes: its code words (at the
-// bound code_words_bound gives, 16-byte aligned) and its scratch tiles.
-size_t round_scratch_bytes(const UpdJob &J, uint32_t r) {
-  const size_t w = code_words_bound(J.n, r, J.nbins, J.nblk, J.chunk);
-  return ((2 * w + 3) & ~(size_t)3) * 4 + (w / APPLY_ITEM + 1) * (size_t)BIN_TILE_WORDS * 4;
+  const size_t batches = (chunk + 1024 * s->scatter_ppt - 1) / (1024 * s->scatter_ppt);
+  J.sample = s->bin_sample ? s->bin_sample
+                           : (uint32_t)std::max<size_t>(1, std::min<size_t>(BIN_SAMPLE, batches / 4));
+  J.rscale = s->bin_rscale;
 }
 
 // Checks the jobs of an update of several sketches on one device.
@@ -1098,7 +1149,8 @@ struct PlanJob {
   double theta = 0;
   Thresholds t{};
   uint32_t *hist = nullptr, *totals = nullptr, *base = nullptr, *item_start = nullptr,
-           *xslot = nullptr, *n_items = nullptr, *item_tile = nullptr, *gcur = nullptr;
+           *xslot = nullptr, *n_items = nullptr, *item_tile = nullptr, *gcur = nullptr,
+           *tst = nullptr;
   DevState *st = nullptr;
   DevState *h_state = nullptr, *d_h_state = nullptr;   // pinned
   uint4 *h_recs = nullptr, *d_h_recs = nullptr;         // pinned
@@ -1158,6 +1210,7 @@ void plan_free(sketch_plan *P) {
     dev_free(j.n_items);
     dev_free(j.item_tile);
     dev_free(j.gcur);
+    dev_free(j.tst);
     dev_free(j.st);
     dev_free(j.sorted);
     pinned_free(j.h_state, j.d_h_state);
@@ -1219,7 +1272,7 @@ int plan_build_graph(sketch_plan *P) {
   if (rc) return rc;
   for (PlanLaunch &L : P->launches) {
     if (!L.binned) continue;
-    place_arena(L.h.data(), (uint32_t)L.h.size(), L.r, c->codes, c->scratch);
+    place_arena(L.h.data(), (uint32_t)L.h.size(), L.r, L.ppt, c->codes, c->scratch);
     HIP_OK(hipMemcpy(L.d, L.h.data(), sizeof(UpdJob) * L.h.size(), hipMemcpyHostToDevice));
   }
   HIP_OK(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
@@ -1325,7 +1378,8 @@ int sketch_create(const sketch_params_t *params, sketch_t **out) {
     if (!rc) rc = dev_alloc(&s->item_start, s->nbins + 1, "tile items");
     if (!rc) rc = dev_alloc(&s->xslot, s->nbins + 1, "tile scratch slots");
     if (!rc) rc = dev_alloc(&s->item_tile, ITEM_TILE_SLOTS(s->nbins), "item tiles");
-    if (!rc) rc = dev_alloc(&s->gcur, (size_t)BIN_GROUPS * s->nbins, "tile stream cursors");
+    if (!rc) rc = dev_alloc(&s->gcur, (size_t)BIN_GROUPS * s->nbins, "tile region cursors");
+    if (!rc) rc = dev_alloc(&s->tst, tile_state_words(s->nbins), "tile regions");
     if (!rc && lez_kept(params->g)) rc = dev_alloc(&s->lez, n_le, "LE zero counts");
     if (!rc) rc = dev_alloc(&s->n_items, 1, "tile item count");
   }
@@ -1626,6 +1680,14 @@ int sketch_set_option(sketch_t *s, int option, int64_t value) {
       if (value < 1024 || (uint64_t)value > ARENA_MAX_PAIRS) break;
       s->binned_round = (size_t)value;
       return SKETCH_OK;
+    case SKETCH_OPT_BINNED_SAMPLE:
+      if (value < 0 || value > 1024) break;
+      s->bin_sample = (uint32_t)value;
+      return SKETCH_OK;
+    case SKETCH_OPT_BINNED_REGIONS:
+      if (value < 0 || value > 1024) break;
+      s->bin_rscale = (uint32_t)value;
+      return SKETCH_OK;
     case SKETCH_OPT_CANDIDATES:
       if (value < 0 || value > 2) break;
       if (value == 2 && !s->lat.ok)
@@ -1675,14 +1737,21 @@ int sketch_timings(sketch_t *s, sketch_timings_t *out) {
   const uint64_t n_le = (uint64_t)s->p.r << s->p.k;
   out->hot_scan_bytes = s->timed_lez ? n_le * 4 : n_le * (s->p.g / 8);
   if (!h.saturated) {
-    // stage 1 probes every (CL_0, CL_1); stage i probes stage i-1's outputs
-    uint64_t probes = (uint64_t)h.he_count[0] * h.he_count[1], outputs = 0;
-    for (uint32_t i = 2; i + 1 < s->p.r; i++) {
-      outputs += h.n_out[i];
-      probes += h.n_out[i];
+    out->search = h.search;
+    if (h.search == 2) {
+      // every address of every hot row-0 LE: 2^(32-k) per LE
+      out->lattice_points = (uint64_t)h.he_count[0] << (32 - s->p.k);
+      out->join_outputs = h.n_cand;
+    } else {
+      // stage 1 probes every (CL_0, CL_1); stage i probes stage i-1's outputs
+      uint64_t probes = (uint64_t)h.he_count[0] * h.he_count[1], outputs = 0;
+      for (uint32_t i = 2; i + 1 < s->p.r; i++) {
+        outputs += h.n_out[i];
+        probes += h.n_out[i];
+      }
+      out->join_probes = probes;
+      out->join_outputs = outputs + h.n_cand;
     }
-    out->join_probes = probes;
-    out->join_outputs = outputs + h.n_cand;
     out->estimate_bytes = h.n_cand * (uint64_t)s->p.r * (s->p.g / 8);
   }
   return SKETCH_OK;
@@ -1766,7 +1835,8 @@ int sketch_plan_create(const sketch_plan_job_t *jobs, size_t n_jobs, int flags,
       if (!rc) rc = dev_alloc(&pj.item_start, s->nbins + 1, "plan tile items");
       if (!rc) rc = dev_alloc(&pj.xslot, s->nbins + 1, "plan tile scratch slots");
       if (!rc) rc = dev_alloc(&pj.item_tile, ITEM_TILE_SLOTS(s->nbins), "plan item tiles");
-      if (!rc) rc = dev_alloc(&pj.gcur, (size_t)BIN_GROUPS * s->nbins, "plan tile stream cursors");
+      if (!rc) rc = dev_alloc(&pj.gcur, (size_t)BIN_GROUPS * s->nbins, "plan tile region cursors");
+      if (!rc) rc = dev_alloc(&pj.tst, tile_state_words(s->nbins), "plan tile regions");
       if (!rc) rc = dev_alloc(&pj.n_items, 1, "plan tile item count");
     }
     if (!rc) rc = dev_alloc(&pj.st, 1, "plan state");
@@ -1801,6 +1871,7 @@ int sketch_plan_create(const sketch_plan_job_t *jobs, size_t n_jobs, int flags,
           J.n_items = pj.n_items;
           J.item_tile = pj.item_tile;
           J.gcur = pj.gcur;
+          J.tst = pj.tst;
           return J;
         },
         [&](Group &g) {
@@ -1809,7 +1880,7 @@ int sketch_plan_create(const sketch_plan_job_t *jobs, size_t n_jobs, int flags,
             PlanLaunch L;
             L.h.assign(g.jobs.begin() + at, g.jobs.begin() + at + n);
             size_t words, tiles;
-            layout_launch(L.h.data(), n, g.binned, g.r, &words, &tiles);
+            layout_launch(L.h.data(), n, g.binned, g.r, g.ppt, &words, &tiles);
             P->arena_words = std::max(P->arena_words, words);
             P->arena_tiles = std::max(P->arena_tiles, tiles);
             L.binned = g.binned;

@@ -50,7 +50,8 @@ struct DevState {
   uint32_t szmax;
   uint32_t saturated;
   uint32_t seg_max[8];               // largest block segment of join stage i
-  uint32_t pad[2];
+  uint32_t search;                   // candidate search that ran: 1 join, 2 lattice
+  uint32_t pad;
 };
 
 // Row 0's hash DH0(a) = ((A0 a + B0) mod 2^64) >> (64 - k) puts a in cell c
@@ -90,7 +91,10 @@ struct RestoreBufs {
   uint4 *spl_sorted;      // the same, ascending by ip
   size_t spl_cap;
   uint32_t *cand_sorted;
-  uint32_t *rank;         // sort ranks (16384 entries)
+  uint32_t *rank;         // sort ranks: at least 16384 entries and the
+                          // larger of cand_cap and spl_cap
+  uint32_t *skeys;        // tile-sorted keys of a long list: that many,
+                          // rounded up to 4096
   // pinned host memory (device-side addresses) the last step writes: the
   // device state and the first min(n, h_recs_cap) sorted records
   DevState *h_state;
@@ -143,8 +147,39 @@ constexpr bool lez_kept(uint32_t g) { return g >= 128 && g <= 8192; }
 // Scatter blocks are put in BIN_GROUPS groups by block index mod BIN_GROUPS:
 // gfx950 hands workgroups of a dispatch to its 8 XCDs in turn, so a group is
 // the blocks that share one XCD and its L2. The blocks of a group write
-// every tile's codes into one shared stream, not one stream each.
+// every tile's codes into one shared region, not one region each.
 constexpr uint32_t BIN_GROUPS = 8;
+
+// The count pass estimates each (group, tile) region from every
+// BIN_SAMPLE-th batch of each block; the region gets the estimate plus an
+// eighth plus BIN_REGION_PAD words. A run that does not fit its region goes
+// whole to the spill area and is listed in its tile's spill runs.
+constexpr uint32_t BIN_SAMPLE = 16;
+constexpr uint32_t BIN_REGION_PAD = 64;
+
+// Per-tile region state of one job, one array of tile_state_words(nbins)
+// words: per (group, tile) region its capacity (then, once laid out, its
+// end), its start and the end of its written part, in 64-bit words from
+// the job's codes; then per tile the count and the words of its spill
+// runs; then the spill area's cursor.
+__host__ __device__ constexpr uint64_t tile_state_words(uint32_t nbins) {
+  return (uint64_t)26 * nbins + 1;
+}
+struct TileState {
+  uint32_t *capg, *regb, *fill;   // [BIN_GROUPS][nbins]
+  uint32_t *dcnt, *swords;        // [nbins]
+  uint32_t *spill_cur;            // [1]
+};
+__host__ __device__ inline TileState tile_state(uint32_t *p, uint32_t nbins) {
+  TileState T;
+  T.capg = p;
+  T.regb = p + (size_t)BIN_GROUPS * nbins;
+  T.fill = p + (size_t)2 * BIN_GROUPS * nbins;
+  T.dcnt = p + (size_t)3 * BIN_GROUPS * nbins;
+  T.swords = T.dcnt + nbins;
+  T.spill_cur = T.swords + nbins;
+  return T;
+}
 
 // One sketch's share of an update launch. Kernels of a launch take a table
 // of these (device memory) and map each block, tile or work item to its
@@ -166,12 +201,19 @@ struct UpdJob {
                          // read, and every tile is written
   uint32_t *hist, *totals, *base, *item_start, *xslot, *n_items;
   uint32_t *item_tile;   // tile of each apply item (ITEM_TILE_SLOTS(nbins) entries)
-  uint32_t *gcur;        // [BIN_GROUPS][nbins]: next slot of each group's stream per tile
+  uint32_t *gcur;        // [BIN_GROUPS][nbins]: claim cursor of each group's region per tile
+  uint32_t *tst;         // region state (tile_state_words(nbins) words)
   uint32_t *lez;         // zeros of every LE of each tile the update writes
                          // (one word per LE), or null
   uint32_t *codes, *scratch;
+  uint2 *desc;           // spill runs of tile t: desc[t * dmax + i] = (start, words)
+  uint64_t rcap;         // 64-bit words of the regions; the spill area follows
+  uint32_t dmax;         // spill runs per tile at most (the job's batches)
   uint32_t item0;        // first global apply item (written on the device)
   uint32_t check;        // direct kernel: test the bit before the atomicOr
+  uint32_t sample;       // count every sample-th batch of a block (1: all)
+  uint32_t rscale;       // region = estimate * rscale / 64 + pad (0: the default
+                         // 9/8 of a sampled estimate, or the exact count)
 };
 
 constexpr uint32_t MAX_JOBS = 256;     // jobs per launch group
@@ -194,6 +236,33 @@ inline uint64_t code_words_bound(uint64_t n, uint32_t r, uint32_t nbins, uint32_
   const uint64_t runs = (uint64_t)nbins * nblk * ((chunk + 2047) / 2048);
   const uint64_t b = (codes + 2 * runs) / 3 + 1;
   return b < codes ? b : codes;
+}
+
+// Pairs per thread of the scatter (and count) batches for r rows, the
+// largest tile count of a launch and the requested setting (see
+// launch_update_jobs): 6, 5, 4 or 2.
+inline uint32_t scatter_ppt(uint32_t r, uint32_t max_tiles, uint32_t ppt) {
+  if (max_tiles <= 2048) {
+    const uint32_t p4 = r <= 7 ? 4 : 2, p6 = r <= 5 ? 6 : p4;
+    return ppt == 2 ? 2 : (ppt == 6 ? p6 : p4);
+  }
+  if (r <= 5 && max_tiles <= 3072 && ppt != 2) return 5;
+  return ppt == 2 ? 2 : (r <= 5 ? 4 : 2);
+}
+
+// Code buffer of one binned job, in 64-bit words: the regions (the bound
+// plus room for every region's pad) and then the spill area (the bound:
+// it never holds more than every word), 16-byte aligned.
+inline uint64_t job_region_words(uint64_t bound, uint32_t nbins) {
+  return (bound + (uint64_t)BIN_GROUPS * nbins * (BIN_REGION_PAD + 2) + 1) & ~(uint64_t)1;
+}
+inline uint64_t job_code_words(uint64_t bound, uint32_t nbins) {
+  return job_region_words(bound, nbins) + ((bound + 1) & ~(uint64_t)1);
+}
+// Batches of a job (an upper bound of the spill runs of any one tile).
+inline uint32_t job_batches(uint32_t nblk, uint64_t chunk, uint32_t ppt) {
+  const uint64_t step = 1024ull * ppt;
+  return (uint32_t)(nblk * ((chunk + step - 1) / step));
 }
 
 // Launches one update round for n_jobs jobs that share r: `h_jobs` is the

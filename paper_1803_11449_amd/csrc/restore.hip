@@ -448,97 +448,189 @@ __device__ __forceinline__ bool lattice_chosen(const Geom &G, const DevState *st
 // and Y = c S - B0 (mod 2^64). Every lattice point is p0 + i u + j v for a
 // point p0 near (0, Y) and integers (i, j); the box is a parallelogram in
 // (i, j). One work item is one line j of one cell: its lane solves the
-// line's range of i (in double, widened by one on each side; every point is
-// then tested exactly in 64-bit integers) and walks it. A point whose LE in
-// row 1 is hot (row 1's hot bitmap is in LDS) is tested in rows 2..r-1 and,
-// if hot everywhere, checked once more by hashing (DH0(a) == c) and
-// appended. Each address lies in exactly one cell, so there are no
-// duplicates.
+// line's range of i (in double, widened, then narrowed exactly in 64-bit
+// integers to the first and last points inside) and walks it, four points
+// per trip, testing each point's LE in row 1 against row 1's hot bitmap in
+// LDS. About |HE(1)| / 2^k of the points pass (a few percent); they go to
+// a queue per wave in LDS, and each time the queue holds 64 the wave tests
+// them together, one per lane: the LEs of rows 0 and 2..r-1 read from the
+// hot bitmap in global memory all at once, then one atomic per wave for
+// the appends. The walk runs in step across the wave (a lane whose line is
+// done walks no points), so the queue's fill is the same in every lane.
+// Each address lies in exactly one cell, so there are no duplicates.
 
 constexpr int LAT_THREADS = 256;
-constexpr uint32_t LATTICE_LDS_MAX = 131072;           // row 1's bitmap for k <= 20
+constexpr uint32_t LAT_QUEUE = 320;                     // survivors per wave
+constexpr uint32_t LAT_QUEUE_BYTES = (LAT_THREADS / 64) * LAT_QUEUE * 4;
+// row 1's bitmap for k <= 20, and the queues
+constexpr uint32_t LATTICE_LDS_MAX = 131072 + LAT_QUEUE_BYTES;
 
 __device__ __forceinline__ int64_t mul_hi_s(int64_t m, uint64_t y) {
   return (int64_t)(((__int128)m * (__int128)(unsigned __int128)y) >> 64);
+}
+
+// Lanes below this one whose bit is set in mask.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
 __global__ __launch_bounds__(LAT_THREADS) void k_lattice(
     Geom G, Lattice L, uint32_t path, const uint32_t *__restrict__ he,
     const uint32_t *__restrict__ hotmask, DevState *__restrict__ st,
     uint32_t *__restrict__ cand, size_t cand_cap) {
-  extern __shared__ uint32_t row1[];                   // 2^k bits
+  extern __shared__ uint32_t row1[];                   // 2^k bits, then the queues
   if (st->saturated || !lattice_chosen(G, st, L, path)) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->search = 2;
   const uint32_t k = G.k, kw = 1u << (k - 5);
   for (uint32_t w = threadIdx.x; w < kw; w += blockDim.x) row1[w] = hotmask[kw + w];
   __syncthreads();
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t *queue = row1 + kw + (threadIdx.x >> 6) * LAT_QUEUE;
+  uint32_t qn = 0;                                       // queue fill, wave-uniform
+
+  // one survivor of row 1 per lane (ok = the lane has one): its LEs in row
+  // 0 and rows 2..r-1 all hot -> a candidate
+  auto test = [&](uint32_t ad, bool ok) {
+    const uint32_t c = hash_dh0(G, ad);
+    uint32_t wv[8], bit[8];
+    bit[0] = c;
+    // BL(row) of ad, its shift (row-1)*alpha (0 past bit 31) worked out
+    // here rather than read from G, which would hold six more scalar
+    // registers through the walk
+#pragma unroll
+    for (uint32_t row = 2; row < 8; row++)
+      if (row < G.r) {
+        const uint32_t sh = (row - 1) * G.alpha;
+        const uint32_t blk = sh < 32 ? (ad >> sh) & ((1u << k) - 1) : 0u;
+        bit[row] = (row << k) | (c ^ blk);
+      }
+    if (ok) {
+      wv[0] = hotmask[bit[0] >> 5];
+#pragma unroll
+      for (uint32_t row = 2; row < 8; row++)
+        if (row < G.r) wv[row] = hotmask[bit[row] >> 5];
+      ok = (wv[0] >> (bit[0] & 31)) & 1u;
+#pragma unroll
+      for (uint32_t row = 2; row < 8; row++)
+        if (row < G.r) ok = ok && ((wv[row] >> (bit[row] & 31)) & 1u);
+    }
+    const uint64_t m = __ballot(ok);
+    if (m) {
+      unsigned long long b = 0;
+      if (lane == (uint32_t)__builtin_ctzll(m)) b = atomicAdd(&st->n_cand, (unsigned long long)__popcll(m));
+      b = wave_lane64(b, (int)__builtin_ctzll(m));
+      const unsigned long long slot = b + lanes_below(m);
+      if (ok && slot < cand_cap) cand[slot] = ad;
+    }
+  };
+  // append the points of this trip that passed row 1 (bit q of hit: point
+  // b + q step), placed by a prefix sum over the wave; test 64 at a time
+  // while the queue holds them (it holds at most 63 + 4*64 entries)
+  auto push = [&](uint32_t b, uint32_t step_, uint32_t hit) {
+    const uint32_t cnt = __popc(hit);
+    const uint32_t incl = wave_scan_incl(cnt);
+    uint32_t pos = qn + incl - cnt;
+    for (uint32_t h = hit; h; h &= h - 1) queue[pos++] = b + (uint32_t)__builtin_ctz(h) * step_;
+    qn += wave_lane(incl, 63);
+    __builtin_amdgcn_wave_barrier();
+    while (qn >= 64) {
+      qn -= 64;
+      const uint32_t ad2 = queue[qn + lane];
+      __builtin_amdgcn_wave_barrier();
+      test(ad2, true);
+    }
+  };
+
   const uint32_t s = 64 - k;
   const uint64_t S = 1ull << s;
   const uint32_t kmask = (1u << k) - 1;
   const double D = L.dneg ? -0x1p64 : 0x1p64;
   const uint32_t lines = L.lines;
   const uint32_t items = st->he_count[0] * lines;      // < 2^32 for k <= 24
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < items;
-       t += gridDim.x * blockDim.x) {
-    const uint32_t x = t / lines, line = t - x * lines;
-    const uint32_t c = he[x];
-    const uint64_t Y = ((uint64_t)c << s) - G.b0;
-    // p0 = i0 u + j0 v with (i0, j0) ~ M^-1 (0, Y), M = [u v]; its offsets
-    // from (0, Y) are small, so wrapping 64-bit arithmetic gives them exactly
-    int64_t i0 = mul_hi_s(-L.va, Y), j0 = mul_hi_s(L.ua, Y);
-    if (L.dneg) {
-      i0 = -i0;
-      j0 = -j0;
-    }
-    const int64_t a0 = (int64_t)((uint64_t)i0 * (uint64_t)L.ua + (uint64_t)j0 * (uint64_t)L.va);
-    const int64_t dy0 =
-        (int64_t)((uint64_t)i0 * (uint64_t)L.uy + (uint64_t)j0 * (uint64_t)L.vy - Y);
-    // the cell's lines: j over the box corners
-    double jmin = 0, jmax = 0;
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-      const double da = ((q & 1) ? 4294967296.0 : 0.0) - (double)a0;
-      const double dy = ((q & 2) ? (double)S : 0.0) - (double)dy0;
-      const double j = (-(double)L.uy * da + (double)L.ua * dy) / D;
-      jmin = q ? fmin(jmin, j) : j;
-      jmax = q ? fmax(jmax, j) : j;
-    }
-    const int64_t jlo = (int64_t)floor(jmin) - 1, jhi = (int64_t)ceil(jmax) + 1;
-    const int64_t j = jlo + line;
-    if (j > jhi) continue;
-    // this line's i: 0 <= a0 + i ua + j va < 2^32, 0 <= dy0 + i uy + j vy < S
-    const double al = -(double)a0 - (double)j * (double)L.va, ah = al + 4294967296.0;
-    const double yl = -(double)dy0 - (double)j * (double)L.vy, yh = yl + (double)S;
-    double lo = -1e300, hi = 1e300;
-    if (L.ua) {
-      const double p = al / (double)L.ua, q = ah / (double)L.ua;
-      lo = fmax(lo, fmin(p, q));
-      hi = fmin(hi, fmax(p, q));
-    }
-    if (L.uy) {
-      const double p = yl / (double)L.uy, q = yh / (double)L.uy;
-      lo = fmax(lo, fmin(p, q));
-      hi = fmin(hi, fmax(p, q));
-    }
-    if (!(lo <= hi + 2.0)) continue;
-    const int64_t ilo = (int64_t)floor(lo) - 1, ihi = (int64_t)ceil(hi) + 1;
-    int64_t a = a0 + ilo * L.ua + j * L.va;
-    int64_t dy = dy0 + ilo * L.uy + j * L.vy;
-    for (int64_t i = ilo; i <= ihi; i++, a += L.ua, dy += L.uy) {
-      if ((uint64_t)a >= 4294967296ull || (uint64_t)dy >= S) continue;
-      const uint32_t ad = (uint32_t)a;
-      const uint32_t c1 = c ^ (ad & kmask);            // row 1: BL(1) xor DH0
-      if (!((row1[c1 >> 5] >> (c1 & 31)) & 1u)) continue;
-      bool all = true;
-      for (uint32_t row = 2; row < G.r && all; row++) {
-        const uint32_t ci = c ^ bit_block(G, row, ad);
-        const uint32_t bit = (row << k) | ci;
-        all = (hotmask[bit >> 5] >> (bit & 31)) & 1u;
+  const uint32_t step = (uint32_t)L.ua;
+  // every lane of a block takes the same trips (uniform bounds)
+  for (uint32_t t0 = blockIdx.x * blockDim.x; t0 < items; t0 += gridDim.x * blockDim.x) {
+    const uint32_t t = t0 + threadIdx.x;
+    uint32_t n = 0, a = 0, c = 0;                      // n points from address a in cell c
+    if (t < items) {
+      const uint32_t x = t / lines, line = t - x * lines;
+      c = he[x];
+      const uint64_t Y = ((uint64_t)c << s) - G.b0;
+      // p0 = i0 u + j0 v with (i0, j0) ~ M^-1 (0, Y), M = [u v]; its offsets
+      // from (0, Y) are small, so wrapping 64-bit arithmetic gives them exactly
+      int64_t i0 = mul_hi_s(-L.va, Y), j0 = mul_hi_s(L.ua, Y);
+      if (L.dneg) {
+        i0 = -i0;
+        j0 = -j0;
       }
-      if (!all || hash_dh0(G, ad) != c) continue;
-      const unsigned long long slot = atomicAdd(&st->n_cand, 1ull);
-      if (slot < cand_cap) cand[slot] = ad;
+      const int64_t a0 = (int64_t)((uint64_t)i0 * (uint64_t)L.ua + (uint64_t)j0 * (uint64_t)L.va);
+      const int64_t dy0 =
+          (int64_t)((uint64_t)i0 * (uint64_t)L.uy + (uint64_t)j0 * (uint64_t)L.vy - Y);
+      // the cell's lines: j over the box corners
+      double jmin = 0, jmax = 0;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const double da = ((q & 1) ? 4294967296.0 : 0.0) - (double)a0;
+        const double dy = ((q & 2) ? (double)S : 0.0) - (double)dy0;
+        const double j = (-(double)L.uy * da + (double)L.ua * dy) / D;
+        jmin = q ? fmin(jmin, j) : j;
+        jmax = q ? fmax(jmax, j) : j;
+      }
+      const int64_t jlo = (int64_t)floor(jmin) - 1, jhi = (int64_t)ceil(jmax) + 1;
+      const int64_t j = jlo + line;
+      if (j <= jhi) {
+        // this line's i: 0 <= a0 + i ua + j va < 2^32, 0 <= dy0 + i uy + j vy < S
+        const double al = -(double)a0 - (double)j * (double)L.va, ah = al + 4294967296.0;
+        const double yl = -(double)dy0 - (double)j * (double)L.vy, yh = yl + (double)S;
+        double lo = -1e300, hi = 1e300;
+        if (L.ua) {
+          const double p = al / (double)L.ua, q = ah / (double)L.ua;
+          lo = fmax(lo, fmin(p, q));
+          hi = fmin(hi, fmax(p, q));
+        }
+        if (L.uy) {
+          const double p = yl / (double)L.uy, q = yh / (double)L.uy;
+          lo = fmax(lo, fmin(p, q));
+          hi = fmin(hi, fmax(p, q));
+        }
+        if (lo <= hi + 2.0) {
+          // the box cuts the line in one run of i: the estimate, widened,
+          // then narrowed exactly to the first and last points inside
+          int64_t ilo = (int64_t)floor(lo) - 1, ihi = (int64_t)ceil(hi) + 1;
+          const int64_t aj = a0 + j * L.va, yj = dy0 + j * L.vy;
+          auto inside = [&](int64_t i) {
+            return (uint64_t)(aj + i * L.ua) < 4294967296ull &&
+                   (uint64_t)(yj + i * L.uy) < S;
+          };
+          while (ilo <= ihi && !inside(ilo)) ilo++;
+          while (ihi >= ilo && !inside(ihi)) ihi--;
+          if (ilo <= ihi) {
+            // every point of [ilo, ihi] is an address of cell c
+            a = (uint32_t)(aj + ilo * L.ua);
+            n = (uint32_t)(ihi - ilo + 1);
+          }
+        }
+      }
+    }
+    // the walk: four points per trip (their row-1 words read together)
+    while (__ballot(n != 0)) {
+      const uint32_t m = n < 4 ? n : 4;
+      const uint32_t b0 = a, b1 = b0 + step, b2 = b1 + step, b3 = b2 + step;
+      const uint32_t x0 = (c ^ b0) & kmask, x1 = (c ^ b1) & kmask;   // row-1 LEs
+      const uint32_t x2 = (c ^ b2) & kmask, x3 = (c ^ b3) & kmask;
+      const uint32_t w0 = row1[x0 >> 5], w1 = row1[x1 >> 5];
+      const uint32_t w2 = row1[x2 >> 5], w3 = row1[x3 >> 5];
+      const uint32_t hit = (((w0 >> (x0 & 31)) & 1u) | (((w1 >> (x1 & 31)) & 1u) << 1) |
+                            (((w2 >> (x2 & 31)) & 1u) << 2) | (((w3 >> (x3 & 31)) & 1u) << 3)) &
+                           ((1u << m) - 1);
+      a = b0 + m * step;
+      n -= m;
+      push(b0, step, hit);
     }
   }
+  // what is left in the queue
+  if (qn) test(queue[lane < qn ? lane : 0], lane < qn);
 }
 
 // ------------------------------------------------------------------ 5: join
@@ -776,6 +868,7 @@ __global__ __launch_bounds__(JOIN_THREADS) void k_join(
   __shared__ uint16_t w_own[(JOIN_THREADS / 64) * OWN_MAX];
   __shared__ uint32_t seg_fill;
   if (st->saturated || lattice_chosen(G, st, Lt, path)) return;
+  if (FIRST && blockIdx.x == 0 && threadIdx.x == 0) st->search = 1;
 
   const uint32_t nb = 1u << (G.k - G.alpha), M = nb - 1;
   const uint32_t h = st->he_count[row];
@@ -898,16 +991,20 @@ __global__ __launch_bounds__(256) void k_estimate(Geom G, const uint32_t *__rest
 //
 // Records with distinct 32-bit keys (the address in .x for uint4 records,
 // the value itself for uint32) are sorted ascending by rank = the number
-// of smaller keys. Up to SMALL_SORT entries the ranks are counted by a
-// (SMALL_SORT/256) x RANK_SPLIT grid, block (x, y) comparing 256 elements
-// against the y-th slice of the keys and adding its counts to a zeroed rank
-// array; a second kernel places each record at its rank. Larger lists use
-// one kernel in which each element scans all keys. 64 slices rather than 8
-// spread a few thousand records over more blocks, each with a shorter
-// compare loop: 11.3 -> 5.5 us for the 100M-pair window's 5.7k records
-// (32 slices: 7.7 us).
+// of smaller keys; a last kernel places each record at its rank.
+// Up to SMALL_SORT entries the ranks are counted by a (SMALL_SORT/256) x
+// RANK_SPLIT grid, block (x, y) comparing 256 elements against the y-th
+// slice of the keys and adding its counts to a zeroed rank array. 64
+// slices rather than 8 spread a few thousand records over more blocks,
+// each with a shorter compare loop: 11.3 -> 5.5 us for the 100M-pair
+// window's 5.7k records (32 slices: 7.7 us).
+// Longer lists: each tile of SORT_TILE keys is sorted in LDS (bitonic), and
+// a record's rank is the sum over the tiles of the keys below its own, one
+// binary search per tile: n * (n / SORT_TILE) * log2(SORT_TILE) steps
+// rather than n^2 compares.
 constexpr uint32_t SMALL_SORT = 16384;
 constexpr uint32_t RANK_SPLIT = 64;
+constexpr uint32_t SORT_TILE = 4096;
 
 template <typename T>
 __device__ __forceinline__ uint32_t sort_key(const T &v);
@@ -938,49 +1035,101 @@ __global__ __launch_bounds__(256) void k_rank_count(const T *__restrict__ in,
   if (c) atomicAdd(&rank[j], c);
 }
 
-// Lists of up to SMALL_SORT records: each record goes to its counted rank.
-// Longer lists: every record ranks itself against all keys, a tile of keys
-// at a time through LDS (grid-stride over the records).
+// Longer lists, step 1 (block = tile): the tile's keys sorted in LDS and
+// written to skeys (the last tile padded with 0xFFFFFFFF, which is below no
+// key), and the tile's ranks zeroed.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_tile_sort(const T *__restrict__ in,
+                                                    const unsigned long long *__restrict__ count,
+                                                    size_t cap, uint32_t *__restrict__ skeys,
+                                                    uint32_t *__restrict__ rank) {
+  __shared__ uint32_t key[SORT_TILE];
+  const unsigned long long n_all = *count;
+  const uint64_t n = n_all < cap ? n_all : cap;
+  const uint64_t t0 = (uint64_t)blockIdx.x * SORT_TILE;
+  if (n <= SMALL_SORT || t0 >= n) return;
+  for (uint32_t i = threadIdx.x; i < SORT_TILE; i += blockDim.x) {
+    const uint64_t e = t0 + i;
+    key[i] = e < n ? sort_key<T>(in[e]) : 0xFFFFFFFFu;
+    if (e < n) rank[e] = 0;
+  }
+  __syncthreads();
+  // bitonic network: pair p of a stage joins i = 2p - (p mod stride) and
+  // i + stride, ascending where bit `size` of i is clear
+  for (uint32_t size = 2; size <= SORT_TILE; size <<= 1)
+    for (uint32_t stride = size >> 1; stride; stride >>= 1) {
+      for (uint32_t p = threadIdx.x; p < SORT_TILE / 2; p += blockDim.x) {
+        const uint32_t i = 2 * p - (p & (stride - 1)), j = i + stride;
+        const uint32_t a = key[i], b = key[j];
+        if ((a > b) == ((i & size) == 0)) {
+          key[i] = b;
+          key[j] = a;
+        }
+      }
+      __syncthreads();
+    }
+  for (uint32_t i = threadIdx.x; i < SORT_TILE; i += blockDim.x) skeys[t0 + i] = key[i];
+}
+
+// Longer lists, step 2: for every (element tile, key tile) pair, each
+// element adds the keys of the key tile below its own to its rank. The
+// grid strides over the pairs.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tile_rank(const T *__restrict__ in,
+                                                   const unsigned long long *__restrict__ count,
+                                                   size_t cap, const uint32_t *__restrict__ skeys,
+                                                   uint32_t *__restrict__ rank) {
+  __shared__ uint32_t key[SORT_TILE];
+  const unsigned long long n_all = *count;
+  const uint64_t n = n_all < cap ? n_all : cap;
+  if (n <= SMALL_SORT) return;
+  const uint64_t nt = (n + SORT_TILE - 1) / SORT_TILE;
+  for (uint64_t pr = blockIdx.x; pr < nt * nt; pr += gridDim.x) {
+    const uint64_t xt = pr / nt, yt = pr - xt * nt;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < SORT_TILE; i += blockDim.x)
+      key[i] = skeys[yt * SORT_TILE + i];
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < SORT_TILE; i += blockDim.x) {
+      const uint64_t e = xt * SORT_TILE + i;
+      if (e >= n) break;
+      const uint32_t x = sort_key<T>(in[e]);
+      // keys below x: the largest prefix whose last key is below x
+      uint32_t pos = 0;
+#pragma unroll
+      for (uint32_t step = SORT_TILE / 2; step; step >>= 1)
+        if (key[pos + step - 1] < x) pos += step;
+      pos += key[pos] < x;                                // pos <= SORT_TILE - 1 here
+      if (pos) atomicAdd(&rank[e], pos);
+    }
+  }
+}
+
+// Each record to its counted rank.
 template <typename T>
 __global__ __launch_bounds__(256) void k_rank_place(const T *__restrict__ in,
                                                     const unsigned long long *__restrict__ count,
                                                     size_t cap, const uint32_t *__restrict__ rank,
                                                     T *__restrict__ out) {
-  constexpr int TILE = 2048;
-  __shared__ uint32_t tile[TILE];
   const unsigned long long n_all = *count;
   const uint64_t n = n_all < cap ? n_all : cap;
-  if (n <= SMALL_SORT) {
-    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
-    if (j < n) out[rank[j]] = in[j];
-    return;
-  }
-  for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < n;
-       base += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t j = base + threadIdx.x;
-    T mine{};
-    uint32_t key = 0xFFFFFFFFu;
-    if (j < n) {
-      mine = in[j];
-      key = sort_key<T>(mine);
-    }
-    uint32_t rk = 0;
-    for (uint64_t t0 = 0; t0 < n; t0 += TILE) {
-      const uint32_t len = (uint32_t)((n - t0) < TILE ? (n - t0) : TILE);
-      __syncthreads();
-      for (uint32_t t = threadIdx.x; t < len; t += blockDim.x) tile[t] = sort_key<T>(in[t0 + t]);
-      __syncthreads();
-      for (uint32_t t = 0; t < len; t++) rk += tile[t] < key;
-    }
-    if (j < n) out[rk] = mine;
-  }
+  for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+       j += (uint64_t)gridDim.x * blockDim.x)
+    out[rank[j]] = in[j];
 }
 
-// rank must hold SMALL_SORT zeroed entries.
+// rank must hold SMALL_SORT zeroed entries and room for cap; skeys room for
+// cap rounded up to SORT_TILE. The kernels of the path a list does not take
+// return at once.
 template <typename T>
 static void launch_sort(const T *in, const unsigned long long *count, size_t cap, T *out,
-                        uint32_t *rank, int grid, hipStream_t st) {
+                        uint32_t *rank, uint32_t *skeys, int grid, hipStream_t st) {
   k_rank_count<T><<<dim3(SMALL_SORT / 256, RANK_SPLIT), 256, 0, st>>>(in, count, cap, rank);
+  if (cap > SMALL_SORT) {
+    const size_t tiles = (cap + SORT_TILE - 1) / SORT_TILE;
+    k_tile_sort<T><<<(unsigned)tiles, 1024, 0, st>>>(in, count, cap, skeys, rank);
+    k_tile_rank<T><<<grid * 2, 256, 0, st>>>(in, count, cap, skeys, rank);
+  }
   const int pg = grid > (int)(SMALL_SORT / 256) ? grid : (int)(SMALL_SORT / 256);
   k_rank_place<T><<<pg, 256, 0, st>>>(in, count, cap, rank, out);
 }
@@ -1045,7 +1194,7 @@ static hipError_t launch_wpl(const Geom &G, const uint32_t *sketch, const Restor
   // 5: candidates, by the lattice search or the join (each kernel returns
   // at once unless its search is the chosen one)
   if (B.lat.ok) {
-    const size_t lds = (size_t)4 << (k - 5);          // row 1's hot bitmap
+    const size_t lds = ((size_t)4 << (k - 5)) + LAT_QUEUE_BYTES;   // row 1's bitmap, queues
     static bool lds_raised = false;                   // above 64 KiB needs the attribute
     if (lds > 65536 && !lds_raised) {
       if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_lattice),
@@ -1087,7 +1236,8 @@ static hipError_t launch_wpl(const Geom &G, const uint32_t *sketch, const Restor
   mark(3);
   if (!estimate) {
     mark(4);
-    launch_sort<uint32_t>(B.cand, &B.st->n_cand, B.cand_cap, B.cand_sorted, B.rank, grid, st);
+    launch_sort<uint32_t>(B.cand, &B.st->n_cand, B.cand_cap, B.cand_sorted, B.rank, B.skeys,
+                          grid, st);
     k_publish<<<1, 256, 0, st>>>(B.st, nullptr, 0, B.h_state, nullptr, 0);
     mark(5);
     return hipGetLastError();
@@ -1097,7 +1247,7 @@ static hipError_t launch_wpl(const Geom &G, const uint32_t *sketch, const Restor
                                         B.spl_cap);
   mark(4);
   // 7: sort
-  launch_sort<uint4>(B.spl, &B.st->n_spl, B.spl_cap, B.spl_sorted, B.rank, grid, st);
+  launch_sort<uint4>(B.spl, &B.st->n_spl, B.spl_cap, B.spl_sorted, B.rank, B.skeys, grid, st);
   // 8: state and records to the host
   k_publish<<<16, 256, 0, st>>>(B.st, B.spl_sorted, B.spl_cap, B.h_state, B.h_recs,
                                 B.h_recs_cap);

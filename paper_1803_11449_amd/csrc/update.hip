@@ -24,27 +24,32 @@
 //          three to a 64-bit word; every run a block writes for one tile in
 //          one batch is padded to whole words with copies of a code of the
 //          run (setting a bit twice sets it once).
-//            count    each block walks its chunk in the scatter's batches
-//                     and adds, per tile, the words each batch will write
-//            scan     per tile, the blocks' counts become the starts of
-//                     the block groups' parts of the tile's run; over tiles,
-//                     the totals become run starts; a tile with many words
-//                     is cut into several apply items
+//            count    each block walks a sample of its chunk's batches (every
+//                     sample-th, in the scatter's batching) and estimates,
+//                     per tile, the words its batches will write
+//            layout   per tile and block group (the blocks of one XCD), a
+//                     region of the estimate plus an eighth plus a pad;
+//                     the regions are laid out tile after tile
 //            scatter  each block sorts a batch of pairs' codes by tile in
-//                     LDS, claims room in its group's part of each tile's
-//                     run with one atomicAdd per tile and writes the codes
-//                     there. A group is the blocks of one XCD: they fill
-//                     each tile's stream together, so the L2 holds one
-//                     partly written line per tile and stream rather than
-//                     one per tile and block, and lines leave it whole
+//                     LDS, claims room for each tile's run in its group's
+//                     region with one atomicAdd and writes the codes there.
+//                     A run that does not fit goes whole to the spill area
+//                     and into its tile's list of spill runs. The blocks of
+//                     a group fill each region together, so the L2 holds
+//                     one partly written line per region rather than one
+//                     per tile and block, and lines leave it whole
+//            items    per tile, the words written (regions and spill runs);
+//                     a tile with many words is cut into several apply items
 //            apply    one workgroup per item: the tile in LDS (up to 160 KiB
-//                     per workgroup on gfx950), ds_or per code. The first
-//                     item of a tile reads and writes the tile itself (or,
-//                     after a reset, builds it from zeros); the other items
-//                     of a cut tile write scratch tiles instead. A finished
-//                     tile's LE zero counts are written with it
+//                     per workgroup on gfx950), ds_or per code, over the
+//                     tile's regions and spill runs. The first item of a
+//                     tile reads and writes the tile itself (or, after a
+//                     reset, builds it from zeros); the other items of a cut
+//                     tile write scratch tiles instead. A finished tile's LE
+//                     zero counts are written with it
 //            merge    each cut tile ORs its scratch tiles into the sketch
-//          Only the pairs, the code runs and whole tiles move through HBM.
+//          Only the pairs (once, plus the sample), the code runs and whole
+//          tiles move through HBM.
 #include <type_traits>
 
 #include "ddhf_internal.h"
@@ -160,10 +165,12 @@ __device__ __forceinline__ void count_pair(const Geom &G, uint2 p, uint32_t *h) 
 
 // Codes are stored three to a 64-bit word (bits 0-19, 20-39, 40-59), and
 // every run the scatter writes (one tile, one batch of a block) is padded
-// to whole words. Per block and tile, the count therefore is the words its
-// batches will write there: it walks the same batches as the scatter (PPT
-// pairs per thread of 1024, from the start of the block's chunk) and adds
-// ceil(c / 3) for a batch with c codes in the tile.
+// to whole words. Per block and tile, the count therefore estimates the
+// words its batches will write there: it walks the same batches as the
+// scatter (PPT pairs per thread of 1024, from the start of the block's
+// chunk), but only every J.sample-th of them, adds ceil(c / 3) for a
+// sampled batch with c codes in the tile and scales the sum by the
+// block's batches over its sampled ones (exact for J.sample = 1).
 //
 // A full batch's pairs are read as uint4 (two pairs per lane per load)
 // when PPT is even; a job's pairs start 16-byte aligned and its chunks and
@@ -176,7 +183,7 @@ __device__ __forceinline__ void count_pair(const Geom &G, uint2 p, uint32_t *h) 
 // the compiler then still needs no spills (several instantiations spill
 // under it, and a spill stalls every batch on the scratch access).
 template <int R, int PPT> constexpr int count_waves_per_eu() {
-  return (R == 4 && PPT >= 5) || (R == 5 && PPT >= 5) || (R == 7 && PPT == 4) ? 8 : 1;
+  return (R == 4 && PPT >= 6) || (R == 5 && PPT >= 5) || (R == 7 && PPT == 4) ? 8 : 1;
 }
 
 template <int R, int PPT>
@@ -205,25 +212,30 @@ void k_bin_count(const UpdJob *__restrict__ jobs, uint32_t nj) {
   const size_t p0 = (size_t)lb * J.chunk;
   const size_t p1 = p0 + J.chunk < J.n ? p0 + J.chunk : J.n;
   const size_t step = (size_t)blockDim.x * PPT;
+  const uint32_t stride = (uint32_t)step * J.sample;    // sampled batches
   const GMEM uint4 *q = gmem(reinterpret_cast<const uint4 *>(J.pairs + p0));
   const size_t nq = (p1 - p0) / 2;                      // whole uint4 of the chunk
   size_t i0 = p0;
   if constexpr (PPT % 2 == 0) {
     if (i0 + step <= p1) {                               // uniform over the block
       uint4 nxt[V4];
+      // the thread index is taken afresh per load (see the scatter), so the
+      // per-load offsets are recomputed rather than held across the loop
       auto load = [&](size_t b0) {                       // b0: the batch's first pair
+        uint32_t tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
 #pragma unroll
         for (int k = 0; k < V4; k++) {
-          const size_t i = (b0 - p0) / 2 + (size_t)k * blockDim.x + threadIdx.x;
+          const size_t i = (b0 - p0) / 2 + (size_t)k * blockDim.x + tid;
           nxt[k] = ld4(q + (i < nq ? i : nq - 1));
         }
       };
       load(i0);
-      for (; i0 + step <= p1; i0 += step) {
+      for (; i0 + step <= p1; i0 += stride) {
         uint4 cur[V4];
 #pragma unroll
         for (int k = 0; k < V4; k++) cur[k] = nxt[k];
-        load(i0 + step);
+        load(i0 + stride);
 #pragma unroll
         for (int k = 0; k < V4; k++) {
           count_pair<R>(G, make_uint2(cur[k].x, cur[k].y), h);
@@ -238,26 +250,28 @@ void k_bin_count(const UpdJob *__restrict__ jobs, uint32_t nj) {
     if (i0 + step <= p1) {
       uint2 nxt[PPT];
       auto load = [&](size_t b0) {
+        uint32_t tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
 #pragma unroll
         for (int k = 0; k < PPT; k++) {
-          const size_t i = b0 + (size_t)k * blockDim.x + threadIdx.x;
+          const size_t i = b0 + (size_t)k * blockDim.x + tid;
           nxt[k] = ld2(pairs + (i < p1 ? i : p1 - 1));
         }
       };
       load(i0);
-      for (; i0 + step <= p1; i0 += step) {
+      for (; i0 + step <= p1; i0 += stride) {
         uint2 cur[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; k++) cur[k] = nxt[k];
-        load(i0 + step);
+        load(i0 + stride);
 #pragma unroll
         for (int k = 0; k < PPT; k++) count_pair<R>(G, cur[k], h);
         close_batch();
       }
     }
   }
-  if (i0 < p1) {                                         // the chunk's partial batch
-    const GMEM uint2 *pairs = gmem(J.pairs);
+  if (i0 < p1) {                                         // the chunk's partial batch,
+    const GMEM uint2 *pairs = gmem(J.pairs);             // when it is a sampled one
 #pragma unroll
     for (int k = 0; k < PPT; k++) {
       const size_t i = i0 + (size_t)k * blockDim.x + threadIdx.x;
@@ -265,10 +279,17 @@ void k_bin_count(const UpdJob *__restrict__ jobs, uint32_t nj) {
     }
     close_batch();
   }
+  // sampled: scaled by the chunk's batches over the sampled ones (an
+  // estimate, in float); every batch: the exact count
+  const uint32_t nb = p1 > p0 ? (uint32_t)((p1 - p0 + step - 1) / step) : 0;
+  const uint32_t ns = (nb + J.sample - 1) / J.sample;
+  const float scale = ns ? (float)nb / (float)ns : 0.f;
   GMEM uint32_t *hist = gmem(J.hist);
 #pragma unroll
   for (uint32_t u = 0; u < TPT; u++)
-    if (t0 + u < nbins) hist[(size_t)(t0 + u) * J.hstride + lb] = acc[u];
+    if (t0 + u < nbins)
+      hist[(size_t)(t0 + u) * J.hstride + lb] =
+          J.sample == 1 ? acc[u] : (uint32_t)fminf((float)acc[u] * scale + 0.5f, 4.0e9f);
 }
 
 // Exclusive prefix sum over a workgroup of 1024 threads.
@@ -289,8 +310,11 @@ __device__ __forceinline__ uint32_t blk_scan_1024(uint32_t v, uint32_t *total, u
   return off + inc - v;
 }
 
-// Per tile: the blocks' counts -> the start of each block group's part of
-// the tile's run, relative to the run (gcur), and the tile's total.
+// Per tile: the blocks' estimates -> each block group's region capacity
+// (the group's estimate plus an eighth plus a pad when sampled, exactly the
+// count when not, or rscale/64 of it plus the pad when rscale is set; even,
+// so that every region starts 16-byte aligned), the tile's spill-run count
+// and words, and the tile's capacity.
 __global__ __launch_bounds__(1024) void k_bin_scan_cols(const UpdJob *__restrict__ jobs,
                                                         uint32_t nj) {
   __shared__ uint32_t sg[BIN_GROUPS];
@@ -303,14 +327,20 @@ __global__ __launch_bounds__(1024) void k_bin_scan_cols(const UpdJob *__restrict
   if (v) atomicAdd(&sg[(J.blk0 + threadIdx.x) % BIN_GROUPS], v);
   __syncthreads();
   if (threadIdx.x == 0) {
-    GMEM uint32_t *gc = gmem(J.gcur);
-    uint32_t ex = 0;
+    const TileState S = tile_state(J.tst, J.nbins);
+    uint32_t tot = 0;
 #pragma unroll
     for (uint32_t g = 0; g < BIN_GROUPS; g++) {
-      gc[(size_t)g * J.nbins + t] = ex;
-      ex += sg[g];
+      const uint32_t e = sg[g];
+      uint32_t cap = J.rscale ? (uint32_t)((uint64_t)e * J.rscale / 64) + BIN_REGION_PAD
+                              : (J.sample > 1 ? e + e / 8 + BIN_REGION_PAD : e);
+      cap += cap & 1;
+      gmem(S.capg)[(size_t)g * J.nbins + t] = cap;
+      tot += cap;
     }
-    gmem(J.totals)[t] = ex;
+    gmem(S.dcnt)[t] = 0;
+    gmem(S.swords)[t] = 0;
+    gmem(J.totals)[t] = tot;
   }
 }
 
@@ -321,39 +351,109 @@ __device__ __forceinline__ uint32_t tile_items(uint32_t v, uint32_t fresh) {
   return v == 0 ? (fresh ? 1u : 0u) : (v <= SPLIT_MIN ? 1u : (v + APPLY_ITEM - 1) / APPLY_ITEM);
 }
 
-// Over one job's tiles (block = job): run starts (which also turn the
-// groups' relative starts in gcur into slots), apply-item starts,
-// scratch-slot starts (a tile cut into j items owns j-1 scratch tiles) and
-// the item count.
-__global__ __launch_bounds__(1024) void k_bin_scan_tiles(const UpdJob *__restrict__ jobs) {
+// Over one job's tiles (block = job): the regions laid out tile after tile
+// (base[t] = the tile's first region; the group regions of a tile follow
+// each other), scaled down to the room the job has if the estimates
+// exceed it. Per region, in words from the job's codes: its start (regb),
+// its end (capg, which held the capacity until here), its claim cursor
+// (gcur, at the start) and its written end (fill, at the end until a run
+// crosses it). The spill cursor zeroed.
+__global__ __launch_bounds__(1024) void k_bin_layout(const UpdJob *__restrict__ jobs) {
   __shared__ uint32_t sh[16];
   const UpdJob &J = jobs[blockIdx.x];
   const uint32_t nbins = J.nbins;
-  const GMEM uint32_t *totals = gmem(J.totals);
-  GMEM uint32_t *base = gmem(J.base), *item_start = gmem(J.item_start), *xslot = gmem(J.xslot);
-  GMEM uint32_t *item_tile = gmem(J.item_tile), *gcur = gmem(J.gcur);
+  const TileState S = tile_state(J.tst, nbins);
+  GMEM uint32_t *capg = gmem(S.capg), *fill = gmem(S.fill), *regb = gmem(S.regb);
+  GMEM uint32_t *base = gmem(J.base);
   constexpr uint32_t PER = (BIN_MAX + 1) / 1024;
   const uint32_t t0 = threadIdx.x * PER;
-  // the thread's tile totals and group cursors are all loaded before any
-  // store (the stores below could alias them, so a later load would wait)
-  uint32_t v[PER], gc[PER][BIN_GROUPS];
+  uint32_t cap[PER][BIN_GROUPS];
+  uint64_t mine = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < PER; k++)
+#pragma unroll
+    for (uint32_t g = 0; g < BIN_GROUPS; g++) {
+      const uint32_t t = t0 + k;
+      cap[k][g] = t < nbins ? capg[(size_t)g * nbins + t] : 0;
+      mine += cap[k][g];
+    }
+  uint32_t tot;
+  // the job's words fit 32 bits (its code buffer is indexed so)
+  uint32_t ex = blk_scan_1024((uint32_t)mine, &tot, sh);
+  if (tot > J.rcap) {                                   // uniform over the block
+    mine = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < PER; k++)
+#pragma unroll
+      for (uint32_t g = 0; g < BIN_GROUPS; g++) {
+        const uint32_t c = (uint32_t)((uint64_t)cap[k][g] * J.rcap / tot) & ~1u;
+        cap[k][g] = c;
+        mine += c;
+      }
+    ex = blk_scan_1024((uint32_t)mine, &tot, sh);
+  }
+  GMEM uint32_t *gcur = gmem(J.gcur);
 #pragma unroll
   for (uint32_t k = 0; k < PER; k++) {
     const uint32_t t = t0 + k;
-    v[k] = t < nbins ? totals[t] : 0;
+    if (t < nbins) {
+      base[t] = ex;
 #pragma unroll
-    for (uint32_t g = 0; g < BIN_GROUPS; g++) gc[k][g] = t < nbins ? gcur[(size_t)g * nbins + t] : 0;
+      for (uint32_t g = 0; g < BIN_GROUPS; g++) {
+        const size_t x = (size_t)g * nbins + t;
+        regb[x] = ex;
+        gcur[x] = ex;
+        ex += cap[k][g];
+        capg[x] = ex;
+        fill[x] = ex;
+      }
+    }
   }
-  uint32_t c = 0, it = 0, xs = 0;
+  if (threadIdx.x == 0) {
+    base[nbins] = tot;
+    *gmem(S.spill_cur) = 0;
+  }
+}
+
+// Over one job's tiles (block = job), after the scatter: the words each
+// tile got (the written part of its regions and its spill runs), its apply
+// items, their starts, the scratch-slot starts (a tile cut into j items
+// owns j-1 scratch tiles) and the item count.
+__global__ __launch_bounds__(1024) void k_bin_items(const UpdJob *__restrict__ jobs) {
+  __shared__ uint32_t sh[16];
+  const UpdJob &J = jobs[blockIdx.x];
+  const uint32_t nbins = J.nbins;
+  const TileState S = tile_state(J.tst, nbins);
+  const GMEM uint32_t *gcur = gmem(J.gcur), *fill = gmem(S.fill), *swords = gmem(S.swords);
+  const GMEM uint32_t *regb = gmem(S.regb);
+  GMEM uint32_t *totals = gmem(J.totals), *item_start = gmem(J.item_start);
+  GMEM uint32_t *xslot = gmem(J.xslot), *item_tile = gmem(J.item_tile);
+  constexpr uint32_t PER = (BIN_MAX + 1) / 1024;
+  const uint32_t t0 = threadIdx.x * PER;
+  uint32_t v[PER];
+#pragma unroll
+  for (uint32_t k = 0; k < PER; k++) {
+    const uint32_t t = t0 + k;
+    uint32_t w = 0;
+    if (t < nbins) {
+      w = swords[t];
+#pragma unroll
+      for (uint32_t g = 0; g < BIN_GROUPS; g++) {
+        const size_t x = (size_t)g * nbins + t;
+        const uint32_t c = gcur[x], f = fill[x];
+        w += (c < f ? c : f) - regb[x];
+      }
+    }
+    v[k] = w;
+  }
+  uint32_t it = 0, xs = 0;
 #pragma unroll
   for (uint32_t k = 0; k < PER; k++) {
     const uint32_t ni = t0 + k < nbins ? tile_items(v[k], J.fresh) : 0;
-    c += v[k];
     it += ni;
     xs += ni > 1 ? ni - 1 : 0;
   }
-  uint32_t tot_c, tot_it, tot_xs;
-  uint32_t ec = blk_scan_1024(c, &tot_c, sh);
+  uint32_t tot_it, tot_xs;
   uint32_t ei = blk_scan_1024(it, &tot_it, sh);
   uint32_t ex = blk_scan_1024(xs, &tot_xs, sh);
 #pragma unroll
@@ -361,19 +461,15 @@ __global__ __launch_bounds__(1024) void k_bin_scan_tiles(const UpdJob *__restric
     const uint32_t t = t0 + k;
     if (t < nbins) {
       const uint32_t ni = tile_items(v[k], J.fresh);
-      base[t] = ec;
-#pragma unroll
-      for (uint32_t g = 0; g < BIN_GROUPS; g++) gcur[(size_t)g * nbins + t] = gc[k][g] + ec;
+      totals[t] = v[k];
       item_start[t] = ei;
       xslot[t] = ex;
       for (uint32_t q = 0; q < ni; q++) item_tile[ei + q] = t;
-      ec += v[k];
       ei += ni;
       ex += ni > 1 ? ni - 1 : 0;
     }
   }
   if (threadIdx.x == 0) {
-    base[nbins] = tot_c;
     item_start[nbins] = tot_it;
     xslot[nbins] = tot_xs;
     *gmem(J.n_items) = tot_it;
@@ -424,8 +520,12 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
   const uint32_t lb = blockIdx.x - J.blk0;
   const GMEM uint2 *__restrict__ pairs = gmem(J.pairs);
   GMEM uint64_t *__restrict__ words = gmem(reinterpret_cast<uint64_t *>(J.codes));
-  // this block's group's stream cursors (in words), one per tile
-  GMEM uint32_t *gcur = gmem(J.gcur) + (size_t)(blockIdx.x % BIN_GROUPS) * J.nbins;
+  // this block's group's regions, one per tile: claim cursors and ends (in
+  // words from the job's codes)
+  const size_t grow = (size_t)(blockIdx.x % BIN_GROUPS) * J.nbins;
+  const TileState TS = tile_state(J.tst, J.nbins);
+  GMEM uint32_t *gcur = gmem(J.gcur) + grow;
+  const GMEM uint32_t *rend = gmem(TS.capg) + grow;
   for (uint32_t t = threadIdx.x; t < TMAX; t += blockDim.x) cnt[t] = 0;
   __syncthreads();
   const size_t p0 = (size_t)lb * J.chunk;
@@ -460,7 +560,10 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
     const uint32_t t0 = tid * TPT;                      // tiles this thread keeps
     // ranks are < BATCH <= 2^15: two per register
     uint32_t v[PPT * R], rk2[(PPT * R + 1) / 2];
-    // 1: codes and their rank inside their tile's run of this batch
+    // 1: codes and their rank inside their tile's run of this batch (an
+    // LDS atomic that returns the rank; a plain count here and a returning
+    // placement cursor in step 3 instead was slower: 692 against 608 us
+    // for the 100M-pair window)
 #pragma unroll
     for (int k = 0; k < PPT; k++) {
       const size_t i = i0 + (size_t)k * blockDim.x + tid;
@@ -479,26 +582,29 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
     }
     load(i0 + step, tid);
     __syncthreads();
-    // 2: claim each tile's run, ceil(c / 3) words, in the group's stream
-    // (the claims' latency is hidden behind the scan and step 3); run
-    // starts; the pad slots of each run get the marker ~0
-    uint32_t c[TPT], run[TPT], sum = 0;
+    // 2: claim each tile's run, ceil(c / 3) words, in the group's region,
+    // and read the region's end (the latency of both is hidden behind the
+    // scan and step 3); run starts; the pad slots of each run get the
+    // marker ~0. The counts stay in cnt and the claimed positions wait in
+    // dst (the scan is done with it) until after the grouping: held in
+    // registers through it they would not fit the 6-pair, 5-row variant
+    uint32_t run[TPT], end[TPT], sum = 0;
 #pragma unroll
     for (uint32_t u = 0; u < TPT; u++) {
-      c[u] = cnt[t0 + u];                   // 0 for the LDS slots past the tiles
-      const uint32_t w = (c[u] + 2) / 3;
+      const uint32_t w = (cnt[t0 + u] + 2) / 3;       // 0 for the slots past the tiles
       sum += 3 * w;
       run[u] = w ? atomicAdd((uint32_t *)&gcur[t0 + u], w) : 0;
+      end[u] = w ? rend[t0 + u] : 0;
     }
     uint32_t total;
     uint32_t ex = blk_scan_1024(sum, &total, sh, tid);
 #pragma unroll
     for (uint32_t u = 0; u < TPT; u++) {
-      const uint32_t t = t0 + u, padded = 3 * ((c[u] + 2) / 3);
+      const uint32_t t = t0 + u, c = cnt[t], padded = 3 * ((c + 2) / 3);
       lofs[t] = ex;
-      cnt[t] = 0;
-      if (padded > c[u]) sorted[ex + c[u]] = ~0u;         // at most two pad slots
-      if (padded > c[u] + 1) sorted[ex + c[u] + 1] = ~0u;
+      dst[t] = run[u];
+      if (padded > c) sorted[ex + c] = ~0u;             // at most two pad slots
+      if (padded > c + 1) sorted[ex + c + 1] = ~0u;
       ex += padded;
     }
     __syncthreads();
@@ -506,8 +612,27 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
 #pragma unroll
     for (int q = 0; q < PPT * R; q++)
       if (FULL || v[q] != ~0u) sorted[lofs[v[q] >> BIN_TILE_LOG2] + get_rank(rk2, q)] = v[q];
+    // a run that fits its region goes there; one that does not goes whole
+    // to the spill area (the run that crosses the region's end marks where
+    // the region's written part ends) and joins its tile's spill runs
 #pragma unroll
-    for (uint32_t u = 0; u < TPT; u++) dst[t0 + u] = run[u] - lofs[t0 + u] / 3;
+    for (uint32_t u = 0; u < TPT; u++) {
+      const uint32_t t = t0 + u;
+      const uint32_t w = (cnt[t] + 2) / 3;
+      cnt[t] = 0;                                       // for the next batch
+      if (!w) continue;
+      const uint32_t pos = dst[t];
+      uint32_t at = pos;
+      if (pos + w > end[u]) {
+        if (pos < end[u]) gmem(TS.fill)[grow + t] = pos;
+        const uint32_t so = atomicAdd((uint32_t *)TS.spill_cur, w);
+        const uint32_t d = atomicAdd((uint32_t *)&TS.dcnt[t], 1u);
+        J.desc[(size_t)t * J.dmax + d] = make_uint2(so, w);
+        atomicAdd((uint32_t *)&TS.swords[t], w);
+        at = (uint32_t)J.rcap + so;
+      }
+      dst[t] = at - lofs[t] / 3;
+    }
     __syncthreads();
     // 4: write the words; batch word j holds sorted slots 3j..3j+2, whose
     // first is always a code of the run and stands in for a pad (a code
@@ -557,6 +682,36 @@ __device__ __forceinline__ void or_word(uint32_t *tile, uint2 w) {
   atomicOr(&tile[c >> 5], 1u << (c & 31));
 }
 
+// The code words [c0, c1) of one region or spill run into the LDS tile: a
+// single word up to an even index, uint4 bodies (two words each; whole
+// rounds of APPLY_UNROLL per thread with no bounds test, then one at a
+// time), a single word at the end.
+__device__ __forceinline__ void apply_words(uint32_t *tile, const GMEM uint2 *__restrict__ codes,
+                                            uint32_t c0, uint32_t c1) {
+  const uint32_t a0 = (c0 & 1) && c0 < c1 ? c0 + 1 : c0;
+  const uint32_t a1 = a0 + ((c1 - a0) & ~1u);
+  if (threadIdx.x == 0 && a0 != c0) or_word(tile, ld2(codes + c0));
+  if (threadIdx.x == 0 && a1 != c1) or_word(tile, ld2(codes + a1));
+  const GMEM uint4 *q = reinterpret_cast<const GMEM uint4 *>(codes + a0);
+  const uint32_t nq = (a1 - a0) / 2;
+  uint32_t i = threadIdx.x;
+  for (; i + (APPLY_UNROLL - 1) * blockDim.x < nq; i += blockDim.x * APPLY_UNROLL) {
+    uint4 x[APPLY_UNROLL];
+#pragma unroll
+    for (int u = 0; u < APPLY_UNROLL; u++) x[u] = ld4(q + i + u * blockDim.x);
+#pragma unroll
+    for (int u = 0; u < APPLY_UNROLL; u++) {
+      or_word(tile, make_uint2(x[u].x, x[u].y));
+      or_word(tile, make_uint2(x[u].z, x[u].w));
+    }
+  }
+  for (; i < nq; i += blockDim.x) {
+    const uint4 x = ld4(q + i);
+    or_word(tile, make_uint2(x.x, x.y));
+    or_word(tile, make_uint2(x.z, x.w));
+  }
+}
+
 __global__ __launch_bounds__(1024) void k_bin_apply(const UpdJob *__restrict__ jobs, uint32_t nj,
                                                     const uint32_t *__restrict__ n_items_p) {
   __shared__ __attribute__((aligned(16))) uint32_t tile[BIN_TILE_WORDS];
@@ -566,13 +721,15 @@ __global__ __launch_bounds__(1024) void k_bin_apply(const UpdJob *__restrict__ j
   for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const UpdJob &J = jobs[job_of_item(jobs, nj, it)];
     const uint32_t jit = it - J.item0;
-    const GMEM uint32_t *item_start = gmem(J.item_start), *base = gmem(J.base);
+    const GMEM uint32_t *item_start = gmem(J.item_start);
     const uint32_t t = gmem(J.item_tile)[jit];                // tile of this item
     const uint32_t sub = jit - item_start[t];
     const bool whole = item_start[t + 1] - item_start[t] == 1;
-    const uint32_t c_end = base[t + 1];
-    const uint32_t c0 = whole ? base[t] : base[t] + sub * APPLY_ITEM;
-    const uint32_t c1 = whole ? c_end : (c_end - c0 > APPLY_ITEM ? c0 + APPLY_ITEM : c_end);
+    // this item's words of the tile's code stream: its regions in group
+    // order, then its spill runs
+    const uint32_t v_end = gmem(J.totals)[t];
+    const uint32_t v0 = whole ? 0 : sub * APPLY_ITEM;
+    const uint32_t v1 = whole ? v_end : (v_end - v0 > APPLY_ITEM ? v0 + APPLY_ITEM : v_end);
     const size_t w0 = (size_t)t * BIN_TILE_WORDS;
     const uint32_t tw = (uint32_t)(J.words - w0 < BIN_TILE_WORDS ? J.words - w0 : BIN_TILE_WORDS);
     const GMEM uint2 *__restrict__ codes = gmem(reinterpret_cast<const uint2 *>(J.codes));
@@ -597,31 +754,26 @@ __global__ __launch_bounds__(1024) void k_bin_apply(const UpdJob *__restrict__ j
       for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) tile[w] = dstp[w];
     }
     __syncthreads();
-    // words [c0,c1): a single word up to an even index, uint4 body (two
-    // words), a single word at the end
-    const uint32_t a0 = (c0 & 1) && c0 < c1 ? c0 + 1 : c0;
-    const uint32_t a1 = a0 + ((c1 - a0) & ~1u);
-    if (threadIdx.x == 0 && a0 != c0) or_word(tile, ld2(codes + c0));
-    if (threadIdx.x == 0 && a1 != c1) or_word(tile, ld2(codes + a1));
-    const GMEM uint4 *q = reinterpret_cast<const GMEM uint4 *>(codes + a0);
-    const uint32_t nq = (a1 - a0) / 2;
-    // whole rounds of APPLY_UNROLL uint4 per thread with no bounds test,
-    // then the rest one uint4 at a time
-    uint32_t i = threadIdx.x;
-    for (; i + (APPLY_UNROLL - 1) * blockDim.x < nq; i += blockDim.x * APPLY_UNROLL) {
-      uint4 x[APPLY_UNROLL];
-#pragma unroll
-      for (int u = 0; u < APPLY_UNROLL; u++) x[u] = ld4(q + i + u * blockDim.x);
-#pragma unroll
-      for (int u = 0; u < APPLY_UNROLL; u++) {
-        or_word(tile, make_uint2(x[u].x, x[u].y));
-        or_word(tile, make_uint2(x[u].z, x[u].w));
+    {
+      const TileState S = tile_state(J.tst, J.nbins);
+      const uint32_t nd = gmem(S.dcnt)[t];
+      uint32_t vo = 0;                                  // stream offset of the segment
+      for (uint32_t sg = 0; sg < BIN_GROUPS + nd && vo < v1; sg++) {
+        uint32_t off, len;
+        if (sg < BIN_GROUPS) {
+          const size_t x = (size_t)sg * J.nbins + t;
+          const uint32_t c = gmem(J.gcur)[x], f = gmem(S.fill)[x];
+          off = gmem(S.regb)[x];
+          len = (c < f ? c : f) - off;
+        } else {
+          const uint2 d = ld2(gmem(J.desc) + (size_t)t * J.dmax + (sg - BIN_GROUPS));
+          off = (uint32_t)J.rcap + d.x;
+          len = d.y;
+        }
+        const uint32_t a = v0 > vo ? v0 : vo, b = v1 < vo + len ? v1 : vo + len;
+        if (a < b) apply_words(tile, codes, off + (a - vo), off + (b - vo));
+        vo += len;
       }
-    }
-    for (; i < nq; i += blockDim.x) {
-      const uint4 x = ld4(q + i);
-      or_word(tile, make_uint2(x.x, x.y));
-      or_word(tile, make_uint2(x.z, x.w));
     }
     __syncthreads();
     // a tile with one item is final here: its LEs' zero counts go out too
@@ -705,14 +857,15 @@ __global__ __launch_bounds__(256) void k_bin_merge(const UpdJob *__restrict__ jo
 
 // ---------------------------------------------------------------- launch
 
-// count, the two scans and the scatter of a binned round
+// count, the region layout, the scatter and the apply items of a binned round
 template <int R, int PPT, int TMAX>
 static void launch_front(UpdJob *d, uint32_t nj, uint32_t blocks, uint32_t tiles,
                          hipStream_t st) {
   k_bin_count<R, PPT><<<blocks, 1024, 0, st>>>(d, nj);
   k_bin_scan_cols<<<tiles, 1024, 0, st>>>(d, nj);
-  k_bin_scan_tiles<<<nj, 1024, 0, st>>>(d);
+  k_bin_layout<<<nj, 1024, 0, st>>>(d);
   k_bin_scatter<R, PPT, TMAX><<<blocks, 1024, 0, st>>>(d, nj);
+  k_bin_items<<<nj, 1024, 0, st>>>(d);
 }
 
 template <int R>
@@ -732,8 +885,9 @@ static hipError_t launch_r(const UpdJob *h, UpdJob *d, uint32_t nj, uint32_t *d_
   // LDS of the scatter: 4*(1024*PPT*r + 2*TMAX) bytes of sorted codes +
   // 12*TMAX bytes of tile arrays <= 160 KiB. Up to 2048 tiles: 6 pairs per
   // thread for r <= 5, 4 for r <= 7, else 2. Up to 3072 tiles and r <= 5: 5.
-  // Up to 4095 tiles: 4 for r <= 5, else 2. The count pass walks the
-  // scatter's batches, so both take the same PPT.
+  // Up to 4095 tiles: 4 for r <= 5, else 2 (scatter_ppt gives the same
+  // choice to the host, which sizes the spill-run lists by it). The count
+  // pass walks the scatter's batches, so both take the same PPT.
   uint32_t max_tiles = 0;
   for (uint32_t j = 0; j < nj; j++) max_tiles = max_tiles > h[j].nbins ? max_tiles : h[j].nbins;
   if (max_tiles <= 2048) {

@@ -48,6 +48,8 @@ SKETCH_OPT_TRIM_POOLS = 8
 SKETCH_OPT_APPLY_BLOCKS = 9
 SKETCH_OPT_TIMING = 10
 SKETCH_OPT_CANDIDATES = 11
+SKETCH_OPT_BINNED_SAMPLE = 12
+SKETCH_OPT_BINNED_REGIONS = 13
 
 c_u32, c_u64, c_i32, c_sz, c_dbl, c_vp = (ctypes.c_uint32, ctypes.c_uint64,
                                           ctypes.c_int32, ctypes.c_size_t,
@@ -75,7 +77,9 @@ class sketch_timings_t(ctypes.Structure):
     _fields_ = [("hot_scan_ms", ctypes.c_float), ("rows_ms", ctypes.c_float),
                 ("join_ms", ctypes.c_float), ("estimate_ms", ctypes.c_float),
                 ("sort_publish_ms", ctypes.c_float), ("hot_scan_bytes", c_u64),
-                ("join_probes", c_u64), ("join_outputs", c_u64), ("estimate_bytes", c_u64)]
+                ("join_probes", c_u64), ("join_outputs", c_u64), ("estimate_bytes", c_u64),
+                ("search", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("lattice_points", c_u64)]
 
 
 class sketch_update_job_t(ctypes.Structure):

@@ -276,13 +276,14 @@ class ContinuousServer(_Server):
         return sorted(out, key=lambda r: r.rid)
 
     def overlaps(self) -> int:
-        """Batches whose update had finished on the device before the
-        previous batch's restore had (from the trace's timing events): the
-        update of one batch ran while an earlier batch restored."""
+        """Batches whose work began on the device before the previous batch's
+        restore had ended (from the trace's timing events: the start marker
+        on the batch's own stream against the previous batch's restore end
+        on the other stream): the two batches were on the GPU together."""
         torch.cuda.synchronize(self.dev)
         n = 0
         for (base, ev, _), (_, prev, _) in zip(self.trace[1:], self.trace[:-1]):
-            if base.elapsed_time(ev[1]) < base.elapsed_time(prev[2]):
+            if base.elapsed_time(ev[0]) < base.elapsed_time(prev[2]):
                 n += 1
         return n
 

@@ -27,12 +27,21 @@ def test_cpu_baseline_leg_reports_the_oracle():
 def test_restore_roofline_arithmetic():
     t = {"hot_scan_ms": 0.01, "rows_ms": 0.02, "join_ms": 0.1, "estimate_ms": 0.01,
          "sort_publish_ms": 0.01, "hot_scan_bytes": 8e7, "join_probes": 1e6,
-         "join_outputs": 2e6, "estimate_bytes": 6.4e6}
+         "join_outputs": 2e6, "estimate_bytes": 6.4e6, "search": 1, "lattice_points": 0}
     rr = bench.restore_roofline([t, t, t])
     assert rr["hot_scan"]["achieved"] == 8000.0 and rr["hot_scan"]["frac"] == 1.0
     ops = bench.JOIN_LDS_OPS_PER_OUTPUT * 2e6 + bench.JOIN_LDS_OPS_PER_PROBE * 1e6
-    assert abs(rr["join"]["achieved"] - ops / 1e-4 / 1e12) < 1e-3
+    cs = rr["candidate_search"]
+    assert cs["kind"] == "join" and cs["bound"] == "lds"
+    assert abs(cs["achieved"] - ops / 1e-4 / 1e12) < 1e-3
     assert rr["estimate"]["achieved"] == 640.0
+    # the lattice search: integer operations per address walked vs the ALU peak
+    t2 = dict(t, search=2, join_probes=0, join_outputs=5000, lattice_points=1e8)
+    cs = bench.restore_roofline([t2])["candidate_search"]
+    assert cs["kind"] == "lattice" and cs["bound"] == "alu"
+    assert bench.VALU_LANE_OPS_PEAK == 256 * 64 * 2.4e9
+    assert abs(cs["achieved"] - bench.LATTICE_OPS_PER_POINT * 1e8 / 1e-4 / 1e12) < 1e-3
+    assert abs(cs["frac"] - bench.LATTICE_OPS_PER_POINT * 1e12 / bench.VALU_LANE_OPS_PEAK) < 1e-5
 
 
 def test_more_than_one_gpu_is_refused():

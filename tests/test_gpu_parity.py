@@ -151,6 +151,55 @@ def test_binned_rounds_and_split_tiles():
             assert np.array_equal(sk.download(), ref), rnd
 
 
+@pytest.mark.parametrize("sample,regions", [(1, 0), (0, 0), (64, 0), (0, 1), (0, 32), (1024, 1)],
+                         ids=["exact", "auto", "one-batch", "all-spill", "half", "one-batch-spill"])
+def test_binned_regions_and_spill_runs(sample, regions):
+    """The count pass sizes each (block group, tile) region of code words
+    from a sample of the batches; a run that does not fit its region goes
+    to the spill area. Exact counts, sampled estimates, a one-batch
+    estimate and regions far too small (nearly every run spills) give the
+    oracle's sketch: the window's first update after a reset (tiles built
+    from zeros), a second update on top, tiles cut into several apply
+    items, a batch of two sketches, and the restore from the kept zero
+    counts."""
+    say(f"binned regions sample={sample} regions={regions}")
+    p = oracle.Params(1024, 18, 5, 5)
+    rng = np.random.default_rng(77)
+    hosts = rng.choice(2**32, size=5, replace=False).astype(np.uint32)
+    heavy = np.stack([np.full(1_200_000, hosts[0], dtype=np.uint32),
+                      rng.integers(0, 2**32, size=1_200_000, dtype=np.uint64).astype(np.uint32)], 1)
+    pairs = np.concatenate([rand_pairs(rng, 2_000_000, 100_000), heavy] + planted(rng, hosts[1:], 3000))
+    pairs = pairs[rng.permutation(len(pairs))]
+    ref = oracle.build_sketch(p, pairs)
+    q = oracle.Params()
+    pairs2 = rand_pairs(rng, 400_001, 20_000)
+    ref2 = oracle.build_sketch(q, pairs2)
+    d, d2 = to_dev(pairs), to_dev(pairs2)
+    with make_sketch(p, 2) as sk, make_sketch(q, 2) as sk2:
+        for s_ in (sk, sk2):
+            s_.set_option(ddhf.SKETCH_OPT_BINNED_SAMPLE, sample)
+            s_.set_option(ddhf.SKETCH_OPT_BINNED_REGIONS, regions)
+        sk.reset()
+        sk.update(d)
+        torch.cuda.synchronize()
+        assert np.array_equal(sk.download(), ref)
+        recs, info = sk.restore(1024.0)
+        ip, sz, c, _ = oracle.restore(p, ref, 1024.0)
+        assert_not_boundary(info)
+        assert_spl_equal(recs, ip, sz, c)
+        assert set(hosts.tolist()) <= set(recs["ip"].tolist())
+        # a second update on top of the written sketch, batched with another
+        # sketch's window
+        sk.reset()
+        sk2.reset()
+        n3 = len(pairs) // 3
+        ddhf.update_batch([(sk, d[:n3]), (sk2, d2)])
+        ddhf.update_batch([(sk, d[n3:])])
+        torch.cuda.synchronize()
+        assert np.array_equal(sk.download(), ref)
+        assert np.array_equal(sk2.download(), ref2)
+
+
 @pytest.mark.parametrize("p", [oracle.Params(1024, 19, 5, 5), oracle.Params(2048, 18, 7, 3)],
                          ids=lambda p: f"g{p.g}k{p.k}r{p.r}a{p.alpha}")
 def test_binned_sketch_over_2048_tiles(p):
@@ -168,6 +217,8 @@ def test_binned_sketch_over_2048_tiles(p):
     for ppt in (4, 2):
         with make_sketch(p, 2) as sk:
             sk.set_option(ddhf.SKETCH_OPT_SCATTER_PPT, ppt)
+            if ppt == 2:                    # regions far too small: runs spill
+                sk.set_option(ddhf.SKETCH_OPT_BINNED_REGIONS, 1)
             sk.update(to_dev(pairs))
             torch.cuda.synchronize()
             assert np.array_equal(sk.download(), ref), ppt
@@ -321,7 +372,8 @@ def test_set_option_rejects_bad_values():
         for opt, val in ((ddhf.SKETCH_OPT_UPDATE_PATH, 3), (ddhf.SKETCH_OPT_UPDATE_GRID, 0),
                          (ddhf.SKETCH_OPT_BINNED_ROUND, 10),
                          (ddhf.SKETCH_OPT_TRIM_POOLS, -1), (ddhf.SKETCH_OPT_APPLY_BLOCKS, -1),
-                         (99, 1)):
+                         (ddhf.SKETCH_OPT_BINNED_SAMPLE, 1025),
+                         (ddhf.SKETCH_OPT_BINNED_REGIONS, -1), (99, 1)):
             with pytest.raises(ddhf.SketchError) as e:
                 sk.set_option(opt, val)
             assert e.value.code == ddhf.SKETCH_E_INVAL
@@ -462,6 +514,42 @@ def test_more_super_points_than_the_small_sort():
     assert_not_boundary(info)
     assert_spl_equal(recs, ip, sz, c)
     assert np.array_equal(again, recs)
+
+
+def crafted_hot_sketch(p: oracle.Params, frac: float, seed: int) -> np.ndarray:
+    """A sketch in which a random fraction of each row's LEs have every bit
+    set (z0 = 0: hot at any theta) and the rest none: every address whose r
+    LEs are among them is a candidate with SZ = 0, reported with C = +inf;
+    about 2^32 * frac^r of them."""
+    rng = np.random.default_rng(seed)
+    w = p.g // 32
+    words = np.zeros(p.words(), dtype=np.uint32).reshape(p.r, 1 << p.k, w)
+    words[rng.random((p.r, 1 << p.k)) < frac] = 0xFFFFFFFF
+    return words.reshape(-1)
+
+
+@pytest.mark.parametrize("frac", [0.086, 0.136], ids=["20k", "200k"])
+def test_long_lists_sort(frac):
+    """Lists far past the small sort: the candidates and the records of a
+    crafted sketch (about 20k and 200k of each) come out sorted and equal
+    to the oracle's; the restore is timed."""
+    import time
+    p = oracle.Params()
+    ref = crafted_hot_sketch(p, frac, 41)
+    with make_sketch(p) as sk:
+        sk.upload(ref)
+        cand = sk.candidates(1024.0)
+        sk.restore(1024.0)                      # buffers grown to the list
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        recs, info = sk.restore(1024.0)
+        ms = (time.perf_counter() - t0) * 1e3
+    say(f"  {len(recs)} records, {len(cand)} candidates, restore {ms:.3f} ms")
+    assert len(recs) > 16384 and len(cand) == len(recs)
+    assert np.array_equal(cand, oracle.candidates(p, ref, 1024.0, "brute"))
+    ip, sz, c, _ = oracle.restore(p, ref, 1024.0, mode="brute")
+    assert_spl_equal(recs, ip, sz, c)
+    assert np.all(np.diff(recs["ip"].astype(np.int64)) > 0)
 
 
 def test_empty_and_saturated_sketch():

@@ -30,11 +30,25 @@ def test_restore_timings():
         # a fresh binned update kept the zero counts: 4 bytes per LE
         assert t["hot_scan_bytes"] == 4 * n_le
         he = info["he_count"]
-        parts = info["n_partials"]
-        assert t["join_probes"] == he[0] * he[1] + sum(parts[2:p.r - 1])
-        assert t["join_outputs"] == sum(parts[2:p.r - 1]) + info["n_candidates"]
         assert t["estimate_bytes"] == info["n_candidates"] * p.r * p.g // 8
         assert len(recs) >= len(hosts)
+        # each candidate search reports its own work
+        for path in (1, 2):
+            sk.set_option(ddhf.SKETCH_OPT_CANDIDATES, path)
+            again, info = sk.restore(700.0)
+            assert np.array_equal(again, recs)
+            t = ddhf.sketch_timings(sk.handle)
+            parts = info["n_partials"]
+            assert t["search"] == path
+            if path == 1:
+                assert t["join_probes"] == he[0] * he[1] + sum(parts[2:p.r - 1])
+                assert t["join_outputs"] == sum(parts[2:p.r - 1]) + info["n_candidates"]
+                assert t["lattice_points"] == 0
+            else:
+                assert t["join_probes"] == 0 and not any(parts)
+                assert t["join_outputs"] == info["n_candidates"]
+                assert t["lattice_points"] == he[0] << (32 - p.k)
+        sk.set_option(ddhf.SKETCH_OPT_CANDIDATES, 0)
         # after a direct update the hot scan reads the sketch itself
         sk.set_option(ddhf.SKETCH_OPT_UPDATE_PATH, 1)
         sk.update(to_dev(pairs[:1000]))

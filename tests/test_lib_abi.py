@@ -43,7 +43,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(ddhf.sketch_update_job_t) == 24
     assert ctypes.sizeof(ddhf.sketch_restore_job_t) == 56
     assert ctypes.sizeof(ddhf.sketch_plan_job_t) == 32
-    assert ctypes.sizeof(ddhf.sketch_timings_t) == 56
+    assert ctypes.sizeof(ddhf.sketch_timings_t) == 72
 
 
 def test_params_default_check_and_bytes(L):

@@ -488,6 +488,17 @@ def log(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
+def _line(value, steps, warmup, ms_per_step, config, extra) -> None:
+    """The one JSON line of a --workload run other than the headline: value
+    in Mpps for that workload, its config, and its own fields."""
+    out = {"metric": METRIC, "value": round(value, 3), "unit": "Mpps", "n_gpus": 1,
+           "steps": steps, "warmup": warmup, "ms_per_step": round(ms_per_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+           "data": "synthetic", "config": config}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
 def batched_links(dev, n_links=64, seed=0x640):
     """The links of the batched workload: (n_pairs, zipf_s, n_planted, theta,
     pairs tensor) each, windows log-uniform in [1e6, 2e8] pairs."""

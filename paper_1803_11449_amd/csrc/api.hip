@@ -374,6 +374,8 @@ int ctx_acquire(int dev, int n_cu, DevCtx **out) {
     if (!rc) rc = lane_init(c->pool_lane);
     if (!rc) rc = lane_init(c->arena_lane);
     if (!rc) rc = lane_init(c->noalloc_lane);
+    if (!rc && prepare_restore_kernels() != hipSuccess)
+      rc = fail(SKETCH_E_HIP, "device context: restore kernel attributes");
     // the caller made dev current: this is dev's copy of the array
     if (!rc && hipGetSymbolAddress((void **)&c->noalloc, HIP_SYMBOL(scratch)) != hipSuccess) {
       c->noalloc = nullptr;
@@ -716,6 +718,9 @@ int materialize(sketch *s, hipStream_t st) {
   s->lez_valid = false;
   return SKETCH_OK;
 }
+
+// Enqueue the restore kernels on buffers B, whose shared part is ordered by
+// `pool`, and the copy of the device state (no wait). Caller holds ctx->mu.
 
 // Enqueue the restore kernels on buffers B, whose shared part is ordered by
 // `pool`, and the copy of the device state (no wait). Caller holds ctx->mu.

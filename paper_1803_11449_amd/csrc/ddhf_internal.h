@@ -279,6 +279,9 @@ hipError_t launch_or_u32(uint32_t *dst, const uint32_t *src, size_t n_words, int
                          hipStream_t st);
 
 // ---- launchers (restore.hip) ----
+// Once per device, before any restore (and outside graph capture): lets the
+// lattice search take more than 64 KiB of LDS.
+hipError_t prepare_restore_kernels();
 // Runs every restore step up to and including the candidate list (and, when
 // estimate != 0, the estimate, report filter and sort). All counts stay on
 // the device; the caller reads DevState afterwards.

@@ -1194,15 +1194,9 @@ static hipError_t launch_wpl(const Geom &G, const uint32_t *sketch, const Restor
   // 5: candidates, by the lattice search or the join (each kernel returns
   // at once unless its search is the chosen one)
   if (B.lat.ok) {
-    const size_t lds = ((size_t)4 << (k - 5)) + LAT_QUEUE_BYTES;   // row 1's bitmap, queues
-    static bool lds_raised = false;                   // above 64 KiB needs the attribute
-    if (lds > 65536 && !lds_raised) {
-      if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_lattice),
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)LATTICE_LDS_MAX) != hipSuccess)
-        return hipErrorInvalidValue;
-      lds_raised = true;
-    }
+    // row 1's bitmap and the queues (above 64 KiB by the attribute that
+    // prepare_restore_kernels sets)
+    const size_t lds = ((size_t)4 << (k - 5)) + LAT_QUEUE_BYTES;
     // half the usual grid: each block first copies row 1's bitmap
     k_lattice<<<grid > 1 ? grid / 2 : 1, LAT_THREADS, lds, st>>>(
         G, B.lat, B.cand_path, B.he, B.hotmask, B.st, B.cand, B.cand_cap);
@@ -1253,6 +1247,11 @@ static hipError_t launch_wpl(const Geom &G, const uint32_t *sketch, const Restor
                                 B.h_recs_cap);
   mark(5);
   return hipGetLastError();
+}
+
+hipError_t prepare_restore_kernels() {
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(k_lattice),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)LATTICE_LDS_MAX);
 }
 
 hipError_t launch_restore(const Geom &G, const uint32_t *sketch, const RestoreBufs &B,

@@ -57,3 +57,16 @@ def test_workload_choices_are_listed():
     assert r.returncode == 0
     for w in ("large_window_100m", "batched_64_links", "serving_256_links"):
         assert w in r.stdout
+
+
+def test_workload_line_has_the_contract_fields(capsys):
+    """The --workload modes print one JSON line through bench._line."""
+    import json
+    bench._line(1234.5678, 5, 1, 52.61, {"workload": "batched_64_links"},
+                {"plan_update_launches": 18})
+    line = json.loads(capsys.readouterr().out.strip())
+    for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config"):
+        assert key in line, key
+    assert line["value"] == 1234.568 and line["config"]["workload"] == "batched_64_links"
+    assert line["plan_update_launches"] == 18

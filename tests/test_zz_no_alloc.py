@@ -103,3 +103,26 @@ def test_noalloc_capacity_and_bad_arguments():
         sk.set_option(ddhf.SKETCH_OPT_CANDIDATES, 1)
         got, _ = sk.restore_noalloc(1024.0)
     assert_same(got, ref)
+
+
+def test_noalloc_join_beyond_the_array():
+    """A crafted sketch with about a thousand hot LEs per row: the join's
+    partial addresses (millions) outgrow the fixed array. Forced to the
+    join, the call fails with CAPACITY; left to choose, it takes the
+    lattice search and gives sketch_restore's list."""
+    p = oracle.Params()
+    rng = np.random.default_rng(43)
+    words = np.zeros(p.words(), dtype=np.uint32).reshape(p.r, 1 << p.k, p.g // 32)
+    words[rng.random((p.r, 1 << p.k)) < 0.06] = 0xFFFFFFFF
+    with ddhf.Sketch(p.g, p.k, p.r, p.alpha, p.seed, device=0) as sk:
+        sk.upload(words.reshape(-1))
+        ref, _ = sk.restore(1024.0)
+        got, _ = sk.restore_noalloc(1024.0)
+        assert_same(got, ref)
+        sk.set_option(ddhf.SKETCH_OPT_CANDIDATES, 1)
+        with pytest.raises(ddhf.SketchError) as e:
+            sk.restore_noalloc(1024.0)
+        assert e.value.code == ddhf.SKETCH_E_CAPACITY
+        assert "partial addresses" in str(e.value)
+        again, _ = sk.restore(1024.0)           # the growing restore still serves it
+    assert_same(again, ref)

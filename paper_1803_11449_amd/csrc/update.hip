@@ -170,7 +170,7 @@ __device__ __forceinline__ void count_pair(const Geom &G, uint2 p, uint32_t *h) 
 // scatter (PPT pairs per thread of 1024, from the start of the block's
 // chunk), but only every J.sample-th of them, adds ceil(c / 3) for a
 // sampled batch with c codes in the tile and scales the sum by the
-// block's batches over its sampled ones (exact for J.sample = 1).
+// block's pairs over its sampled batches' pairs (exact for J.sample = 1).
 //
 // A full batch's pairs are read as uint4 (two pairs per lane per load)
 // when PPT is even; a job's pairs start 16-byte aligned and its chunks and
@@ -279,11 +279,13 @@ void k_bin_count(const UpdJob *__restrict__ jobs, uint32_t nj) {
     }
     close_batch();
   }
-  // sampled: scaled by the chunk's batches over the sampled ones (an
-  // estimate, in float); every batch: the exact count
-  const uint32_t nb = p1 > p0 ? (uint32_t)((p1 - p0 + step - 1) / step) : 0;
-  const uint32_t ns = (nb + J.sample - 1) / J.sample;
-  const float scale = ns ? (float)nb / (float)ns : 0.f;
+  // sampled: scaled by the chunk's pairs over the sampled batches' pairs
+  // (an estimate, in float; a chunk's last batch is partial, so a count of
+  // batches would under- or overweight it); every batch: the exact count
+  const size_t len = p1 > p0 ? p1 - p0 : 0, nfull = len / step, rem = len - nfull * step;
+  const size_t sampled = (nfull + J.sample - 1) / J.sample * step +
+                         (rem && nfull % J.sample == 0 ? rem : 0);
+  const float scale = sampled ? (float)len / (float)sampled : 0.f;
   GMEM uint32_t *hist = gmem(J.hist);
 #pragma unroll
   for (uint32_t u = 0; u < TPT; u++)

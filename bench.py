@@ -339,6 +339,28 @@ def headline(args, dev) -> dict:
     return out
 
 
+def config1_oracle_leg(pairs, gpu_recs) -> dict:
+    """The oracle on one host thread over the whole 1M-pair window: Alg. 1
+    as a sequential loop, then Alg. 2's restore with the candidates from
+    the join of Algs. 3-4 (the paper's own restore, not the 2^32 scan),
+    and whether its list equals the GPU's."""
+    import numpy as np
+    import oracle
+    from paper_1803_11449_amd import traffic
+    host = pairs.cpu().numpy().view(np.uint32).reshape(-1)
+    p = oracle.Params(1024, 14, 5, 6, traffic.HASH_SEED)
+    t0 = time.perf_counter()
+    sk = oracle.build_sketch(p, host)
+    t1 = time.perf_counter()
+    ip, sz, _, _ = oracle.restore(p, sk, 1024.0, mode="join", nthreads=1)
+    t2 = time.perf_counter()
+    same = bool(np.array_equal(ip, gpu_recs["ip"]) and np.array_equal(sz, gpu_recs["sz"]))
+    return {"kind": "oracle", "threads": 1, "update_s": round(t1 - t0, 4),
+            "restore_join_s": round(t2 - t1, 4),
+            "step_mpps": round(len(host) / 2 / (t2 - t0) / 1e6, 3),
+            "same_list_as_gpu": same}
+
+
 def config1_run(args, dev) -> dict:
     """The 1M-pair single window on the default sketch: update rate (HIP
     events, median of 30), restore latency (window close to list on the
@@ -370,8 +392,11 @@ def config1_run(args, dev) -> dict:
             sk.update(w.pairs)
             sk.restore(1024.0)
         step = (time.perf_counter() - t0) / 30
+    out = {}
+    if not args.no_cpu_baseline:
+        out["cpu_oracle"] = config1_oracle_leg(w.pairs, recs)
     return {"workload": "single_window_1m", "n_pairs": n, "g": 1024, "k": 14, "r": 5,
-            "alpha": 6, "theta": 1024.0,
+            "alpha": 6, "theta": 1024.0, **out,
             "update_ms_p50": round(percentile(upd, 50), 4),
             "update_mpps": round(n / (percentile(upd, 50) / 1e3) / 1e6, 1),
             "restore_ms_p50": round(percentile(lat, 50), 4),

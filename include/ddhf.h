@@ -306,8 +306,8 @@ int sketch_merge(sketch_t *dst, const sketch_t *src, void *hip_stream);
 /* Options of sketch_set_option. The update has two kernels computing the
  * same sketch: "direct" (each pair sets its r bits with a check-then-
  * atomicOr in the sketch, Alg. 1 as written) and "binned" (the bit sets are
- * grouped by 128 KiB tile of the sketch and applied in LDS, one workgroup
- * per tile or part of a tile). */
+ * grouped by 160 KiB tile of the sketch and applied in LDS, one workgroup
+ * per tile or part of a tile; sketches of up to 3276 tiles, 511.9 MiB). */
 enum {
   SKETCH_OPT_UPDATE_PATH = 1,       /* 0 = choose by size (default),
                                        1 = direct, 2 = binned */
@@ -325,7 +325,7 @@ enum {
                                        sorting batch: 2, 4 or 6 (default);
                                        capped by LDS at 4 for r in 6..7 and
                                        at 2 for r = 8. Sketches of more than
-                                       2048 tiles (of 128 KiB) take 5 for
+                                       2048 tiles (of 160 KiB) take 5 for
                                        r <= 5 up to 3072 tiles and 4 above
                                        (4 and 6 both ask for that), and 2
                                        for r >= 6 */

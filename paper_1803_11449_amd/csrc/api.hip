@@ -869,6 +869,7 @@ struct Group {
   uint32_t check;
   uint32_t ppt;
   uint32_t apply_grid;
+  bool wide;                    // binned: more than 2048 tiles per sketch
   std::vector<UpdJob> jobs;
 };
 
@@ -953,16 +954,20 @@ int flush_group(DevCtx *c, Group &g, hipStream_t st) {
   return SKETCH_OK;
 }
 
+// Binned jobs share a launch only with sketches of the same tile class: the
+// launch's largest sketch picks the scatter variant, and one of more than
+// 2048 tiles would hold every job of the launch to its smaller batches.
 void add_job(std::vector<Group> &groups, const sketch *s, const UpdJob &J, bool binned) {
+  const bool wide = binned && s->nbins > 2048;
   for (Group &g : groups)
-    if (g.r == s->p.r && g.binned == binned && (binned ? g.ppt == s->scatter_ppt
-                                                       : g.check == J.check)) {
+    if (g.r == s->p.r && g.binned == binned && g.wide == wide &&
+        (binned ? g.ppt == s->scatter_ppt : g.check == J.check)) {
       g.apply_grid = (g.apply_grid == 0 || s->apply_grid == 0)
                          ? 0u : std::max(g.apply_grid, s->apply_grid);
       g.jobs.push_back(J);
       return;
     }
-  groups.push_back(Group{s->p.r, binned, J.check, s->scatter_ppt, s->apply_grid, {J}});
+  groups.push_back(Group{s->p.r, binned, J.check, s->scatter_ppt, s->apply_grid, wide, {J}});
 }
 
 // Pairs, blocks and pairs per block of a binned round of m pairs: about

@@ -128,12 +128,17 @@ __device__ __forceinline__ unsigned long long wave_lane64(unsigned long long v, 
   return ((unsigned long long)hi << 32) | lo;
 }
 
-// Binned update (update.hip): the sketch is cut into 128 KiB tiles; a code
-// is the bit offset inside its tile.
-constexpr uint32_t BIN_TILE_LOG2 = 20;               // bits per tile = 2^20
-constexpr uint32_t BIN_TILE_WORDS = 1u << 15;        // 128 KiB
-constexpr uint32_t BIN_MAX = 4095;                   // tiles (sketch < 512 MiB); the
-                                                     // bit index of a code stays < 2^32 - 1
+// Binned update (update.hip): the sketch is cut into tiles of 160 KiB, the
+// most LDS one gfx950 workgroup can hold (1280 LEs of g = 1024, a whole
+// number of LEs for every g); a code is the bit offset inside its tile
+// (21 bits).
+constexpr uint32_t BIN_TILE_WORDS = 40960;           // 160 KiB
+constexpr uint32_t BIN_TILE_BITS = BIN_TILE_WORDS * 32;
+constexpr uint32_t BIN_SLOTS = 4096;                 // tile slots of the per-block arrays
+constexpr uint32_t BIN_MAX = 3276;                   // tiles: a sketch bit index stays
+                                                     // below 2^32 (BIN_MAX * BIN_TILE_BITS)
+// The tile of sketch bit index B (a division by a constant).
+__host__ __device__ __forceinline__ uint32_t bin_tile(uint32_t B) { return B / BIN_TILE_BITS; }
 constexpr uint32_t SPLIT_MIN = 1u << 18;             // tiles above this many code words
 constexpr uint32_t APPLY_ITEM = 1u << 17;            //   are cut into items of this many
 

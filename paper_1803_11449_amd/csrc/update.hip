@@ -19,9 +19,9 @@
 //
 // binned   The bit sets are moved into LDS. Every (pair, row) gives the bit
 //          index B = ((row * 2^k + cell) * g) + bit of the sketch seen as
-//          one bit string; tile = B >> 20 names the 128 KiB slice it falls
-//          in and code = B mod 2^20 the bit inside it. Codes are stored
-//          three to a 64-bit word; every run a block writes for one tile in
+//          one bit string; tile = B / 1310720 names the 160 KiB slice it
+//          falls in and code = B mod 1310720 the bit inside it (21 bits).
+//          Codes are stored three to a 64-bit word; every run a block writes for one tile in
 //          one batch is padded to whole words with copies of a code of the
 //          run (setting a bit twice sets it once).
 //            count    each block walks a sample of its chunk's batches (every
@@ -141,7 +141,8 @@ __global__ __launch_bounds__(256) void k_update(const UpdJob *__restrict__ jobs,
 
 // ---------------------------------------------------------------- binned
 
-constexpr uint32_t CODE_MASK = (1u << BIN_TILE_LOG2) - 1;
+constexpr uint32_t CODE_BITS = 21;
+constexpr uint32_t CODE_MASK = (1u << CODE_BITS) - 1;
 
 template <int R>
 __device__ __forceinline__ void pair_codes(const Geom &G, uint2 p, uint32_t *B) {
@@ -150,7 +151,7 @@ __device__ __forceinline__ void pair_codes(const Geom &G, uint2 p, uint32_t *B) 
 #pragma unroll
   for (int row = 0; row < R; row++) {
     const uint32_t cell = row == 0 ? c0 : (bit_block(G, row, p.x) ^ c0);
-    // sketch bit index; < 2^31 since a binned sketch has at most BIN_MAX tiles
+    // sketch bit index; < 2^32 since a binned sketch has at most BIN_MAX tiles
     B[row] = ((((uint32_t)row << G.k) | cell) << G.log2g) | bit;
   }
 }
@@ -160,10 +161,10 @@ __device__ __forceinline__ void count_pair(const Geom &G, uint2 p, uint32_t *h) 
   uint32_t B[R];
   pair_codes<R>(G, p, B);
 #pragma unroll
-  for (int row = 0; row < R; row++) atomicAdd(&h[B[row] >> BIN_TILE_LOG2], 1u);
+  for (int row = 0; row < R; row++) atomicAdd(&h[bin_tile(B[row])], 1u);
 }
 
-// Codes are stored three to a 64-bit word (bits 0-19, 20-39, 40-59), and
+// Codes are stored three to a 64-bit word (bits 0-20, 21-41, 42-62), and
 // every run the scatter writes (one tile, one batch of a block) is padded
 // to whole words. Per block and tile, the count therefore estimates the
 // words its batches will write there: it walks the same batches as the
@@ -189,14 +190,14 @@ template <int R, int PPT> constexpr int count_waves_per_eu() {
 template <int R, int PPT>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(count_waves_per_eu<R, PPT>())))
 void k_bin_count(const UpdJob *__restrict__ jobs, uint32_t nj) {
-  constexpr uint32_t TPT = (BIN_MAX + 1) / 1024;       // tiles per thread
+  constexpr uint32_t TPT = BIN_SLOTS / 1024;            // tiles per thread
   constexpr int V4 = PPT / 2;
-  __shared__ uint32_t h[BIN_MAX + 1];
+  __shared__ uint32_t h[BIN_SLOTS];
   const UpdJob &J = jobs[job_of_block(jobs, nj, blockIdx.x)];
   const Geom G = J.G;
   const uint32_t nbins = J.nbins, lb = blockIdx.x - J.blk0;
   const uint32_t t0 = threadIdx.x * TPT;
-  for (uint32_t t = threadIdx.x; t < BIN_MAX + 1; t += blockDim.x) h[t] = 0;
+  for (uint32_t t = threadIdx.x; t < BIN_SLOTS; t += blockDim.x) h[t] = 0;
   __syncthreads();
   uint32_t acc[TPT] = {};
   // a batch's run of c codes in a tile takes ceil(c / 3) words
@@ -367,7 +368,7 @@ __global__ __launch_bounds__(1024) void k_bin_layout(const UpdJob *__restrict__ 
   const TileState S = tile_state(J.tst, nbins);
   GMEM uint32_t *capg = gmem(S.capg), *fill = gmem(S.fill), *regb = gmem(S.regb);
   GMEM uint32_t *base = gmem(J.base);
-  constexpr uint32_t PER = (BIN_MAX + 1) / 1024;
+  constexpr uint32_t PER = BIN_SLOTS / 1024;
   const uint32_t t0 = threadIdx.x * PER;
   uint32_t cap[PER][BIN_GROUPS];
   uint64_t mine = 0;
@@ -430,7 +431,7 @@ __global__ __launch_bounds__(1024) void k_bin_items(const UpdJob *__restrict__ j
   const GMEM uint32_t *regb = gmem(S.regb);
   GMEM uint32_t *totals = gmem(J.totals), *item_start = gmem(J.item_start);
   GMEM uint32_t *xslot = gmem(J.xslot), *item_tile = gmem(J.item_tile);
-  constexpr uint32_t PER = (BIN_MAX + 1) / 1024;
+  constexpr uint32_t PER = BIN_SLOTS / 1024;
   const uint32_t t0 = threadIdx.x * PER;
   uint32_t v[PER];
 #pragma unroll
@@ -500,6 +501,31 @@ __device__ __forceinline__ uint32_t get_rank(const uint32_t *rk2, int q) {
   return (q & 1) ? rk2[q >> 1] >> 16 : rk2[q >> 1] & 0xFFFFu;
 }
 
+// The value the scatter keeps per bit set. Up to 2048 tiles it is the tile
+// (11 bits) over the code (21 bits), split once per bit set; above, the
+// sketch bit index, whose tile takes a division wherever it is needed
+// (a 12-bit tile and a code do not fit 32 bits). ~0 (a slot past the
+// window's end or a pad slot) is neither.
+template <int TMAX> struct ScatterValue {
+  static constexpr bool SPLIT = TMAX <= 2048;
+  __device__ __forceinline__ static uint32_t make(uint32_t B) {
+    if constexpr (SPLIT) {
+      const uint32_t t = bin_tile(B);
+      return (t << CODE_BITS) | (B - t * BIN_TILE_BITS);
+    } else {
+      return B;
+    }
+  }
+  __device__ __forceinline__ static uint32_t tile(uint32_t v) {
+    if constexpr (SPLIT) return v >> CODE_BITS;
+    else return bin_tile(v);
+  }
+  __device__ __forceinline__ static uint32_t code(uint32_t v, uint32_t t) {
+    if constexpr (SPLIT) return v & CODE_MASK;
+    else return v - t * BIN_TILE_BITS;
+  }
+};
+
 // TMAX: tiles the LDS arrays hold (2048, 3072 or 4096), at least the jobs'
 // tiles.
 template <int R, int PPT, int TMAX>
@@ -507,6 +533,7 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
                                                       uint32_t nj) {
   constexpr uint32_t BATCH = 1024 * PPT * R;
   constexpr uint32_t TPT = TMAX / 1024;                // tiles per thread
+  using SV = ScatterValue<TMAX>;
   // a batch's codes grouped by tile, each run padded to whole words (at
   // most 2 pad slots per tile); with the three tile arrays this is at most
   // 160 KiB for every (R, PPT, TMAX) the launcher picks
@@ -574,8 +601,8 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
         pair_codes<R>(G, pr[k], B);
 #pragma unroll
         for (int row = 0; row < R; row++) {
-          v[k * R + row] = B[row];
-          put_rank(rk2, k * R + row, atomicAdd(&cnt[B[row] >> BIN_TILE_LOG2], 1u));
+          v[k * R + row] = SV::make(B[row]);
+          put_rank(rk2, k * R + row, atomicAdd(&cnt[SV::tile(v[k * R + row])], 1u));
         }
       } else {
 #pragma unroll
@@ -613,7 +640,7 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
     // 3: group by tile in LDS; dst maps a batch word to its word slot
 #pragma unroll
     for (int q = 0; q < PPT * R; q++)
-      if (FULL || v[q] != ~0u) sorted[lofs[v[q] >> BIN_TILE_LOG2] + get_rank(rk2, q)] = v[q];
+      if (FULL || v[q] != ~0u) sorted[lofs[SV::tile(v[q])] + get_rank(rk2, q)] = v[q];
     // a run that fits its region goes there; one that does not goes whole
     // to the spill area (the run that crosses the region's end marks where
     // the region's written part ends) and joins its tile's spill runs
@@ -643,9 +670,10 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
     auto put = [&](uint32_t j) {
       const uint32_t x = sorted[3 * j], y0 = sorted[3 * j + 1], z0 = sorted[3 * j + 2];
       const uint32_t y = y0 == ~0u ? x : y0, z = z0 == ~0u ? x : z0;
-      const uint64_t wv = (uint64_t)(x & CODE_MASK) | ((uint64_t)(y & CODE_MASK) << 20) |
-                          ((uint64_t)(z & CODE_MASK) << 40);
-      words[dst[x >> BIN_TILE_LOG2] + j] = wv;
+      const uint32_t t = SV::tile(x);                   // the word's three share it
+      const uint64_t wv = (uint64_t)SV::code(x, t) | ((uint64_t)SV::code(y, t) << CODE_BITS) |
+                          ((uint64_t)SV::code(z, t) << (2 * CODE_BITS));
+      words[dst[t] + j] = wv;
     };
     uint32_t j = tid;
     for (; j + (SCATTER_UNROLL - 1) * 1024 < nw; j += SCATTER_UNROLL * 1024) {
@@ -677,8 +705,8 @@ __device__ __forceinline__ void le_zeros(const Geom &G, GMEM uint32_t *lez, size
 // The three codes of a word (low half lo, high half hi) into the LDS tile.
 __device__ __forceinline__ void or_word(uint32_t *tile, uint2 w) {
   const uint32_t a = w.x & CODE_MASK;
-  const uint32_t b = __builtin_amdgcn_alignbit(w.y, w.x, 20) & CODE_MASK;
-  const uint32_t c = (w.y >> 8) & CODE_MASK;
+  const uint32_t b = __builtin_amdgcn_alignbit(w.y, w.x, CODE_BITS) & CODE_MASK;
+  const uint32_t c = (w.y >> (2 * CODE_BITS - 32)) & CODE_MASK;
   atomicOr(&tile[a >> 5], 1u << (a & 31));
   atomicOr(&tile[b >> 5], 1u << (b & 31));
   atomicOr(&tile[c >> 5], 1u << (c & 31));
@@ -742,7 +770,7 @@ __global__ __launch_bounds__(1024) void k_bin_apply(const UpdJob *__restrict__ j
                  : gmem(J.scratch) + (size_t)(gmem(J.xslot)[t] + sub - 1) * BIN_TILE_WORDS;
     // the tile in: zeros for a scratch tile or a fresh sketch, else a whole
     // tile as 16-byte loads, all in flight before the LDS writes (tiles and
-    // scratch tiles are 128 KiB aligned)
+    // scratch tiles are 160 KiB aligned)
     if (sub != 0 || J.fresh) {
       for (uint32_t w = threadIdx.x; w < tw; w += blockDim.x) tile[w] = 0;
     } else if (tw == BIN_TILE_WORDS) {
@@ -887,7 +915,7 @@ static hipError_t launch_r(const UpdJob *h, UpdJob *d, uint32_t nj, uint32_t *d_
   // LDS of the scatter: 4*(1024*PPT*r + 2*TMAX) bytes of sorted codes +
   // 12*TMAX bytes of tile arrays <= 160 KiB. Up to 2048 tiles: 6 pairs per
   // thread for r <= 5, 4 for r <= 7, else 2. Up to 3072 tiles and r <= 5: 5.
-  // Up to 4095 tiles: 4 for r <= 5, else 2 (scatter_ppt gives the same
+  // Up to 3276 tiles: 4 for r <= 5, else 2 (scatter_ppt gives the same
   // choice to the host, which sizes the spill-run lists by it). The count
   // pass walks the scatter's batches, so both take the same PPT.
   uint32_t max_tiles = 0;

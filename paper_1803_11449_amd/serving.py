@@ -52,7 +52,7 @@ def resident_bytes(g: int, k: int, r: int, alpha: int) -> int:
     n_le = r << k
     sketch = n_le * g // 8
     rows = n_le // 8 + 3 * 4 * n_le + 8 * r * (1 << (k - alpha))
-    tiles = max(1, sketch // (128 << 10)) * 4 * (256 + 4)
+    tiles = max(1, sketch // (160 << 10)) * 4 * (256 + 4)
     return sketch + rows + tiles + (1 << 16)
 
 
@@ -181,6 +181,52 @@ class _Server:
                 time.sleep((t - now) / 2)
 
 
+# Streams checked to run their work concurrently, per device (see
+# concurrent_streams); every server of the process reuses them.
+_CONCURRENT: dict = {}
+
+
+def _spin_pair_s(a, b, cycles: int) -> float:
+    """Host seconds for one spin kernel on each of two streams."""
+    torch.cuda.synchronize(a.device)
+    t0 = time.perf_counter()
+    for s in (a, b):
+        with torch.cuda.stream(s):
+            torch.cuda._sleep(cycles)
+    torch.cuda.synchronize(a.device)
+    return time.perf_counter() - t0
+
+
+def concurrent_streams(device: int, n: int = 2, tries: int = 8, cycles: int = 2_000_000):
+    """n streams of the default priority whose work runs at the same time.
+
+    HIP runs streams on a few hardware queues per process (four by default)
+    and streams that share a queue run their work in submission order, one
+    after the other; which queue a new stream gets depends on the streams
+    made before it. So each new stream is checked against the ones kept: a
+    spin kernel of about a millisecond on both must end in about the time
+    of one (below 1.5 times). A stream that fails is dropped and another
+    made, up to `tries`; past that the last one is kept (work is still
+    correct, only in order). The result is cached per device."""
+    if device in _CONCURRENT and len(_CONCURRENT[device]) >= n:
+        return _CONCURRENT[device][:n]
+    dev = torch.device("cuda", device)
+    kept = list(_CONCURRENT.get(device, []))
+    if not kept:
+        kept.append(torch.cuda.Stream(dev))
+    with torch.cuda.device(dev):
+        one = min(_spin_pair_s(kept[0], kept[0], cycles) for _ in range(2)) / 2
+        while len(kept) < n:
+            cand = None
+            for _ in range(tries):
+                cand = torch.cuda.Stream(dev)
+                if all(_spin_pair_s(k, cand, cycles) < 1.5 * one for k in kept):
+                    break
+            kept.append(cand)
+    _CONCURRENT[device] = kept
+    return kept[:n]
+
+
 class ContinuousServer(_Server):
     """Continuous batching with two batches in flight: see the module
     docstring. With trace=True every batch records timing events on its
@@ -191,8 +237,9 @@ class ContinuousServer(_Server):
         super().__init__(budget_bytes, g, r, device)
         self.max_batch = max_batch
         self.depth = max(1, depth)
-        # streams of the default priority, one per batch in flight
-        self.streams = [torch.cuda.Stream(self.dev) for _ in range(self.depth)]
+        # streams of the default priority, one per batch in flight, checked
+        # to run concurrently
+        self.streams = concurrent_streams(device, self.depth)
         self.trace_on = trace
         self.trace = []
 

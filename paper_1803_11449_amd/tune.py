@@ -103,7 +103,7 @@ def tune(g: int, k: int, r: int, alpha: int, pairs: torch.Tensor, seed: int = dd
         return db[key]
     n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
     words = (r << k) * g // 32
-    binned_ok = -(-words // (1 << 15)) <= 4095          # the binned kernels' tile limit
+    binned_ok = -(-words // 40960) <= 3276             # the binned kernels' limit: 160 KiB tiles
     best = None
     with ddhf.Sketch(g, k, r, alpha, seed, device=dev) as sk:
         for opts in candidates(n_cu, binned_ok):

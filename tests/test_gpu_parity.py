@@ -200,12 +200,15 @@ def test_binned_regions_and_spill_runs(sample, regions):
         assert np.array_equal(sk2.download(), ref2)
 
 
-@pytest.mark.parametrize("p", [oracle.Params(1024, 19, 5, 5), oracle.Params(2048, 18, 7, 3)],
+@pytest.mark.parametrize("p", [oracle.Params(1024, 19, 5, 5), oracle.Params(1024, 20, 3, 12),
+                               oracle.Params(2048, 18, 7, 3)],
                          ids=lambda p: f"g{p.g}k{p.k}r{p.r}a{p.alpha}")
-def test_binned_sketch_over_2048_tiles(p):
-    """Sketches of 2049..4095 tiles (320 and 448 MiB) take the scatter's
-    4096-tile variant: every pairs-per-thread setting it has, a heavy source
-    whose tiles are cut into several apply items, and (r = 5) the restore."""
+def test_binned_sketch_of_2048_tiles_and_over(p):
+    """The largest binned sketches: 320 MiB (2048 tiles of 160 KiB, the top
+    of the scatter's 2048-tile variant), 384 MiB (2458 tiles, r = 3: the
+    3072-tile variant) and 448 MiB (2868 tiles, r = 7: the 4096-tile one);
+    every pairs-per-thread setting, a heavy source whose tiles are cut into
+    several apply items, and (r = 5) the restore."""
     say(f"binned over 2048 tiles: g={p.g} k={p.k} r={p.r} alpha={p.alpha}")
     rng = np.random.default_rng(p.k * 11 + p.r)
     hosts = rng.choice(2**32, size=6, replace=False).astype(np.uint32)

@@ -118,8 +118,8 @@ def test_plan_update_in_rounds_and_without_restore():
 # The 64-link batch's shape at reduced sizes: link windows from the same
 # generator (Zipf sources over n/25 hosts, planted log-uniform in
 # [1024, 50000]), exponents across [0.8, 1.3], theta 512 and 1024, one
-# k = 19 sketch (2560 tiles: the scatter's 3072-tile variant for the whole
-# launch group) next to k = 14..15 ones, autotuned update options.
+# k = 19 sketch (2048 tiles of 160 KiB, the most the scatter's 2048-tile
+# variant takes) next to k = 14..15 ones, autotuned update options.
 LINKS = [  # (n_pairs, zipf_s, planted, theta, forced (k, alpha) or None)
     (2_000_000, 0.80, 10, 512.0, None),
     (9_000_000, 0.85, 200, 512.0, None),

@@ -3,6 +3,8 @@ sketch cache under its HBM budget, and the continuous batcher's admission.
 The library calls are replaced by stand-ins that record what the server asks
 for (the GPU serving tests check the results themselves).
 """
+import contextlib
+
 import numpy as np
 import pytest
 import torch
@@ -112,6 +114,7 @@ def fake_lib(monkeypatch):
     monkeypatch.setattr(ddhf, "restore_batch_begin", Pending)
     monkeypatch.setattr(serving.torch.cuda, "Stream", lambda device=None: object())
     monkeypatch.setattr(serving.torch.cuda, "Event", FakeEvent)
+    monkeypatch.setattr(serving, "concurrent_streams", lambda device, n: [object()] * n)
     batches.peak = peak
     return batches
 
@@ -227,3 +230,46 @@ def test_plain_server_serves_one_at_a_time(fake_lib):
     assert [r.rid for r in out] == list(range(10))
     assert all(len(b) == 1 for b in fake_lib) and len(fake_lib) == 10
     assert all(r.batch == 1 for r in out)
+
+
+class FakeQueues:
+    """Streams on hardware queues in a given order; a pair of spin kernels
+    takes 2 units on one queue and 1 on two."""
+
+    def __init__(self, order):
+        self.order = list(order)
+        self.made = []
+
+    def stream(self, device=None):
+        st = type("S", (), {})()
+        st.q = self.order[len(self.made) % len(self.order)]
+        self.made.append(st)
+        return st
+
+    def spin(self, a, b, cycles):
+        return 2.0 if a.q == b.q else 1.0
+
+
+@pytest.mark.parametrize("order", [[0, 1, 2, 3, 3, 2, 1, 0], [2, 2, 2, 1], [0, 0, 0, 0, 0, 3]])
+def test_concurrent_streams_skips_streams_on_a_shared_queue(monkeypatch, order):
+    fq = FakeQueues(order)
+    monkeypatch.setattr(serving, "_CONCURRENT", {})
+    monkeypatch.setattr(serving.torch.cuda, "Stream", fq.stream)
+    monkeypatch.setattr(serving.torch.cuda, "device", lambda d: contextlib.nullcontext())
+    monkeypatch.setattr(serving, "_spin_pair_s", fq.spin)
+    a, b = serving.concurrent_streams(0, 2)
+    assert a.q != b.q
+    # cached: later servers get the same pair without new checks
+    made = len(fq.made)
+    assert serving.concurrent_streams(0, 2) == [a, b]
+    assert len(fq.made) == made
+
+
+def test_concurrent_streams_gives_up_after_its_tries(monkeypatch):
+    fq = FakeQueues([1])                      # one queue: nothing is concurrent
+    monkeypatch.setattr(serving, "_CONCURRENT", {})
+    monkeypatch.setattr(serving.torch.cuda, "Stream", fq.stream)
+    monkeypatch.setattr(serving.torch.cuda, "device", lambda d: contextlib.nullcontext())
+    monkeypatch.setattr(serving, "_spin_pair_s", fq.spin)
+    streams = serving.concurrent_streams(0, 2, tries=3)
+    assert len(streams) == 2 and len(fq.made) == 1 + 3

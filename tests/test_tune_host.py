@@ -106,8 +106,8 @@ def test_apply_sets_each_named_option(fake_device):
 
 
 def test_past_the_tile_limit_only_direct_settings(fake_device):
-    """g = 65536, k = 14, r = 5: 5 * 2^14 LEs of 2^16 bits = 5120 tiles of
-    2^20 bits, more than the binned kernels' 4095."""
+    """g = 65536, k = 14, r = 5: 5 * 2^14 LEs of 2^16 bits = 640 MiB, 4096
+    tiles of 160 KiB, more than the binned kernels' 3276."""
     timed = fake_device
     best = tune.tune(65536, 14, 5, 6, torch.zeros((1000, 2), dtype=torch.int32), use_cache=False)
     assert best["path"] == 1 and all(o["path"] == 1 for o in timed)

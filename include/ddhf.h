@@ -316,7 +316,8 @@ enum {
   SKETCH_OPT_UPDATE_GRID = 3,       /* blocks of the direct kernel */
   SKETCH_OPT_UPDATE_CHECK = 4,      /* direct kernel: 1 = test the bit before
                                        the atomicOr (default), 0 = always OR */
-  SKETCH_OPT_BINNED_ROUND = 5,      /* binned: pairs per round; the round's
+  SKETCH_OPT_BINNED_ROUND = 5,      /* binned: pairs per round, 1024 to 2^28
+                                       (default 2^28); the round's
                                        codes (three per 8 bytes, in regions
                                        and a spill area of that size each)
                                        take about 5.4*r bytes per pair of

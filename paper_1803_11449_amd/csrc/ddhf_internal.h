@@ -227,7 +227,7 @@ constexpr uint32_t MAX_JOBS = 256;     // jobs per launch group
 // of a job: a tile with v code words makes at most 1 + v / APPLY_ITEM of
 // them, and a round has at most 8 * MAX_ROUND_PAIRS codes (and no more
 // words than codes).
-constexpr uint64_t MAX_ROUND_PAIRS = (uint64_t)1 << 27;
+constexpr uint64_t MAX_ROUND_PAIRS = (uint64_t)1 << 28;
 constexpr uint64_t ITEM_TILE_SLOTS(uint32_t nbins) {
   return (uint64_t)nbins + 8 * MAX_ROUND_PAIRS / APPLY_ITEM + 1;
 }

@@ -170,6 +170,30 @@ constexpr size_t NOALLOC_CAND = (size_t)1 << 20;      // candidates (and sorted 
 constexpr size_t NOALLOC_SPL = (size_t)1 << 18;       // records (and sorted copy)
 static __device__ __align__(256) uint8_t scratch[NOALLOC_BYTES];
 
+// One restore pool: the work buffers a restore shares with the restores
+// before and after it (join partials, candidates, unsorted records, sort
+// ranks), and the last work that used them. Pool 0 serves single restores
+// on the caller's stream; a batch spreads its jobs over every pool, pools
+// 1.. on streams of their own that fork from the caller's stream and join
+// it again, so the restores of different jobs run at the same time.
+struct RPool {
+  uint2 *part[2] = {};
+  uint32_t *segc[2] = {};
+  size_t seg_cap = 0;
+  uint32_t *cand = nullptr, *cand_sorted = nullptr;
+  size_t cand_cap = 0;
+  uint4 *spl = nullptr;
+  size_t spl_cap = 0;
+  uint32_t *rank = nullptr, *skeys = nullptr;
+  size_t rank_cap = 0;           // entries of rank and skeys
+  Lane lane;
+  bool ready = false;            // buffers, lane (and stream) exist
+  hipStream_t stream = nullptr;  // pools 1..: the pool's stream (default priority)
+  hipEvent_t join = nullptr;     // pools 1..: marks the end of the pool's part of a batch
+};
+
+constexpr int RESTORE_POOLS = 4;
+
 struct DevCtx {
   static constexpr int SLOTS = 16;
   int dev = -1;
@@ -188,21 +212,14 @@ struct DevCtx {
   size_t codes_cap = 0;          // words
   uint32_t *scratch = nullptr;
   size_t scratch_tiles = 0;
-  // restore pool
+  // restore pools
   uint32_t jblk = 0;             // blocks of the join kernels
-  uint2 *part[2] = {};
-  uint32_t *segc[2] = {};
-  size_t seg_cap = 0;
-  uint32_t *cand = nullptr, *cand_sorted = nullptr;
-  size_t cand_cap = 0;
-  uint4 *spl = nullptr;
-  size_t spl_cap = 0;
-  uint32_t *rank = nullptr, *skeys = nullptr;
-  size_t rank_cap = 0;           // entries of rank and skeys
-  // last work that used the update arena, and the restore pool: separate,
-  // so that one batch's update can run while another batch's restore does
-  Lane arena_lane, pool_lane;
-  uint64_t gen = 0;              // bumped whenever the arena or the pool moves
+  RPool pool[RESTORE_POOLS];
+  hipEvent_t fork = nullptr;     // a batch's start on the caller's stream
+  // last work that used the update arena (the pools have their own): so
+  // one batch's update can run while another batch's restore does
+  Lane arena_lane;
+  uint64_t gen = 0;              // bumped whenever the arena or a pool moves
   // this device's copy of the no-alloc restore's work array (its address
   // from hipGetSymbolAddress at set-up) and the last work that used it
   uint8_t *noalloc = nullptr;
@@ -212,70 +229,82 @@ struct DevCtx {
 std::mutex g_ctx_mu;
 DevCtx *g_ctx[256] = {};
 
-// Wait on the host until the restore pool is idle (before reallocating it).
-int pool_idle(DevCtx *c) { return lane_idle(c->pool_lane); }
+// Wait on the host until a restore pool is idle (before reallocating it).
+int pool_idle(RPool &p) { return lane_idle(p.lane); }
+int pools_idle(DevCtx *c) {
+  for (RPool &p : c->pool)
+    if (p.ready) {
+      int rc = pool_idle(p);
+      if (rc) return rc;
+    }
+  return SKETCH_OK;
+}
 int arena_idle(DevCtx *c) { return lane_idle(c->arena_lane); }
 
 // Sort ranks and tile-sorted keys for the longer of the candidate and
 // record buffers (after the pool is idle).
-int ensure_rank(DevCtx *c) {
-  const size_t need = (std::max<size_t>({c->cand_cap, c->spl_cap, 16384}) + 4095) & ~(size_t)4095;
-  if (c->rank_cap >= need) return SKETCH_OK;
+int ensure_rank(DevCtx *c, RPool &p) {
+  const size_t need = (std::max<size_t>({p.cand_cap, p.spl_cap, 16384}) + 4095) & ~(size_t)4095;
+  if (p.rank_cap >= need) return SKETCH_OK;
   c->gen++;
-  dev_free(c->rank);
-  dev_free(c->skeys);
-  c->rank_cap = 0;
-  int rc = dev_alloc(&c->rank, need, "sort ranks");
-  if (!rc) rc = dev_alloc(&c->skeys, need, "sort keys");
-  if (!rc) c->rank_cap = need;
+  dev_free(p.rank);
+  dev_free(p.skeys);
+  p.rank_cap = 0;
+  int rc = dev_alloc(&p.rank, need, "sort ranks");
+  if (!rc) rc = dev_alloc(&p.skeys, need, "sort keys");
+  if (!rc) p.rank_cap = need;
   return rc;
 }
 
 // Restore pool buffers at exactly `cap` entries (after the pool is idle).
-int alloc_partials(DevCtx *c, size_t cap) {
-  int rc = pool_idle(c);
+int alloc_partials(DevCtx *c, RPool &p, size_t cap) {
+  int rc = pool_idle(p);
   if (rc) return rc;
   c->gen++;
-  dev_free(c->part[0]);
-  dev_free(c->part[1]);
-  c->seg_cap = 0;
-  rc = dev_alloc(&c->part[0], cap * c->jblk, "partials");
-  if (!rc) rc = dev_alloc(&c->part[1], cap * c->jblk, "partials");
-  if (!rc) c->seg_cap = cap;
+  dev_free(p.part[0]);
+  dev_free(p.part[1]);
+  p.seg_cap = 0;
+  rc = dev_alloc(&p.part[0], cap * c->jblk, "partials");
+  if (!rc) rc = dev_alloc(&p.part[1], cap * c->jblk, "partials");
+  if (!rc) p.seg_cap = cap;
   return rc;
 }
 
-int alloc_cand(DevCtx *c, size_t cap) {
-  int rc = pool_idle(c);
+int alloc_cand(DevCtx *c, RPool &p, size_t cap) {
+  int rc = pool_idle(p);
   if (rc) return rc;
   c->gen++;
-  dev_free(c->cand);
-  dev_free(c->cand_sorted);
-  c->cand_cap = 0;
-  rc = dev_alloc(&c->cand, cap, "candidates");
-  if (!rc) rc = dev_alloc(&c->cand_sorted, cap, "candidates");
-  if (!rc) c->cand_cap = cap;
-  if (!rc) rc = ensure_rank(c);
+  dev_free(p.cand);
+  dev_free(p.cand_sorted);
+  p.cand_cap = 0;
+  rc = dev_alloc(&p.cand, cap, "candidates");
+  if (!rc) rc = dev_alloc(&p.cand_sorted, cap, "candidates");
+  if (!rc) p.cand_cap = cap;
+  if (!rc) rc = ensure_rank(c, p);
   return rc;
 }
 
-int alloc_pool_spl(DevCtx *c, size_t cap) {
-  int rc = pool_idle(c);
+int alloc_pool_spl(DevCtx *c, RPool &p, size_t cap) {
+  int rc = pool_idle(p);
   if (rc) return rc;
   c->gen++;
-  dev_free(c->spl);
-  c->spl_cap = 0;
-  rc = dev_alloc(&c->spl, cap, "records");
-  if (!rc) c->spl_cap = cap;
-  if (!rc) rc = ensure_rank(c);
+  dev_free(p.spl);
+  p.spl_cap = 0;
+  rc = dev_alloc(&p.spl, cap, "records");
+  if (!rc) p.spl_cap = cap;
+  if (!rc) rc = ensure_rank(c, p);
   return rc;
 }
 
 // Growth by at least half of what was asked, at least doubling.
 size_t grown(size_t need, size_t cap) { return std::max(need + need / 2, cap * 2); }
-int grow_partials(DevCtx *c, size_t need) { return alloc_partials(c, grown(need, c->seg_cap)); }
-int grow_cand(DevCtx *c, size_t need) { return alloc_cand(c, grown(need, c->cand_cap)); }
-int grow_pool_spl(DevCtx *c, size_t need) { return alloc_pool_spl(c, grown(need, c->spl_cap)); }
+int grow_partials(DevCtx *c, RPool &p, size_t need) {
+  return alloc_partials(c, p, grown(need, p.seg_cap));
+}
+int grow_cand(DevCtx *c, RPool &p, size_t need) { return alloc_cand(c, p, grown(need, p.cand_cap)); }
+int grow_pool_spl(DevCtx *c, RPool &p, size_t need) {
+  return alloc_pool_spl(c, p, grown(need, p.spl_cap));
+}
 
 // Initial restore pool: partial addresses per join block, candidates, records.
 constexpr size_t POOL_SEG0 = (size_t)1 << 12, POOL_CAND0 = (size_t)1 << 16,
@@ -305,10 +334,52 @@ int ensure_arena(DevCtx *c, size_t words, size_t tiles) {
   return SKETCH_OK;
 }
 
-// Free the update arena and reallocate the restore pool at `entries` per
-// buffer (0: the initial sizes). Caller holds c->mu.
+// Buffers of pool i at `entries` per buffer (0: the initial sizes), its
+// lane, and for i >= 1 its stream and join event. Caller holds c->mu.
+int pool_init(DevCtx *c, int i, size_t entries) {
+  RPool &p = c->pool[i];
+  int rc = SKETCH_OK;
+  if (!p.lane.ev) rc = lane_init(p.lane);
+  if (!rc && i > 0 && !p.stream &&
+      hipStreamCreateWithFlags(&p.stream, hipStreamNonBlocking) != hipSuccess) {
+    p.stream = nullptr;
+    rc = fail(SKETCH_E_HIP, "device context: hipStreamCreate failed");
+  }
+  if (!rc && i > 0 && !p.join &&
+      hipEventCreateWithFlags(&p.join, hipEventDisableTiming) != hipSuccess) {
+    p.join = nullptr;
+    rc = fail(SKETCH_E_HIP, "device context: hipEventCreate failed");
+  }
+  if (!rc && !p.segc[0]) rc = dev_alloc(&p.segc[0], c->jblk, "segment counts");
+  if (!rc && !p.segc[1]) rc = dev_alloc(&p.segc[1], c->jblk, "segment counts");
+  if (!rc) rc = alloc_partials(c, p, entries ? entries : POOL_SEG0);
+  if (!rc) rc = alloc_cand(c, p, entries ? entries : POOL_CAND0);
+  if (!rc) rc = alloc_pool_spl(c, p, entries ? entries : POOL_SPL0);
+  p.ready = rc == SKETCH_OK;
+  return rc;
+}
+
+// A pool's device buffers freed (its lane idle first); the lane, stream
+// and event stay.
+void pool_free_buffers(RPool &p) {
+  (void)pool_idle(p);
+  dev_free(p.part[0]);
+  dev_free(p.part[1]);
+  dev_free(p.segc[0]);
+  dev_free(p.segc[1]);
+  dev_free(p.cand);
+  dev_free(p.cand_sorted);
+  dev_free(p.spl);
+  dev_free(p.rank);
+  dev_free(p.skeys);
+  p.seg_cap = p.cand_cap = p.spl_cap = p.rank_cap = 0;
+  p.ready = false;
+}
+
+// Free the update arena and the batch pools, and reallocate pool 0 at
+// `entries` per buffer (0: the initial sizes). Caller holds c->mu.
 int trim_pools(DevCtx *c, size_t entries) {
-  int rc = pool_idle(c);
+  int rc = pools_idle(c);
   if (!rc) rc = arena_idle(c);
   if (rc) return rc;
   c->gen++;
@@ -316,13 +387,13 @@ int trim_pools(DevCtx *c, size_t entries) {
   c->codes_cap = 0;
   dev_free(c->scratch);
   c->scratch_tiles = 0;
-  dev_free(c->rank);
-  dev_free(c->skeys);
-  c->rank_cap = 0;
-  rc = alloc_partials(c, entries ? entries : POOL_SEG0);
-  if (!rc) rc = alloc_cand(c, entries ? entries : POOL_CAND0);
-  if (!rc) rc = alloc_pool_spl(c, entries ? entries : POOL_SPL0);
-  return rc;
+  for (int i = 1; i < RESTORE_POOLS; i++)
+    if (c->pool[i].ready) pool_free_buffers(c->pool[i]);
+  RPool &p = c->pool[0];
+  dev_free(p.rank);
+  dev_free(p.skeys);
+  p.rank_cap = 0;
+  return pool_init(c, 0, entries);
 }
 
 void ctx_free(DevCtx *c) {
@@ -332,21 +403,18 @@ void ctx_free(DevCtx *c) {
     if (c->h_jobs[i]) (void)hipHostFree(c->h_jobs[i]);
     dev_free(c->d_jobs[i]);
   }
-  lane_free(c->pool_lane);
+  for (RPool &p : c->pool) {
+    pool_free_buffers(p);
+    lane_free(p.lane);
+    if (p.stream) (void)hipStreamDestroy(p.stream);
+    if (p.join) (void)hipEventDestroy(p.join);
+  }
+  if (c->fork) (void)hipEventDestroy(c->fork);
   lane_free(c->arena_lane);
   lane_free(c->noalloc_lane);
   dev_free(c->d_total);
   dev_free(c->codes);
   dev_free(c->scratch);
-  dev_free(c->part[0]);
-  dev_free(c->part[1]);
-  dev_free(c->segc[0]);
-  dev_free(c->segc[1]);
-  dev_free(c->cand);
-  dev_free(c->cand_sorted);
-  dev_free(c->spl);
-  dev_free(c->rank);
-  dev_free(c->skeys);
   delete c;
 }
 
@@ -371,8 +439,11 @@ int ctx_acquire(int dev, int n_cu, DevCtx **out) {
       if (!rc && hipEventCreateWithFlags(&c->ev[i], hipEventDisableTiming) != hipSuccess)
         rc = fail(SKETCH_E_HIP, "device context: hipEventCreate failed");
     }
-    if (!rc) rc = lane_init(c->pool_lane);
     if (!rc) rc = lane_init(c->arena_lane);
+    if (!rc && hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess) {
+      c->fork = nullptr;
+      rc = fail(SKETCH_E_HIP, "device context: hipEventCreate failed");
+    }
     if (!rc) rc = lane_init(c->noalloc_lane);
     if (!rc && prepare_restore_kernels() != hipSuccess)
       rc = fail(SKETCH_E_HIP, "device context: restore kernel attributes");
@@ -382,11 +453,7 @@ int ctx_acquire(int dev, int n_cu, DevCtx **out) {
       rc = fail(SKETCH_E_HIP, "device context: hipGetSymbolAddress(scratch) failed");
     }
     if (!rc) rc = dev_alloc(&c->d_total, DevCtx::SLOTS, "item totals");
-    if (!rc) rc = dev_alloc(&c->segc[0], c->jblk, "segment counts");
-    if (!rc) rc = dev_alloc(&c->segc[1], c->jblk, "segment counts");
-    if (!rc) rc = alloc_partials(c, POOL_SEG0);
-    if (!rc) rc = alloc_cand(c, POOL_CAND0);
-    if (!rc) rc = alloc_pool_spl(c, POOL_SPL0);
+    if (!rc) rc = pool_init(c, 0, 0);
     if (rc) {
       ctx_free(c);
       return rc;
@@ -583,6 +650,8 @@ struct sketch {
   // capacities the last enqueued restore ran with (the pools may grow
   // between its launch and its check when restores are batched)
   size_t ran_seg_cap = 0, ran_cand_cap = 0, ran_spl_cap = 0, ran_h_recs_cap = 0;
+  int ran_pool = 0;             // the pool that restore ran on
+  uint64_t cost_hint = 0;       // the last restore's row-0 cells times their addresses
 };
 
 namespace {
@@ -629,7 +698,7 @@ int grow_sorted(sketch *s, size_t need) {
   return rc;
 }
 
-RestoreBufs restore_bufs(const sketch *s) {
+RestoreBufs restore_bufs(const sketch *s, const RPool &p) {
   const DevCtx *c = s->ctx;
   RestoreBufs B{};
   B.lez = s->lez_valid ? s->lez : nullptr;
@@ -639,20 +708,20 @@ RestoreBufs restore_bufs(const sketch *s) {
   B.bk_off = s->bk_off;
   B.bk_cur = s->bk_cur;
   B.bk_val = s->bk_val;
-  B.part[0] = c->part[0];
-  B.part[1] = c->part[1];
-  B.segc[0] = c->segc[0];
-  B.segc[1] = c->segc[1];
-  B.seg_cap = c->seg_cap;
+  B.part[0] = p.part[0];
+  B.part[1] = p.part[1];
+  B.segc[0] = p.segc[0];
+  B.segc[1] = p.segc[1];
+  B.seg_cap = p.seg_cap;
   B.jblk = c->jblk;
-  B.cand = c->cand;
-  B.cand_sorted = c->cand_sorted;
-  B.cand_cap = c->cand_cap;
-  B.spl = c->spl;
+  B.cand = p.cand;
+  B.cand_sorted = p.cand_sorted;
+  B.cand_cap = p.cand_cap;
+  B.spl = p.spl;
   B.spl_sorted = s->spl_sorted;
-  B.spl_cap = std::min(c->spl_cap, s->spl_sorted_cap);
-  B.rank = c->rank;
-  B.skeys = c->skeys;
+  B.spl_cap = std::min(p.spl_cap, s->spl_sorted_cap);
+  B.rank = p.rank;
+  B.skeys = p.skeys;
   B.h_state = s->d_h_state;
   B.h_recs = s->d_h_recs;
   B.h_recs_cap = s->h_recs_cap;
@@ -741,21 +810,95 @@ int restore_launch_on(sketch *s, const RestoreBufs &B, Lane &pool, const Thresho
   return rc;
 }
 
-// The restore on the device's restore pool.
-int restore_launch(sketch *s, const Thresholds &t, int estimate, hipStream_t st) {
-  const RestoreBufs B = restore_bufs(s);
+// The restore on restore pool i, enqueued on st.
+int restore_launch_pool(sketch *s, const Thresholds &t, int estimate, int i, hipStream_t st) {
+  RPool &p = s->ctx->pool[i];
+  const RestoreBufs B = restore_bufs(s, p);
   s->ran_seg_cap = B.seg_cap;
   s->ran_cand_cap = B.cand_cap;
   s->ran_spl_cap = B.spl_cap;
   s->ran_h_recs_cap = B.h_recs_cap;
-  return restore_launch_on(s, B, s->ctx->pool_lane, t, estimate, st);
+  s->ran_pool = i;
+  return restore_launch_on(s, B, p.lane, t, estimate, st);
+}
+
+// The restore on the device's first restore pool (the caller's stream).
+int restore_launch(sketch *s, const Thresholds &t, int estimate, hipStream_t st) {
+  return restore_launch_pool(s, t, estimate, 0, st);
+}
+
+// Relative work of a restore of s: its LEs, and the row-0 addresses the
+// candidate search covered the last time (|HE(0)| 2^(32-k)).
+double restore_cost(const sketch *s) {
+  return (double)((size_t)s->p.r << s->p.k) / 4.0 + (double)s->cost_hint;
+}
+
+void note_cost(sketch *s, const DevState &h) {
+  if (!h.saturated) s->cost_hint = (uint64_t)h.he_count[0] << (32 - s->p.k);
+}
+
+// Pools of a batch's jobs: the costliest job first, each to the pool with
+// the least work so far (longest processing time first); every pool that
+// gets a job is made ready. Caller holds c->mu.
+int assign_pools(DevCtx *c, const std::vector<const sketch *> &ss, std::vector<int> &pools) {
+  const size_t n = ss.size();
+  pools.assign(n, 0);
+  if (n < 2) return SKETCH_OK;
+  std::vector<size_t> order(n);
+  for (size_t i = 0; i < n; i++) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+    return restore_cost(ss[a]) > restore_cost(ss[b]);
+  });
+  const int np = (int)std::min<size_t>(RESTORE_POOLS, n);
+  double load[RESTORE_POOLS] = {};
+  for (size_t i : order) {
+    int best = 0;
+    for (int q = 1; q < np; q++)
+      if (load[q] < load[best]) best = q;
+    pools[i] = best;
+    load[best] += restore_cost(ss[i]);
+  }
+  for (int q = 1; q < np; q++)
+    if (!c->pool[q].ready) {
+      int rc = pool_init(c, q, 0);
+      if (rc) return rc;
+    }
+  return SKETCH_OK;
+}
+
+// The stream that pool i's restores of a batch run on (pool 0: the
+// caller's).
+hipStream_t pool_stream(const DevCtx *c, int i, hipStream_t st) {
+  return i == 0 ? st : c->pool[i].stream;
+}
+
+// The pools' streams (used[i] for i >= 1) start after what st holds so far.
+hipError_t batch_fork(DevCtx *c, const uint8_t *used, hipStream_t st) {
+  bool any = false;
+  for (int i = 1; i < RESTORE_POOLS; i++) any = any || used[i];
+  if (!any) return hipSuccess;
+  hipError_t e = hipEventRecord(c->fork, st);
+  for (int i = 1; i < RESTORE_POOLS && e == hipSuccess; i++)
+    if (used[i]) e = hipStreamWaitEvent(c->pool[i].stream, c->fork, 0);
+  return e;
+}
+
+// st continues after what the pools' streams (used[i], i >= 1) hold.
+hipError_t batch_join(DevCtx *c, const uint8_t *used, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  for (int i = 1; i < RESTORE_POOLS && e == hipSuccess; i++)
+    if (used[i]) {
+      e = hipEventRecord(c->pool[i].join, c->pool[i].stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, c->pool[i].join, 0);
+    }
+  return e;
 }
 
 // The restore's shared buffers carved from the no-alloc array at `base`:
 // sort ranks, segment counts, candidates and records (each with its sorted
 // copy) at fixed sizes, the rest split into the join's partial segments.
 RestoreBufs noalloc_bufs(const sketch *s, uint8_t *base) {
-  RestoreBufs B = restore_bufs(s);
+  RestoreBufs B = restore_bufs(s, s->ctx->pool[0]);   // every pool buffer replaced below
   const uint32_t jb = s->ctx->jblk;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -784,29 +927,31 @@ RestoreBufs noalloc_bufs(const sketch *s, uint8_t *base) {
 int restore_check(sketch *s, int estimate, bool *again) {
   const DevState &h = *s->h_state;
   DevCtx *c = s->ctx;
+  RPool &p = c->pool[s->ran_pool];
   *again = false;
   if (h.saturated) return SKETCH_E_SATURATED;
+  note_cost(s, h);
   // a stage overflowed if its count passed the capacity the run had; the
   // buffer grows only if it has not grown enough since
   size_t need_part = 0;
   for (uint32_t i = 2; i + 1 < s->p.r; i++) need_part = std::max<size_t>(need_part, h.seg_max[i]);
   if (need_part > s->ran_seg_cap) {
-    if (need_part > c->seg_cap) {
-      int rc = grow_partials(c, need_part);
+    if (need_part > p.seg_cap) {
+      int rc = grow_partials(c, p, need_part);
       if (rc) return rc;
     }
     *again = true;
   }
   if (h.n_cand > s->ran_cand_cap) {
-    if (h.n_cand > c->cand_cap) {
-      int rc = grow_cand(c, h.n_cand);
+    if (h.n_cand > p.cand_cap) {
+      int rc = grow_cand(c, p, h.n_cand);
       if (rc) return rc;
     }
     *again = true;
   }
   if (estimate && h.n_spl > s->ran_spl_cap) {
-    if (h.n_spl > c->spl_cap) {
-      int rc = grow_pool_spl(c, h.n_spl);
+    if (h.n_spl > p.spl_cap) {
+      int rc = grow_pool_spl(c, p, h.n_spl);
       if (rc) return rc;
     }
     if (h.n_spl > s->spl_sorted_cap) {
@@ -1168,6 +1313,8 @@ struct PlanJob {
   uint4 *sorted = nullptr;
   size_t sorted_cap = 0;
   size_t ran_spl_cap = 0;       // record capacity the captured restore has
+  size_t ran_seg_cap = 0, ran_cand_cap = 0;   // pool capacities of the capture
+  int pool = 0;                 // restore pool of the captured restore
   bool eager = false;           // this result comes from an eager rerun
   bool fresh = false;           // RESET plan: the first binned round writes every
                                 // tile from zeros, so no zero fill
@@ -1195,7 +1342,6 @@ struct sketch_plan {
   uint64_t gen = ~0ull;         // device context generation at the capture
   bool ran = false;             // the graph has run at least once
   hipStream_t run_stream = nullptr;
-  size_t ran_seg_cap = 0, ran_cand_cap = 0;   // pool capacities of the capture
 };
 
 namespace {
@@ -1243,13 +1389,14 @@ int plan_alloc_sorted(PlanJob &j, size_t cap) {
 }
 
 RestoreBufs plan_restore_bufs(const sketch_plan *P, const PlanJob &j) {
-  RestoreBufs B = restore_bufs(j.s);      // the sketch's rows, the shared pool
+  const RPool &pool = P->ctx->pool[j.pool];
+  RestoreBufs B = restore_bufs(j.s, pool);    // the sketch's rows, the job's pool
   // the zero counts are known valid at capture only when each run starts
   // the window and its update writes every tile
   B.lez = (P->flags & SKETCH_PLAN_RESET) && j.fresh ? j.s->lez : nullptr;
   B.st = j.st;
   B.spl_sorted = j.sorted;
-  B.spl_cap = std::min(P->ctx->spl_cap, j.sorted_cap);
+  B.spl_cap = std::min(pool.spl_cap, j.sorted_cap);
   B.h_state = j.d_h_state;
   B.h_recs = j.d_h_recs;
   B.h_recs_cap = j.h_recs_cap;
@@ -1265,11 +1412,17 @@ int plan_enqueue(sketch_plan *P, hipStream_t st) {
   for (PlanLaunch &L : P->launches)
     HIP_OK(launch_update_jobs(L.h.data(), L.d, (uint32_t)L.h.size(), L.d_total, L.binned, L.r,
                               L.ppt, L.apply_grid, st));
-  if (P->flags & SKETCH_PLAN_RESTORE)
+  if (P->flags & SKETCH_PLAN_RESTORE) {
+    std::vector<uint8_t> used(RESTORE_POOLS, 0);
+    for (const PlanJob &j : P->jobs) used[j.pool] = 1;
+    HIP_OK(batch_fork(P->ctx, used.data(), st));
     for (PlanJob &j : P->jobs) {
+      hipStream_t js = pool_stream(P->ctx, j.pool, st);
       HIP_OK(launch_restore(j.s->G, j.s->d_sketch, plan_restore_bufs(P, j), j.t.zhot,
-                            j.t.e_theta, 1, j.s->grid, st));
+                            j.t.e_theta, 1, j.s->grid, js));
     }
+    HIP_OK(batch_join(P->ctx, used.data(), st));
+  }
   return SKETCH_OK;
 }
 
@@ -1280,6 +1433,14 @@ int plan_build_graph(sketch_plan *P) {
   plan_free_graph(P);
   int rc = ensure_arena(c, P->arena_words, P->arena_tiles);
   if (rc) return rc;
+  if (P->flags & SKETCH_PLAN_RESTORE) {
+    std::vector<const sketch *> ss;
+    for (const PlanJob &j : P->jobs) ss.push_back(j.s);
+    std::vector<int> pools;
+    rc = assign_pools(c, ss, pools);
+    if (rc) return rc;
+    for (size_t i = 0; i < P->jobs.size(); i++) P->jobs[i].pool = pools[i];
+  }
   for (PlanLaunch &L : P->launches) {
     if (!L.binned) continue;
     place_arena(L.h.data(), (uint32_t)L.h.size(), L.r, L.ppt, c->codes, c->scratch);
@@ -1297,10 +1458,11 @@ int plan_build_graph(sketch_plan *P) {
     return fail(SKETCH_E_HIP, "plan: capture failed: %s", hipGetErrorString(e));
   P->graph = g;
   HIP_OK(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
-  P->ran_seg_cap = c->seg_cap;
-  P->ran_cand_cap = c->cand_cap;
   for (PlanJob &j : P->jobs) {
-    j.ran_spl_cap = std::min(c->spl_cap, j.sorted_cap);
+    const RPool &pool = c->pool[j.pool];
+    j.ran_seg_cap = pool.seg_cap;
+    j.ran_cand_cap = pool.cand_cap;
+    j.ran_spl_cap = std::min(pool.spl_cap, j.sorted_cap);
     j.ran_h_recs_cap = j.h_recs_cap;
   }
   P->gen = c->gen;
@@ -1561,16 +1723,35 @@ int sketch_restore_batch_begin(sketch_restore_job_t *jobs, size_t n_jobs, void *
   hipStream_t st = (hipStream_t)hip_stream;
   DevCtx *c = jobs[0].sketch->ctx;
   std::lock_guard<std::mutex> lk(c->mu);
-  // every restore enqueued; each one's end is marked by its sketch's event
-  for (size_t j = 0; j < n_jobs; j++) {
+  // the jobs spread over the restore pools (pools 1.. on their own streams,
+  // forked from st and joined back to it), costliest first in each; every
+  // restore enqueued, each one's end marked by its sketch's event
+  std::vector<const sketch *> ss(n_jobs);
+  for (size_t j = 0; j < n_jobs; j++) ss[j] = jobs[j].sketch;
+  std::vector<int> pools;
+  rc = assign_pools(c, ss, pools);
+  if (rc) return rc;
+  std::vector<size_t> order(n_jobs);
+  for (size_t j = 0; j < n_jobs; j++) order[j] = j;
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+    return restore_cost(ss[a]) > restore_cost(ss[b]);
+  });
+  uint8_t used[RESTORE_POOLS] = {};
+  for (int q : pools) used[q] = 1;
+  if (batch_fork(c, used, st) != hipSuccess)
+    return fail(SKETCH_E_HIP, "sketch_restore_batch_begin: stream fork failed");
+  for (size_t j : order) {
     sketch *s = jobs[j].sketch;
+    const hipStream_t js = pool_stream(c, pools[j], st);
     s->pend_t = thresholds(s, jobs[j].theta);
-    rc = restore_launch(s, s->pend_t, 1, st);
-    if (!rc && hipEventRecord(s->restore_ev, st) != hipSuccess)
+    rc = restore_launch_pool(s, s->pend_t, 1, pools[j], js);
+    if (!rc && hipEventRecord(s->restore_ev, js) != hipSuccess)
       rc = fail(SKETCH_E_HIP, "sketch_restore_batch_begin: hipEventRecord failed");
     if (rc) return rc;
     s->pending = true;
   }
+  if (batch_join(c, used, st) != hipSuccess)
+    return fail(SKETCH_E_HIP, "sketch_restore_batch_begin: stream join failed");
   return SKETCH_OK;
 }
 
@@ -1638,7 +1819,7 @@ int sketch_candidates(sketch_t *s, double theta, uint32_t *out, size_t cap, size
   if (h.n_cand > cap)
     return fail(SKETCH_E_CAPACITY, "sketch_candidates: %llu candidates, cap %zu", h.n_cand, cap);
   if (h.n_cand)
-    HIP_OK(hipMemcpyAsync(out, s->ctx->cand_sorted, h.n_cand * sizeof(uint32_t),
+    HIP_OK(hipMemcpyAsync(out, s->ctx->pool[0].cand_sorted, h.n_cand * sizeof(uint32_t),
                           hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
   return SKETCH_OK;
@@ -1913,7 +2094,7 @@ int sketch_plan_create(const sketch_plan_job_t *jobs, size_t n_jobs, int flags,
           rc = fail(SKETCH_E_HIP, "plan: job table upload: %s", hipGetErrorString(e));
       }
     }
-    if (!rc) rc = pool_idle(c);           // nothing else uses the shared buffers now
+    if (!rc) rc = pools_idle(c);          // nothing else uses the shared buffers now
     if (!rc) rc = arena_idle(c);
     if (!rc) rc = plan_build_graph(P);
   }
@@ -1935,7 +2116,7 @@ int sketch_plan_run(sketch_plan_t *P, void *hip_stream) {
   if (P->dirty || P->gen != c->gen ||
       c->codes_cap < P->arena_words || c->scratch_tiles < P->arena_tiles) {
     if (P->ran) HIP_OK(hipStreamSynchronize(P->run_stream));   // the old graph is done
-    int rc = pool_idle(c);
+    int rc = pools_idle(c);
     if (!rc) rc = arena_idle(c);
     if (!rc) rc = plan_build_graph(P);
     if (rc) return rc;
@@ -1954,11 +2135,14 @@ int sketch_plan_run(sketch_plan_t *P, void *hip_stream) {
       j.s->lez_valid = false;
     }
   }
-  int rc = lane_enter(c->pool_lane, st);
+  int rc = SKETCH_OK;
+  for (RPool &p : c->pool)
+    if (!rc && p.ready) rc = lane_enter(p.lane, st);
   if (!rc) rc = lane_enter(c->arena_lane, st);
   if (rc) return rc;
   HIP_OK(hipGraphLaunch(P->exec, st));
-  rc = lane_leave(c->pool_lane, st);
+  for (RPool &p : c->pool)
+    if (!rc && p.ready) rc = lane_leave(p.lane, st);
   if (!rc) rc = lane_leave(c->arena_lane, st);
   for (PlanJob &j : P->jobs)
     if (!rc) rc = lane_leave(j.s->lane, st);
@@ -1998,6 +2182,7 @@ int sketch_plan_results(sketch_plan_t *P, sketch_restore_job_t *out, size_t n_ou
     const uint4 *src = pj.sorted;
     int rc = SKETCH_OK;
     pj.eager = false;
+    note_cost(s, *h);
     if (h->saturated) {
       rc = SKETCH_E_SATURATED;
     } else {
@@ -2007,12 +2192,17 @@ int sketch_plan_results(sketch_plan_t *P, sketch_restore_job_t *out, size_t n_ou
       // a stage overflowed if its count passed the capacity the graph ran
       // with; the shared buffers grow as for an eager restore (which moves
       // them, so the next run captures again) and this job runs again alone
-      if (need_part > P->ran_seg_cap || h->n_cand > P->ran_cand_cap ||
+      if (need_part > pj.ran_seg_cap || h->n_cand > pj.ran_cand_cap ||
           h->n_spl > pj.ran_spl_cap) {
         if (h->n_spl > pj.sorted_cap) {
           rc = plan_alloc_sorted(pj, grown(h->n_spl, pj.sorted_cap));
           P->dirty = true;
         }
+        // the job's pool grows for the next runs (a move recaptures the graph)
+        RPool &pool = c->pool[pj.pool];
+        if (!rc && need_part > pool.seg_cap) rc = grow_partials(c, pool, need_part);
+        if (!rc && h->n_cand > pool.cand_cap) rc = grow_cand(c, pool, h->n_cand);
+        if (!rc && h->n_spl > pool.spl_cap) rc = grow_pool_spl(c, pool, h->n_spl);
         if (!rc) rc = run_restore(s, pj.t, 1, st);
         h = s->h_state;
         src = s->spl_sorted;

@@ -569,6 +569,18 @@ def batched_run(args, dev) -> dict:
         tune.apply(sk, tuned[key])
         sks.append(sk)
     items = [(sk, x[4], x[3]) for sk, x in zip(sks, links)]
+    # the restore's candidate search per (shape, size class, theta), tuned
+    # on the first link of each class with its window in the sketch
+    rtuned = {}
+    for (n, s, planted, theta, pairs), sk in zip(links, sks):
+        key = (sk.params.k, tune.size_class(n), theta)
+        if key not in rtuned:
+            log(f"tuning the restore k={key[0]} n~2^{key[1]} theta={theta:g}")
+            sk.reset()
+            sk.update(pairs)
+            rtuned[key] = tune.tune_restore(sk, theta, n, use_cache=False)
+        else:
+            tune.apply(sk, rtuned[key])
 
     def batched():
         for sk in sks:
@@ -627,7 +639,9 @@ def batched_run(args, dev) -> dict:
            "speedup_vs_plain": round(tp / tg, 3),
            "windows_differing": differ,
            "super_points": int(sum(len(r[0]) for r in rg)),
-           "tuned": {f"k{k}_n2^{c}": v for (k, c), v in sorted(tuned.items())}}
+           "tuned": {f"k{k}_n2^{c}": v for (k, c), v in sorted(tuned.items())},
+           "restore_tuned": {f"k{k}_n2^{c}_theta{t:g}": v
+                             for (k, c, t), v in sorted(rtuned.items())}}
     plan.close()
     for sk in sks:
         sk.close()

@@ -362,13 +362,19 @@ enum {
                                        regions sized exactly); 0 = 16 for
                                        blocks of 64 batches or more, fewer
                                        below (default) */
-  SKETCH_OPT_BINNED_REGIONS = 13    /* binned: a region holds value/64 of its
+  SKETCH_OPT_BINNED_REGIONS = 13,   /* binned: a region holds value/64 of its
                                        estimate plus 64 code words, 0..1024;
                                        0 = 9/8 of a sampled estimate, the
                                        exact count when every batch is read
                                        (default). Runs that do not fit go to
                                        a spill area (small values force that,
                                        for tests) */
+  SKETCH_OPT_JOIN_BLOCKS = 14       /* blocks of each join stage (Algs. 3-4),
+                                       1 to four per compute unit; 0 = four
+                                       per compute unit (default). Each block
+                                       takes an equal share of the stage's
+                                       items and writes its own segment of
+                                       partial addresses */
 };
 
 /* Phases of the last restore that ran with SKETCH_OPT_TIMING on (device

@@ -594,6 +594,7 @@ struct sketch {
   Geom G;
   Lattice lat{};                // row 0's cells as lattice boxes (restore)
   uint32_t cand_path = 0;       // SKETCH_OPT_CANDIDATES: 0 auto, 1 join, 2 lattice
+  uint32_t join_blocks = 0;     // SKETCH_OPT_JOIN_BLOCKS: 0 = the device's (4 per CU)
   DevCtx *ctx = nullptr;
   mutable Lane lane;            // last work on this sketch (any stream)
   // a restore begun by sketch_restore_batch_begin and not yet ended: its
@@ -713,7 +714,8 @@ RestoreBufs restore_bufs(const sketch *s, const RPool &p) {
   B.segc[0] = p.segc[0];
   B.segc[1] = p.segc[1];
   B.seg_cap = p.seg_cap;
-  B.jblk = c->jblk;
+  // fewer join blocks use the first of the pool's segments
+  B.jblk = s->join_blocks ? std::min(s->join_blocks, c->jblk) : c->jblk;
   B.cand = p.cand;
   B.cand_sorted = p.cand_sorted;
   B.cand_cap = p.cand_cap;
@@ -1878,6 +1880,10 @@ int sketch_set_option(sketch_t *s, int option, int64_t value) {
     case SKETCH_OPT_BINNED_REGIONS:
       if (value < 0 || value > 1024) break;
       s->bin_rscale = (uint32_t)value;
+      return SKETCH_OK;
+    case SKETCH_OPT_JOIN_BLOCKS:
+      if (value < 0 || value > (int64_t)s->ctx->jblk) break;
+      s->join_blocks = (uint32_t)value;
       return SKETCH_OK;
     case SKETCH_OPT_CANDIDATES:
       if (value < 0 || value > 2) break;

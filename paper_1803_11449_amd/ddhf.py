@@ -50,6 +50,7 @@ SKETCH_OPT_TIMING = 10
 SKETCH_OPT_CANDIDATES = 11
 SKETCH_OPT_BINNED_SAMPLE = 12
 SKETCH_OPT_BINNED_REGIONS = 13
+SKETCH_OPT_JOIN_BLOCKS = 14
 
 c_u32, c_u64, c_i32, c_sz, c_dbl, c_vp = (ctypes.c_uint32, ctypes.c_uint64,
                                           ctypes.c_int32, ctypes.c_size_t,

@@ -1,4 +1,5 @@
-"""Autotuner for the update's launch options (sketch_set_option).
+"""Autotuner for the update's and the restore's launch options
+(sketch_set_option).
 
 For one sketch shape (g, k, r, alpha) and one window size it times the
 update under each candidate setting on the device and keeps the fastest:
@@ -10,9 +11,16 @@ update under each candidate setting on the device and keeps the fastest:
 and whether the window takes the direct or the binned kernels. Each
 setting is timed with HIP events on the stream the update runs on, as the
 median of a few updates of the same pairs into a freshly reset sketch.
+
+For the restore of a window at one theta it times the candidate search
+each way: the join of Algs. 3-4 at JOIN_BLOCKS of one, two or four per
+compute unit, and the lattice search (k <= 20), as the host time from the
+call to the list, the median of a few restores of the same sketch. Both
+searches give the same candidates; the choice only moves time.
+
 Results are cached in a JSON file keyed by device name, shape and size
-class (the window size rounded to a power of two), so a process pays for a
-sweep once per (shape, size class).
+class (the window size rounded to a power of two; for the restore also
+theta), so a process pays for a sweep once per key.
 """
 from __future__ import annotations
 
@@ -20,6 +28,7 @@ import json
 import math
 import os
 import statistics
+import time
 
 import torch
 
@@ -30,7 +39,8 @@ CACHE = os.environ.get("DDHF_TUNE_CACHE",
 
 OPTION = {"path": ddhf.SKETCH_OPT_UPDATE_PATH, "grid": ddhf.SKETCH_OPT_UPDATE_GRID,
           "check": ddhf.SKETCH_OPT_UPDATE_CHECK, "ppt": ddhf.SKETCH_OPT_SCATTER_PPT,
-          "blocks": ddhf.SKETCH_OPT_BINNED_BLOCKS}
+          "blocks": ddhf.SKETCH_OPT_BINNED_BLOCKS, "cand": ddhf.SKETCH_OPT_CANDIDATES,
+          "jblocks": ddhf.SKETCH_OPT_JOIN_BLOCKS}
 
 
 def size_class(n_pairs: int) -> int:
@@ -47,6 +57,13 @@ def candidates(n_cu: int, binned_ok: bool) -> list:
     if binned_ok:
         out += [{"path": 2, "ppt": ppt, "blocks": b}
                 for ppt in (2, 4, 6) for b in (n_cu // 2, n_cu, 2 * n_cu)]
+    return out
+
+
+def restore_candidates(n_cu: int, k: int) -> list:
+    out = [{"cand": 1, "jblocks": n_cu * m} for m in (1, 2, 4)]
+    if k <= 20:
+        out.append({"cand": 2, "jblocks": 0})
     return out
 
 
@@ -111,6 +128,43 @@ def tune(g: int, k: int, r: int, alpha: int, pairs: torch.Tensor, seed: int = dd
             ms = time_update(sk, pairs, trials)
             if best is None or ms < best["ms"]:
                 best = {"ms": round(ms, 5), **opts}
+    db = _load()
+    db[key] = best
+    if use_cache:
+        _save(db)
+    return best
+
+
+def time_restore(sk: ddhf.Sketch, theta: float, trials: int = 3) -> float:
+    """Median milliseconds from the restore call to the list on the host."""
+    ts = []
+    for _ in range(trials + 1):
+        torch.cuda.synchronize(sk.device)
+        t0 = time.perf_counter()
+        sk.restore(theta)
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return statistics.median(ts[1:])        # the first run grows buffers
+
+
+def tune_restore(sk: ddhf.Sketch, theta: float, n_pairs: int, trials: int = 3,
+                 use_cache: bool = True) -> dict:
+    """The fastest candidate search for windows like the one sk holds now
+    (updated, not reset) at theta: {"ms": ..., "cand": ..., "jblocks": ...}.
+    The sketch keeps the best setting."""
+    p = sk.params
+    key = _key(sk.device, p.g, p.k, p.r, p.alpha, n_pairs) + f"/restore_theta{theta:g}"
+    db = _load() if use_cache else {}
+    if key in db:
+        apply(sk, db[key])
+        return db[key]
+    n_cu = torch.cuda.get_device_properties(sk.device).multi_processor_count
+    best = None
+    for opts in restore_candidates(n_cu, p.k):
+        apply(sk, opts)
+        ms = time_restore(sk, theta, trials)
+        if best is None or ms < best["ms"]:
+            best = {"ms": round(ms, 5), **opts}
+    apply(sk, best)
     db = _load()
     db[key] = best
     if use_cache:

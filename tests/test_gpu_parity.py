@@ -376,7 +376,9 @@ def test_set_option_rejects_bad_values():
                          (ddhf.SKETCH_OPT_BINNED_ROUND, 10),
                          (ddhf.SKETCH_OPT_TRIM_POOLS, -1), (ddhf.SKETCH_OPT_APPLY_BLOCKS, -1),
                          (ddhf.SKETCH_OPT_BINNED_SAMPLE, 1025),
-                         (ddhf.SKETCH_OPT_BINNED_REGIONS, -1), (99, 1)):
+                         (ddhf.SKETCH_OPT_BINNED_REGIONS, -1),
+                         (ddhf.SKETCH_OPT_JOIN_BLOCKS, -1), (ddhf.SKETCH_OPT_JOIN_BLOCKS, 1 << 20),
+                         (99, 1)):
             with pytest.raises(ddhf.SketchError) as e:
                 sk.set_option(opt, val)
             assert e.value.code == ddhf.SKETCH_E_INVAL
@@ -486,6 +488,32 @@ def test_candidate_search_join_and_lattice_vs_bruteforce(p, path):
         assert not any(info["n_partials"])        # no partial addresses
     elif p.r > 3 and he[0] * he[1] > 0:
         assert info["n_partials"][2] > 0
+
+
+@pytest.mark.parametrize("blocks", [1, 7, 256])
+def test_join_with_fewer_blocks_equals_oracle(blocks):
+    """The join at 1, 7 and 256 blocks per stage (each block an equal share
+    of a stage's items, its own segment of partials): the brute-force
+    candidate set and the oracle's list."""
+    p = oracle.Params(1024, 14, 5, 6)
+    say(f"join blocks={blocks}")
+    rng = np.random.default_rng(71 + blocks)
+    hosts = rng.choice(2**32, size=12, replace=False).astype(np.uint32)
+    pairs = np.concatenate([rand_pairs(rng, 600_000, 30_000)] + planted(rng, hosts, 3000))
+    theta = 0.7 * p.g
+    ref = oracle.build_sketch(p, pairs)
+    with make_sketch(p) as sk:
+        sk.set_option(ddhf.SKETCH_OPT_CANDIDATES, 1)
+        sk.set_option(ddhf.SKETCH_OPT_JOIN_BLOCKS, blocks)
+        sk.upload(ref)
+        cand = sk.candidates(theta)
+        recs, info = sk.restore(theta)
+    assert np.array_equal(cand, oracle.candidates(p, ref, theta, "brute"))
+    ip, sz, c, _ = oracle.restore(p, ref, theta, mode="brute")
+    assert_not_boundary(info)
+    assert_spl_equal(recs, ip, sz, c)
+    assert info["n_partials"][2] > 0
+    assert set(hosts.tolist()) <= set(recs["ip"].tolist())
 
 
 def test_lattice_option_needs_k_at_most_20():

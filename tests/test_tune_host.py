@@ -1,7 +1,9 @@
 """Host logic of the autotuner, on the CPU: the candidate settings stay inside
 the ranges sketch_set_option accepts, the fastest candidate wins, sketches
-past the binned kernels' tile limit get only direct candidates, and the
-result is cached by shape and size class. The device queries, the sketch
+past the binned kernels' tile limit get only direct candidates, the restore
+tuner offers the lattice search only where it runs (k <= 20) and leaves the
+sketch on its best setting, and results are cached by shape and size class
+(and theta for the restore). The device queries, the sketch
 and the timer are replaced by stand-ins (the GPU tuning test times the real
 kernels).
 """
@@ -19,6 +21,8 @@ VALID = {
     "check": lambda v: v in (0, 1),
     "ppt": lambda v: v in (2, 4, 6),
     "blocks": lambda v: 1 <= v <= 1024,
+    "cand": lambda v: v in (0, 1, 2),
+    "jblocks": lambda v: 0 <= v <= 4 * 1024,     # at most four per compute unit
 }
 
 
@@ -112,3 +116,60 @@ def test_past_the_tile_limit_only_direct_settings(fake_device):
     best = tune.tune(65536, 14, 5, 6, torch.zeros((1000, 2), dtype=torch.int32), use_cache=False)
     assert best["path"] == 1 and all(o["path"] == 1 for o in timed)
     assert len(timed) == len(tune.candidates(256, False))
+
+
+@pytest.mark.parametrize("n_cu", [80, 256, 304])
+@pytest.mark.parametrize("k", [14, 20, 21])
+def test_restore_candidates_are_valid_settings(n_cu, k):
+    cands = tune.restore_candidates(n_cu, k)
+    assert len({json.dumps(c, sort_keys=True) for c in cands}) == len(cands)
+    for c in cands:
+        assert set(c) <= set(tune.OPTION)
+        assert all(VALID[name](v) for name, v in c.items()), c
+        assert c["jblocks"] <= 4 * n_cu
+    assert any(c["cand"] == 2 for c in cands) == (k <= 20)
+    assert any(c["cand"] == 1 for c in cands)
+
+
+class RestoreSketch:
+    def __init__(self, k):
+        self.params = ddhf.sketch_params_t(1024, k, 5, 5, 1, 0)
+        self.device = 0
+        self.opts = {}
+        self.restores = 0
+
+    def set_option(self, option, value):
+        self.opts[option] = value
+
+    def restore(self, theta):
+        self.restores += 1
+
+
+@pytest.mark.parametrize("k,lattice_fast", [(18, True), (18, False), (21, False)])
+def test_tune_restore_picks_the_fastest_and_keeps_it(monkeypatch, tmp_path, k, lattice_fast):
+    monkeypatch.setattr(tune, "CACHE", str(tmp_path / "tune.json"))
+    monkeypatch.setattr(torch.cuda, "get_device_name", lambda dev=None: "Test GPU")
+    monkeypatch.setattr(torch.cuda, "get_device_properties", lambda dev=None: Props())
+
+    def time_restore(sk, theta, trials=3):
+        cand = sk.opts[ddhf.SKETCH_OPT_CANDIDATES]
+        jb = sk.opts[ddhf.SKETCH_OPT_JOIN_BLOCKS]
+        if cand == 2:
+            return 0.1 if lattice_fast else 0.9
+        return 0.3 + abs(jb - 512) / 10000        # the join is best at 512 blocks
+
+    monkeypatch.setattr(tune, "time_restore", time_restore)
+    sk = RestoreSketch(k)
+    best = tune.tune_restore(sk, 512.0, 1 << 20)
+    want = {"cand": 2, "jblocks": 0} if (lattice_fast and k <= 20) else {"cand": 1, "jblocks": 512}
+    assert {n: best[n] for n in ("cand", "jblocks")} == want
+    assert sk.opts == {ddhf.SKETCH_OPT_CANDIDATES: want["cand"],
+                       ddhf.SKETCH_OPT_JOIN_BLOCKS: want["jblocks"]}
+    # cached per theta: the same key skips the sweep, another theta does not
+    calls = []
+    monkeypatch.setattr(tune, "time_restore", lambda sk, th, trials=3: calls.append(th) or 1.0)
+    again = RestoreSketch(k)
+    assert tune.tune_restore(again, 512.0, (1 << 20) + 7) == best and not calls
+    assert again.opts[ddhf.SKETCH_OPT_CANDIDATES] == want["cand"]
+    tune.tune_restore(RestoreSketch(k), 1024.0, 1 << 20)
+    assert calls

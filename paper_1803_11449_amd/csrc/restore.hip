@@ -459,8 +459,9 @@ __device__ __forceinline__ bool lattice_chosen(const Geom &G, const DevState *st
 // done walks no points), so the queue's fill is the same in every lane.
 // Each address lies in exactly one cell, so there are no duplicates.
 
-constexpr int LAT_THREADS = 256;
-constexpr uint32_t LAT_QUEUE = 320;                     // survivors per wave
+constexpr int LAT_THREADS = 512;
+constexpr uint32_t LAT_TRIP = 8;                        // points per lane per trip
+constexpr uint32_t LAT_QUEUE = 63 + LAT_TRIP * 64 + 1;  // survivors per wave
 constexpr uint32_t LAT_QUEUE_BYTES = (LAT_THREADS / 64) * LAT_QUEUE * 4;
 // row 1's bitmap for k <= 20, and the queues
 constexpr uint32_t LATTICE_LDS_MAX = 131072 + LAT_QUEUE_BYTES;
@@ -526,7 +527,7 @@ __global__ __launch_bounds__(LAT_THREADS) void k_lattice(
   };
   // append the points of this trip that passed row 1 (bit q of hit: point
   // b + q step), placed by a prefix sum over the wave; test 64 at a time
-  // while the queue holds them (it holds at most 63 + 4*64 entries)
+  // while the queue holds them (it holds at most 63 + LAT_TRIP*64 entries)
   auto push = [&](uint32_t b, uint32_t step_, uint32_t hit) {
     const uint32_t cnt = __popc(hit);
     const uint32_t incl = wave_scan_incl(cnt);
@@ -544,7 +545,7 @@ __global__ __launch_bounds__(LAT_THREADS) void k_lattice(
 
   const uint32_t s = 64 - k;
   const uint64_t S = 1ull << s;
-  const uint32_t kmask = (1u << k) - 1;
+  const uint32_t bmask = (kw - 1) << 2;                 // byte offsets of row 1's words
   const double D = L.dneg ? -0x1p64 : 0x1p64;
   const uint32_t lines = L.lines;
   const uint32_t items = st->he_count[0] * lines;      // < 2^32 for k <= 24
@@ -613,20 +614,28 @@ __global__ __launch_bounds__(LAT_THREADS) void k_lattice(
         }
       }
     }
-    // the walk: four points per trip (their row-1 words read together)
+    // the walk: LAT_TRIP points per trip, their row-1 words read together.
+    // Point b's row-1 LE is (c ^ b) mod 2^k: its word is bits 5..k-1 of
+    // c ^ b (byte offset: bits 3..k-4) and its bit bits 0..4. Points past
+    // the line's end read a valid word and are masked out of hit.
     while (__ballot(n != 0)) {
-      const uint32_t m = n < 4 ? n : 4;
-      const uint32_t b0 = a, b1 = b0 + step, b2 = b1 + step, b3 = b2 + step;
-      const uint32_t x0 = (c ^ b0) & kmask, x1 = (c ^ b1) & kmask;   // row-1 LEs
-      const uint32_t x2 = (c ^ b2) & kmask, x3 = (c ^ b3) & kmask;
-      const uint32_t w0 = row1[x0 >> 5], w1 = row1[x1 >> 5];
-      const uint32_t w2 = row1[x2 >> 5], w3 = row1[x3 >> 5];
-      const uint32_t hit = (((w0 >> (x0 & 31)) & 1u) | (((w1 >> (x1 & 31)) & 1u) << 1) |
-                            (((w2 >> (x2 & 31)) & 1u) << 2) | (((w3 >> (x3 & 31)) & 1u) << 3)) &
-                           ((1u << m) - 1);
-      a = b0 + m * step;
+      const uint32_t m = n < LAT_TRIP ? n : LAT_TRIP;
+      uint32_t cb[LAT_TRIP], w[LAT_TRIP];
+      uint32_t b = a;
+#pragma unroll
+      for (uint32_t q = 0; q < LAT_TRIP; q++) {
+        cb[q] = c ^ b;
+        w[q] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(row1) +
+                                                    ((cb[q] >> 3) & bmask));
+        b += step;
+      }
+      uint32_t hit = 0;
+#pragma unroll
+      for (uint32_t q = 0; q < LAT_TRIP; q++) hit |= __builtin_amdgcn_ubfe(w[q], cb[q] & 31u, 1u) << q;
+      hit &= (1u << m) - 1;
+      push(a, step, hit);
+      a += m * step;
       n -= m;
-      push(b0, step, hit);
     }
   }
   // what is left in the queue

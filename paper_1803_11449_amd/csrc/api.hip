@@ -1018,6 +1018,7 @@ struct Group {
   uint32_t apply_grid;
   bool wide;                    // binned: more than 2048 tiles per sketch
   std::vector<UpdJob> jobs;
+  size_t pairs = 0;             // binned: pairs of the jobs (the arena's share)
 };
 
 // The scatter batch (pairs per thread) of a binned launch of n jobs with
@@ -1104,17 +1105,25 @@ int flush_group(DevCtx *c, Group &g, hipStream_t st) {
 // Binned jobs share a launch only with sketches of the same tile class: the
 // launch's largest sketch picks the scatter variant, and one of more than
 // 2048 tiles would hold every job of the launch to its smaller batches.
-void add_job(std::vector<Group> &groups, const sketch *s, const UpdJob &J, bool binned) {
+size_t group_of(std::vector<Group> &groups, const sketch *s, const UpdJob &J, bool binned) {
   const bool wide = binned && s->nbins > 2048;
-  for (Group &g : groups)
+  for (size_t i = 0; i < groups.size(); i++) {
+    const Group &g = groups[i];
     if (g.r == s->p.r && g.binned == binned && g.wide == wide &&
-        (binned ? g.ppt == s->scatter_ppt : g.check == J.check)) {
-      g.apply_grid = (g.apply_grid == 0 || s->apply_grid == 0)
-                         ? 0u : std::max(g.apply_grid, s->apply_grid);
-      g.jobs.push_back(J);
-      return;
-    }
-  groups.push_back(Group{s->p.r, binned, J.check, s->scatter_ppt, s->apply_grid, wide, {J}});
+        (binned ? g.ppt == s->scatter_ppt : g.check == J.check))
+      return i;
+  }
+  groups.push_back(Group{s->p.r, binned, J.check, s->scatter_ppt, s->apply_grid, wide, {}});
+  return groups.size() - 1;
+}
+
+void add_job(std::vector<Group> &groups, const sketch *s, const UpdJob &J, bool binned) {
+  Group &g = groups[group_of(groups, s, J, binned)];
+  g.apply_grid = g.jobs.empty() ? s->apply_grid
+                 : (g.apply_grid == 0 || s->apply_grid == 0) ? 0u
+                                                             : std::max(g.apply_grid, s->apply_grid);
+  g.jobs.push_back(J);
+  if (binned) g.pairs += J.n;
 }
 
 // Pairs, blocks and pairs per block of a binned round of m pairs: about
@@ -1155,9 +1164,11 @@ int check_update_jobs(const sketch_update_job_t *jobs, size_t n_jobs, const char
 }
 
 // Splits the update of several distinct sketches into launch groups and
-// hands them, in order, to flush(Group&). Binned work runs in rounds of at
-// most ARENA_MAX_PAIRS pairs in total (and a job's binned_round each); job
-// j's per-sketch arrays come from base(j).
+// hands them, in order, to flush(Group&). A pass takes one round of every
+// job with pairs left (a job's binned_round at most); a binned launch group
+// holds at most ARENA_MAX_PAIRS pairs, and one that is full is flushed
+// during the pass, the rest at its end, so a job's rounds run in order.
+// Job j's per-sketch arrays come from base(j).
 // Whether an update of n pairs at p takes binned rounds from its first pair
 // on (no pair goes through the direct kernel first).
 bool binned_from_start(const sketch *s, const uint32_t *p, size_t n) {
@@ -1192,16 +1203,20 @@ int schedule_update(const sketch_update_job_t *jobs, size_t n_jobs, Base base, F
   }
   for (;;) {
     bool any = false;
-    size_t room = ARENA_MAX_PAIRS;
     for (size_t j = 0; j < n_jobs; j++) {
       if (!left[j]) continue;
       sketch *s = jobs[j].sketch;
       UpdJob J = base(j);
       J.pairs = reinterpret_cast<const uint2 *>(ptr[j]);
       if (binned[j]) {
-        const size_t m = std::min({left[j], s->binned_round, room});
-        if (m == 0) continue;
-        room -= m;
+        Group &g = groups[group_of(groups, s, J, true)];
+        if (g.pairs >= ARENA_MAX_PAIRS) {
+          int rc = flush(g);
+          if (rc) return rc;
+          g.jobs.clear();
+          g.pairs = 0;
+        }
+        const size_t m = std::min({left[j], s->binned_round, ARENA_MAX_PAIRS - g.pairs});
         bin_shape(s, m, J);
         if (fresh) {
           J.fresh = (uint32_t)fresh[j];
@@ -1224,6 +1239,7 @@ int schedule_update(const sketch_update_job_t *jobs, size_t n_jobs, Base base, F
       int rc = flush(g);
       if (rc) return rc;
       g.jobs.clear();
+      g.pairs = 0;
     }
     if (!any) break;
   }

@@ -266,6 +266,11 @@ def headline(args, dev) -> dict:
     log("warmup")
     for _ in range(args.warmup):
         step()
+    # the restore's candidate search as the autotuner picks it for this
+    # window (the sketch holds the window after the warmup)
+    from paper_1803_11449_amd import tune
+    rtuned = tune.tune_restore(sk, args.theta, n, use_cache=False)
+    log(f"restore tuned: {rtuned}")
     rec = {"events": [], "restore_ms": [], "phases": []}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -324,6 +329,7 @@ def headline(args, dev) -> dict:
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": hbm_traffic},
         "restore_roofline": restore_roofline(rec["phases"]),
+        "restore_tuned": rtuned,
     }
     if hbm_traffic:
         out["roofline"]["traffic_gbs"] = round(hbm_traffic / (upd_mean / 1e3) / 1e9, 1)

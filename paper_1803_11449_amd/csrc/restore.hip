@@ -1201,8 +1201,9 @@ static hipError_t launch_wpl(const Geom &G, const uint32_t *sketch, const Restor
   k_rows<<<r, 1024, 0, st>>>(G, B.hotmask, B.he, B.bk_off, B.bk_cur, B.bk_val, B.st, e_theta);
   mark(2);
   // 5: candidates, by the lattice search or the join (each kernel returns
-  // at once unless its search is the chosen one)
-  if (B.lat.ok) {
+  // at once unless its search is the chosen one; a search ruled out by the
+  // sketch's setting is not launched)
+  if (B.lat.ok && B.cand_path != 1) {
     // row 1's bitmap and the queues (above 64 KiB by the attribute that
     // prepare_restore_kernels sets)
     const size_t lds = ((size_t)4 << (k - 5)) + LAT_QUEUE_BYTES;
@@ -1210,7 +1211,7 @@ static hipError_t launch_wpl(const Geom &G, const uint32_t *sketch, const Restor
     k_lattice<<<grid > 1 ? grid / 2 : 1, LAT_THREADS, lds, st>>>(
         G, B.lat, B.cand_path, B.he, B.hotmask, B.st, B.cand, B.cand_cap);
   }
-  {
+  if (!(B.lat.ok && B.cand_path == 2)) {
     const uint32_t jb = B.jblk;
     const Lattice &Lt = B.lat;
     const uint32_t pth = B.cand_path;

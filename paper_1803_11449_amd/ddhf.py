@@ -211,10 +211,21 @@ def sketch_reset(h: int, stream: int = 0) -> None:
     _check(lib().sketch_reset(h, stream))
 
 
-def sketch_restore(h: int, theta: float, cap: int, stream: int = 0, _fn="sketch_restore"):
+def _host_buf(cap: int, buf=None) -> np.ndarray:
+    """A record buffer of at least cap entries: buf when it is large
+    enough (a buffer kept across calls avoids a fresh allocation's page
+    faults on every restore), else a new one."""
+    if buf is not None and len(buf) >= max(cap, 1):
+        return buf
+    return np.empty(max(cap, 1), dtype=SP_DTYPE)
+
+
+def sketch_restore(h: int, theta: float, cap: int, stream: int = 0, _fn="sketch_restore",
+                   buf=None):
     """Returns (records[:n], info). Raises SketchError (with n_needed on
-    CAPACITY)."""
-    out = np.empty(max(cap, 1), dtype=SP_DTYPE)       # the first n are written
+    CAPACITY). buf: an optional record buffer of at least cap entries to
+    write into (the returned records are a copy)."""
+    out = _host_buf(cap, buf)                          # the first n are written
     n = c_sz(0)
     info = sketch_info_t()
     rc = getattr(lib(), _fn)(h, float(theta), out.ctypes.data, cap,
@@ -226,10 +237,10 @@ def sketch_restore(h: int, theta: float, cap: int, stream: int = 0, _fn="sketch_
     return out[: n.value].copy(), info_dict(info)
 
 
-def sketch_restore_noalloc(h: int, theta: float, cap: int, stream: int = 0):
+def sketch_restore_noalloc(h: int, theta: float, cap: int, stream: int = 0, buf=None):
     """sketch_restore_noalloc: as sketch_restore, on the library's fixed
     per-GPU work array (no allocation inside the call)."""
-    return sketch_restore(h, theta, cap, stream, _fn="sketch_restore_noalloc")
+    return sketch_restore(h, theta, cap, stream, _fn="sketch_restore_noalloc", buf=buf)
 
 
 class _RestoreJobs:
@@ -237,11 +248,13 @@ class _RestoreJobs:
     entries point at (kept alive together)."""
 
     def __init__(self, items):
+        """items: (handle, theta, cap) or (handle, theta, cap, buffer)."""
         self.n = len(items)
         self.arr = (sketch_restore_job_t * max(1, self.n))()
         self.outs, self.infos = [], []
-        for i, (h, theta, cap) in enumerate(items):
-            out = np.empty(max(cap, 1), dtype=SP_DTYPE)   # the first n are written
+        for i, item in enumerate(items):
+            h, theta, cap = item[:3]
+            out = _host_buf(cap, item[3] if len(item) > 3 else None)   # the first n are written
             info = sketch_info_t()
             self.outs.append(out)
             self.infos.append(info)
@@ -301,13 +314,14 @@ def sketch_plan_run(plan: int, stream: int = 0) -> None:
 
 
 def sketch_plan_results(plan: int, items, stream: int = 0):
-    """items: sequence of (handle, cap) in job order. Returns a list of
-    (records, info, status, n_needed)."""
+    """items: sequence of (handle, cap) or (handle, cap, buffer) in job
+    order. Returns a list of (records, info, status, n_needed)."""
     n = len(items)
     arr = (sketch_restore_job_t * max(1, n))()
     outs, infos = [], []
-    for i, (h, cap) in enumerate(items):
-        out = np.empty(max(cap, 1), dtype=SP_DTYPE)       # the first n are written
+    for i, item in enumerate(items):
+        h, cap = item[:2]
+        out = _host_buf(cap, item[2] if len(item) > 2 else None)   # the first n are written
         info = sketch_info_t()
         outs.append(out)
         infos.append(info)
@@ -404,7 +418,7 @@ def restore_batch(items, stream=None, raise_errors: bool = True):
         return []
     dev = items[0][0].device
     s = _stream_handle(stream, dev)
-    res = sketch_restore_batch([(sk.handle, th, sk._cap) for sk, th in items], s)
+    res = sketch_restore_batch([(sk.handle, th, sk._cap, sk._buf()) for sk, th in items], s)
     return _collect(items, res, stream, raise_errors)
 
 
@@ -441,7 +455,7 @@ class PendingRestore:
         self.jobs = None
         if self.items:
             self.jobs = sketch_restore_batch_begin(
-                [(sk.handle, th, sk._cap) for sk, th in self.items],
+                [(sk.handle, th, sk._cap, sk._buf()) for sk, th in self.items],
                 _stream_handle(stream, self.dev))
 
     def end(self, raise_errors: bool = True):
@@ -485,7 +499,7 @@ class Plan:
         """[(records, info)] of the last run, in item order."""
         s = _stream_handle(stream, self.device)
         while True:
-            res = sketch_plan_results(self.handle, [(sk.handle, sk._cap)
+            res = sketch_plan_results(self.handle, [(sk.handle, sk._cap, sk._buf())
                                                     for sk, _, _ in self.items], s)
             retry = False
             for (sk, _, _), (_, _, st, need) in zip(self.items, res):
@@ -533,6 +547,7 @@ class Sketch:
         self.words = sketch_bytes(self.params) // 4
         self.handle = sketch_create(self.params)
         self._cap = 1 << 12
+        self._outbuf = None
 
     # pairs: CUDA tensor of 2n 32-bit words (int32/uint32, [n,2] or [2n])
     def update(self, pairs, stream=None) -> None:
@@ -546,12 +561,19 @@ class Sketch:
     def update_ptr(self, d_pairs: int, n_pairs: int, stream: int = 0) -> None:
         sketch_update(self.handle, d_pairs, n_pairs, stream)
 
+    def _buf(self) -> np.ndarray:
+        """This handle's host record buffer, at least _cap entries (restores
+        write into it; what they return is a copy)."""
+        if self._outbuf is None or len(self._outbuf) < max(self._cap, 1):
+            self._outbuf = np.empty(max(self._cap, 1), dtype=SP_DTYPE)
+        return self._outbuf
+
     def restore(self, theta: float, stream=None):
         """(records ascending by ip, info dict)."""
         s = _stream_handle(stream, self.device)
         while True:
             try:
-                recs, info = sketch_restore(self.handle, theta, self._cap, s)
+                recs, info = sketch_restore(self.handle, theta, self._cap, s, buf=self._buf())
                 return recs, info
             except SketchError as e:
                 if e.code != SKETCH_E_CAPACITY:
@@ -563,7 +585,7 @@ class Sketch:
         s = _stream_handle(stream, self.device)
         while True:
             try:
-                return sketch_restore_noalloc(self.handle, theta, self._cap, s)
+                return sketch_restore_noalloc(self.handle, theta, self._cap, s, buf=self._buf())
             except SketchError as e:
                 if e.code != SKETCH_E_CAPACITY or not e.n_needed or e.n_needed <= self._cap:
                     raise

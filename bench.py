@@ -271,14 +271,54 @@ def headline(args, dev) -> dict:
     from paper_1803_11449_amd import tune
     rtuned = tune.tune_restore(sk, args.theta, n, use_cache=False)
     log(f"restore tuned: {rtuned}")
+
+    # the monitor's loop: two sketches and two streams, so window w+1 is
+    # reset and updated while window w's restore runs (Sec. 4's cycle:
+    # each period's data comes in while the last period is processed); a
+    # step still takes every pair of its window through update and restore
+    # to the list on the host
+    from paper_1803_11449_amd import serving
+    sk2 = ddhf.Sketch(g, k, r, alpha, traffic.HASH_SEED, device=0)
+    if args.update_path:
+        sk2.set_option(ddhf.SKETCH_OPT_UPDATE_PATH, args.update_path)
+    tune.apply(sk2, rtuned)
+    pipe = [sk, sk2]
+    streams = serving.concurrent_streams(0, 2)
+
+    def piped_steps(steps, record=None):
+        pending = None
+        for i in range(steps):
+            s_, st_ = pipe[i % 2], streams[i % 2]
+            s_.reset(st_)
+            s_.update(pairs, st_)
+            nxt = ddhf.restore_batch_begin([(s_, args.theta)], st_)
+            if pending is not None:
+                recs, info = pending.end()[0]
+                if record is not None:
+                    record["piped_sp"] = len(recs)
+            pending = nxt
+        recs, info = pending.end()[0]
+        if record is not None:
+            record["piped_sp"] = len(recs)
+
+    piped_steps(max(2, args.warmup))
     rec = {"events": [], "restore_ms": [], "phases": []}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    piped_steps(args.steps, rec)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    log(f"{args.steps} pipelined steps in {total:.3f} s")
+    # the same steps one after another on one stream (no overlap); the
+    # update's events come from these, where nothing runs beside it
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step(rec)
     torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-    log(f"{args.steps} steps in {total:.3f} s")
+    serial = time.perf_counter() - t0
+    sk2.close()
+    assert rec["piped_sp"] == rec["n_sp"], "pipelined and serial lists differ in length"
     rec["update_ms"] = [a.elapsed_time(b) for a, b in rec["events"]]
     sk.set_option(ddhf.SKETCH_OPT_TIMING, 1)
     for _ in range(max(20, min(args.steps, 50))):
@@ -330,6 +370,8 @@ def headline(args, dev) -> dict:
                      "traffic": hbm_traffic},
         "restore_roofline": restore_roofline(rec["phases"]),
         "restore_tuned": rtuned,
+        "serial_ms_per_step": round(serial / args.steps * 1e3, 4),
+        "serial_mpps": round(n * args.steps / serial / 1e6, 3),
     }
     if hbm_traffic:
         out["roofline"]["traffic_gbs"] = round(hbm_traffic / (upd_mean / 1e3) / 1e9, 1)
@@ -460,7 +502,7 @@ def stream_run(args, dev) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--pairs", type=int, default=100_000_000)
     ap.add_argument("--theta", type=float, default=1024.0)

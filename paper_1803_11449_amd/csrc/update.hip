@@ -526,8 +526,8 @@ template <int TMAX> struct ScatterValue {
   }
 };
 
-// TMAX: tiles the LDS arrays hold (2048, 3072 or 4096), at least the jobs'
-// tiles.
+// TMAX: tiles the LDS arrays hold (1024, 2048, 3072 or 4096), at least the
+// jobs' tiles.
 template <int R, int PPT, int TMAX>
 __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__ jobs,
                                                       uint32_t nj) {
@@ -914,7 +914,9 @@ static hipError_t launch_r(const UpdJob *h, UpdJob *d, uint32_t nj, uint32_t *d_
   }
   // LDS of the scatter: 4*(1024*PPT*r + 2*TMAX) bytes of sorted codes +
   // 12*TMAX bytes of tile arrays <= 160 KiB. Up to 2048 tiles: 6 pairs per
-  // thread for r <= 5, 4 for r <= 7, else 2. Up to 3072 tiles and r <= 5: 5.
+  // thread for r <= 5, 4 for r <= 7, else 2; the 6-pair variant has a copy
+  // with arrays of 1024 tiles (a k = 18 sketch at r = 5), one tile per
+  // thread in the per-batch tile steps. Up to 3072 tiles and r <= 5: 5.
   // Up to 3276 tiles: 4 for r <= 5, else 2 (scatter_ppt gives the same
   // choice to the host, which sizes the spill-run lists by it). The count
   // pass walks the scatter's batches, so both take the same PPT.
@@ -924,6 +926,7 @@ static hipError_t launch_r(const UpdJob *h, UpdJob *d, uint32_t nj, uint32_t *d_
     constexpr int P4 = R <= 7 ? 4 : 2;
     constexpr int P6 = R <= 5 ? 6 : P4;
     if (ppt == 2) launch_front<R, 2, 2048>(d, nj, blocks, tiles, st);
+    else if (ppt == 6 && max_tiles <= 1024) launch_front<R, P6, 1024>(d, nj, blocks, tiles, st);
     else if (ppt == 6) launch_front<R, P6, 2048>(d, nj, blocks, tiles, st);
     else launch_front<R, P4, 2048>(d, nj, blocks, tiles, st);
   } else if (R <= 5 && max_tiles <= 3072 && ppt != 2) {

@@ -215,6 +215,7 @@ struct DevCtx {
   // restore pools
   uint32_t jblk = 0;             // blocks of the join kernels
   RPool pool[RESTORE_POOLS];
+  size_t pool_entries = 0;       // buffer entries of a pool made on demand (0: initial)
   hipEvent_t fork = nullptr;     // a batch's start on the caller's stream
   // last work that used the update arena (the pools have their own): so
   // one batch's update can run while another batch's restore does
@@ -389,6 +390,7 @@ int trim_pools(DevCtx *c, size_t entries) {
   c->scratch_tiles = 0;
   for (int i = 1; i < RESTORE_POOLS; i++)
     if (c->pool[i].ready) pool_free_buffers(c->pool[i]);
+  c->pool_entries = entries;            // the batch pools come back at this size
   RPool &p = c->pool[0];
   dev_free(p.rank);
   dev_free(p.skeys);
@@ -862,7 +864,7 @@ int assign_pools(DevCtx *c, const std::vector<const sketch *> &ss, std::vector<i
   }
   for (int q = 1; q < np; q++)
     if (!c->pool[q].ready) {
-      int rc = pool_init(c, q, 0);
+      int rc = pool_init(c, q, c->pool_entries);
       if (rc) return rc;
     }
   return SKETCH_OK;

@@ -220,6 +220,15 @@ def _host_buf(cap: int, buf=None) -> np.ndarray:
     return np.empty(max(cap, 1), dtype=SP_DTYPE)
 
 
+def _records(buf: np.ndarray, n: int) -> np.ndarray:
+    """A copy of the first n records of buf, copied as bytes (numpy copies
+    a structured array field by field, several times slower)."""
+    out = np.empty(n, dtype=SP_DTYPE)
+    if n:
+        out.view(np.uint8)[:] = buf[:n].view(np.uint8)
+    return out
+
+
 def sketch_restore(h: int, theta: float, cap: int, stream: int = 0, _fn="sketch_restore",
                    buf=None):
     """Returns (records[:n], info). Raises SketchError (with n_needed on
@@ -234,7 +243,7 @@ def sketch_restore(h: int, theta: float, cap: int, stream: int = 0, _fn="sketch_
         err = SketchError(rc, last_error(), n.value)
         err.info = info_dict(info)
         raise err
-    return out[: n.value].copy(), info_dict(info)
+    return _records(out, n.value), info_dict(info)
 
 
 def sketch_restore_noalloc(h: int, theta: float, cap: int, stream: int = 0, buf=None):
@@ -270,8 +279,7 @@ class _RestoreJobs:
         res = []
         for i in range(self.n):
             st = self.arr[i].status
-            recs = self.outs[i][: self.arr[i].n_out].copy() if st == SKETCH_OK \
-                else self.outs[i][:0].copy()
+            recs = _records(self.outs[i], self.arr[i].n_out if st == SKETCH_OK else 0)
             res.append((recs, info_dict(self.infos[i]), st, self.arr[i].n_out))
         return res
 
@@ -332,7 +340,7 @@ def sketch_plan_results(plan: int, items, stream: int = 0):
     res = []
     for i in range(n):
         st = arr[i].status
-        recs = outs[i][: arr[i].n_out].copy() if st == SKETCH_OK else outs[i][:0].copy()
+        recs = _records(outs[i], arr[i].n_out if st == SKETCH_OK else 0)
         res.append((recs, info_dict(infos[i]), st, arr[i].n_out))
     return res
 

@@ -394,20 +394,21 @@ __device__ __forceinline__ void scalars(const Geom &G, DevState *st, double e_th
 }
 
 // One block per row i: HE(i) from the hot bitmap (step 2), its bucket table
-// when i >= 2 (step 3), and in row 0's block the scalars (step 4), which
-// need only the ZR(i) of the hot scan.
+// when i >= 2 and the join may run (step 3), and in row 0's block the
+// scalars (step 4), which need only the ZR(i) of the hot scan.
 __global__ __launch_bounds__(1024) void k_rows(Geom G, const uint32_t *__restrict__ hotmask,
                                                uint32_t *__restrict__ he,
                                                uint32_t *__restrict__ bk_off,
                                                uint32_t *__restrict__ bk_cur,
                                                uint32_t *__restrict__ bk_val,
-                                               DevState *__restrict__ st, double e_theta) {
+                                               DevState *__restrict__ st, double e_theta,
+                                               uint32_t buckets) {
   __shared__ uint32_t sh[17];
   __shared__ uint32_t lcur[BK_LDS];
   const uint32_t row = blockIdx.x;
   compact_row(G, row, hotmask, he, st, sh);
   if (row == 0 && threadIdx.x == 0) scalars(G, st, e_theta);
-  if (row < 2) return;                                 // uniform over the block
+  if (row < 2 || !buckets) return;                     // uniform over the block
   __syncthreads();                                     // this row's HE and count
   const uint32_t nb = 1u << (G.k - G.alpha);
   uint32_t *off = bk_off + (size_t)row * (nb + 1);
@@ -449,9 +450,9 @@ __device__ __forceinline__ bool lattice_chosen(const Geom &G, const DevState *st
 // point p0 near (0, Y) and integers (i, j); the box is a parallelogram in
 // (i, j). One work item is one line j of one cell: its lane solves the
 // line's range of i (in double, widened, then narrowed exactly in 64-bit
-// integers to the first and last points inside) and walks it, four points
-// per trip, testing each point's LE in row 1 against row 1's hot bitmap in
-// LDS. About |HE(1)| / 2^k of the points pass (a few percent); they go to
+// integers to the first and last points inside) and walks it, LAT_TRIP
+// points per trip, testing each point's LE in row 1 against row 1's hot
+// bitmap in LDS. About |HE(1)| / 2^k of the points pass (a few percent); they go to
 // a queue per wave in LDS, and each time the queue holds 64 the wave tests
 // them together, one per lane: the LEs of rows 0 and 2..r-1 read from the
 // hot bitmap in global memory all at once, then one atomic per wave for
@@ -1198,7 +1199,11 @@ static hipError_t launch_wpl(const Geom &G, const uint32_t *sketch, const Restor
   }
   mark(1);
   // 2-4: HE(i), bucket tables of rows 2..r-1, scalars
-  k_rows<<<r, 1024, 0, st>>>(G, B.hotmask, B.he, B.bk_off, B.bk_cur, B.bk_val, B.st, e_theta);
+  // the bucket tables serve only the join: none when the sketch is set to
+  // the lattice search
+  const uint32_t buckets = !(B.lat.ok && B.cand_path == 2);
+  k_rows<<<r, 1024, 0, st>>>(G, B.hotmask, B.he, B.bk_off, B.bk_cur, B.bk_val, B.st, e_theta,
+                             buckets);
   mark(2);
   // 5: candidates, by the lattice search or the join (each kernel returns
   // at once unless its search is the chosen one; a search ruled out by the

@@ -549,14 +549,19 @@ __global__ __launch_bounds__(LAT_THREADS) void k_lattice(
   const uint32_t bmask = (kw - 1) << 2;                 // byte offsets of row 1's words
   const double D = L.dneg ? -0x1p64 : 0x1p64;
   const uint32_t lines = L.lines;
-  const uint32_t items = st->he_count[0] * lines;      // < 2^32 for k <= 24
+  const uint32_t h0 = st->he_count[0];
+  const uint32_t items = h0 * lines;                    // < 2^32 for k <= 24
   const uint32_t step = (uint32_t)L.ua;
   // every lane of a block takes the same trips (uniform bounds)
   for (uint32_t t0 = blockIdx.x * blockDim.x; t0 < items; t0 += gridDim.x * blockDim.x) {
     const uint32_t t = t0 + threadIdx.x;
     uint32_t n = 0, a = 0, c = 0;                      // n points from address a in cell c
     if (t < items) {
-      const uint32_t x = t / lines, line = t - x * lines;
+      // line-major: the lanes of a wave take the same line of consecutive
+      // hot cells; every cell's box is the same parallelogram shifted, so
+      // these lines are about equally long and the lanes end their walks
+      // together (cell-major, a wave's lines differ by up to 2x)
+      const uint32_t line = t / h0, x = t - line * h0;
       c = he[x];
       const uint64_t Y = ((uint64_t)c << s) - G.b0;
       // p0 = i0 u + j0 v with (i0, j0) ~ M^-1 (0, Y), M = [u v]; its offsets

@@ -359,9 +359,10 @@ enum {
   SKETCH_OPT_BINNED_SAMPLE = 12,    /* binned: the count pass, which sizes
                                        each tile's code regions, reads every
                                        n-th batch of pairs, 1..1024 (1: all,
-                                       regions sized exactly); 0 = 16 for
-                                       blocks of 64 batches or more, fewer
-                                       below (default) */
+                                       regions sized exactly); 0 = 16 when
+                                       the job has 4096 batches or more over
+                                       its blocks, fewer below, keeping about
+                                       256 sampled (default) */
   SKETCH_OPT_BINNED_REGIONS = 13,   /* binned: a region holds value/64 of its
                                        estimate plus 64 code words, 0..1024;
                                        0 = 9/8 of a sampled estimate, the

@@ -1130,8 +1130,9 @@ void add_job(std::vector<Group> &groups, const sketch *s, const UpdJob &J, bool 
 
 // Pairs, blocks and pairs per block of a binned round of m pairs: about
 // 32k pairs or more per block, at most the sketch's configured count. The
-// count samples every BIN_SAMPLE-th batch of a block once the block has
-// four samples' worth of batches (fewer: a smaller stride; one: all).
+// count samples every BIN_SAMPLE-th batch of a block once the job has 256
+// samples' worth of batches over its blocks (fewer: a smaller stride; a
+// block with fewer batches than the stride samples its first).
 void bin_shape(const sketch *s, size_t m, UpdJob &J) {
   J.n = m;
   const size_t want = (m + 32767) / 32768;
@@ -1141,8 +1142,11 @@ void bin_shape(const sketch *s, size_t m, UpdJob &J) {
   J.chunk = chunk;
   J.nblk = (uint32_t)((m + chunk - 1) / chunk);
   const size_t batches = (chunk + 1024 * s->scatter_ppt - 1) / (1024 * s->scatter_ppt);
+  // about 256 sampled batches over the job's blocks at least (32 per XCD
+  // group, whose regions the estimates size), at most one in BIN_SAMPLE
   J.sample = s->bin_sample ? s->bin_sample
-                           : (uint32_t)std::max<size_t>(1, std::min<size_t>(BIN_SAMPLE, batches / 4));
+                           : (uint32_t)std::max<size_t>(
+                                 1, std::min<size_t>(BIN_SAMPLE, batches * J.nblk / 256));
   J.rscale = s->bin_rscale;
 }
 

@@ -23,6 +23,7 @@ update and the restore runs in the HIP library.
 from __future__ import annotations
 
 import dataclasses
+import gc
 import math
 import time
 from collections import OrderedDict
@@ -165,6 +166,49 @@ class _Server:
     def close(self):
         self.links.close()
 
+    def serve(self, requests) -> list:
+        """Serve the requests (see the class); one response per request, in
+        request order. Python's cycle collector is off meanwhile: a full
+        collection in the loop would stall every request in flight by
+        tens of milliseconds (reference counting still frees what the
+        loop drops)."""
+        was = gc.isenabled()
+        gc.disable()
+        try:
+            return self._serve(requests)
+        finally:
+            if was:
+                gc.enable()
+
+    def warm(self, requests, n: int = 16):
+        """Grow the device's shared buffers (update arena, restore pools)
+        before serving: one batched update of the largest windows, one per
+        link (at most n, within the budget), their batched restore and each
+        one's restore alone. The sketches are reset when their requests are
+        served, so results do not change."""
+        chosen, links, pending = [], set(), 0
+        for q in sorted(requests, key=lambda q: -q.n_pairs):
+            if len(chosen) == n:
+                break
+            need = self.links.need(q.link, q.n_pairs)
+            if q.link in links or not self.links.fits(need, links | {q.link}, pending):
+                continue
+            chosen.append(q)
+            links.add(q.link)
+            pending += need
+        if not chosen:
+            return
+        sks = [self.links.get(q.link, q.n_pairs, links) for q in chosen]
+        for sk in sks:
+            sk.reset()
+        ddhf.update_batch([(sk, q.pairs) for sk, q in zip(sks, chosen)])
+        # the batch grows the pools its jobs land on; one job alone always
+        # takes the first pool, so each window is also restored by itself
+        ddhf.restore_batch([(sk, q.theta) for sk, q in zip(sks, chosen)], raise_errors=False)
+        for sk, q in zip(sks, chosen):
+            ddhf.restore_batch([(sk, q.theta)], raise_errors=False)
+        torch.cuda.synchronize(self.dev)
+
     def __enter__(self):
         return self
 
@@ -271,7 +315,7 @@ class ContinuousServer(_Server):
             batch = [waiting[0]]
         return batch
 
-    def serve(self, requests) -> list:
+    def _serve(self, requests) -> list:
         reqs = sorted(requests, key=lambda q: q.arrival)
         out, waiting, nxt = [], [], 0
         inflight = []         # (batch, PendingRestore, done event, trace events), oldest first
@@ -338,7 +382,7 @@ class ContinuousServer(_Server):
 class PlainServer(_Server):
     """One request at a time, in arrival order: reset, update, restore."""
 
-    def serve(self, requests) -> list:
+    def _serve(self, requests) -> list:
         reqs = sorted(requests, key=lambda q: q.arrival)
         out = []
         t0 = time.perf_counter()

@@ -273,3 +273,22 @@ def test_concurrent_streams_gives_up_after_its_tries(monkeypatch):
     monkeypatch.setattr(serving, "_spin_pair_s", fq.spin)
     streams = serving.concurrent_streams(0, 2, tries=3)
     assert len(streams) == 2 and len(fq.made) == 1 + 3
+
+
+def test_warm_takes_the_largest_windows_one_per_link_within_budget(fake_lib, monkeypatch):
+    """warm() runs one batched update of the largest windows, one per link,
+    at most n, only as many as the budget holds at once."""
+    monkeypatch.setattr(serving.torch.cuda, "synchronize", lambda dev=None: None)
+    restores = []
+    monkeypatch.setattr(ddhf, "restore_batch",
+                        lambda items, stream=None, raise_errors=True: restores.append(
+                            [sk for sk, _ in items]))
+    reqs = requests(40, 10)
+    with serving.ContinuousServer(4 * one_link_bytes(max(q.n_pairs for q in reqs))) as srv:
+        srv.warm(reqs, n=6)
+    assert len(fake_lib) == 1                   # one batched update
+    batch = fake_lib[0]
+    assert 1 <= len(batch) <= 4
+    assert len({id(sk) for sk in batch}) == len(batch)
+    # their batched restore, then each one alone
+    assert restores == [batch] + [[sk] for sk in batch]

@@ -255,6 +255,11 @@ def concurrent_streams(device: int, n: int = 2, tries: int = 8, cycles: int = 2_
     if device in _CONCURRENT and len(_CONCURRENT[device]) >= n:
         return _CONCURRENT[device][:n]
     dev = torch.device("cuda", device)
+    if not hasattr(torch.cuda, "_sleep"):          # no spin kernel to check with
+        kept = list(_CONCURRENT.get(device, []))
+        kept += [torch.cuda.Stream(dev) for _ in range(n - len(kept))]
+        _CONCURRENT[device] = kept
+        return kept[:n]
     kept = list(_CONCURRENT.get(device, []))
     if not kept:
         kept.append(torch.cuda.Stream(dev))

@@ -60,9 +60,10 @@ def test_plan_replays_match_oracle_and_eager():
 
 def test_plan_buffers_grow_and_graph_is_rebuilt():
     """Plan buffers start at 16 entries: the first run's results come from
-    eager reruns, the next runs from the rebuilt graph; all match."""
+    eager reruns, the next runs from the rebuilt graph; all match. Six jobs
+    spread over all four restore pools, each of which starts small."""
     p = oracle.Params()
-    data = windows(67, [(p, 400_000, m) for m in (6, 18, 30)])
+    data = windows(67, [(p, 400_000, m) for m in (6, 10, 14, 18, 24, 30)])
     refs = [oracle.restore(p, oracle.build_sketch(p, x), 0.7 * p.g) for _, x in data]
     sks = [make_sketch(p) for _ in data]
     bufs = [to_dev(x) for _, x in data]

@@ -612,11 +612,14 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
     load(i0 + step, tid);
     __syncthreads();
     // 2: claim each tile's run, ceil(c / 3) words, in the group's region,
-    // and read the region's end (the latency of both is hidden behind the
-    // scan and step 3); run starts; the pad slots of each run get the
-    // marker ~0. The counts stay in cnt and the claimed positions wait in
-    // dst (the scan is done with it) until after the grouping: held in
-    // registers through it they would not fit the 6-pair, 5-row variant
+    // and read the region's end; run starts; the pad slots of each run get
+    // the marker ~0. The counts stay in cnt. With one tile per thread the
+    // claimed start stays in a register until after the grouping, so the
+    // wait for the atomic's return (and, the counter being in order, for
+    // the next batch's pairs) falls behind the scan and step 3, not before
+    // them; with more tiles per thread the claimed positions wait in dst
+    // (the scan is done with it): held in registers through the grouping
+    // they would not fit the 6-pair, 5-row variant
     uint32_t run[TPT], end[TPT], sum = 0;
 #pragma unroll
     for (uint32_t u = 0; u < TPT; u++) {
@@ -631,7 +634,7 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
     for (uint32_t u = 0; u < TPT; u++) {
       const uint32_t t = t0 + u, c = cnt[t], padded = 3 * ((c + 2) / 3);
       lofs[t] = ex;
-      dst[t] = run[u];
+      if constexpr (TPT > 1) dst[t] = run[u];
       if (padded > c) sorted[ex + c] = ~0u;             // at most two pad slots
       if (padded > c + 1) sorted[ex + c + 1] = ~0u;
       ex += padded;
@@ -650,7 +653,7 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
       const uint32_t w = (cnt[t] + 2) / 3;
       cnt[t] = 0;                                       // for the next batch
       if (!w) continue;
-      const uint32_t pos = dst[t];
+      const uint32_t pos = TPT > 1 ? dst[t] : run[u];
       uint32_t at = pos;
       if (pos + w > end[u]) {
         if (pos < end[u]) gmem(TS.fill)[grow + t] = pos;

@@ -325,8 +325,10 @@ def headline(args, dev) -> dict:
     sk2.close()
     assert rec["piped_sp"] == rec["n_sp"], "pipelined and serial lists differ in length"
     rec["update_ms"] = [a.elapsed_time(b) for a, b in rec["events"]]
+    # 200 latency samples at the default 50 steps, so that p99 is not the
+    # maximum of a few dozen
     sk.set_option(ddhf.SKETCH_OPT_TIMING, 1)
-    for _ in range(max(20, min(args.steps, 50))):
+    for _ in range(max(20, min(4 * args.steps, 200))):
         latency_step(rec)
     sk.set_option(ddhf.SKETCH_OPT_TIMING, 0)
     gc.enable()

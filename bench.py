@@ -683,6 +683,25 @@ def batched_run(args, dev) -> dict:
         return (time.perf_counter() - t0) / steps
 
     tg, tb, tp = timed(planned), timed(batched), timed(plain)
+
+    # where an eager cycle's time goes: the batched update by events on its
+    # stream, then (after it has finished) the batched restore of every link
+    # from the call to the lists on the host
+    stream = torch.cuda.current_stream(dev)
+    upd_ms, rst_ms = [], []
+    for _ in range(steps):
+        for sk in sks:
+            sk.reset()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ddhf.update_batch([(sk, p) for sk, p, _ in items])
+        e1.record(stream)
+        e1.synchronize()
+        upd_ms.append(e0.elapsed_time(e1))
+        t0 = time.perf_counter()
+        ddhf.restore_batch([(sk, th) for sk, _, th in items])
+        rst_ms.append((time.perf_counter() - t0) * 1e3)
     out = {"config": {"workload": "batched_64_links", "links": 64, "pairs": total,
                       "window_pairs": "log-uniform [1e6, 2e8]", "zipf_s": "U[0.8, 1.3]",
                       "planted": "U{10..500}", "theta": "512 or 1024", "k_max": 19},
@@ -693,6 +712,8 @@ def batched_run(args, dev) -> dict:
            "eager_batched_ms_per_step": round(tb * 1e3, 3),
            "plain_mpps": round(total / tp / 1e6, 2), "plain_ms_per_step": round(tp * 1e3, 3),
            "speedup_vs_plain": round(tp / tg, 3),
+           "eager_update_ms_p50": round(percentile(upd_ms, 50), 3),
+           "eager_restore_ms_p50": round(percentile(rst_ms, 50), 3),
            "windows_differing": differ,
            "super_points": int(sum(len(r[0]) for r in rg)),
            "tuned": {f"k{k}_n2^{c}": v for (k, c), v in sorted(tuned.items())},

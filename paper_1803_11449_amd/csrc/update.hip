@@ -360,7 +360,10 @@ __device__ __forceinline__ uint32_t tile_items(uint32_t v, uint32_t fresh) {
 // exceed it. Per region, in words from the job's codes: its start (regb),
 // its end (capg, which held the capacity until here), its claim cursor
 // (gcur, at the start) and its written end (fill, at the end until a run
-// crosses it). The spill cursor zeroed.
+// crosses it). The spill cursor zeroed. Thread x takes tiles x, x + 1024,
+// ... (one per round of 1024 tiles), so that a wave's loads and stores of
+// a group's row are consecutive words; a round's scan continues from the
+// rounds before it.
 __global__ __launch_bounds__(1024) void k_bin_layout(const UpdJob *__restrict__ jobs) {
   __shared__ uint32_t sh[16];
   const UpdJob &J = jobs[blockIdx.x];
@@ -369,46 +372,61 @@ __global__ __launch_bounds__(1024) void k_bin_layout(const UpdJob *__restrict__ 
   GMEM uint32_t *capg = gmem(S.capg), *fill = gmem(S.fill), *regb = gmem(S.regb);
   GMEM uint32_t *base = gmem(J.base);
   constexpr uint32_t PER = BIN_SLOTS / 1024;
-  const uint32_t t0 = threadIdx.x * PER;
-  uint32_t cap[PER][BIN_GROUPS];
-  uint64_t mine = 0;
+  const uint32_t rounds = (nbins + 1023) / 1024;
+  uint32_t cap[PER][BIN_GROUPS], mine[PER], ex[PER];
 #pragma unroll
-  for (uint32_t k = 0; k < PER; k++)
+  for (uint32_t k = 0; k < PER; k++) {
+    const uint32_t t = k * 1024 + threadIdx.x;
+    mine[k] = 0;
+    ex[k] = 0;
 #pragma unroll
     for (uint32_t g = 0; g < BIN_GROUPS; g++) {
-      const uint32_t t = t0 + k;
       cap[k][g] = t < nbins ? capg[(size_t)g * nbins + t] : 0;
-      mine += cap[k][g];
+      mine[k] += cap[k][g];
     }
-  uint32_t tot;
+  }
   // the job's words fit 32 bits (its code buffer is indexed so)
-  uint32_t ex = blk_scan_1024((uint32_t)mine, &tot, sh);
-  if (tot > J.rcap) {                                   // uniform over the block
-    mine = 0;
+  uint32_t tot = 0;
+  auto starts = [&]() {
+    tot = 0;
 #pragma unroll
-    for (uint32_t k = 0; k < PER; k++)
+    for (uint32_t k = 0; k < PER; k++) {
+      if (k < rounds) {                                 // uniform over the block
+        uint32_t tk;
+        ex[k] = tot + blk_scan_1024(mine[k], &tk, sh);
+        tot += tk;
+      }
+    }
+  };
+  starts();
+  if (tot > J.rcap) {                                   // uniform over the block
+#pragma unroll
+    for (uint32_t k = 0; k < PER; k++) {
+      mine[k] = 0;
 #pragma unroll
       for (uint32_t g = 0; g < BIN_GROUPS; g++) {
         const uint32_t c = (uint32_t)((uint64_t)cap[k][g] * J.rcap / tot) & ~1u;
         cap[k][g] = c;
-        mine += c;
+        mine[k] += c;
       }
-    ex = blk_scan_1024((uint32_t)mine, &tot, sh);
+    }
+    starts();
   }
   GMEM uint32_t *gcur = gmem(J.gcur);
 #pragma unroll
   for (uint32_t k = 0; k < PER; k++) {
-    const uint32_t t = t0 + k;
+    const uint32_t t = k * 1024 + threadIdx.x;
     if (t < nbins) {
-      base[t] = ex;
+      uint32_t e = ex[k];
+      base[t] = e;
 #pragma unroll
       for (uint32_t g = 0; g < BIN_GROUPS; g++) {
         const size_t x = (size_t)g * nbins + t;
-        regb[x] = ex;
-        gcur[x] = ex;
-        ex += cap[k][g];
-        capg[x] = ex;
-        fill[x] = ex;
+        regb[x] = e;
+        gcur[x] = e;
+        e += cap[k][g];
+        capg[x] = e;
+        fill[x] = e;
       }
     }
   }
@@ -421,7 +439,8 @@ __global__ __launch_bounds__(1024) void k_bin_layout(const UpdJob *__restrict__ 
 // Over one job's tiles (block = job), after the scatter: the words each
 // tile got (the written part of its regions and its spill runs), its apply
 // items, their starts, the scratch-slot starts (a tile cut into j items
-// owns j-1 scratch tiles) and the item count.
+// owns j-1 scratch tiles) and the item count. Tiles map to threads as in
+// the layout.
 __global__ __launch_bounds__(1024) void k_bin_items(const UpdJob *__restrict__ jobs) {
   __shared__ uint32_t sh[16];
   const UpdJob &J = jobs[blockIdx.x];
@@ -432,11 +451,11 @@ __global__ __launch_bounds__(1024) void k_bin_items(const UpdJob *__restrict__ j
   GMEM uint32_t *totals = gmem(J.totals), *item_start = gmem(J.item_start);
   GMEM uint32_t *xslot = gmem(J.xslot), *item_tile = gmem(J.item_tile);
   constexpr uint32_t PER = BIN_SLOTS / 1024;
-  const uint32_t t0 = threadIdx.x * PER;
+  const uint32_t rounds = (nbins + 1023) / 1024;
   uint32_t v[PER];
 #pragma unroll
   for (uint32_t k = 0; k < PER; k++) {
-    const uint32_t t = t0 + k;
+    const uint32_t t = k * 1024 + threadIdx.x;
     uint32_t w = 0;
     if (t < nbins) {
       w = swords[t];
@@ -449,33 +468,30 @@ __global__ __launch_bounds__(1024) void k_bin_items(const UpdJob *__restrict__ j
     }
     v[k] = w;
   }
-  uint32_t it = 0, xs = 0;
+  uint32_t ci = 0, cx = 0;                              // items, scratch slots so far
 #pragma unroll
   for (uint32_t k = 0; k < PER; k++) {
-    const uint32_t ni = t0 + k < nbins ? tile_items(v[k], J.fresh) : 0;
-    it += ni;
-    xs += ni > 1 ? ni - 1 : 0;
-  }
-  uint32_t tot_it, tot_xs;
-  uint32_t ei = blk_scan_1024(it, &tot_it, sh);
-  uint32_t ex = blk_scan_1024(xs, &tot_xs, sh);
-#pragma unroll
-  for (uint32_t k = 0; k < PER; k++) {
-    const uint32_t t = t0 + k;
-    if (t < nbins) {
-      const uint32_t ni = tile_items(v[k], J.fresh);
-      totals[t] = v[k];
-      item_start[t] = ei;
-      xslot[t] = ex;
-      for (uint32_t q = 0; q < ni; q++) item_tile[ei + q] = t;
-      ei += ni;
-      ex += ni > 1 ? ni - 1 : 0;
+    if (k < rounds) {                                   // uniform over the block
+      const uint32_t t = k * 1024 + threadIdx.x;
+      const uint32_t ni = t < nbins ? tile_items(v[k], J.fresh) : 0;
+      const uint32_t xs = ni > 1 ? ni - 1 : 0;
+      uint32_t ti, tx;
+      const uint32_t ei = ci + blk_scan_1024(ni, &ti, sh);
+      const uint32_t ex = cx + blk_scan_1024(xs, &tx, sh);
+      if (t < nbins) {
+        totals[t] = v[k];
+        item_start[t] = ei;
+        xslot[t] = ex;
+        for (uint32_t q = 0; q < ni; q++) item_tile[ei + q] = t;
+      }
+      ci += ti;
+      cx += tx;
     }
   }
   if (threadIdx.x == 0) {
-    item_start[nbins] = tot_it;
-    xslot[nbins] = tot_xs;
-    *gmem(J.n_items) = tot_it;
+    item_start[nbins] = ci;
+    xslot[nbins] = cx;
+    *gmem(J.n_items) = ci;
   }
 }
 
@@ -562,11 +578,12 @@ __global__ __launch_bounds__(1024) void k_bin_scatter(const UpdJob *__restrict__
   if (p0 >= p1) return;                                // uniform over the block
   const size_t step = (size_t)blockDim.x * PPT;
   // A batch's pairs are held in pr. The next batch's pairs are loaded into
-  // pr as soon as this batch's codes are made (step 1), so they arrive
-  // while the batch is sorted and written, and no second set of registers
-  // is live. Loads past the chunk re-read its last pair (their lanes are
-  // masked later): with no branch around them the compiler need not wait
-  // for every load in flight.
+  // pr as soon as this batch's codes are made (step 1), so they are in
+  // flight through the claims and the scan (and, with one tile per thread,
+  // the grouping: the first wait that covers them is the one for the
+  // claims, see step 2), and no second set of registers is live. Loads past
+  // the chunk re-read its last pair (their lanes are masked later): with no
+  // branch around them the compiler need not wait for every load in flight.
   uint2 pr[PPT];
   auto load = [&](size_t b0, uint32_t tid) {
 #pragma unroll

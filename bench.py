@@ -466,8 +466,9 @@ def stream_run(args, dev) -> dict:
     over 8M sources, 1000 planted with 20% replaced each window), each
     generated on the device from its own seed before timing, then processed
     back to back on one k = 18 sketch: reset, update, restore with the list
-    on the host. Sustained rate against the 117 Mpps line rate (750 Gb/s at
-    800-byte packets)."""
+    on the host; then the same windows double-buffered on two sketches and
+    two streams. Sustained rates against the 117 Mpps line rate (750 Gb/s
+    at 800-byte packets)."""
     import torch
     from paper_1803_11449_amd import ddhf, traffic
     nw = args.stream_windows
@@ -495,6 +496,35 @@ def stream_run(args, dev) -> dict:
             recs, _ = sk.restore(1024.0)
             sps.append(len(recs))
         dt = time.perf_counter() - t0
+    # the same windows double-buffered, as a monitor would run them: two
+    # sketches on two streams, window w+1 reset and updated while window w
+    # restores (the headline step's pipelining)
+    from paper_1803_11449_amd import serving
+    streams = serving.concurrent_streams(0, 2)
+    piped_sps = []
+    with ddhf.Sketch(1024, k, 5, alpha, traffic.HASH_SEED, device=0) as s0, \
+            ddhf.Sketch(1024, k, 5, alpha, traffic.HASH_SEED, device=0) as s1:
+        pipe = [s0, s1]
+
+        def piped(ws, out):
+            pending = None
+            for i, p in enumerate(ws):
+                s_, st_ = pipe[i % 2], streams[i % 2]
+                s_.reset(st_)
+                s_.update(p, st_)
+                nxt = ddhf.restore_batch_begin([(s_, 1024.0)], st_)
+                if pending is not None:
+                    out.append(len(pending.end()[0][0]))
+                pending = nxt
+            out.append(len(pending.end()[0][0]))
+
+        piped(wins[:2], [])                                 # warm up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        piped(wins, piped_sps)
+        torch.cuda.synchronize()
+        dt_piped = time.perf_counter() - t0
+    assert piped_sps == sps, "pipelined and serial stream lists differ in length"
     del wins
     torch.cuda.empty_cache()
     total = n * nw
@@ -504,6 +534,9 @@ def stream_run(args, dev) -> dict:
             "line_rate_mpps": 117.0,
             "x_line_rate": round(total / dt / 1e6 / 117.0, 1),
             "ms_per_window": round(dt / nw * 1e3, 4),
+            "pipelined_mpps": round(total / dt_piped / 1e6, 1),
+            "pipelined_x_line_rate": round(total / dt_piped / 1e6 / 117.0, 1),
+            "pipelined_ms_per_window": round(dt_piped / nw * 1e3, 4),
             "super_points_mean": round(sum(sps) / len(sps), 1)}
 
 

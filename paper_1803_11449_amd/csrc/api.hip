@@ -1129,13 +1129,14 @@ void add_job(std::vector<Group> &groups, const sketch *s, const UpdJob &J, bool 
 }
 
 // Pairs, blocks and pairs per block of a binned round of m pairs: about
-// 32k pairs or more per block, at most the sketch's configured count. The
+// min_chunk pairs or more per block, at most the sketch's configured
+// count. The
 // count samples every BIN_SAMPLE-th batch of a block once the job has 256
 // samples' worth of batches over its blocks (fewer: a smaller stride; a
 // block with fewer batches than the stride samples its first).
-void bin_shape(const sketch *s, size_t m, UpdJob &J) {
+void bin_shape(const sketch *s, size_t m, size_t min_chunk, UpdJob &J) {
   J.n = m;
-  const size_t want = (m + 32767) / 32768;
+  const size_t want = (m + min_chunk - 1) / min_chunk;
   J.nblk = (uint32_t)std::max<size_t>(1, std::min<size_t>(s->bin_nblk, want));
   size_t chunk = (m + J.nblk - 1) / J.nblk;
   chunk += chunk & 1;
@@ -1207,6 +1208,13 @@ int schedule_update(const sketch_update_job_t *jobs, size_t n_jobs, Base base, F
       left[j]--;
     }
   }
+  // pairs per block at least: 4096 per binned job of the call, up to 32768.
+  // A window alone spreads over many compute units (a 1M-pair window takes
+  // 245 blocks, against 31 at 32k pairs per block); the jobs of a batch
+  // share them, and more blocks per job would only add per-block work
+  size_t n_binned = 0;
+  for (size_t j = 0; j < n_jobs; j++) n_binned += binned[j] ? 1 : 0;
+  const size_t min_chunk = std::min<size_t>(32768, 4096 * std::max<size_t>(1, n_binned));
   for (;;) {
     bool any = false;
     for (size_t j = 0; j < n_jobs; j++) {
@@ -1223,7 +1231,7 @@ int schedule_update(const sketch_update_job_t *jobs, size_t n_jobs, Base base, F
           g.pairs = 0;
         }
         const size_t m = std::min({left[j], s->binned_round, ARENA_MAX_PAIRS - g.pairs});
-        bin_shape(s, m, J);
+        bin_shape(s, m, min_chunk, J);
         if (fresh) {
           J.fresh = (uint32_t)fresh[j];
           fresh[j] = 0;

@@ -45,9 +45,12 @@ def check_against(resps, ref, what):
 
 
 def test_servers_equal_oracle_and_alone(pools):
-    # a burst of windows from 12 links within 1 ms, so batches form, links repeat
-    reqs = serving.poisson_windows(pools, n_links=12, rate_pps=4e10, duration_s=0.001,
-                                   lo=100_000, hi=3_000_000, seed=3, theta=(512.0, 1024.0))
+    # a burst of windows from 12 links within 3 ms, so batches form and links
+    # repeat; windows of 1M-6M pairs, so that a batch's work on the device
+    # outlasts the host's turn between batches (with windows of 0.1M-3M the
+    # device could finish a batch before the host enqueued the next)
+    reqs = serving.poisson_windows(pools, n_links=12, rate_pps=4e10, duration_s=0.003,
+                                   lo=1_000_000, hi=6_000_000, seed=3, theta=(512.0, 1024.0))
     assert len(reqs) >= 20
     print(f"serving: {len(reqs)} windows, oracle restores", flush=True)
     ref = oracle_results(reqs)

@@ -146,7 +146,7 @@ def time_restore(sk: ddhf.Sketch, theta: float, trials: int = 3) -> float:
     return statistics.median(ts[1:])        # the first run grows buffers
 
 
-def tune_restore(sk: ddhf.Sketch, theta: float, n_pairs: int, trials: int = 3,
+def tune_restore(sk: ddhf.Sketch, theta: float, n_pairs: int, trials: int = 5,
                  use_cache: bool = True) -> dict:
     """The fastest candidate search for windows like the one sk holds now
     (updated, not reset) at theta: {"ms": ..., "cand": ..., "jblocks": ...}.

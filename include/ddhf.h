@@ -371,11 +371,14 @@ enum {
                                        a spill area (small values force that,
                                        for tests) */
   SKETCH_OPT_JOIN_BLOCKS = 14       /* blocks of each join stage (Algs. 3-4),
-                                       1 to four per compute unit; 0 = four
-                                       per compute unit (default). Each block
-                                       takes an equal share of the stage's
-                                       items and writes its own segment of
-                                       partial addresses */
+                                       1 to four per compute unit; 0
+                                       (default) = four per compute unit, or
+                                       one when the sketch's last restore
+                                       had fewer stage-1 wave items (|HE(0)|
+                                       times ceil(|HE(1)| / 64)) than compute
+                                       units. Each block takes an equal share
+                                       of the stage's items and writes its
+                                       own segment of partial addresses */
 };
 
 /* Phases of the last restore that ran with SKETCH_OPT_TIMING on (device

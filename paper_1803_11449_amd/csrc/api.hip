@@ -596,7 +596,7 @@ struct sketch {
   Geom G;
   Lattice lat{};                // row 0's cells as lattice boxes (restore)
   uint32_t cand_path = 0;       // SKETCH_OPT_CANDIDATES: 0 auto, 1 join, 2 lattice
-  uint32_t join_blocks = 0;     // SKETCH_OPT_JOIN_BLOCKS: 0 = the device's (4 per CU)
+  uint32_t join_blocks = 0;     // SKETCH_OPT_JOIN_BLOCKS: 0 = by the last restore's hot lists
   DevCtx *ctx = nullptr;
   mutable Lane lane;            // last work on this sketch (any stream)
   // a restore begun by sketch_restore_batch_begin and not yet ended: its
@@ -655,6 +655,7 @@ struct sketch {
   size_t ran_seg_cap = 0, ran_cand_cap = 0, ran_spl_cap = 0, ran_h_recs_cap = 0;
   int ran_pool = 0;             // the pool that restore ran on
   uint64_t cost_hint = 0;       // the last restore's row-0 cells times their addresses
+  uint64_t join_hint = 0;       // the last restore's join wave items of stage 1 (0: none yet)
 };
 
 namespace {
@@ -716,8 +717,15 @@ RestoreBufs restore_bufs(const sketch *s, const RPool &p) {
   B.segc[0] = p.segc[0];
   B.segc[1] = p.segc[1];
   B.seg_cap = p.seg_cap;
-  // fewer join blocks use the first of the pool's segments
-  B.jblk = s->join_blocks ? std::min(s->join_blocks, c->jblk) : c->jblk;
+  // fewer join blocks use the first of the pool's segments. Unset, the
+  // join takes four blocks per compute unit, or one when the sketch's last
+  // restore had fewer stage-1 wave items than compute units: short hot
+  // lists leave most of a larger grid idle, and each block still loads its
+  // bucket table
+  const uint32_t n_cu = c->jblk / 4;
+  B.jblk = s->join_blocks ? std::min(s->join_blocks, c->jblk)
+           : (s->join_hint && s->join_hint < n_cu) ? n_cu
+                                                    : c->jblk;
   B.cand = p.cand;
   B.cand_sorted = p.cand_sorted;
   B.cand_cap = p.cand_cap;
@@ -838,7 +846,9 @@ double restore_cost(const sketch *s) {
 }
 
 void note_cost(sketch *s, const DevState &h) {
-  if (!h.saturated) s->cost_hint = (uint64_t)h.he_count[0] << (32 - s->p.k);
+  if (h.saturated) return;
+  s->cost_hint = (uint64_t)h.he_count[0] << (32 - s->p.k);
+  s->join_hint = std::max<uint64_t>(1, (uint64_t)h.he_count[0] * ((h.he_count[1] + 63) / 64));
 }
 
 // Pools of a batch's jobs: the costliest job first, each to the pool with

@@ -1140,10 +1140,9 @@ void add_job(std::vector<Group> &groups, const sketch *s, const UpdJob &J, bool 
 
 // Pairs, blocks and pairs per block of a binned round of m pairs: about
 // min_chunk pairs or more per block, at most the sketch's configured
-// count. The
-// count samples every BIN_SAMPLE-th batch of a block once the job has 256
-// samples' worth of batches over its blocks (fewer: a smaller stride; a
-// block with fewer batches than the stride samples its first).
+// count. The count samples every BIN_SAMPLE-th batch of a block once the
+// job has 256 samples' worth of batches over its blocks (fewer: a smaller
+// stride; a block with fewer batches than the stride samples its first).
 void bin_shape(const sketch *s, size_t m, size_t min_chunk, UpdJob &J) {
   J.n = m;
   const size_t want = (m + min_chunk - 1) / min_chunk;

@@ -331,8 +331,11 @@ enum {
                                        (4 and 6 both ask for that), and 2
                                        for r >= 6 */
   SKETCH_OPT_BINNED_BLOCKS = 7,     /* binned: blocks of the count and
-                                       scatter passes, 1..1024 (default: one
-                                       per compute unit) */
+                                       scatter passes at most, 1..1024
+                                       (default: one per compute unit); a
+                                       window takes fewer when it has less
+                                       than 4096 pairs per block per binned
+                                       job of the call (32768 at most) */
   SKETCH_OPT_TRIM_POOLS = 8,        /* device-wide, acts at once: waits for
                                        pending work on the shared buffers,
                                        frees the update arena and reallocates
